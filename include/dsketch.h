@@ -1,0 +1,192 @@
+/*
+ * dsketch.h -- C ABI of the deterministic-sketch low-rank SVD / row-ID path
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Dunton & Doostan, "Deterministic matrix sketches for low-rank
+ * compression of high-dimensional simulation data" (arXiv 2105.01271).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * A is an m x n snapshot matrix, ROW-MAJOR with leading dimension lda >= n:
+ *    one row per snapshot (time step / parameter), one column per fine-grid
+ *    dof (Sec. 2).  A 2-D field on an ny x nx grid is flattened y-major
+ *    (column = iy*nx + ix).
+ *  * Every array argument is a DEVICE pointer owned by the caller unless it is
+ *    marked "host".  The library never frees caller memory and keeps no
+ *    pointer past the call.
+ *  * Storage dtypes of A: DSK_F64, DSK_F32, DSK_BF16, DSK_F16.  The work dtype
+ *    (dtype of every floating output except S and P) is F64 for F64 input and
+ *    F32 otherwise.  Singular values S and the interpolation matrix P are F64.
+ *  * Work is enqueued on the handle's stream and is asynchronous: outputs are
+ *    valid after the stream is synchronised.  Passing a non-NULL dsk_info
+ *    makes the call synchronise the stream before it returns.
+ *  * Return value: 0 on success; -i when argument i (1-based) is invalid,
+ *    detected on the host before anything is enqueued (no side effects);
+ *    DSK_ERR_* (> 100) for HIP runtime errors (100 + hipError_t).
+ *    Numerical events (fallback taken, rank deficiency, non-finite input)
+ *    are reported through dsk_info.flags, not through the return value.
+ *  * Scratch memory comes from a per-handle arena that grows on demand
+ *    (hipMalloc) and is reused across calls; the first call at a new largest
+ *    size allocates.
+ *  * A handle is bound to one device and one stream and must not be used by
+ *    two host threads at once.
+ */
+#ifndef DSKETCH_H
+#define DSKETCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dsk_handle dsk_handle;
+
+enum { DSK_F64 = 0, DSK_F32 = 1, DSK_BF16 = 2, DSK_F16 = 3 };
+
+/* Restriction kinds: the sketch D of A_c = A D (Sec. 2), never formed. */
+enum {
+  DSK_R_INDEX = 0,   /* direct injection / Gram sub-sample: A_c = A(:, index) (Sec. 2; Alg. 7) */
+  DSK_R_NN = 1,      /* nearest neighbour, weights (1/4,1/2,1/4) per axis around DI points (Sec. 2) */
+  DSK_R_GLOBAL = 2,  /* global sketch: mean over the sy x sx block at each DI point (Sec. 2) */
+  DSK_R_LEARNED = 3  /* learned linear 2-layer strided conv (not in the paper) */
+};
+
+/* Product modes for F32 input (B = Q^T A and the coarse power products). */
+enum {
+  DSK_MODE_DEFAULT = 0,  /* = DSK_MODE_SPLIT6 */
+  DSK_MODE_SPLIT3 = 1,   /* A and Q split into bf16 hi+lo halves, 3 bf16 MFMA products (~2^-16 relative) */
+  DSK_MODE_F32 = 2,      /* plain f32 MFMA products */
+  DSK_MODE_SPLIT6 = 3    /* A and Q split exactly into three bf16 pieces, the 6 products of order >= 2^-16
+                            kept (~2^-24 relative, f32 rounding level), f32 accumulation */
+};
+
+/* flag bits reported in dsk_info.flags */
+enum {
+  DSK_FLAG_FALLBACK = 1,        /* a shifted Cholesky-QR fallback was taken */
+  DSK_FLAG_RANK_DEFICIENT = 2,  /* a triangular factor had a negligible pivot */
+  DSK_FLAG_NONFINITE = 4,       /* NaN/Inf met in a Gram or residual norm */
+  DSK_FLAG_BAD_INDEX = 8        /* an index of the restriction was outside [0, n); column 0 was used */
+};
+
+typedef struct {
+  int32_t kind;            /* DSK_R_* */
+  int64_t s;               /* DSK_R_INDEX: number of coarse columns |I| */
+  const int64_t *index;    /* DSK_R_INDEX: device, s distinct column indices in [0, n) */
+  int32_t ny, nx;          /* NN / GLOBAL / LEARNED: fine grid, n = ny*nx */
+  int32_t sy, sx;          /* NN / GLOBAL: coarse factor per axis (coarse grid ceil(ny/sy) x ceil(nx/sx)) */
+  int32_t channels;        /* LEARNED: hidden channels C */
+  const float *w1;         /* LEARNED: device, layer-1 taps [C][5][5], stride 2, pad 2 */
+  const float *w2;         /* LEARNED: device, layer-2 taps [C][5][5], stride 2, pad 2 */
+} dsk_restriction;
+
+typedef struct {
+  int32_t p;          /* oversampling; range-finder width ell = min(k+p, s, m); default 10 */
+  const void *S;      /* optional device s x ell second-level sketch, row-major, work dtype;
+                         NULL = nested direct injection (every floor(s/ell)-th coarse column) */
+  int32_t ell;        /* width of S when S != NULL */
+  double tau;         /* coarse Gram scale (Sec. 5); <= 0 means n/s */
+  int32_t id_projected; /* sketch_id: 0 = ID of W_q = (tau A_c A_c^T)^q A_c (full coarse sketch),
+                           1 = ID of the ell-wide block (tau A_c A_c^T)^q A_c S */
+  int32_t mode;       /* DSK_MODE_* (F32 input only) */
+  int32_t refine;     /* 1 = one refinement sweep (second orthonormalisation + re-projection) */
+} dsk_opts;
+
+typedef struct {       /* host struct, filled when passed */
+  int32_t ell;         /* range-finder width used */
+  int32_t flags;       /* DSK_FLAG_* bits */
+  double normA_fro2;   /* ||A||_F^2 (sketch_svd only) */
+  double normB_fro2;   /* ||Q^T A||_F^2 (sketch_svd only): projection error^2 = normA - normB */
+  double sigma_tail;   /* sigma_{k+1} of B = Q^T A when ell > k, else 0 */
+} dsk_info;
+
+/* Fill *o with the defaults listed above. */
+void dsk_opts_default(dsk_opts *o);
+
+/* Create a handle bound to `device` and `stream` (a hipStream_t; NULL = default stream).
+   *h receives the handle.  Errors: -1 (h NULL), DSK_ERR_* (HIP). */
+int dsk_create(dsk_handle **h, int device, void *stream);
+int dsk_destroy(dsk_handle *h);
+/* Rebind the handle's stream. */
+int dsk_set_stream(dsk_handle *h, void *stream);
+
+/*
+ * dsk_restrict -- A_c = A D for the given restriction (Sec. 2 sketch equation;
+ * direct injection, nearest-neighbour and global sketch equations; learned conv).
+ *   A    (1) device m x n, row-major, lda
+ *   Ac   (8) device m x s output, row-major compact, work dtype
+ * Argument numbers: h=1, A=2, dtype=3, m=4, n=5, lda=6, R=7, Ac=8.
+ */
+int dsk_restrict(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                 const dsk_restriction *R, void *Ac);
+
+/*
+ * dsk_project -- B^T = A^T Q, the projection B = Q^T A of TPC-SVD (Alg. 2;
+ * Sec. 3.1) written transposed: the one full pass over A.
+ * Arguments: h=1, A=2, dtype=3, m=4, n=5, lda=6, Q=7 (m x ell row-major, work dtype),
+ *   ell=8 (1..112), Bt=9 (n x ell row-major, work dtype), mode=10 (DSK_MODE_*).
+ */
+int dsk_project(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                const void *Q, int32_t ell, void *Bt, int32_t mode);
+
+/*
+ * dsk_sketch_svd -- rank-k SVD A ~ U diag(S) V^T by TPC-SVD (Alg. 2) with q
+ * steps of the single-pass coarse power iteration C-PWR (Alg. 7):
+ *   A_c = A D; Y = A_c S_ell; Q = orth(Y); q times { Z = orth(tau A_c^T Q); Q = orth(A_c Z) };
+ *   B = Q^T A (the one full pass over A); SVD(B) = U_B Sigma V_B^T;
+ *   U = Q U_B(:, :k), S = Sigma(:k), V = V_B(:, :k).
+ * Each (u_j, v_j) is sign-normalised so the largest-magnitude entry of u_j
+ * (lowest index on ties) is positive.
+ * Arguments: h=1, A=2, dtype=3, m=4, n=5, lda=6, k=7 (1 <= k <= ell), R=8, q=9 (>= 0),
+ *   o=10 (host, may be NULL = defaults), U=11 (m x k row-major, work dtype),
+ *   S=12 (k, F64), V=13 (n x k row-major, work dtype), info=14 (host, may be NULL).
+ */
+int dsk_sketch_svd(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                   int32_t k, const dsk_restriction *R, int32_t q, const dsk_opts *o,
+                   void *U, double *S, void *V, dsk_info *info);
+
+/*
+ * dsk_sketch_id -- rank-k row interpolative decomposition A ~ P A(I, :) by
+ * TPC-ID (Alg. 4): column-pivoted QR of W^T (Sec. 4, row ID) with W = A_c, or
+ * W = (tau A_c A_c^T)^q A_c for q >= 1 (C-PWR without re-orthonormalisation),
+ * pivots = largest residual norm, recomputed every step (lowest index on
+ * exact ties); C = R_1^{-1} R_2; P(I, :) = I_k, P(rest, :) = C^T.
+ * Arguments: h=1, A=2, dtype=3, m=4, n=5, lda=6, k=7 (1 <= k <= min(m, s) or ell),
+ *   R=8, q=9, o=10 (host, may be NULL), skel=11 (k int64, 0-based row indices in pivot order),
+ *   P=12 (m x k row-major F64), skel_rows=13 (k x n row-major in A's dtype, or NULL),
+ *   info=14 (host, may be NULL).
+ */
+int dsk_sketch_id(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                  int32_t k, const dsk_restriction *R, int32_t q, const dsk_opts *o,
+                  int64_t *skel, double *P, void *skel_rows, dsk_info *info);
+
+/*
+ * dsk_power_iter -- the C-PWR loop alone (Alg. 7):
+ *   q times { G = tau A_c^T G; [G = orth(G)]; G = A_c G; [G = orth(G)] }
+ * starting from G = Q0.  reorth = 1 orthonormalises after every product
+ * (result = orthonormal m x ell basis), reorth = 0 returns the raw block.
+ * Arguments: h=1, Ac=2 (m x s row-major, ldc), dtype=3 (DSK_F64 or DSK_F32), m=4, s=5,
+ *   ldc=6, Q0=7 (m x ell row-major), ell=8, q=9, tau=10, reorth=11, Qout=12 (m x ell).
+ */
+int dsk_power_iter(dsk_handle *h, const void *Ac, int32_t dtype, int64_t m, int64_t s, int64_t ldc,
+                   const void *Q0, int32_t ell, int32_t q, double tau, int32_t reorth, void *Qout);
+
+/*
+ * Event timing of the projection kernel B^T = A^T Q (the dominant pass), for
+ * benchmarks.  While enabled, dsk_sketch_svd and dsk_project bracket that one
+ * kernel with two hipEvents recorded on the handle's stream (up to 4096 launches).
+ * dsk_timing_read synchronises the stream, returns the number of timed launches
+ * and their summed duration in milliseconds, and restarts the count.
+ * Arguments: h=1, enable=2 / h=1, count=2 (host), total_ms=3 (host).
+ */
+int dsk_timing_enable(dsk_handle *h, int enable);
+int dsk_timing_read(dsk_handle *h, int *count, double *total_ms);
+
+/* Human-readable text of a return code. */
+const char *dsk_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DSKETCH_H */

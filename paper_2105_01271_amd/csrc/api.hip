@@ -1,0 +1,507 @@
+// extern "C" entry points of libdsketch: argument validation, workspace
+// carving and the launch sequence of each operation.  Every numerical step is
+// one of the HIP kernels of this library; the host only validates, carves the
+// arena and enqueues work on the handle's stream.
+#include <string.h>
+
+#include <algorithm>
+
+#include "dsk_internal.h"
+
+namespace {
+
+constexpr int ELL_CAP = 112;
+
+__global__ void k_zero_flags(int *f) {
+  if (threadIdx.x < FLAGW_COUNT) f[threadIdx.x] = 0;
+}
+
+__global__ void k_scale(void *x, int f64, int64_t count, double a) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
+    if (f64) reinterpret_cast<double *>(x)[t] *= a;
+    else reinterpret_cast<float *>(x)[t] = (float)(reinterpret_cast<float *>(x)[t] * a);
+  }
+}
+
+// sigma from eigenvalues (is_lam) or singular values; S out; V column scale;
+// info scalars: [0] = sum of all sigma^2 (= ||B||_F^2), [1] = sigma_{k+1}.
+__global__ void k_finish(const double *__restrict__ vals, int is_lam, int ell, int k, const double *__restrict__ sign,
+                         int divide, double *__restrict__ S, double *__restrict__ colscale, double *__restrict__ info) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s1 = 0.0, tot = 0.0;
+  for (int j = 0; j < ell; ++j) {
+    const double v = vals[j];
+    const double sg = is_lam ? sqrt(v > 0.0 ? v : 0.0) : v;
+    tot += sg * sg;
+    if (j == 0) s1 = sg;
+    if (j < k) {
+      S[j] = sg;
+      double cs = sign ? sign[j] : 1.0;
+      if (divide) cs = (sg > 1e-300 && sg > 1e-13 * s1) ? cs / sg : 0.0;
+      colscale[j] = cs;
+    }
+  }
+  info[0] = tot;
+  info[1] = (ell > k) ? (is_lam ? sqrt(vals[k] > 0.0 ? vals[k] : 0.0) : vals[k]) : 0.0;
+}
+
+void launch_scale(hipStream_t st, void *x, int f64, int64_t count, double a) {
+  const unsigned blocks = (unsigned)std::min<int64_t>((count + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_scale, dim3(blocks), dim3(256), 0, st, x, f64, count, a);
+}
+
+int valid_dtype(int dt) { return dt >= DSK_F64 && dt <= DSK_F16; }
+
+// coarse size of a restriction, or a negative value when invalid
+int64_t coarse_size(const dsk_restriction *R, int64_t n) {
+  if (!R) return -1;
+  switch (R->kind) {
+    case DSK_R_INDEX:
+      if (R->s < 1 || R->s > n || !R->index) return -1;
+      return R->s;
+    case DSK_R_NN:
+    case DSK_R_GLOBAL:
+      if (R->ny < 1 || R->nx < 1 || (int64_t)R->ny * R->nx != n || R->sy < 1 || R->sx < 1) return -1;
+      return (int64_t)((R->ny + R->sy - 1) / R->sy) * ((R->nx + R->sx - 1) / R->sx);
+    default:
+      return -1;   // learned restriction: dsk_conv_restrict_fwd
+  }
+}
+
+struct Finish {
+  dsk_handle *h;
+  int flags_on_host;
+};
+
+int read_info(dsk_handle *h, const double *dinfo, dsk_info *info, int ell) {
+  if (!info) return 0;
+  int flags = 0;
+  double vals[3] = {0, 0, 0};
+  DSK_TRY(hipMemcpyAsync(&flags, h->dflags, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  if (dinfo) DSK_TRY(hipMemcpyAsync(vals, dinfo, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  DSK_TRY(hipStreamSynchronize(h->stream));
+  info->ell = ell;
+  info->flags = flags;
+  info->normA_fro2 = vals[2];
+  info->normB_fro2 = vals[0];
+  info->sigma_tail = vals[1];
+  return 0;
+}
+
+// Orthonormalise a rows x ell block in place-ish: Q = orth(Y).  f64 uses
+// Householder (tmp: rows*ell f64 scratch, R: ell^2), f32 uses CholeskyQR2.
+int orth(dsk_handle *h, const void *Y, int f64, int64_t rows, int ell, void *Q, void *tmp, void *cws, double *R) {
+  if (f64) {
+    DSK_RET(launch_convert(h->stream, Y, 1, tmp, 1, rows * ell));
+    return launch_hhqr(h->stream, (double *)tmp, rows, ell, (double *)Q, R, h->dflags);
+  }
+  return launch_cholqr2(h->stream, Y, 0, rows, ell, Q, cws, h->dflags, R);
+}
+
+}  // namespace
+
+int arena_reserve(dsk_handle *h, size_t bytes) {
+  if (bytes <= h->arena_bytes) return 0;
+  if (h->arena) {
+    DSK_TRY(hipStreamSynchronize(h->stream));
+    DSK_TRY(hipFree(h->arena));
+    h->arena = nullptr;
+    h->arena_bytes = 0;
+  }
+  const size_t want = (bytes + (size_t(1) << 20) - 1) & ~((size_t(1) << 20) - 1);
+  DSK_TRY(hipMalloc(&h->arena, want));
+  h->arena_bytes = want;
+  return 0;
+}
+
+extern "C" {
+
+void dsk_opts_default(dsk_opts *o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->p = 10;
+  o->tau = 0.0;
+  o->mode = DSK_MODE_DEFAULT;
+}
+
+int dsk_create(dsk_handle **h, int device, void *stream) {
+  if (!h) return -1;
+  *h = nullptr;
+  DSK_TRY(hipSetDevice(device));
+  dsk_handle *x = new dsk_handle();
+  x->device = device;
+  x->stream = reinterpret_cast<hipStream_t>(stream);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 256;
+  x->cu_count = cus;
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) lds = 65536;
+  x->max_lds = (size_t)lds;
+  if (hipMalloc(&x->dflags, 256) != hipSuccess) {
+    delete x;
+    return DSK_ERR_BASE + (int)hipErrorOutOfMemory;
+  }
+  hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, x->stream, x->dflags);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(x->stream) != hipSuccess) {
+    hipFree(x->dflags);
+    delete x;
+    return DSK_ERR_BASE + (int)hipErrorLaunchFailure;
+  }
+  *h = x;
+  return 0;
+}
+
+int dsk_destroy(dsk_handle *h) {
+  if (!h) return -1;
+  hipSetDevice(h->device);
+  hipStreamSynchronize(h->stream);
+  if (h->arena) (void)hipFree(h->arena);
+  if (h->dflags) (void)hipFree(h->dflags);
+  if (h->tev) {
+    for (int i = 0; i < 2 * TIMING_CAP; ++i) (void)hipEventDestroy(h->tev[i]);
+    delete[] h->tev;
+  }
+  delete h;
+  return 0;
+}
+
+int dsk_set_stream(dsk_handle *h, void *stream) {
+  if (!h) return -1;
+  h->stream = reinterpret_cast<hipStream_t>(stream);
+  return 0;
+}
+
+const char *dsk_status_string(int status) {
+  if (status == 0) return "success";
+  if (status < 0) {
+    static const char *names[] = {"", "argument 1 invalid", "argument 2 invalid", "argument 3 invalid",
+                                  "argument 4 invalid", "argument 5 invalid", "argument 6 invalid",
+                                  "argument 7 invalid", "argument 8 invalid", "argument 9 invalid",
+                                  "argument 10 invalid", "argument 11 invalid", "argument 12 invalid",
+                                  "argument 13 invalid", "argument 14 invalid"};
+    const int i = -status;
+    return i < 15 ? names[i] : "invalid argument";
+  }
+  if (status >= DSK_ERR_BASE) return hipGetErrorString((hipError_t)(status - DSK_ERR_BASE));
+  return "unknown status";
+}
+
+int dsk_restrict(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                 const dsk_restriction *R, void *Ac) {
+  if (!h) return -1;
+  if (!A) return -2;
+  if (!valid_dtype(dtype)) return -3;
+  if (m < 1) return -4;
+  if (n < 1) return -5;
+  if (lda < n) return -6;
+  const int64_t s = coarse_size(R, n);
+  if (s < 1) return -7;
+  if (!Ac) return -8;
+  DSK_TRY(hipSetDevice(h->device));
+  hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, h->stream, h->dflags);
+  return launch_restrict(h->stream, A, dtype, m, n, lda, R, s, dtype == DSK_F64, Ac, nullptr, h->dflags);
+}
+
+int dsk_project(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, const void *Q,
+                int32_t ell, void *Bt, int32_t mode) {
+  if (!h) return -1;
+  if (!A) return -2;
+  if (!valid_dtype(dtype)) return -3;
+  if (m < 1) return -4;
+  if (n < 1) return -5;
+  if (lda < n) return -6;
+  if (!Q) return -7;
+  if (ell < 1 || ell > ELL_CAP) return -8;
+  if (!Bt) return -9;
+  if (mode < 0 || mode > DSK_MODE_SPLIT6) return -10;
+  DSK_TRY(hipSetDevice(h->device));
+  DSK_RET(arena_reserve(h, stream_ws_bytes(dtype, m, n, ell, mode)));
+  hipEvent_t e0, e1;
+  timing_slot(h, &e0, &e1);
+  return launch_stream(h->stream, A, dtype, m, n, lda, Q, dtype == DSK_F64, ell, Bt, ell, mode, h->arena,
+                       h->cu_count, e0, e1);
+}
+
+int dsk_timing_enable(dsk_handle *h, int enable) {
+  if (!h) return -1;
+  DSK_TRY(hipSetDevice(h->device));
+  if (enable && !h->tev) {
+    h->tev = new hipEvent_t[2 * TIMING_CAP];
+    for (int i = 0; i < 2 * TIMING_CAP; ++i) DSK_TRY(hipEventCreate(&h->tev[i]));
+  }
+  h->timing = enable ? 1 : 0;
+  h->tcount = 0;
+  return 0;
+}
+
+int dsk_timing_read(dsk_handle *h, int *count, double *total_ms) {
+  if (!h) return -1;
+  if (!count) return -2;
+  if (!total_ms) return -3;
+  *count = 0;
+  *total_ms = 0.0;
+  if (!h->tev || h->tcount == 0) return 0;
+  DSK_TRY(hipStreamSynchronize(h->stream));
+  double tot = 0.0;
+  for (int i = 0; i < h->tcount; ++i) {
+    float ms = 0.f;
+    DSK_TRY(hipEventElapsedTime(&ms, h->tev[2 * i], h->tev[2 * i + 1]));
+    tot += ms;
+  }
+  *count = h->tcount;
+  *total_ms = tot;
+  h->tcount = 0;
+  return 0;
+}
+
+int dsk_sketch_svd(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,
+                   const dsk_restriction *R, int32_t q, const dsk_opts *o, void *U, double *S, void *V,
+                   dsk_info *info) {
+  if (!h) return -1;
+  if (!A) return -2;
+  if (!valid_dtype(dtype)) return -3;
+  if (m < 1) return -4;
+  if (n < 1) return -5;
+  if (lda < n) return -6;
+  const int64_t s = coarse_size(R, n);
+  dsk_opts od;
+  dsk_opts_default(&od);
+  if (o) od = *o;
+  if (od.p < 0) return -10;
+  int64_t ell = od.S ? od.ell : std::min<int64_t>(std::min<int64_t>((int64_t)k + od.p, s), m);
+  if (s < 1) return -8;
+  if (od.S && (od.ell < 1 || od.ell > std::min<int64_t>(s, m))) return -10;
+  ell = std::min<int64_t>(ell, ELL_CAP);
+  if (k < 1 || k > ell) return -7;
+  if (q < 0 || q > 64) return -9;
+  if (od.mode < 0 || od.mode > DSK_MODE_SPLIT6) return -10;
+  if (!U) return -11;
+  if (!S) return -12;
+  if (!V) return -13;
+  DSK_TRY(hipSetDevice(h->device));
+  hipStream_t st = h->stream;
+  const int f64 = dtype == DSK_F64;
+  const size_t we = f64 ? 8 : 4;
+  const int L = (int)ell;
+  const int64_t rmax = std::max<int64_t>(std::max<int64_t>(m, s), n);
+  // ---- workspace
+  Carve c{nullptr, 0, 0, true};
+  for (int pass = 0; pass < 2; ++pass) {
+    c.off = 0;
+    char *Ac = c.take<char>((size_t)m * s * we);
+    char *Y = c.take<char>((size_t)m * L * we);
+    char *Q = c.take<char>((size_t)m * L * we);
+    char *Z = c.take<char>((size_t)s * L * we);
+    char *Bt = c.take<char>((size_t)n * L * we);
+    double *tmp = f64 ? c.take<double>((size_t)rmax * L) : nullptr;
+    double *QB = f64 ? c.take<double>((size_t)n * L) : nullptr;
+    char *cws = c.take<char>(cholqr2_ws_bytes(std::max(m, s), L));
+    size_t sws_b = std::max(stream_ws_bytes(dtype, m, n, L, od.mode), stream_ws_bytes(f64 ? DSK_F64 : DSK_F32, m, s, L, od.mode));
+    sws_b = std::max(sws_b, stream_ws_bytes(f64 ? DSK_F64 : DSK_F32, s, m, L, od.mode));
+    char *sws = c.take<char>(sws_b);
+    const int nparts = 240;
+    double *part = c.take<double>((size_t)nparts * L * L);
+    double *lam = c.take<double>(L);
+    double *UB = c.take<double>((size_t)L * L);
+    double *Ur = c.take<double>((size_t)L * L);
+    double *RB = c.take<double>((size_t)L * L);
+    double *Rsm = c.take<double>((size_t)L * L);
+    double *sign = c.take<double>(L);
+    double *colscale = c.take<double>(L);
+    double *dinfo = c.take<double>(4);
+    double *fpart = c.take<double>(1024);
+    if (pass == 0) {
+      DSK_RET(arena_reserve(h, c.off));
+      c.base = h->arena;
+      c.cap = h->arena_bytes;
+      c.dry = false;
+      continue;
+    }
+    // ---- launch sequence
+    hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, st, h->dflags);
+    const int wdt = f64 ? DSK_F64 : DSK_F32;
+    DSK_RET(launch_restrict(st, A, dtype, m, n, lda, R, s, f64, Ac, nullptr, h->dflags));
+    if (od.S) DSK_RET(launch_stream_nn(st, Ac, wdt, m, s, s, od.S, L, Y, L, od.mode, sws, h->cu_count));
+    else DSK_RET(launch_select_cols(st, Ac, f64, m, s, s, L, Y));
+    DSK_RET(orth(h, Y, f64, m, L, Q, tmp, cws, Rsm));
+    for (int it = 0; it < q; ++it) {
+      // Z = A_c^T Q (s x ell), orthonormalised; Q = orth(A_c Z).  tau cancels under re-orthonormalisation.
+      DSK_RET(launch_stream(st, Ac, wdt, m, s, s, Q, f64, L, Z, L, od.mode, sws, h->cu_count));
+      DSK_RET(orth(h, Z, f64, s, L, Z, tmp, cws, Rsm));
+      DSK_RET(launch_stream_nn(st, Ac, wdt, m, s, s, Z, L, Y, L, od.mode, sws, h->cu_count));
+      DSK_RET(orth(h, Y, f64, m, L, Q, tmp, cws, Rsm));
+    }
+    // B^T = A^T Q: the single full pass over A
+    hipEvent_t e0, e1;
+    timing_slot(h, &e0, &e1);
+    DSK_RET(launch_stream(st, A, dtype, m, n, lda, Q, f64, L, Bt, L, od.mode, sws, h->cu_count, e0, e1));
+    if (od.refine && !f64) {
+      // one refinement sweep: re-orthonormalise Q against the projected block and re-project
+      DSK_RET(orth(h, Q, f64, m, L, Y, tmp, cws, Rsm));
+      DSK_RET(launch_convert(st, Y, 0, Q, 0, m * L));
+      DSK_RET(launch_stream(st, A, dtype, m, n, lda, Q, f64, L, Bt, L, od.mode, sws, h->cu_count));
+    }
+    if (!f64) {
+      DSK_RET(launch_gram(st, Bt, 0, n, L, nullptr, part, nparts));
+      DSK_RET(launch_jacobi_eig_parts(st, part, nparts, L, lam, UB, h->dflags));
+      DSK_RET(launch_tsmm(st, Q, 0, m, L, L, UB, L, k, nullptr, U, k));
+      DSK_RET(launch_sign_fix(st, U, 0, m, k, sign));
+      hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, lam, 1, L, k, sign, 1, S, colscale, dinfo);
+      DSK_RET(launch_tsmm(st, Bt, 0, n, L, L, UB, L, k, colscale, V, k));
+    } else {
+      DSK_RET(launch_convert(st, Bt, 1, tmp, 1, n * L));
+      DSK_RET(launch_hhqr(st, tmp, n, L, QB, RB, h->dflags));
+      DSK_RET(launch_jacobi_svd(st, RB, L, lam, UB, Ur, h->dflags));
+      DSK_RET(launch_tsmm(st, Q, 1, m, L, L, UB, L, k, nullptr, U, k));
+      DSK_RET(launch_sign_fix(st, U, 1, m, k, sign));
+      hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, lam, 0, L, k, sign, 0, S, colscale, dinfo);
+      DSK_RET(launch_tsmm(st, QB, 1, n, L, L, Ur, L, k, colscale, V, k));
+    }
+    DSK_TRY(hipGetLastError());
+    if (info) {
+      DSK_RET(launch_fro2(st, A, dtype, m, n, lda, fpart, 1024, dinfo + 2));
+    }
+    return read_info(h, dinfo, info, L);
+  }
+  return 0;
+}
+
+int dsk_sketch_id(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,
+                  const dsk_restriction *R, int32_t q, const dsk_opts *o, int64_t *skel, double *P, void *skel_rows,
+                  dsk_info *info) {
+  if (!h) return -1;
+  if (!A) return -2;
+  if (!valid_dtype(dtype)) return -3;
+  if (m < 1) return -4;
+  if (n < 1) return -5;
+  if (lda < n) return -6;
+  const int64_t s = coarse_size(R, n);
+  if (s < 1) return -8;
+  dsk_opts od;
+  dsk_opts_default(&od);
+  if (o) od = *o;
+  if (od.p < 0) return -10;
+  int64_t cols = s;
+  int64_t ell = 0;
+  if (od.id_projected) {
+    ell = od.S ? od.ell : std::min<int64_t>(std::min<int64_t>((int64_t)k + od.p, s), m);
+    if (od.S && (od.ell < 1 || od.ell > s)) return -10;
+    ell = std::min<int64_t>(ell, ELL_CAP);
+    cols = ell;
+  }
+  if (k < 1 || k > std::min<int64_t>(m, cols) || k > 112) return -7;
+  if (q < 0 || q > 64) return -9;
+  if (!skel) return -11;
+  if (!P) return -12;
+  DSK_TRY(hipSetDevice(h->device));
+  hipStream_t st = h->stream;
+  const double tau = od.tau > 0.0 ? od.tau : (double)n / (double)s;
+  Carve c{nullptr, 0, 0, true};
+  for (int pass = 0; pass < 2; ++pass) {
+    c.off = 0;
+    double *Ac = c.take<double>((size_t)m * s);
+    double *W = c.take<double>((size_t)m * cols);
+    double *W2 = c.take<double>((size_t)m * cols);
+    double *M = (q > 0 && !od.id_projected) ? c.take<double>((size_t)m * m) : nullptr;
+    double *Zs = od.id_projected ? c.take<double>((size_t)s * cols) : nullptr;
+    char *sws = c.take<char>(std::max(stream_ws_bytes(DSK_F64, m, s, (int)std::max<int64_t>(ell, 1), 0),
+                                      stream_ws_bytes(DSK_F64, s, m, (int)std::max<int64_t>(ell, 1), 0)));
+    double *nu0 = c.take<double>(m);
+    double *nu1 = c.take<double>(m);
+    double *Rk = c.take<double>((size_t)k * m);
+    if (pass == 0) {
+      DSK_RET(arena_reserve(h, c.off));
+      c.base = h->arena;
+      c.cap = h->arena_bytes;
+      c.dry = false;
+      continue;
+    }
+    hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, st, h->dflags);
+    // A_c in FP64 (exact for every storage dtype)
+    DSK_RET(launch_restrict(st, A, dtype, m, n, lda, R, s, 1, Ac, nullptr, h->dflags));
+    double *Wcur = nullptr;
+    if (od.id_projected) {
+      if (od.S) {
+        DSK_RET(launch_stream_nn(st, Ac, DSK_F64, m, s, s, od.S, (int)ell, W, ell, 0, sws, h->cu_count));
+      } else {
+        DSK_RET(launch_select_cols(st, Ac, 1, m, s, s, (int)ell, W));
+      }
+      for (int it = 0; it < q; ++it) {
+        DSK_RET(launch_stream(st, Ac, DSK_F64, m, s, s, W, 1, (int)ell, Zs, ell, 0, sws, h->cu_count));
+        launch_scale(st, Zs, 1, s * ell, tau);
+        DSK_RET(launch_stream_nn(st, Ac, DSK_F64, m, s, s, Zs, (int)ell, W, ell, 0, sws, h->cu_count));
+      }
+      Wcur = W;
+    } else if (q > 0) {
+      // (tau A_c A_c^T)^q A_c evaluated as M = tau A_c A_c^T, W <- M W (same product, reassociated)
+      DSK_RET(launch_gemm64(st, 0, 1, m, m, s, tau, Ac, s, Ac, s, M, m));
+      const double *src = Ac;
+      double *bufs[2] = {W, W2};
+      for (int it = 0; it < q; ++it) {
+        DSK_RET(launch_gemm64(st, 0, 0, m, s, m, 1.0, M, m, src, s, bufs[it & 1], s));
+        src = bufs[it & 1];
+      }
+      Wcur = const_cast<double *>(src);
+    } else {
+      Wcur = Ac;
+    }
+    DSK_RET(launch_cpqr(st, Wcur, m, cols, k, nu0, nu1, Rk, skel, h->dflags));
+    const double *nu_final = ((k - 1) & 1) ? nu0 : nu1;
+    DSK_RET(launch_id_solve(st, Rk, skel, nu_final, m, k, P, h->dflags));
+    if (skel_rows) DSK_RET(launch_gather_rows(st, A, dtype, m, n, lda, skel, k, skel_rows));
+    DSK_TRY(hipGetLastError());
+    return read_info(h, nullptr, info, (int)(od.id_projected ? ell : 0));
+  }
+  return 0;
+}
+
+int dsk_power_iter(dsk_handle *h, const void *Ac, int32_t dtype, int64_t m, int64_t s, int64_t ldc, const void *Q0,
+                   int32_t ell, int32_t q, double tau, int32_t reorth, void *Qout) {
+  if (!h) return -1;
+  if (!Ac) return -2;
+  if (dtype != DSK_F64 && dtype != DSK_F32) return -3;
+  if (m < 1) return -4;
+  if (s < 1) return -5;
+  if (ldc < s) return -6;
+  if (!Q0) return -7;
+  if (ell < 1 || ell > std::min<int64_t>(std::min<int64_t>(m, s), ELL_CAP)) return -8;
+  if (q < 0 || q > 64) return -9;
+  if (!(tau > 0.0)) return -10;
+  if (!Qout) return -12;
+  DSK_TRY(hipSetDevice(h->device));
+  hipStream_t st = h->stream;
+  const int f64 = dtype == DSK_F64;
+  const size_t we = f64 ? 8 : 4;
+  Carve c{nullptr, 0, 0, true};
+  for (int pass = 0; pass < 2; ++pass) {
+    c.off = 0;
+    char *Z = c.take<char>((size_t)s * ell * we);
+    char *G = c.take<char>((size_t)m * ell * we);
+    double *tmp = c.take<double>((size_t)std::max(m, s) * ell);
+    char *cws = c.take<char>(cholqr2_ws_bytes(std::max(m, s), ell));
+    char *sws = c.take<char>(std::max(stream_ws_bytes(dtype, m, s, ell, 0), stream_ws_bytes(dtype, s, m, ell, 0)));
+    double *Rsm = c.take<double>((size_t)ell * ell);
+    if (pass == 0) {
+      DSK_RET(arena_reserve(h, c.off));
+      c.base = h->arena;
+      c.cap = h->arena_bytes;
+      c.dry = false;
+      continue;
+    }
+    hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, st, h->dflags);
+    DSK_RET(launch_convert(st, Q0, f64, Qout, f64, m * ell));
+    for (int it = 0; it < q; ++it) {
+      DSK_RET(launch_stream(st, Ac, dtype, m, s, ldc, Qout, f64, ell, Z, ell, 0, sws, h->cu_count));
+      if (reorth) DSK_RET(orth(h, Z, f64, s, ell, Z, tmp, cws, Rsm));
+      else launch_scale(st, Z, f64, s * ell, tau);
+      DSK_RET(launch_stream_nn(st, Ac, dtype, m, s, ldc, Z, ell, G, ell, 0, sws, h->cu_count));
+      if (reorth) DSK_RET(orth(h, G, f64, m, ell, Qout, tmp, cws, Rsm));
+      else DSK_RET(launch_convert(st, G, f64, Qout, f64, m * ell));
+    }
+    DSK_TRY(hipGetLastError());
+    return 0;
+  }
+  return 0;
+}
+
+}  // extern "C"

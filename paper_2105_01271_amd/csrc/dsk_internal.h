@@ -1,0 +1,130 @@
+// Internal declarations shared by the HIP translation units of libdsketch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/dsketch.h"
+
+#define DSK_ERR_BASE 100
+#define DSK_TRY(expr)                                          \
+  do {                                                         \
+    hipError_t e__ = (expr);                                   \
+    if (e__ != hipSuccess) return DSK_ERR_BASE + (int)e__;     \
+  } while (0)
+#define DSK_RET(expr)                                          \
+  do {                                                         \
+    int r__ = (expr);                                          \
+    if (r__ != 0) return r__;                                  \
+  } while (0)
+
+// Device-side status words (one int per flag slot).
+enum { FLAGW_BITS = 0, FLAGW_COUNT = 4 };
+
+struct dsk_handle {
+  int device;
+  hipStream_t stream;
+  char *arena;
+  size_t arena_bytes;
+  int *dflags;        // device flag words (FLAGW_COUNT ints), persistent
+  int cu_count;
+  size_t max_lds;
+  // optional event timing of the projection kernel (B^T = A^T Q)
+  int timing;
+  int tcount;
+  hipEvent_t *tev;    // 2 * TIMING_CAP events
+};
+
+constexpr int TIMING_CAP = 4096;
+
+// next (start, stop) event pair for a timed projection launch, or nulls
+inline void timing_slot(dsk_handle *h, hipEvent_t *e0, hipEvent_t *e1) {
+  *e0 = *e1 = nullptr;
+  if (h->timing && h->tev && h->tcount < TIMING_CAP) {
+    *e0 = h->tev[2 * h->tcount];
+    *e1 = h->tev[2 * h->tcount + 1];
+    ++h->tcount;
+  }
+}
+
+// Bump allocator over the handle arena; sizes are 256-byte aligned.
+struct Carve {
+  char *base;
+  size_t off;
+  size_t cap;
+  bool dry;           // true: only count bytes
+  template <class T>
+  T *take(size_t count) {
+    size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+    T *p = dry ? nullptr : reinterpret_cast<T *>(base + off);
+    off += bytes;
+    return p;
+  }
+};
+
+int arena_reserve(dsk_handle *h, size_t bytes);
+
+// Kernels whose dynamic LDS exceeds 64 KB must opt in (gfx950 offers 160 KB per workgroup).
+template <typename K>
+inline void allow_lds(K kernel, size_t bytes) {
+  if (bytes > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)bytes);
+}
+
+// ---------------------------------------------------------------- launchers
+// restrict.hip
+int launch_restrict(hipStream_t st, const void *A, int dtype, int64_t m, int64_t n, int64_t lda,
+                    const dsk_restriction *R, int64_t s, int work_f64, void *Ac, void *AcT, int *dflags);
+int launch_select_cols(hipStream_t st, const void *Ac, int work_f64, int64_t m, int64_t s,
+                       int64_t ldc, int ell, void *Y);
+int launch_gather_rows(hipStream_t st, const void *A, int dtype, int64_t m, int64_t n, int64_t lda,
+                       const int64_t *rows, int k, void *out);
+int launch_convert(hipStream_t st, const void *src, int src_f64, void *dst, int dst_f64, int64_t count);
+int launch_transpose(hipStream_t st, const void *src, int f64, int64_t rows, int64_t cols, void *dst);
+
+// smallmat.hip (tall-skinny orthonormalisation, small factorizations)
+size_t cholqr2_ws_bytes(int64_t rows, int ell);
+int launch_cholqr2(hipStream_t st, const void *Y, int f64, int64_t rows, int ell, void *Q,
+                   void *ws, int *dflags, double *Rout);
+int launch_hhqr(hipStream_t st, double *X, int64_t rows, int ell, double *Q, double *R, int *dflags);
+int launch_gram(hipStream_t st, const void *X, int f64, int64_t rows, int ell, double *G,
+                double *part, int nparts);
+int launch_jacobi_eig_parts(hipStream_t st, const double *part, int nparts, int ell, double *lam, double *V,
+                            int *dflags);
+int launch_jacobi_eig(hipStream_t st, const double *G, int ell, double *lam, double *V, int *dflags);
+int launch_jacobi_svd(hipStream_t st, const double *Rm, int ell, double *sig, double *Vr,
+                      double *Ur, int *dflags);
+int launch_tsmm(hipStream_t st, const void *X, int f64, int64_t rows, int ell, int64_t ldx,
+                const double *M, int ldm, int kout, const double *colscale, void *out, int64_t ldo);
+int launch_sign_fix(hipStream_t st, void *U, int f64, int64_t m, int k, double *sign);
+int launch_fro2(hipStream_t st, const void *A, int dtype, int64_t m, int64_t n, int64_t lda,
+                double *part, int nparts, double *out);
+
+// stream.hip (B^T = X^T Y and X Y for tall-skinny Y)
+size_t stream_ws_bytes(int dtype, int64_t K, int64_t N, int ell, int mode);
+int launch_stream(hipStream_t st, const void *X, int dtype, int64_t K, int64_t N, int64_t ldx,
+                  const void *Y, int f64y, int ell, void *out, int64_t ldo, int mode, void *ws,
+                  int cu_count, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+int launch_stream_nn(hipStream_t st, const void *X, int dtype, int64_t M, int64_t K, int64_t ldx,
+                     const void *Y, int ell, void *out, int64_t ldo, int mode, void *ws, int cu_count);
+
+// cpqr.hip (row ID)
+int launch_cpqr(hipStream_t st, double *W, int64_t m, int64_t s, int k, double *nu0, double *nu1,
+                double *Rk, int64_t *piv, int *dflags);
+int launch_id_solve(hipStream_t st, const double *Rk, const int64_t *piv, const double *nu_final,
+                    int64_t m, int k, double *P, int *dflags);
+
+// gemm64.hip (small FP64 GEMM for the full-sketch ID power block)
+int launch_gemm64(hipStream_t st, int transA, int transB, int64_t M, int64_t N, int64_t K,
+                  double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                  double *C, int64_t ldc);
+
+// device helpers
+__device__ __forceinline__ float bf16_bits_to_f32(unsigned short b) {
+  return __uint_as_float(((unsigned)b) << 16);
+}
+__device__ __forceinline__ float f16_bits_to_f32(unsigned short b) {
+  return (float)__builtin_bit_cast(_Float16, b);
+}

@@ -1,0 +1,602 @@
+// Tall-skinny products of the sketch pipeline:
+//   TN form  out (N x ell) = X^T Y,  X is K x N row-major  (B^T = A^T Q, Eq. for B in
+//            Sec. 3.1 / Alg. 2; Z = A_c^T Q of Alg. 7)
+//   NN form  out (M x ell) = X Y,    X is M x K row-major  (A_c Z of Alg. 7; A_c S)
+// Y is K x ell row-major.  The TN form with X = A is the single full pass over
+// the snapshot matrix and dominates the memory traffic of the method (its
+// leading mnn_c cost, Sec. 5 complexity table).
+//
+// MFMA path (f32 / bf16 / f16 storage of X):
+//   * A wave owns JT 16-wide column tiles of the output rows (j) and all
+//     NCT 16-wide tiles of ell (c).  D[c][j] += Y^T[c][k] X[k][j] on the
+//     16x16 MFMA shapes; lane l handles k = k0 + 8*(l/16) + e, e = 0..7, for
+//     both operands, so the K order inside one instruction is the same for A
+//     and B and the lane layout of K never matters.
+//   * Y is packed once per call into that lane order (NV x uint4 per lane per
+//     (32-row block, c tile)) so each wave reads it with 16-byte loads.
+//   * SPLIT6 mode (default for f32): every f32 value is split exactly into
+//     three bf16 pieces x = x1 + x2 + x3 (RNE, each remainder exact in f32);
+//     the product keeps the six terms y_i x_j with i + j <= 4, each exact on
+//     the bf16 MFMA pipe, so the dropped terms are ~2^-24 relative: f32
+//     rounding level with f32 accumulation.
+//   * SPLIT3 mode: two pieces, Yhi*Xhi + Yhi*Xlo + Ylo*Xhi (dropped terms
+//     ~2^-16 relative).  F32 mode uses the f32 MFMA (16x16x4) directly.
+//     Stored bf16/f16 X needs no split: Yhi*X + Ylo*X.
+//   * The 4 waves of a workgroup share the same output tile and take every
+//     4th 32-row block of the K range; their accumulators are reduced in LDS
+//     in a fixed order (deterministic).  Small N is split over K across
+//     workgroups (grid.y) and summed by a second kernel in a fixed order.
+// FP64 path: VALU kernel with LDS tiles (f64 FMA), same TN/NN forms.
+#include <algorithm>
+
+#include "dsk_internal.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int MODE_SPLIT3 = 1;
+constexpr int MODE_F32 = 2;
+constexpr int MODE_BF16X = 3;   // X stored bf16, Y split hi/lo
+constexpr int MODE_F16X = 4;    // X stored f16, Y split hi/lo (f16)
+constexpr int MODE_SPLIT6 = 5;  // f32 X and Y in three bf16 pieces each
+
+template <int MODE>
+constexpr int nv_of() { return MODE == MODE_SPLIT6 ? 3 : 2; }
+
+// ---------------------------------------------------------------- Y packing
+// Yp[((kb*nct + ct)*NV + v)*64 + lane] : uint4
+//   SPLIT6:       v=0,1,2 -> 8 bf16 pieces y1, y2, y3
+//   SPLIT3/BF16X: v=0 -> 8 bf16 hi, v=1 -> 8 bf16 lo
+//   F16X:         v=0 -> 8 f16 hi,  v=1 -> 8 f16 lo
+//   F32:          v=0 -> floats e=0..3, v=1 -> floats e=4..7
+// with element e of lane l holding Y[kb*32 + 8*(l/16) + e][ct*16 + l%16] (0 outside).
+template <int MODE, typename TY>
+__global__ void __launch_bounds__(64) k_pack_y(const TY *__restrict__ Y, int64_t K, int ell,
+                                               int64_t ldy, int nct, uint4 *__restrict__ Yp) {
+  const int kb = blockIdx.x, ct = blockIdx.y, l = threadIdx.x;
+  const int c = ct * 16 + (l & 15);
+  float v[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int64_t k = (int64_t)kb * 32 + 8 * (l >> 4) + e;
+    v[e] = (k < K && c < ell) ? (float)Y[k * ldy + c] : 0.0f;
+  }
+  constexpr int NV = nv_of<MODE>();
+  uint4 *dst = Yp + ((int64_t)(kb * nct + ct) * NV) * 64 + l;
+  if constexpr (MODE == MODE_SPLIT6) {
+    bf16x8 p1, p2, p3;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const __bf16 a1 = (__bf16)v[e];
+      const float r1 = v[e] - (float)a1;
+      const __bf16 a2 = (__bf16)r1;
+      const float r2 = r1 - (float)a2;
+      p1[e] = a1;
+      p2[e] = a2;
+      p3[e] = (__bf16)r2;
+    }
+    dst[0] = __builtin_bit_cast(uint4, p1);
+    dst[64] = __builtin_bit_cast(uint4, p2);
+    dst[128] = __builtin_bit_cast(uint4, p3);
+  } else if constexpr (MODE == MODE_F32) {
+    dst[0] = make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]), __float_as_uint(v[3]));
+    dst[64] = make_uint4(__float_as_uint(v[4]), __float_as_uint(v[5]), __float_as_uint(v[6]), __float_as_uint(v[7]));
+  } else if constexpr (MODE == MODE_F16X) {
+    f16x8 hi, lo;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const _Float16 h = (_Float16)v[e];
+      hi[e] = h;
+      lo[e] = (_Float16)(v[e] - (float)h);
+    }
+    dst[0] = __builtin_bit_cast(uint4, hi);
+    dst[64] = __builtin_bit_cast(uint4, lo);
+  } else {
+    bf16x8 hi, lo;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const __bf16 h = (__bf16)v[e];
+      hi[e] = h;
+      lo[e] = (__bf16)(v[e] - (float)h);
+    }
+    dst[0] = __builtin_bit_cast(uint4, hi);
+    dst[64] = __builtin_bit_cast(uint4, lo);
+  }
+}
+
+// ---------------------------------------------------------------- X fragment loads
+// Raw 8 K-values of one output column j for this lane, as 32-bit floats or
+// 16-bit patterns.  TN: X[k][j] (k strided by ldx).  NN: X[j][k] (contiguous).
+template <bool NN>
+__device__ __forceinline__ void load_x_f32(const float *__restrict__ X, int64_t K, int64_t N, int64_t ldx,
+                                           int64_t kbase, int64_t j, float (&x)[8]) {
+  if (j >= N) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x[e] = 0.0f;
+    return;
+  }
+  if constexpr (NN) {
+    const float *p = X + j * ldx + kbase;
+    if (kbase + 8 <= K && ((reinterpret_cast<uintptr_t>(p) & 15) == 0)) {
+      const float4 a = *reinterpret_cast<const float4 *>(p);
+      const float4 b = *reinterpret_cast<const float4 *>(p + 4);
+      x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+      x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) x[e] = (kbase + e < K) ? p[e] : 0.0f;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x[e] = (kbase + e < K) ? X[(kbase + e) * ldx + j] : 0.0f;
+  }
+}
+
+template <bool NN>
+__device__ __forceinline__ void load_x_u16(const unsigned short *__restrict__ X, int64_t K, int64_t N,
+                                           int64_t ldx, int64_t kbase, int64_t j, unsigned short (&x)[8]) {
+  if (j >= N) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x[e] = 0;
+    return;
+  }
+  if constexpr (NN) {
+    const unsigned short *p = X + j * ldx + kbase;
+    if (kbase + 8 <= K && ((reinterpret_cast<uintptr_t>(p) & 15) == 0)) {
+      const uint4 a = *reinterpret_cast<const uint4 *>(p);
+      const unsigned w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        x[2 * e] = (unsigned short)(w[e] & 0xffffu);
+        x[2 * e + 1] = (unsigned short)(w[e] >> 16);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) x[e] = (kbase + e < K) ? p[e] : (unsigned short)0;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x[e] = (kbase + e < K) ? X[(kbase + e) * ldx + j] : (unsigned short)0;
+  }
+}
+
+__device__ __forceinline__ f32x4 mfma_bf16(uint4 a, uint4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                 c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma_f16(uint4 a, uint4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
+                                                0, 0, 0);
+}
+
+// ---------------------------------------------------------------- MFMA stream kernel
+// grid: x = ceil(N / (16*JT)) column groups, y = K splits.  block: 256 (4 waves).
+// Split y covers 32-row blocks [y*kb_per_split, min(nkb, (y+1)*kb_per_split)).
+// Output: out[j*ldo + c] (+ split*N*ldo when nsplit > 1, written to `out` as partials).
+template <int MODE, bool NN, int NCT, int JT>
+__global__ void __launch_bounds__(256) k_stream_mfma(const void *__restrict__ Xv, int64_t K, int64_t N,
+                                                     int64_t ldx, const uint4 *__restrict__ Yp, int ell,
+                                                     float *__restrict__ out, int64_t ldo, int kb_per_split) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, col = lane & 15;
+  const int nkb = (int)((K + 31) / 32);
+  const int kb_begin = blockIdx.y * kb_per_split;
+  const int kb_end = min(nkb, kb_begin + kb_per_split);
+  const int64_t j0 = (int64_t)blockIdx.x * (16 * JT);
+
+  f32x4 acc[NCT][JT];
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+    for (int jt = 0; jt < JT; ++jt) acc[ct][jt] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  constexpr int NV = nv_of<MODE>();
+  for (int kb = kb_begin + wave; kb < kb_end; kb += 4) {
+    const int64_t kbase = (int64_t)kb * 32 + 8 * g;
+    uint4 ya[NCT], yb[NCT], yc[NCT];
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+      const uint4 *src = Yp + ((int64_t)(kb * NCT + ct) * NV) * 64 + lane;
+      ya[ct] = src[0];
+      yb[ct] = src[64];
+      if constexpr (NV == 3) yc[ct] = src[128];
+    }
+    if constexpr (MODE == MODE_SPLIT3 || MODE == MODE_F32 || MODE == MODE_SPLIT6) {
+      const float *X = reinterpret_cast<const float *>(Xv);
+      float xv[JT][8];
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt) load_x_f32<NN>(X, K, N, ldx, kbase, j0 + 16 * jt + col, xv[jt]);
+      if constexpr (MODE == MODE_SPLIT6) {
+#pragma unroll
+        for (int jt = 0; jt < JT; ++jt) {
+          bf16x8 p1, p2, p3;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const __bf16 a1 = (__bf16)xv[jt][e];
+            const float r1 = xv[jt][e] - (float)a1;
+            const __bf16 a2 = (__bf16)r1;
+            p1[e] = a1;
+            p2[e] = a2;
+            p3[e] = (__bf16)(r1 - (float)a2);
+          }
+          const uint4 x1 = __builtin_bit_cast(uint4, p1), x2 = __builtin_bit_cast(uint4, p2),
+                      x3 = __builtin_bit_cast(uint4, p3);
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct) {
+            // smallest terms first into the running sum: (1,3),(3,1),(2,2),(1,2),(2,1),(1,1)
+            acc[ct][jt] = mfma_bf16(ya[ct], x3, acc[ct][jt]);
+            acc[ct][jt] = mfma_bf16(yc[ct], x1, acc[ct][jt]);
+            acc[ct][jt] = mfma_bf16(yb[ct], x2, acc[ct][jt]);
+            acc[ct][jt] = mfma_bf16(ya[ct], x2, acc[ct][jt]);
+            acc[ct][jt] = mfma_bf16(yb[ct], x1, acc[ct][jt]);
+            acc[ct][jt] = mfma_bf16(ya[ct], x1, acc[ct][jt]);
+          }
+        }
+      } else if constexpr (MODE == MODE_SPLIT3) {
+#pragma unroll
+        for (int jt = 0; jt < JT; ++jt) {
+          bf16x8 hi, lo;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const __bf16 h = (__bf16)xv[jt][e];
+            hi[e] = h;
+            lo[e] = (__bf16)(xv[jt][e] - (float)h);
+          }
+          const uint4 xh = __builtin_bit_cast(uint4, hi), xl = __builtin_bit_cast(uint4, lo);
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct) {
+            acc[ct][jt] = mfma_bf16(ya[ct], xh, acc[ct][jt]);
+            acc[ct][jt] = mfma_bf16(ya[ct], xl, acc[ct][jt]);
+            acc[ct][jt] = mfma_bf16(yb[ct], xh, acc[ct][jt]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+          const float yv[8] = {__uint_as_float(ya[ct].x), __uint_as_float(ya[ct].y), __uint_as_float(ya[ct].z),
+                               __uint_as_float(ya[ct].w), __uint_as_float(yb[ct].x), __uint_as_float(yb[ct].y),
+                               __uint_as_float(yb[ct].z), __uint_as_float(yb[ct].w)};
+#pragma unroll
+          for (int jt = 0; jt < JT; ++jt)
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+              acc[ct][jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(yv[e], xv[jt][e], acc[ct][jt], 0, 0, 0);
+        }
+      }
+    } else {
+      const unsigned short *X = reinterpret_cast<const unsigned short *>(Xv);
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt) {
+        unsigned short xs[8];
+        load_x_u16<NN>(X, K, N, ldx, kbase, j0 + 16 * jt + col, xs);
+        const uint4 xp = make_uint4((unsigned)xs[0] | ((unsigned)xs[1] << 16), (unsigned)xs[2] | ((unsigned)xs[3] << 16),
+                                    (unsigned)xs[4] | ((unsigned)xs[5] << 16), (unsigned)xs[6] | ((unsigned)xs[7] << 16));
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+          if constexpr (MODE == MODE_BF16X) {
+            acc[ct][jt] = mfma_bf16(ya[ct], xp, acc[ct][jt]);
+            acc[ct][jt] = mfma_bf16(yb[ct], xp, acc[ct][jt]);
+          } else {
+            acc[ct][jt] = mfma_f16(ya[ct], xp, acc[ct][jt]);
+            acc[ct][jt] = mfma_f16(yb[ct], xp, acc[ct][jt]);
+          }
+        }
+      }
+    }
+  }
+
+  // fixed-order reduction of the 4 waves' partial tiles: ((w2+w0)+(w3+w1)), then (w1'+w0')
+  __shared__ f32x4 red[2][NCT * JT][64];
+  if (wave >= 2) {
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt) red[wave - 2][ct * JT + jt][lane] = acc[ct][jt];
+  }
+  __syncthreads();
+  if (wave < 2) {
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt) acc[ct][jt] += red[wave][ct * JT + jt][lane];
+  }
+  __syncthreads();
+  if (wave == 1) {
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt) red[0][ct * JT + jt][lane] = acc[ct][jt];
+  }
+  __syncthreads();
+  if (wave != 0) return;
+  float *dst = out + (int64_t)blockIdx.y * N * ldo;
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) {
+    const int c0 = ct * 16 + 4 * g;
+#pragma unroll
+    for (int jt = 0; jt < JT; ++jt) {
+      const f32x4 v = acc[ct][jt] + red[0][ct * JT + jt][lane];
+      const int64_t j = j0 + 16 * jt + col;
+      if (j >= N) continue;
+      float *p = dst + j * ldo + c0;
+      if (c0 + 3 < ell && ((reinterpret_cast<uintptr_t>(p) & 15) == 0)) {
+        *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (c0 + r < ell) p[r] = v[r];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- FP64 VALU stream kernel
+// Block 256 threads computes a 64 (j) x ELLP (c) tile; thread t owns columns
+// j = 4*(t%16)+0..3 and c = (t/16) + 16*u, u < ELLP/16.
+template <bool NN, int ELLP>
+__global__ void __launch_bounds__(256) k_stream_f64(const double *__restrict__ X, int64_t K, int64_t N,
+                                                    int64_t ldx, const double *__restrict__ Y, int ell,
+                                                    double *__restrict__ out, int64_t ldo, int kb_per_split) {
+  constexpr int KT = 16;
+  constexpr int CU = ELLP / 16;
+  __shared__ double xs[KT][64 + 1];
+  __shared__ double ys[KT][ELLP + 1];
+  const int t = threadIdx.x;
+  const int tj = t & 15, tc = t >> 4;
+  const int64_t j0 = (int64_t)blockIdx.x * 64;
+  const int64_t kbeg = (int64_t)blockIdx.y * kb_per_split * KT;
+  const int64_t kend = std::min<int64_t>(K, kbeg + (int64_t)kb_per_split * KT);
+  double acc[4][CU];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int u = 0; u < CU; ++u) acc[a][u] = 0.0;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += KT) {
+    // X tile: xs[kk][jj]
+    for (int e = t; e < KT * 64; e += 256) {
+      int kk, jj;
+      if constexpr (NN) { jj = e / KT; kk = e % KT; } else { kk = e / 64; jj = e % 64; }
+      const int64_t k = k0 + kk, j = j0 + jj;
+      double v = 0.0;
+      if (k < kend && j < N) v = NN ? X[j * ldx + k] : X[k * ldx + j];
+      xs[kk][jj] = v;
+    }
+    for (int e = t; e < KT * ELLP; e += 256) {
+      const int kk = e / ELLP, c = e % ELLP;
+      const int64_t k = k0 + kk;
+      ys[kk][c] = (k < kend && c < ell) ? Y[k * ell + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < KT; ++kk) {
+      double xv[4], yv[CU];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) xv[a] = xs[kk][4 * tj + a];
+#pragma unroll
+      for (int u = 0; u < CU; ++u) yv[u] = ys[kk][tc + 16 * u];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int u = 0; u < CU; ++u) acc[a][u] = fma(xv[a], yv[u], acc[a][u]);
+    }
+    __syncthreads();
+  }
+  double *dst = out + (int64_t)blockIdx.y * N * ldo;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int64_t j = j0 + 4 * tj + a;
+    if (j >= N) continue;
+#pragma unroll
+    for (int u = 0; u < CU; ++u) {
+      const int c = tc + 16 * u;
+      if (c < ell) dst[j * ldo + c] = acc[a][u];
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_split_reduce(const T *__restrict__ part, int nsplit, int64_t N, int ell, int64_t ldp,
+                               T *__restrict__ out, int64_t ldo) {
+  const int64_t total = N * ell;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = t / ell;
+    const int c = (int)(t % ell);
+    T s = 0;
+    for (int p = 0; p < nsplit; ++p) s += part[(int64_t)p * N * ldp + j * ldp + c];   // fixed order
+    out[j * ldo + c] = s;
+  }
+}
+
+// ---------------------------------------------------------------- dispatch helpers
+struct Plan {
+  int nsplit;
+  int kb_per_split;
+  unsigned gx;
+};
+
+Plan plan_split(int64_t K, int64_t N, int cols_per_block, int kblk, int cu_count, int min_kb_per_split) {
+  Plan p{};
+  const int64_t nkb = (K + kblk - 1) / kblk;
+  p.gx = (unsigned)((N + cols_per_block - 1) / cols_per_block);
+  const int64_t target = 2LL * std::max(cu_count, 1);
+  int64_t ns = 1;
+  if ((int64_t)p.gx < target) ns = (target + p.gx - 1) / p.gx;
+  ns = std::min<int64_t>(ns, std::max<int64_t>(1, nkb / min_kb_per_split));
+  ns = std::max<int64_t>(ns, 1);
+  p.kb_per_split = (int)((nkb + ns - 1) / ns);
+  p.nsplit = (int)((nkb + p.kb_per_split - 1) / p.kb_per_split);
+  if (p.nsplit < 1) p.nsplit = 1;
+  return p;
+}
+
+template <int MODE, bool NN, int NCT, int JT>
+void launch_mfma_t(hipStream_t st, dim3 grid, const void *X, int64_t K, int64_t N, int64_t ldx, const uint4 *Yp,
+                   int ell, float *out, int64_t ldo, int kbps) {
+  hipLaunchKernelGGL((k_stream_mfma<MODE, NN, NCT, JT>), grid, dim3(256), 0, st, X, K, N, ldx, Yp, ell, out, ldo,
+                     kbps);
+}
+
+template <int MODE, bool NN>
+int launch_mfma_nct(hipStream_t st, int nct, dim3 grid, const void *X, int64_t K, int64_t N, int64_t ldx,
+                    const uint4 *Yp, int ell, float *out, int64_t ldo, int kbps) {
+  switch (nct) {
+    case 1: launch_mfma_t<MODE, NN, 1, 4>(st, grid, X, K, N, ldx, Yp, ell, out, ldo, kbps); break;
+    case 2: launch_mfma_t<MODE, NN, 2, 4>(st, grid, X, K, N, ldx, Yp, ell, out, ldo, kbps); break;
+    case 3: launch_mfma_t<MODE, NN, 3, 4>(st, grid, X, K, N, ldx, Yp, ell, out, ldo, kbps); break;
+    case 4: launch_mfma_t<MODE, NN, 4, 4>(st, grid, X, K, N, ldx, Yp, ell, out, ldo, kbps); break;
+    case 5: launch_mfma_t<MODE, NN, 5, 2>(st, grid, X, K, N, ldx, Yp, ell, out, ldo, kbps); break;
+    case 6: launch_mfma_t<MODE, NN, 6, 2>(st, grid, X, K, N, ldx, Yp, ell, out, ldo, kbps); break;
+    case 7: launch_mfma_t<MODE, NN, 7, 2>(st, grid, X, K, N, ldx, Yp, ell, out, ldo, kbps); break;
+    case 8: launch_mfma_t<MODE, NN, 8, 2>(st, grid, X, K, N, ldx, Yp, ell, out, ldo, kbps); break;
+    default: return -1;
+  }
+  DSK_TRY(hipGetLastError());
+  return 0;
+}
+
+template <bool NN>
+int launch_f64_t(hipStream_t st, dim3 grid, int ellp, const double *X, int64_t K, int64_t N, int64_t ldx,
+                 const double *Y, int ell, double *out, int64_t ldo, int kbps) {
+  switch (ellp) {
+    case 16: hipLaunchKernelGGL((k_stream_f64<NN, 16>), grid, dim3(256), 0, st, X, K, N, ldx, Y, ell, out, ldo, kbps); break;
+    case 32: hipLaunchKernelGGL((k_stream_f64<NN, 32>), grid, dim3(256), 0, st, X, K, N, ldx, Y, ell, out, ldo, kbps); break;
+    case 64: hipLaunchKernelGGL((k_stream_f64<NN, 64>), grid, dim3(256), 0, st, X, K, N, ldx, Y, ell, out, ldo, kbps); break;
+    case 128: hipLaunchKernelGGL((k_stream_f64<NN, 128>), grid, dim3(256), 0, st, X, K, N, ldx, Y, ell, out, ldo, kbps); break;
+    default: return -1;
+  }
+  DSK_TRY(hipGetLastError());
+  return 0;
+}
+
+int mode_of(int dtype, int mode) {
+  if (dtype == DSK_BF16) return MODE_BF16X;
+  if (dtype == DSK_F16) return MODE_F16X;
+  if (mode == DSK_MODE_F32) return MODE_F32;
+  if (mode == DSK_MODE_SPLIT3) return MODE_SPLIT3;
+  return MODE_SPLIT6;
+}
+
+int stream_any(hipStream_t st, bool nn, const void *X, int dtype, int64_t K, int64_t N, int64_t ldx,
+               const void *Y, int ell, void *out, int64_t ldo, int mode, void *ws, int cu_count,
+               hipEvent_t ev0, hipEvent_t ev1) {
+  if (ell < 1 || ell > 128) return -1;
+  char *w = reinterpret_cast<char *>(ws);
+  if (dtype == DSK_F64) {
+    const int ellp = ell <= 16 ? 16 : ell <= 32 ? 32 : ell <= 64 ? 64 : 128;
+    Plan p = plan_split(K, N, 64, 16, cu_count, 2);
+    double *dst = reinterpret_cast<double *>(out);
+    int64_t ldd = ldo;
+    if (p.nsplit > 1) { dst = reinterpret_cast<double *>(w); ldd = ell; }
+    dim3 grid(p.gx, (unsigned)p.nsplit);
+    if (ev0) DSK_TRY(hipEventRecord(ev0, st));
+    int r = nn ? launch_f64_t<true>(st, grid, ellp, (const double *)X, K, N, ldx, (const double *)Y, ell, dst, ldd,
+                                    p.kb_per_split)
+               : launch_f64_t<false>(st, grid, ellp, (const double *)X, K, N, ldx, (const double *)Y, ell, dst, ldd,
+                                     p.kb_per_split);
+    if (ev1) DSK_TRY(hipEventRecord(ev1, st));
+    if (r) return r;
+    if (p.nsplit > 1) {
+      const unsigned blocks = (unsigned)std::min<int64_t>((N * ell + 255) / 256, 4096);
+      hipLaunchKernelGGL(k_split_reduce<double>, dim3(blocks), dim3(256), 0, st, (const double *)dst, p.nsplit, N,
+                         ell, (int64_t)ell, (double *)out, ldo);
+      DSK_TRY(hipGetLastError());
+    }
+    return 0;
+  }
+  const int md = mode_of(dtype, mode);
+  const int nct = (ell + 15) / 16;
+  const int jt = nct <= 4 ? 4 : 2;
+  const int64_t nkb = (K + 31) / 32;
+  // packed Y
+  uint4 *Yp = reinterpret_cast<uint4 *>(w);
+  const size_t yp_bytes = ((size_t)nkb * nct * 3 * 64 * sizeof(uint4) + 255) & ~size_t(255);
+  dim3 pgrid((unsigned)nkb, (unsigned)nct);
+  switch (md) {
+    case MODE_SPLIT6:
+      hipLaunchKernelGGL((k_pack_y<MODE_SPLIT6, float>), pgrid, dim3(64), 0, st, (const float *)Y, K, ell,
+                         (int64_t)ell, nct, Yp);
+      break;
+    case MODE_SPLIT3:
+    case MODE_BF16X:
+      hipLaunchKernelGGL((k_pack_y<MODE_SPLIT3, float>), pgrid, dim3(64), 0, st, (const float *)Y, K, ell,
+                         (int64_t)ell, nct, Yp);
+      break;
+    case MODE_F16X:
+      hipLaunchKernelGGL((k_pack_y<MODE_F16X, float>), pgrid, dim3(64), 0, st, (const float *)Y, K, ell,
+                         (int64_t)ell, nct, Yp);
+      break;
+    default:
+      hipLaunchKernelGGL((k_pack_y<MODE_F32, float>), pgrid, dim3(64), 0, st, (const float *)Y, K, ell,
+                         (int64_t)ell, nct, Yp);
+  }
+  DSK_TRY(hipGetLastError());
+  Plan p = plan_split(K, N, 16 * jt, 32, cu_count, 4);
+  float *dst = reinterpret_cast<float *>(out);
+  int64_t ldd = ldo;
+  if (p.nsplit > 1) { dst = reinterpret_cast<float *>(w + yp_bytes); ldd = ell; }
+  dim3 grid(p.gx, (unsigned)p.nsplit);
+  if (ev0) DSK_TRY(hipEventRecord(ev0, st));
+  int r;
+  switch (md) {
+    case MODE_SPLIT6:
+      r = nn ? launch_mfma_nct<MODE_SPLIT6, true>(st, nct, grid, X, K, N, ldx, Yp, ell, dst, ldd, p.kb_per_split)
+             : launch_mfma_nct<MODE_SPLIT6, false>(st, nct, grid, X, K, N, ldx, Yp, ell, dst, ldd, p.kb_per_split);
+      break;
+    case MODE_SPLIT3:
+      r = nn ? launch_mfma_nct<MODE_SPLIT3, true>(st, nct, grid, X, K, N, ldx, Yp, ell, dst, ldd, p.kb_per_split)
+             : launch_mfma_nct<MODE_SPLIT3, false>(st, nct, grid, X, K, N, ldx, Yp, ell, dst, ldd, p.kb_per_split);
+      break;
+    case MODE_F32:
+      r = nn ? launch_mfma_nct<MODE_F32, true>(st, nct, grid, X, K, N, ldx, Yp, ell, dst, ldd, p.kb_per_split)
+             : launch_mfma_nct<MODE_F32, false>(st, nct, grid, X, K, N, ldx, Yp, ell, dst, ldd, p.kb_per_split);
+      break;
+    case MODE_BF16X:
+      r = nn ? launch_mfma_nct<MODE_BF16X, true>(st, nct, grid, X, K, N, ldx, Yp, ell, dst, ldd, p.kb_per_split)
+             : launch_mfma_nct<MODE_BF16X, false>(st, nct, grid, X, K, N, ldx, Yp, ell, dst, ldd, p.kb_per_split);
+      break;
+    default:
+      r = nn ? launch_mfma_nct<MODE_F16X, true>(st, nct, grid, X, K, N, ldx, Yp, ell, dst, ldd, p.kb_per_split)
+             : launch_mfma_nct<MODE_F16X, false>(st, nct, grid, X, K, N, ldx, Yp, ell, dst, ldd, p.kb_per_split);
+  }
+  if (ev1) DSK_TRY(hipEventRecord(ev1, st));
+  if (r) return r;
+  if (p.nsplit > 1) {
+    const unsigned blocks = (unsigned)std::min<int64_t>((N * ell + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_split_reduce<float>, dim3(blocks), dim3(256), 0, st, (const float *)dst, p.nsplit, N, ell,
+                       (int64_t)ell, (float *)out, ldo);
+    DSK_TRY(hipGetLastError());
+  }
+  return 0;
+}
+
+}  // namespace
+
+size_t stream_ws_bytes(int dtype, int64_t K, int64_t N, int ell, int mode) {
+  (void)mode;
+  if (dtype == DSK_F64) {
+    // worst case split partials
+    const int64_t nkb = (K + 15) / 16;
+    const int64_t ns = std::min<int64_t>(nkb, 1024);
+    return (size_t)ns * N * ell * sizeof(double) + 256;
+  }
+  const int nct = (ell + 15) / 16;
+  const int64_t nkb = (K + 31) / 32;
+  size_t yp = ((size_t)nkb * nct * 3 * 64 * sizeof(uint4) + 255) & ~size_t(255);   // same as stream_any
+  const int64_t ns = std::min<int64_t>(std::max<int64_t>(1, nkb / 4), 1024);
+  return yp + (size_t)ns * N * ell * sizeof(float) + 256;
+}
+
+int launch_stream(hipStream_t st, const void *X, int dtype, int64_t K, int64_t N, int64_t ldx, const void *Y,
+                  int f64y, int ell, void *out, int64_t ldo, int mode, void *ws, int cu_count, hipEvent_t ev0,
+                  hipEvent_t ev1) {
+  (void)f64y;
+  return stream_any(st, false, X, dtype, K, N, ldx, Y, ell, out, ldo, mode, ws, cu_count, ev0, ev1);
+}
+
+int launch_stream_nn(hipStream_t st, const void *X, int dtype, int64_t M, int64_t K, int64_t ldx, const void *Y,
+                     int ell, void *out, int64_t ldo, int mode, void *ws, int cu_count) {
+  return stream_any(st, true, X, dtype, K, M, ldx, Y, ell, out, ldo, mode, ws, cu_count, nullptr, nullptr);
+}

@@ -1,0 +1,227 @@
+"""Python binding of libdsketch: argument marshalling only.
+
+Each function has the name of a C entry point of include/dsketch.h and passes
+torch tensors to it as raw device pointers together with torch's current HIP
+stream.  Every step of the computation runs in the library's HIP kernels;
+torch provides device memory and streams.  There is no CPU path: without a
+GPU and the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+
+_DT = {torch.float64: _lib.DSK_F64, torch.float32: _lib.DSK_F32,
+       torch.bfloat16: _lib.DSK_BF16, torch.float16: _lib.DSK_F16}
+_MODES = {"default": _lib.DSK_MODE_DEFAULT, "split3": _lib.DSK_MODE_SPLIT3, "f32": _lib.DSK_MODE_F32,
+          "split6": _lib.DSK_MODE_SPLIT6}
+
+_handles: dict = {}
+
+
+def _handle(device: torch.device):
+    lib = _lib.load()
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    h = _handles.get(idx)
+    if h is None:
+        hp = ctypes.c_void_p()
+        _lib.check("dsk_create", lib.dsk_create(ctypes.byref(hp), idx, None))
+        h = hp
+        _handles[idx] = h
+    stream = torch.cuda.current_stream(idx).cuda_stream
+    _lib.check("dsk_set_stream", lib.dsk_set_stream(h, ctypes.c_void_p(stream)))
+    return h
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _work_dtype(dt: torch.dtype) -> torch.dtype:
+    return torch.float64 if dt == torch.float64 else torch.float32
+
+
+def _check_matrix(A: torch.Tensor):
+    if not A.is_cuda:
+        raise ValueError("A must be a device tensor")
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("A must be a 2-D row-major tensor (unit column stride)")
+    if A.dtype not in _DT:
+        raise ValueError(f"unsupported dtype {A.dtype}")
+
+
+@dataclass
+class Restriction:
+    """Host description of the sketch D of A_c = A D (paper Sec. 2).
+
+    kind: "index" (direct injection / Gram sub-sample), "nn", "global".
+    """
+    kind: str
+    index: torch.Tensor | None = None      # device int64 (s,)
+    ny: int = 0
+    nx: int = 0
+    sy: int = 1
+    sx: int = 1
+
+    @staticmethod
+    def di_grid(ny: int, nx: int, sy: int, sx: int, device="cuda") -> "Restriction":
+        """Direct injection on a y-major ny x nx grid: coarse nodes (sy*b, sx*a)."""
+        ys = np.arange(0, ny, sy, dtype=np.int64)
+        xs = np.arange(0, nx, sx, dtype=np.int64)
+        idx = (ys[:, None] * nx + xs[None, :]).reshape(-1)
+        return Restriction("index", torch.from_numpy(idx).to(device), ny, nx, sy, sx)
+
+    @staticmethod
+    def from_index(index, device="cuda") -> "Restriction":
+        t = torch.as_tensor(index, dtype=torch.int64).to(device)
+        return Restriction("index", t)
+
+    @staticmethod
+    def nn(ny, nx, sy, sx) -> "Restriction":
+        return Restriction("nn", None, ny, nx, sy, sx)
+
+    @staticmethod
+    def global_(ny, nx, sy, sx) -> "Restriction":
+        return Restriction("global", None, ny, nx, sy, sx)
+
+    def coarse_size(self) -> int:
+        if self.kind == "index":
+            return int(self.index.numel())
+        return (-(-self.ny // self.sy)) * (-(-self.nx // self.sx))
+
+    def to_c(self) -> _lib.Restriction:
+        r = _lib.Restriction()
+        r.kind = {"index": _lib.DSK_R_INDEX, "nn": _lib.DSK_R_NN, "global": _lib.DSK_R_GLOBAL}[self.kind]
+        if self.kind == "index":
+            r.s = int(self.index.numel())
+            r.index = self.index.data_ptr()
+        r.ny, r.nx, r.sy, r.sx = self.ny, self.nx, self.sy, self.sx
+        return r
+
+
+def _opts(p=10, S=None, tau=None, id_projected=False, mode="default", refine=False):
+    lib = _lib.load()
+    o = _lib.Opts()
+    lib.dsk_opts_default(ctypes.byref(o))
+    o.p = int(p)
+    if S is not None:
+        o.S = S.data_ptr()
+        o.ell = int(S.shape[1])
+    o.tau = float(tau) if tau is not None else 0.0
+    o.id_projected = int(bool(id_projected))
+    o.mode = _MODES[mode] if isinstance(mode, str) else int(mode)
+    o.refine = int(bool(refine))
+    return o
+
+
+def _info_dict(info: _lib.Info) -> dict:
+    return {"ell": info.ell, "flags": info.flags,
+            "flag_names": [v for b, v in _lib.FLAG_NAMES.items() if info.flags & b],
+            "normA_fro2": info.normA_fro2, "normB_fro2": info.normB_fro2, "sigma_tail": info.sigma_tail}
+
+
+def restrict(A: torch.Tensor, R: Restriction) -> torch.Tensor:
+    """A_c = A D (dsk_restrict)."""
+    _check_matrix(A)
+    lib = _lib.load()
+    m, n = A.shape
+    s = R.coarse_size()
+    Ac = torch.empty((m, s), dtype=_work_dtype(A.dtype), device=A.device)
+    rc = R.to_c()
+    _lib.check("dsk_restrict", lib.dsk_restrict(_handle(A.device), _ptr(A), _DT[A.dtype], m, n, A.stride(0),
+                                                ctypes.byref(rc), _ptr(Ac)))
+    return Ac
+
+
+def project(A: torch.Tensor, Q: torch.Tensor, mode="default") -> torch.Tensor:
+    """B^T = A^T Q (dsk_project); returns the n x ell matrix B^T."""
+    _check_matrix(A)
+    lib = _lib.load()
+    m, n = A.shape
+    Q = Q.contiguous()
+    ell = Q.shape[1]
+    Bt = torch.empty((n, ell), dtype=_work_dtype(A.dtype), device=A.device)
+    _lib.check("dsk_project", lib.dsk_project(_handle(A.device), _ptr(A), _DT[A.dtype], m, n, A.stride(0), _ptr(Q),
+                                              ell, _ptr(Bt), _MODES[mode] if isinstance(mode, str) else int(mode)))
+    return Bt
+
+
+def sketch_svd(A: torch.Tensor, k: int, R: Restriction, q: int = 0, p: int = 10, S=None, tau=None,
+               mode="default", refine=False, want_info: bool = False):
+    """Rank-k SVD by TPC-SVD + C-PWR (dsk_sketch_svd).  Returns U (m x k), S (k, f64), V (n x k)[, info]."""
+    _check_matrix(A)
+    lib = _lib.load()
+    m, n = A.shape
+    wd = _work_dtype(A.dtype)
+    U = torch.empty((m, k), dtype=wd, device=A.device)
+    Sv = torch.empty((k,), dtype=torch.float64, device=A.device)
+    V = torch.empty((n, k), dtype=wd, device=A.device)
+    o = _opts(p=p, S=S, tau=tau, mode=mode, refine=refine)
+    rc = R.to_c()
+    info = _lib.Info()
+    st = lib.dsk_sketch_svd(_handle(A.device), _ptr(A), _DT[A.dtype], m, n, A.stride(0), int(k), ctypes.byref(rc),
+                            int(q), ctypes.byref(o), _ptr(U), _ptr(Sv), _ptr(V),
+                            ctypes.byref(info) if want_info else None)
+    _lib.check("dsk_sketch_svd", st)
+    if want_info:
+        return U, Sv, V, _info_dict(info)
+    return U, Sv, V
+
+
+def sketch_id(A: torch.Tensor, k: int, R: Restriction, q: int = 0, p: int = 10, S=None, tau=None,
+              projected=False, skeleton_rows=False, want_info: bool = False):
+    """Rank-k row ID by TPC-ID (dsk_sketch_id).  Returns I (k, int64), P (m x k, f64)[, A(I,:)][, info]."""
+    _check_matrix(A)
+    lib = _lib.load()
+    m, n = A.shape
+    I = torch.empty((k,), dtype=torch.int64, device=A.device)
+    P = torch.empty((m, k), dtype=torch.float64, device=A.device)
+    rows = torch.empty((k, n), dtype=A.dtype, device=A.device) if skeleton_rows else None
+    o = _opts(p=p, S=S, tau=tau, id_projected=projected)
+    rc = R.to_c()
+    info = _lib.Info()
+    st = lib.dsk_sketch_id(_handle(A.device), _ptr(A), _DT[A.dtype], m, n, A.stride(0), int(k), ctypes.byref(rc),
+                           int(q), ctypes.byref(o), _ptr(I), _ptr(P), _ptr(rows),
+                           ctypes.byref(info) if want_info else None)
+    _lib.check("dsk_sketch_id", st)
+    out = [I, P]
+    if skeleton_rows:
+        out.append(rows)
+    if want_info:
+        out.append(_info_dict(info))
+    return tuple(out)
+
+
+def timing_enable(enable: bool = True, device="cuda"):
+    """Bracket each projection kernel (B^T = A^T Q) with HIP events (dsk_timing_enable)."""
+    lib = _lib.load()
+    _lib.check("dsk_timing_enable", lib.dsk_timing_enable(_handle(torch.device(device)), int(bool(enable))))
+
+
+def timing_read(device="cuda"):
+    """(launches, total milliseconds) of the timed projection kernels since the last read."""
+    lib = _lib.load()
+    cnt = ctypes.c_int()
+    ms = ctypes.c_double()
+    _lib.check("dsk_timing_read", lib.dsk_timing_read(_handle(torch.device(device)), ctypes.byref(cnt),
+                                                      ctypes.byref(ms)))
+    return cnt.value, ms.value
+
+
+def power_iter(Ac: torch.Tensor, Q0: torch.Tensor, q: int, tau: float = 1.0, reorth: bool = True) -> torch.Tensor:
+    """C-PWR loop alone (dsk_power_iter)."""
+    _check_matrix(Ac)
+    lib = _lib.load()
+    m, s = Ac.shape
+    Q0 = Q0.contiguous().to(Ac.dtype)
+    ell = Q0.shape[1]
+    Qout = torch.empty_like(Q0)
+    st = lib.dsk_power_iter(_handle(Ac.device), _ptr(Ac), _DT[Ac.dtype], m, s, Ac.stride(0), _ptr(Q0), ell, int(q),
+                            float(tau), int(bool(reorth)), _ptr(Qout))
+    _lib.check("dsk_power_iter", st)
+    return Qout
