@@ -25,24 +25,37 @@ __global__ void k_scale(void *x, int f64, int64_t count, double a) {
 
 // sigma from eigenvalues (is_lam) or singular values; S out; V column scale;
 // info scalars: [0] = sum of all sigma^2 (= ||B||_F^2), [1] = sigma_{k+1}.
-__global__ void k_finish(const double *__restrict__ vals, int is_lam, int ell, int k, const double *__restrict__ sign,
-                         int divide, double *__restrict__ S, double *__restrict__ colscale, double *__restrict__ info) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double s1 = 0.0, tot = 0.0;
-  for (int j = 0; j < ell; ++j) {
-    const double v = vals[j];
-    const double sg = is_lam ? sqrt(v > 0.0 ? v : 0.0) : v;
-    tot += sg * sg;
-    if (j == 0) s1 = sg;
-    if (j < k) {
-      S[j] = sg;
-      double cs = sign ? sign[j] : 1.0;
-      if (divide) cs = (sg > 1e-300 && sg > 1e-13 * s1) ? cs / sg : 0.0;
-      colscale[j] = cs;
+// When Mv is given (F32 path) it also writes Mv = UB(:, :k) diag(colscale) as f32 (ell x k),
+// the right factor of V = B^T Mv.
+__global__ void __launch_bounds__(256) k_finish(const double *__restrict__ vals, int is_lam, int ell, int k,
+                                                const double *__restrict__ sign, int divide, double *__restrict__ S,
+                                                double *__restrict__ colscale, double *__restrict__ info,
+                                                const double *__restrict__ UB, float *__restrict__ Mv) {
+  __shared__ double cs_sh[128];
+  if (threadIdx.x == 0) {
+    double s1 = 0.0, tot = 0.0;
+    for (int j = 0; j < ell; ++j) {
+      const double v = vals[j];
+      const double sg = is_lam ? sqrt(v > 0.0 ? v : 0.0) : v;
+      tot += sg * sg;
+      if (j == 0) s1 = sg;
+      if (j < k) {
+        S[j] = sg;
+        double cs = sign ? sign[j] : 1.0;
+        if (divide) cs = (sg > 1e-300 && sg > 1e-13 * s1) ? cs / sg : 0.0;
+        colscale[j] = cs;
+        cs_sh[j] = cs;
+      }
     }
+    info[0] = tot;
+    info[1] = (ell > k) ? (is_lam ? sqrt(vals[k] > 0.0 ? vals[k] : 0.0) : vals[k]) : 0.0;
   }
-  info[0] = tot;
-  info[1] = (ell > k) ? (is_lam ? sqrt(vals[k] > 0.0 ? vals[k] : 0.0) : vals[k]) : 0.0;
+  __syncthreads();
+  if (Mv)
+    for (int e = threadIdx.x; e < ell * k; e += 256) {
+      const int i = e / k, c = e - (e / k) * k;
+      Mv[e] = (float)(UB[i * ell + c] * cs_sh[c]);
+    }
 }
 
 void launch_scale(hipStream_t st, void *x, int f64, int64_t count, double a) {
@@ -298,8 +311,10 @@ int dsk_sketch_svd(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64
     char *cws = c.take<char>(cholqr2_ws_bytes(std::max(m, s), L));
     size_t sws_b = std::max(stream_ws_bytes(dtype, m, n, L, od.mode), stream_ws_bytes(f64 ? DSK_F64 : DSK_F32, m, s, L, od.mode));
     sws_b = std::max(sws_b, stream_ws_bytes(f64 ? DSK_F64 : DSK_F32, s, m, L, od.mode));
+    sws_b = std::max(sws_b, stream_ws_bytes(f64 ? DSK_F64 : DSK_F32, L, n, k, od.mode));
     char *sws = c.take<char>(sws_b);
-    const int nparts = 240;
+    float *Mv = c.take<float>((size_t)L * k);
+    const int nparts = (int)std::min<int64_t>(128, std::max<int64_t>(1, (n + 255) / 256));
     double *part = c.take<double>((size_t)nparts * L * L);
     double *lam = c.take<double>(L);
     double *UB = c.take<double>((size_t)L * L);
@@ -343,18 +358,22 @@ int dsk_sketch_svd(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64
     }
     if (!f64) {
       DSK_RET(launch_gram(st, Bt, 0, n, L, nullptr, part, nparts));
-      DSK_RET(launch_jacobi_eig_parts(st, part, nparts, L, lam, UB, h->dflags));
+      // off-diagonal mass <= 1e-12 ||G||_F: eigenvectors far below f32 resolution
+      DSK_RET(launch_jacobi_eig_parts(st, part, nparts, L, lam, UB, h->dflags, 1e-24));
       DSK_RET(launch_tsmm(st, Q, 0, m, L, L, UB, L, k, nullptr, U, k));
       DSK_RET(launch_sign_fix(st, U, 0, m, k, sign));
-      hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, lam, 1, L, k, sign, 1, S, colscale, dinfo);
-      DSK_RET(launch_tsmm(st, Bt, 0, n, L, L, UB, L, k, colscale, V, k));
+      hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, st, lam, 1, L, k, sign, 1, S, colscale, dinfo,
+                         (const double *)UB, Mv);
+      // V = B^T U_B(:, :k) diag(sign / sigma) on the MFMA stream kernel (n rows, K = ell)
+      DSK_RET(launch_stream_nn(st, Bt, DSK_F32, n, L, L, Mv, k, V, k, od.mode, sws, h->cu_count));
     } else {
       DSK_RET(launch_convert(st, Bt, 1, tmp, 1, n * L));
       DSK_RET(launch_hhqr(st, tmp, n, L, QB, RB, h->dflags));
       DSK_RET(launch_jacobi_svd(st, RB, L, lam, UB, Ur, h->dflags));
       DSK_RET(launch_tsmm(st, Q, 1, m, L, L, UB, L, k, nullptr, U, k));
       DSK_RET(launch_sign_fix(st, U, 1, m, k, sign));
-      hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, lam, 0, L, k, sign, 0, S, colscale, dinfo);
+      hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, st, lam, 0, L, k, sign, 0, S, colscale, dinfo,
+                         (const double *)nullptr, (float *)nullptr);
       DSK_RET(launch_tsmm(st, QB, 1, n, L, L, Ur, L, k, colscale, V, k));
     }
     DSK_TRY(hipGetLastError());

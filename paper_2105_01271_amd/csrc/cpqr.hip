@@ -171,44 +171,178 @@ __global__ void __launch_bounds__(NT) k_cpqr_step(double *__restrict__ W, int64_
   }
 }
 
-// C = R_1^{-1} R_2 by back substitution; P(piv[b], :) = e_b, P(i, :) = C(:, i)^T.
-// One wave per block, one candidate per lane; the solution vector lives in LDS.
-constexpr int KMAX = 112;
+// Register-resident variant for s <= 256*SPT: the workgroup's CB candidate
+// rows are loaded before the argmax (they do not depend on the pivot), kept in
+// registers for the dot products and the update, and written back once.
+template <int SPT, int CB>
+__global__ void __launch_bounds__(NT) k_cpqr_step_reg(double *__restrict__ W, int64_t m, int64_t s, int step,
+                                                      const double *__restrict__ nu_in, double *__restrict__ nu_out,
+                                                      double *__restrict__ Rk, int64_t *__restrict__ piv,
+                                                      int *__restrict__ dflags) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  __shared__ double bv[NT / 64];
+  __shared__ int64_t bi[NT / 64];
+  __shared__ int64_t p_sh;
+  __shared__ double red[NT / 64][CB];
+  __shared__ double coef[CB];
 
-__global__ void __launch_bounds__(64) k_id_solve(const double *__restrict__ Rk, const int64_t *__restrict__ piv,
-                                                 const double *__restrict__ nu_final, int64_t m, int k,
-                                                 double *__restrict__ P, int *__restrict__ dflags) {
-  extern __shared__ double dyn[];
-  double *R1 = dyn;              // k x k upper, R1[a][b] = Rk[a, piv[b]]
-  double *cs = dyn + k * k;      // k x 64 per-lane solution
-  const int t = threadIdx.x;
-  for (int e = t; e < k * k; e += 64) {
-    const int a = e / k, b = e % k;
-    const int64_t pb = piv[b];
-    R1[e] = (b >= a && pb >= 0 && pb < m) ? Rk[(int64_t)a * m + pb] : 0.0;
+  int64_t cand[CB];
+  bool live[CB];
+  double w[CB][SPT];
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    cand[c] = (int64_t)blockIdx.x * CB + c;
+    const bool inr = cand[c] < m;
+    live[c] = inr && nu_in[cand[c]] >= 0.0;
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) {
+      const int64_t e = t + (int64_t)NT * u;
+      w[c][u] = (live[c] && e < s) ? W[cand[c] * s + e] : 0.0;
+    }
+  }
+
+  // ---- argmax of nu_in over unselected candidates (ties -> lowest index)
+  double best = -1.0;
+  int64_t bidx = m;
+  for (int64_t i = t; i < m; i += NT) {
+    const double v = nu_in[i];
+    if (v > best) { best = v; bidx = i; }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(best, o, 64);
+    const int64_t oi = __shfl_xor(bidx, o, 64);
+    if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
+  }
+  if (lane == 0) { bv[wave] = best; bi[wave] = bidx; }
+  __syncthreads();
+  if (t == 0) {
+    double b = bv[0];
+    int64_t ix = bi[0];
+    for (int ww = 1; ww < NT / 64; ++ww)
+      if (bv[ww] > b || (bv[ww] == b && bi[ww] < ix)) { b = bv[ww]; ix = bi[ww]; }
+    p_sh = ix;
   }
   __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * 64 + t;
-  if (i >= m) return;
-  if (nu_final[i] < 0.0) {
-    // a pivot: identity row
-    int b = -1;
-    for (int q = 0; q < k; ++q)
-      if (piv[q] == i) b = q;
-    for (int q = 0; q < k; ++q) P[i * k + q] = (q == b) ? 1.0 : 0.0;
-    return;
+  const int64_t p = p_sh;
+  const double nup = (p < m) ? nu_in[p] : 0.0;
+  const double rpp = nup > 0.0 ? sqrt(nup) : 0.0;
+  const double qscale = rpp > 0.0 ? 1.0 / rpp : 0.0;
+  if (blockIdx.x == 0 && t == 0) {
+    piv[step] = p;
+    if (p < m) Rk[(int64_t)step * m + p] = rpp;
+    if (!(rpp > 0.0)) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_RANK_DEFICIENT);
   }
-  const double dmax = fabs(R1[0]);
-  for (int b = 0; b < k; ++b) cs[b * 64 + t] = Rk[(int64_t)b * m + i];
-  for (int b = k - 1; b >= 0; --b) {
-    const double dbb = R1[b * k + b];
-    double x = 0.0;
-    if (fabs(dbb) > 1e-14 * dmax) x = cs[b * 64 + t] / dbb;
-    else if (t == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_RANK_DEFICIENT);
-    cs[b * 64 + t] = x;
-    for (int a = 0; a < b; ++a) cs[a * 64 + t] = fma(-R1[a * k + b], x, cs[a * 64 + t]);
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    if (cand[c] == p) live[c] = false;                         // the pivot itself is never written
+    if (cand[c] < m && !live[c] && t == 0) nu_out[cand[c]] = -1.0;
   }
-  for (int q = 0; q < k; ++q) P[i * k + q] = cs[q * 64 + t];
+  double qv[SPT];
+#pragma unroll
+  for (int u = 0; u < SPT; ++u) {
+    const int64_t e = t + (int64_t)NT * u;
+    qv[u] = (p < m && e < s) ? W[p * s + e] * qscale : 0.0;
+  }
+  double d[CB];
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    double a = 0.0;
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) a = fma(qv[u], w[c][u], a);
+    d[c] = wsum(a);
+    if (lane == 0) red[wave][c] = d[c];
+  }
+  __syncthreads();
+  if (t < CB) {
+    double v = 0.0;
+    for (int ww = 0; ww < NT / 64; ++ww) v += red[ww][t];
+    coef[t] = v;
+  }
+  __syncthreads();
+  double nn[CB];
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    const double r = coef[c];
+    double a = 0.0;
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) {
+      const double x = fma(-r, qv[u], w[c][u]);
+      w[c][u] = x;
+      a = fma(x, x, a);
+    }
+    nn[c] = a;
+    if (live[c]) {
+#pragma unroll
+      for (int u = 0; u < SPT; ++u) {
+        const int64_t e = t + (int64_t)NT * u;
+        if (e < s) W[cand[c] * s + e] = w[c][u];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    const double v = wsum(nn[c]);
+    if (lane == 0) red[wave][c] = v;
+  }
+  __syncthreads();
+  if (t < CB && live[t]) {
+    double v = 0.0;
+    for (int ww = 0; ww < NT / 64; ++ww) v += red[ww][t];
+    nu_out[cand[t]] = v;
+    Rk[(int64_t)step * m + cand[t]] = coef[t];
+    if (!isfinite(v)) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_NONFINITE);
+  }
+}
+
+// C = R_1^{-1} R_2 by back substitution; P(piv[b], :) = e_b, P(i, :) = C(:, i)^T.
+// One wave per candidate: lane l holds entries a = l and a = l + 64 of the
+// right-hand side; the k substitution steps broadcast x_b by a lane shuffle and
+// update all a < b in parallel.  R_1 is staged transposed in LDS (column b of
+// R_1 contiguous), shared by the 4 waves of a workgroup.
+constexpr int KMAX = 112;
+constexpr int SOLVE_WAVES = 4;
+
+__global__ void __launch_bounds__(64 * SOLVE_WAVES) k_id_solve(const double *__restrict__ Rk,
+                                                               const int64_t *__restrict__ piv,
+                                                               const double *__restrict__ nu_final, int64_t m, int k,
+                                                               double *__restrict__ P, int *__restrict__ dflags) {
+  extern __shared__ double dyn[];
+  double *R1t = dyn;             // R1t[b*k + a] = R_1[a][b] = Rk[a, piv[b]] (a <= b)
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  for (int e = t; e < k * k; e += 64 * SOLVE_WAVES) {
+    const int b = e / k, a = e - (e / k) * k;
+    const int64_t pb = piv[b];
+    R1t[e] = (a <= b && pb >= 0 && pb < m) ? Rk[(int64_t)a * m + pb] : 0.0;
+  }
+  __syncthreads();
+  const double dmax = fabs(R1t[0]);
+  for (int64_t i = (int64_t)blockIdx.x * SOLVE_WAVES + wave; i < m; i += (int64_t)gridDim.x * SOLVE_WAVES) {
+    if (nu_final[i] < 0.0) {
+      // a pivot: identity row
+      for (int q = lane; q < k; q += 64) P[i * k + q] = (piv[q] == i) ? 1.0 : 0.0;
+      continue;
+    }
+    double c0 = (lane < k) ? Rk[(int64_t)lane * m + i] : 0.0;
+    double c1 = (lane + 64 < k) ? Rk[(int64_t)(lane + 64) * m + i] : 0.0;
+    bool deficient = false;
+    for (int b = k - 1; b >= 0; --b) {
+      const double cb = __shfl(b < 64 ? c0 : c1, b & 63, 64);
+      const double dbb = R1t[b * k + b];
+      double x = 0.0;
+      if (fabs(dbb) > 1e-14 * dmax) x = cb / dbb;
+      else deficient = true;
+      if (lane == (b & 63)) {
+        if (b < 64) c0 = x; else c1 = x;
+      }
+      if (lane < b) c0 = fma(-R1t[b * k + lane], x, c0);
+      if (lane + 64 < b) c1 = fma(-R1t[b * k + lane + 64], x, c1);
+    }
+    if (deficient && lane == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_RANK_DEFICIENT);
+    if (lane < k) P[i * k + lane] = c0;
+    if (lane + 64 < k) P[i * k + lane + 64] = c1;
+  }
 }
 
 }  // namespace
@@ -224,7 +358,20 @@ int launch_cpqr(hipStream_t st, double *W, int64_t m, int64_t s, int k, double *
   for (int t = 0; t < k; ++t) {
     const double *in = (t & 1) ? nu1 : nu0;
     double *out = (t & 1) ? nu0 : nu1;
-    hipLaunchKernelGGL(k_cpqr_step, dim3(blocks), dim3(NT), 0, st, W, m, s, t, in, out, Rk, piv, dflags);
+    if (s <= 256 * 4)
+      hipLaunchKernelGGL((k_cpqr_step_reg<4, 4>), dim3((unsigned)((m + 3) / 4)), dim3(NT), 0, st, W, m, s, t, in, out,
+                         Rk, piv, dflags);
+    else if (s <= 256 * 8)
+      hipLaunchKernelGGL((k_cpqr_step_reg<8, 4>), dim3((unsigned)((m + 3) / 4)), dim3(NT), 0, st, W, m, s, t, in, out,
+                         Rk, piv, dflags);
+    else if (s <= 256 * 16)
+      hipLaunchKernelGGL((k_cpqr_step_reg<16, 4>), dim3((unsigned)((m + 3) / 4)), dim3(NT), 0, st, W, m, s, t, in,
+                         out, Rk, piv, dflags);
+    else if (s <= 256 * 32)
+      hipLaunchKernelGGL((k_cpqr_step_reg<32, 2>), dim3((unsigned)((m + 1) / 2)), dim3(NT), 0, st, W, m, s, t, in,
+                         out, Rk, piv, dflags);
+    else
+      hipLaunchKernelGGL(k_cpqr_step, dim3(blocks), dim3(NT), 0, st, W, m, s, t, in, out, Rk, piv, dflags);
     DSK_TRY(hipGetLastError());
   }
   return 0;
@@ -234,10 +381,10 @@ int launch_cpqr(hipStream_t st, double *W, int64_t m, int64_t s, int k, double *
 int launch_id_solve(hipStream_t st, const double *Rk, const int64_t *piv, const double *nu_final, int64_t m, int k,
                     double *P, int *dflags) {
   if (k < 1 || k > KMAX) return -1;
-  const size_t lds = ((size_t)k * k + (size_t)k * 64) * sizeof(double);
+  const size_t lds = (size_t)k * k * sizeof(double);
   allow_lds(k_id_solve, lds);
-  hipLaunchKernelGGL(k_id_solve, dim3((unsigned)((m + 63) / 64)), dim3(64), lds, st, Rk, piv, nu_final, m, k, P,
-                     dflags);
+  const unsigned blocks = (unsigned)std::min<int64_t>((m + SOLVE_WAVES - 1) / SOLVE_WAVES, 256);
+  hipLaunchKernelGGL(k_id_solve, dim3(blocks), dim3(64 * SOLVE_WAVES), lds, st, Rk, piv, nu_final, m, k, P, dflags);
   DSK_TRY(hipGetLastError());
   return 0;
 }

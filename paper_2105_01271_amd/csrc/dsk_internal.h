@@ -19,8 +19,9 @@
     if (r__ != 0) return r__;                                  \
   } while (0)
 
-// Device-side status words (one int per flag slot).
-enum { FLAGW_BITS = 0, FLAGW_COUNT = 4 };
+// Device-side status words: [0] DSK_FLAG_* bits, [1] workgroup ticket counter of
+// the fused reduce-and-factor kernels (returns to 0 after every launch).
+enum { FLAGW_BITS = 0, FLAGW_TICKET = 1, FLAGW_COUNT = 4 };
 
 struct dsk_handle {
   int device;
@@ -91,9 +92,9 @@ int launch_cholqr2(hipStream_t st, const void *Y, int f64, int64_t rows, int ell
 int launch_hhqr(hipStream_t st, double *X, int64_t rows, int ell, double *Q, double *R, int *dflags);
 int launch_gram(hipStream_t st, const void *X, int f64, int64_t rows, int ell, double *G,
                 double *part, int nparts);
+// jacobi.hip
 int launch_jacobi_eig_parts(hipStream_t st, const double *part, int nparts, int ell, double *lam, double *V,
-                            int *dflags);
-int launch_jacobi_eig(hipStream_t st, const double *G, int ell, double *lam, double *V, int *dflags);
+                            int *dflags, double tol2_rel);
 int launch_jacobi_svd(hipStream_t st, const double *Rm, int ell, double *sig, double *Vr,
                       double *Ur, int *dflags);
 int launch_tsmm(hipStream_t st, const void *X, int f64, int64_t rows, int ell, int64_t ldx,

@@ -8,10 +8,6 @@
 //    orthonormality (shifted CholeskyQR3, Fukaya et al. 2020).
 //  * Single-workgroup Householder QR with explicit Q (FP64 path, where blocks
 //    may be numerically rank deficient).
-//  * Two-sided cyclic Jacobi eigen-solver of an ell x ell FP64 Gram (core of
-//    SVD(B) through B B^T), one-sided Jacobi SVD of an ell x ell triangular
-//    factor (core of SVD(B) from a QR of B^T without squaring), round-robin
-//    ordering, everything resident in LDS.
 //  * Skinny products out = X M diag(scale) and the sign normalisation of U.
 // All reductions use fixed orders, so repeated runs give identical bytes.
 #include <algorithm>
@@ -20,7 +16,7 @@
 
 namespace {
 
-constexpr int ELL_MAX = 112;   // LDS budget: packed Gram + eigenvectors in 160 KB
+constexpr int ELL_MAX = 112;
 constexpr double U64 = 1.1102230246251565e-16;
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -60,20 +56,15 @@ __device__ __forceinline__ void gram_zero(GramAcc &g) {
 }
 
 __device__ __forceinline__ void pair_of(int pid, int nb, int &bi, int &bj) {
-  // enumerate (bi <= bj) row-major over the upper triangle of an nb x nb block grid
   int r = 0, rem = pid;
   while (rem >= nb - r) { rem -= nb - r; ++r; }
   bi = r;
   bj = r + rem;
 }
 
-template <int U>
-__device__ __forceinline__ void gram_chunk_u(const double *sh, int CH, int ellp, double (&acc)[16]) {
-  const int nb = ellp / 4, npairs = nb * (nb + 1) / 2;
-  const int pid = threadIdx.x + 256 * U;
-  if (pid >= npairs) return;
-  int bi, bj;
-  pair_of(pid, nb, bi, bj);
+__device__ __forceinline__ void gram_chunk_u(const double *sh, int CH, int ellp, int bi, int bj, bool on,
+                                             double (&acc)[16]) {
+  if (!on) return;
   for (int r = 0; r < CH; ++r) {
     const double *row = sh + r * ellp;
     double xs[4], ys[4];
@@ -86,20 +77,33 @@ __device__ __forceinline__ void gram_chunk_u(const double *sh, int CH, int ellp,
   }
 }
 
-// sh: CH x ellp chunk (row-major, zero padded)
-__device__ __forceinline__ void gram_chunk(const double *sh, int CH, int ellp, GramAcc &g) {
-  gram_chunk_u<0>(sh, CH, ellp, g.a0);
-  gram_chunk_u<1>(sh, CH, ellp, g.a1);
-  gram_chunk_u<2>(sh, CH, ellp, g.a2);
+struct GramSlots {
+  int bi[3], bj[3];
+  bool on[3];
+};
+
+__device__ __forceinline__ GramSlots gram_slots(int ellp) {
+  GramSlots s;
+  const int nb = ellp / 4, npairs = nb * (nb + 1) / 2;
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const int pid = threadIdx.x + 256 * u;
+    s.on[u] = pid < npairs;
+    s.bi[u] = s.bj[u] = 0;
+    if (s.on[u]) pair_of(pid, nb, s.bi[u], s.bj[u]);
+  }
+  return s;
 }
 
-template <int U>
-__device__ __forceinline__ void gram_store_u(const double (&acc)[16], int ell, int ellp, double *part) {
-  const int nb = ellp / 4, npairs = nb * (nb + 1) / 2;
-  const int pid = threadIdx.x + 256 * U;
-  if (pid >= npairs) return;
-  int bi, bj;
-  pair_of(pid, nb, bi, bj);
+__device__ __forceinline__ void gram_chunk(const double *sh, int CH, int ellp, const GramSlots &s, GramAcc &g) {
+  gram_chunk_u(sh, CH, ellp, s.bi[0], s.bj[0], s.on[0], g.a0);
+  gram_chunk_u(sh, CH, ellp, s.bi[1], s.bj[1], s.on[1], g.a1);
+  gram_chunk_u(sh, CH, ellp, s.bi[2], s.bj[2], s.on[2], g.a2);
+}
+
+__device__ __forceinline__ void gram_store_u(const double (&acc)[16], int bi, int bj, bool on, int ell,
+                                             double *part) {
+  if (!on) return;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -112,10 +116,10 @@ __device__ __forceinline__ void gram_store_u(const double (&acc)[16], int ell, i
     }
 }
 
-__device__ __forceinline__ void gram_store(const GramAcc &g, int ell, int ellp, double *part) {
-  gram_store_u<0>(g.a0, ell, ellp, part);
-  gram_store_u<1>(g.a1, ell, ellp, part);
-  gram_store_u<2>(g.a2, ell, ellp, part);
+__device__ __forceinline__ void gram_store(const GramAcc &g, const GramSlots &s, int ell, double *part) {
+  gram_store_u(g.a0, s.bi[0], s.bj[0], s.on[0], ell, part);
+  gram_store_u(g.a1, s.bi[1], s.bj[1], s.on[1], ell, part);
+  gram_store_u(g.a2, s.bi[2], s.bj[2], s.on[2], ell, part);
 }
 
 constexpr int GCH = 32;
@@ -127,84 +131,116 @@ __global__ void __launch_bounds__(256) k_gram_part(const T *__restrict__ X, int6
   if (cond && !(dflags[FLAGW_BITS] & DSK_FLAG_FALLBACK)) return;
   __shared__ double sh[GCH * ELL_MAX];
   const int ellp = (ell + 3) & ~3;
+  const GramSlots slots = gram_slots(ellp);
   GramAcc g;
   gram_zero(g);
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
   const int64_t r1 = std::min<int64_t>(rows, r0 + rows_per_blk);
   for (int64_t c0 = r0; c0 < r1; c0 += GCH) {
     for (int e = threadIdx.x; e < GCH * ellp; e += 256) {
-      const int rr = e / ellp, c = e % ellp;
+      const int rr = e / ellp, c = e - rr * ellp;
       const int64_t r = c0 + rr;
       sh[e] = (r < r1 && c < ell) ? (double)X[r * ldx + c] : 0.0;
     }
     __syncthreads();
-    gram_chunk(sh, GCH, ellp, g);
+    gram_chunk(sh, GCH, ellp, slots, g);
     __syncthreads();
   }
-  gram_store(g, ell, ellp, part + (int64_t)blockIdx.x * ell * ell);
+  gram_store(g, slots, ell, part + (int64_t)blockIdx.x * ell * ell);
 }
 
 // ---------------------------------------------------------------- Cholesky + inverse (one block)
 // Sums the Gram partials in a fixed order, factors G = L L^T (retrying once with
 // a shift on breakdown), inverts L in place and writes R = L^T, Rinv = L^{-T}.
-__global__ void __launch_bounds__(256) k_chol(const double *__restrict__ part, int nparts, int ell, int64_t rows,
-                                              double *__restrict__ R, double *__restrict__ Rinv,
-                                              int *__restrict__ dflags, int cond) {
-  if (cond && !(dflags[FLAGW_BITS] & DSK_FLAG_FALLBACK)) return;
-  extern __shared__ double dyn[];
+// Thread t works on rows j + 1 + t/4 (+64) and on every 4th column (t % 4).
+// Runs on one 256-thread workgroup; dyn must hold ell*ell + ell doubles.
+__device__ void chol_body(const double *__restrict__ part, int nparts, int ell, int64_t rows,
+                          double *__restrict__ R, double *__restrict__ Rinv, int *__restrict__ dflags,
+                          double *dyn) {
   double *G = dyn;                 // ell x ell
   double *tmp = dyn + ell * ell;   // ell
   __shared__ double red[8];
   __shared__ int bad;
+  __shared__ double pivinv;
   const int t = threadIdx.x;
+  const int tr4 = t >> 2, tc4 = t & 3;
   const int n2 = ell * ell;
-  double shift = 0.0;
   for (int attempt = 0; attempt < 2; ++attempt) {
-    for (int e = t; e < n2; e += 256) {
-      double s = 0.0;
-      for (int p = 0; p < nparts; ++p) s += part[(int64_t)p * n2 + e];
-      G[e] = s;
+    // fixed association (deterministic); 4 entries x 2 parts of loads in flight per thread
+    for (int e0 = t; e0 < n2; e0 += 4 * 256) {
+      double s[4][2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) s[i][0] = s[i][1] = 0.0;
+      int p = 0;
+      for (; p + 1 < nparts; p += 2) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int e = e0 + 256 * i;
+          if (e < n2) {
+            s[i][0] += part[(int64_t)p * n2 + e];
+            s[i][1] += part[(int64_t)(p + 1) * n2 + e];
+          }
+        }
+      }
+      if (p < nparts) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int e = e0 + 256 * i;
+          if (e < n2) s[i][0] += part[(int64_t)p * n2 + e];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int e = e0 + 256 * i;
+        if (e < n2) G[e] = s[i][0] + s[i][1];
+      }
     }
     __syncthreads();
-    double tr = 0.0;
-    for (int i = t; i < ell; i += 256) tr += G[i * ell + i];
-    tr = block_sum<256>(tr, red);
+    double trc = 0.0;
+    for (int i = t; i < ell; i += 256) trc += G[i * ell + i];
+    trc = block_sum<256>(trc, red);
     if (attempt == 1) {
-      shift = 11.0 * ((double)rows * ell + (double)ell * (ell + 1)) * U64 * tr;
+      const double shift = 11.0 * ((double)rows * ell + (double)ell * (ell + 1)) * U64 * trc;
       for (int i = t; i < ell; i += 256) G[i * ell + i] += shift;
     }
-    if (t == 0) bad = !(tr > 0.0) || !isfinite(tr);
+    if (t == 0) bad = !(trc > 0.0) || !isfinite(trc);
     __syncthreads();
-    const double thr = 1e-15 * tr;
-    for (int j = 0; j < ell && !bad; ++j) {
-      if (t == 0) {
+    const double thr = 1e-15 * trc;
+    for (int j = 0; j < ell; ++j) {
+      if (t == 0 && !bad) {
         const double d = G[j * ell + j];
-        if (!(d > thr) || !isfinite(d)) bad = 1;
-        else G[j * ell + j] = sqrt(d);
+        if (!(d > thr) || !isfinite(d)) {
+          bad = 1;
+        } else {
+          G[j * ell + j] = sqrt(d);
+          pivinv = 1.0 / d;
+        }
       }
       __syncthreads();
       if (bad) break;
-      const double dj = G[j * ell + j];
-      for (int i = j + 1 + t; i < ell; i += 256) G[i * ell + j] /= dj;
-      __syncthreads();
-      const int m = ell - j - 1;
-      for (int e = t; e < m * m; e += 256) {
-        const int i = j + 1 + e / m, c = j + 1 + e % m;
-        if (c <= i) G[i * ell + c] -= G[i * ell + j] * G[c * ell + j];
+      // scale the column of the previous step (no thread reads it in this step)
+      if (j > 0) {
+        const double inv_prev = 1.0 / G[(j - 1) * ell + (j - 1)];
+        for (int i = j + t; i < ell; i += 256) G[i * ell + (j - 1)] *= inv_prev;
+      }
+      // trailing update with the unscaled column j: G_ic -= G_ij G_cj / d
+      const double pinv = pivinv;
+      for (int i = j + 1 + tr4; i < ell; i += 64) {
+        const double gij = G[i * ell + j] * pinv;
+        for (int c = j + 1 + tc4; c <= i; c += 4) G[i * ell + c] -= gij * G[c * ell + j];
       }
       __syncthreads();
     }
-    __syncthreads();
-    if (!bad) break;
+    if (!bad) break;   // (the last column has nothing below its diagonal to scale)
     if (t == 0) atomicOr(&dflags[FLAGW_BITS], attempt == 0 ? DSK_FLAG_FALLBACK : DSK_FLAG_RANK_DEFICIENT);
     __syncthreads();
     if (attempt == 1) {
       // still failing (non-finite input): identity factors keep the pipeline finite
-      for (int e = t; e < n2; e += 256) {
-        const int i = e / ell, c = e % ell;
-        R[e] = (i == c) ? 1.0 : 0.0;
-        Rinv[e] = (i == c) ? 1.0 : 0.0;
-      }
+      for (int i = t >> 6; i < ell; i += 4)
+        for (int c = t & 63; c < ell; c += 64) {
+          R[i * ell + c] = (i == c) ? 1.0 : 0.0;
+          Rinv[i * ell + c] = (i == c) ? 1.0 : 0.0;
+        }
       if (t == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_NONFINITE);
       return;
     }
@@ -212,83 +248,155 @@ __global__ void __launch_bounds__(256) k_chol(const double *__restrict__ part, i
     __syncthreads();
   }
   // R = L^T
-  for (int e = t; e < n2; e += 256) {
-    const int i = e / ell, c = e % ell;
-    R[e] = (c >= i) ? G[c * ell + i] : 0.0;
-  }
+  for (int i = t >> 6; i < ell; i += 4)
+    for (int c = t & 63; c < ell; c += 64) R[i * ell + c] = (c >= i) ? G[c * ell + i] : 0.0;
   __syncthreads();
-  // in-place inverse of lower-triangular L (column j from the already inverted trailing block)
+  // in-place inverse of the lower-triangular L, column j from the inverted trailing block
   for (int j = ell - 1; j >= 0; --j) {
     if (t == 0) G[j * ell + j] = 1.0 / G[j * ell + j];
     for (int i = j + 1 + t; i < ell; i += 256) tmp[i] = G[i * ell + j];
     __syncthreads();
     const double ajj = -G[j * ell + j];
-    for (int i = j + 1 + t; i < ell; i += 256) {
+    for (int ib = j + 1; ib < ell; ib += 64) {
+      const int i = ib + tr4;
       double s = 0.0;
-      for (int c = j + 1; c <= i; ++c) s += G[i * ell + c] * tmp[c];
-      G[i * ell + j] = ajj * s;
+      if (i < ell)
+        for (int c = j + 1 + tc4; c <= i; c += 4) s += G[i * ell + c] * tmp[c];
+      s += __shfl_xor(s, 1, 4);
+      s += __shfl_xor(s, 2, 4);
+      if (i < ell && tc4 == 0) G[i * ell + j] = ajj * s;
     }
     __syncthreads();
   }
-  for (int e = t; e < n2; e += 256) {
-    const int i = e / ell, c = e % ell;
-    Rinv[e] = (c >= i) ? G[c * ell + i] : 0.0;
-  }
+  for (int i = t >> 6; i < ell; i += 4)
+    for (int c = t & 63; c < ell; c += 64) Rinv[i * ell + c] = (c >= i) ? G[c * ell + i] : 0.0;
 }
 
-// ---------------------------------------------------------------- Q = Y Rinv (+ Gram partials of Q)
-template <typename T>
-__global__ void __launch_bounds__(256) k_apply(const T *__restrict__ Y, int64_t rows, int ell, int64_t ldy,
-                                               const double *__restrict__ Rinv, T *__restrict__ Q, int64_t ldq,
-                                               int64_t rows_per_blk, double *__restrict__ part,
-                                               const int *__restrict__ dflags, int cond) {
+__global__ void __launch_bounds__(256) k_chol(const double *__restrict__ part, int nparts, int ell, int64_t rows,
+                                              double *__restrict__ R, double *__restrict__ Rinv,
+                                              int *__restrict__ dflags, int cond) {
   if (cond && !(dflags[FLAGW_BITS] & DSK_FLAG_FALLBACK)) return;
   extern __shared__ double dyn[];
+  chol_body(part, nparts, ell, rows, R, Rinv, dflags, dyn);
+}
+
+// True in exactly one workgroup of the grid: the last one to publish its
+// partial.  Release fence before the ticket, acquire fence after it (device
+// scope), so the elected workgroup sees every partial.  The ticket counter is
+// reset for the next launch by the elected workgroup.
+__device__ bool last_block_done(unsigned *counter) {
+  __shared__ int last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = atomicAdd(counter, 1u);
+    last = (prev == gridDim.x - 1) ? 1 : 0;
+    if (last) atomicExch(counter, 0u);
+  }
+  __syncthreads();
+  if (last) __threadfence();
+  return last != 0;
+}
+
+// Gram partials of X; with a counter, the last workgroup also reduces them and
+// factors (Cholesky + inverse), writing R and Rinv.
+template <typename T>
+__global__ void __launch_bounds__(256) k_gram_chol(const T *__restrict__ X, int64_t rows, int ell, int64_t ldx,
+                                                   int64_t rows_per_blk, double *__restrict__ part,
+                                                   unsigned *__restrict__ counter, double *__restrict__ R,
+                                                   double *__restrict__ Rinv, int *__restrict__ dflags) {
+  extern __shared__ double dyn[];
+  double *sh = dyn;   // GCH x ellp (reused by the factorization afterwards)
   const int ellp = (ell + 3) & ~3;
-  double *Rs = dyn;                   // ell x ell
-  double *sh = dyn + ell * ell;       // GCH x ellp
-  for (int e = threadIdx.x; e < ell * ell; e += 256) Rs[e] = Rinv[e];
+  const GramSlots slots = gram_slots(ellp);
   GramAcc g;
   gram_zero(g);
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
   const int64_t r1 = std::min<int64_t>(rows, r0 + rows_per_blk);
   for (int64_t c0 = r0; c0 < r1; c0 += GCH) {
-    __syncthreads();
     for (int e = threadIdx.x; e < GCH * ellp; e += 256) {
-      const int rr = e / ellp, c = e % ellp;
+      const int rr = e / ellp, c = e - rr * ellp;
       const int64_t r = c0 + rr;
-      sh[e] = (r < r1 && c < ell) ? (double)Y[r * ldy + c] : 0.0;
+      sh[e] = (r < r1 && c < ell) ? (double)X[r * ldx + c] : 0.0;
     }
     __syncthreads();
-    constexpr int NU = (GCH * ELL_MAX + 255) / 256;
-    double outv[NU];
-#pragma unroll
-    for (int u = 0; u < NU; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      double s = 0.0;
-      if (e < GCH * ellp) {
-        const int rr = e / ellp, c = e % ellp;
-        if (c < ell)
-          for (int q = 0; q <= c; ++q) s = fma(sh[rr * ellp + q], Rs[q * ell + c], s);
-      }
-      outv[u] = s;
-    }
+    gram_chunk(sh, GCH, ellp, slots, g);
     __syncthreads();
-#pragma unroll
-    for (int u = 0; u < NU; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      if (e < GCH * ellp) {
-        const int rr = e / ellp, c = e % ellp;
-        const int64_t r = c0 + rr;
-        const T v = (T)outv[u];
-        sh[e] = (r < r1 && c < ell) ? (double)v : 0.0;
-        if (r < r1 && c < ell) Q[r * ldq + c] = v;
-      }
-    }
-    __syncthreads();
-    if (part) gram_chunk(sh, GCH, ellp, g);
   }
-  if (part) gram_store(g, ell, ellp, part + (int64_t)blockIdx.x * ell * ell);
+  gram_store(g, slots, ell, part + (int64_t)blockIdx.x * ell * ell);
+  if (last_block_done(counter)) chol_body(part, gridDim.x, ell, rows, R, Rinv, dflags, dyn);
+}
+
+// ---------------------------------------------------------------- Q = Y Rinv (+ Gram partials of Q)
+// Thread t owns output column c = t % CW and rows t/CW + (256/CW) u of each
+// 32-row chunk; every Rinv entry is read once per chunk and reused across rows.
+// cond = 1: run only after a shifted first pass.  With part != nullptr the
+// workgroup also accumulates the Gram of the rounded output, and with a counter
+// the last workgroup factors it into R, Rinv (all other workgroups have finished
+// reading Rinv by then).  gram_cond = 1: the Gram/factorization only after a
+// shifted first pass.
+template <typename T, int CW>
+__global__ void __launch_bounds__(256) k_apply(const T *__restrict__ Y, int64_t rows, int ell, int64_t ldy,
+                                               double *__restrict__ Rinv, T *__restrict__ Q, int64_t ldq,
+                                               int64_t rows_per_blk, double *__restrict__ part,
+                                               int *__restrict__ dflags, int cond, unsigned *__restrict__ counter,
+                                               double *__restrict__ R, int gram_cond) {
+  const bool fallback = (dflags[FLAGW_BITS] & DSK_FLAG_FALLBACK) != 0;
+  if (cond && !fallback) return;
+  if (gram_cond && !fallback) {
+    part = nullptr;
+    counter = nullptr;
+  }
+  constexpr int RG = 256 / CW;            // row groups
+  constexpr int RPT = GCH / RG;           // rows per thread per chunk
+  extern __shared__ double dyn[];
+  const int ellp = (ell + 3) & ~3;
+  double *Rs = dyn;                       // ell x ell
+  double *sh = dyn + ell * ell;           // GCH x ellp
+  for (int e = threadIdx.x; e < ell * ell; e += 256) Rs[e] = Rinv[e];
+  const GramSlots slots = gram_slots(ellp);
+  GramAcc g;
+  gram_zero(g);
+  const int c = threadIdx.x % CW, rg = threadIdx.x / CW;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+  const int64_t r1 = std::min<int64_t>(rows, r0 + rows_per_blk);
+  for (int64_t c0 = r0; c0 < r1; c0 += GCH) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int rr = rg + RG * u;
+      const int64_t r = c0 + rr;
+      for (int cc = c; cc < ellp; cc += CW) sh[rr * ellp + cc] = (r < r1 && cc < ell) ? (double)Y[r * ldy + cc] : 0.0;
+    }
+    __syncthreads();
+    double acc[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) acc[u] = 0.0;
+    if (c < ell) {
+      for (int q = 0; q <= c; ++q) {
+        const double rv = Rs[q * ell + c];
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) acc[u] = fma(sh[(rg + RG * u) * ellp + q], rv, acc[u]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int rr = rg + RG * u;
+      const int64_t r = c0 + rr;
+      const T v = (T)acc[u];
+      const bool ok = r < r1 && c < ell;
+      if (c < ellp) sh[rr * ellp + c] = ok ? (double)v : 0.0;
+      if (ok) Q[r * ldq + c] = v;
+    }
+    __syncthreads();
+    if (part) gram_chunk(sh, GCH, ellp, slots, g);
+  }
+  if (part) gram_store(g, slots, ell, part + (int64_t)blockIdx.x * ell * ell);
+  if (part && counter) {
+    __syncthreads();   // LDS (Rs, sh) is reused by the factorization
+    if (last_block_done(counter)) chol_body(part, gridDim.x, ell, rows, R, Rinv, dflags, dyn);
+  }
 }
 
 // ---------------------------------------------------------------- Householder QR (one block)
@@ -324,7 +432,6 @@ __global__ void __launch_bounds__(1024) k_hhqr(double *__restrict__ X, int64_t r
       if (alpha == 0.0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_RANK_DEFICIENT);
     }
     __syncthreads();
-    // w_c = x_jc + sum_{i>j} v_i x_ic for trailing columns
     for (int c = j + 1 + grp; c < ell; c += 64) {
       double p = 0.0;
       for (int64_t i = j + 1 + gl; i < rows; i += 16) p += X[i * ell + j] * X[i * ell + c];
@@ -349,7 +456,6 @@ __global__ void __launch_bounds__(1024) k_hhqr(double *__restrict__ X, int64_t r
     if (c > i) R[e] = X[(int64_t)i * ell + c];
     else if (c < i) R[e] = 0.0;
   }
-  // explicit Q = H_0 ... H_{ell-1} [I; 0]
   for (int64_t e = t; e < rows * ell; e += 1024) {
     const int64_t i = e / ell;
     const int c = (int)(e % ell);
@@ -377,245 +483,51 @@ __global__ void __launch_bounds__(1024) k_hhqr(double *__restrict__ X, int64_t r
   }
 }
 
-// ---------------------------------------------------------------- round-robin pairing
-// Circle method on n (even) players: player 0 fixed, others rotate; pair i of
-// round r joins positions i and n-1-i.
-__device__ __forceinline__ int rr_player(int pos, int r, int n) {
-  return pos == 0 ? 0 : ((pos - 1 + r) % (n - 1)) + 1;
-}
-
-__device__ __forceinline__ int pk(int a, int b, int n) {   // packed upper index, a <= b
-  return a * n - (a * (a - 1)) / 2 + (b - a);
-}
-
-// ---------------------------------------------------------------- two-sided Jacobi eigen
-// G (ell x ell, symmetric) given as nparts partial sums.  Outputs eigenvalues in
-// descending order and the matching eigenvectors as columns of V (ell x ell).
-__global__ void __launch_bounds__(1024) k_jacobi_eig(const double *__restrict__ part, int nparts, int ell,
-                                                     double *__restrict__ lam, double *__restrict__ Vout,
-                                                     int *__restrict__ dflags) {
-  extern __shared__ double dyn[];
-  const int n = (ell + 1) & ~1;            // even number of players (one zero pad if odd)
-  const int npk = n * (n + 1) / 2;
-  double *Gp = dyn;                        // packed upper, n x n
-  double *V = dyn + npk;                   // n x n row-major
-  __shared__ double rc[ELL_MAX / 2 + 1], rs[ELL_MAX / 2 + 1];
-  __shared__ int pp[ELL_MAX / 2 + 1], pq[ELL_MAX / 2 + 1];
-  __shared__ double red[17];
-  __shared__ int rank_of[ELL_MAX + 2];
-  const int t = threadIdx.x;
-  const int np = n / 2;
-  for (int e = t; e < npk; e += 1024) Gp[e] = 0.0;
-  __syncthreads();
-  double fro = 0.0;
-  for (int e = t; e < ell * ell; e += 1024) {
-    const int a = e / ell, b = e % ell;
-    double s = 0.0;
-    for (int p = 0; p < nparts; ++p) s += part[(int64_t)p * ell * ell + e];
-    if (a <= b) Gp[pk(a, b, n)] = s;
-    fro += s * s;
-  }
-  for (int e = t; e < n * n; e += 1024) V[e] = (e / n == e % n) ? 1.0 : 0.0;
-  fro = block_sum<1024>(fro, red);
-  if (!isfinite(fro) && t == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_NONFINITE);
-  const double tol2 = 1e-30 * fro;
-  for (int sweep = 0; sweep < 30; ++sweep) {
-    double off = 0.0;
-    for (int e = t; e < npk; e += 1024) {
-      // off-diagonal mass (each strictly-upper entry counted twice)
-      int a = 0, rem = e;
-      while (rem >= n - a) { rem -= n - a; ++a; }
-      const int b = a + rem;
-      if (b > a) off += 2.0 * Gp[e] * Gp[e];
-    }
-    off = block_sum<1024>(off, red);
-    if (!(off > tol2)) break;
-    for (int r = 0; r < n - 1; ++r) {
-      if (t < np) {
-        int p = rr_player(t, r, n), q = rr_player(n - 1 - t, r, n);
-        if (p > q) { const int x = p; p = q; q = x; }
-        const double gpp = Gp[pk(p, p, n)], gqq = Gp[pk(q, q, n)], gpq = Gp[pk(p, q, n)];
-        double c = 1.0, s = 0.0;
-        if (gpq != 0.0 && fabs(gpq) > 1e-300) {
-          const double theta = (gqq - gpp) / (2.0 * gpq);
-          const double tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
-          c = 1.0 / sqrt(1.0 + tt * tt);
-          s = tt * c;
-        }
-        rc[t] = c; rs[t] = s; pp[t] = p; pq[t] = q;
-      }
-      __syncthreads();
-      // G <- J^T G J over 2x2 blocks (P1 <= P2)
-      const int nblk = np * (np + 1) / 2;
-      for (int e = t; e < nblk; e += 1024) {
-        int P1 = 0, rem = e;
-        while (rem >= np - P1) { rem -= np - P1; ++P1; }
-        const int P2 = P1 + rem;
-        const int p1 = pp[P1], q1 = pq[P1], p2 = pp[P2], q2 = pq[P2];
-        const double c1 = rc[P1], s1 = rs[P1], c2 = rc[P2], s2 = rs[P2];
-        if (P1 == P2) {
-          const double gpp = Gp[pk(p1, p1, n)], gqq = Gp[pk(q1, q1, n)], gpq = Gp[pk(p1, q1, n)];
-          Gp[pk(p1, p1, n)] = c1 * c1 * gpp - 2.0 * c1 * s1 * gpq + s1 * s1 * gqq;
-          Gp[pk(q1, q1, n)] = s1 * s1 * gpp + 2.0 * c1 * s1 * gpq + c1 * c1 * gqq;
-          Gp[pk(p1, q1, n)] = 0.0;
-        } else {
-          const int i_pp = pk(min(p1, p2), max(p1, p2), n), i_pq = pk(min(p1, q2), max(p1, q2), n);
-          const int i_qp = pk(min(q1, p2), max(q1, p2), n), i_qq = pk(min(q1, q2), max(q1, q2), n);
-          const double bpp = Gp[i_pp], bpq = Gp[i_pq], bqp = Gp[i_qp], bqq = Gp[i_qq];
-          // rows: p' = c1 p - s1 q ; q' = s1 p + c1 q
-          const double rpp = c1 * bpp - s1 * bqp, rpq = c1 * bpq - s1 * bqq;
-          const double rqp = s1 * bpp + c1 * bqp, rqq = s1 * bpq + c1 * bqq;
-          // cols: p' = c2 p - s2 q ; q' = s2 p + c2 q
-          Gp[i_pp] = c2 * rpp - s2 * rpq;
-          Gp[i_pq] = s2 * rpp + c2 * rpq;
-          Gp[i_qp] = c2 * rqp - s2 * rqq;
-          Gp[i_qq] = s2 * rqp + c2 * rqq;
-        }
-      }
-      // V <- V J
-      for (int e = t; e < n * np; e += 1024) {
-        const int a = e / np, P = e % np;
-        const int p = pp[P], q = pq[P];
-        const double c = rc[P], s = rs[P];
-        const double vp = V[a * n + p], vq = V[a * n + q];
-        V[a * n + p] = c * vp - s * vq;
-        V[a * n + q] = s * vp + c * vq;
-      }
-      __syncthreads();
-    }
-  }
-  // sort eigenvalues (descending, ties by index) among the ell real players
-  for (int a = t; a < ell; a += 1024) {
-    const double da = Gp[pk(a, a, n)];
-    int rnk = 0;
-    for (int b = 0; b < ell; ++b) {
-      const double db = Gp[pk(b, b, n)];
-      if (db > da || (db == da && b < a)) ++rnk;
-    }
-    rank_of[a] = rnk;
-  }
-  __syncthreads();
-  for (int a = t; a < ell; a += 1024) lam[rank_of[a]] = Gp[pk(a, a, n)];
-  for (int e = t; e < ell * ell; e += 1024) {
-    const int i = e / ell, a = e % ell;
-    Vout[i * ell + rank_of[a]] = V[i * n + a];
-  }
-}
-
-// ---------------------------------------------------------------- one-sided Jacobi SVD
-// Rm (ell x ell, row-major).  W = Rm V with orthogonal columns; sig_j = ||w_j||.
-// Outputs (descending): sig, Vr (ell x ell, columns = right vectors V),
-// Ur (ell x ell, columns = w_j / sig_j, 0 where sig_j = 0).
-__global__ void __launch_bounds__(1024) k_jacobi_svd(const double *__restrict__ Rm, int ell,
-                                                     double *__restrict__ sig, double *__restrict__ Vr,
-                                                     double *__restrict__ Ur, int *__restrict__ dflags) {
-  extern __shared__ double dyn[];
-  const int n = (ell + 1) & ~1;
-  double *W = dyn;               // column-major n cols x ell rows: W[col*ell + row]
-  double *V = dyn + n * ell;     // column-major n x n
-  __shared__ int rank_of[ELL_MAX + 2];
-  __shared__ double nrm[ELL_MAX + 2];
-  __shared__ int rotated;
-  const int t = threadIdx.x;
-  const int np = n / 2;
-  for (int e = t; e < n * ell; e += 1024) {
-    const int col = e / ell, row = e % ell;
-    W[e] = (col < ell) ? Rm[row * ell + col] : 0.0;
-  }
-  for (int e = t; e < n * n; e += 1024) V[e] = (e / n == e % n) ? 1.0 : 0.0;
-  __syncthreads();
-  const int gs = 16;   // threads per pair
-  const int grp = t / gs, gl = t % gs;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    if (t == 0) rotated = 0;
-    __syncthreads();
-    for (int r = 0; r < n - 1; ++r) {
-      for (int P = grp; P < np; P += 1024 / gs) {
-        int p = rr_player(P, r, n), q = rr_player(n - 1 - P, r, n);
-        if (p > q) { const int x = p; p = q; q = x; }
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = gl; i < ell; i += gs) {
-          const double wp = W[p * ell + i], wq = W[q * ell + i];
-          al += wp * wp; be += wq * wq; ga += wp * wq;
-        }
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) {
-          al += __shfl_xor(al, o, 16);
-          be += __shfl_xor(be, o, 16);
-          ga += __shfl_xor(ga, o, 16);
-        }
-        if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
-          const double zeta = (be - al) / (2.0 * ga);
-          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + tt * tt), s = tt * c;
-          for (int i = gl; i < ell; i += gs) {
-            const double wp = W[p * ell + i], wq = W[q * ell + i];
-            W[p * ell + i] = c * wp - s * wq;
-            W[q * ell + i] = s * wp + c * wq;
-          }
-          for (int i = gl; i < n; i += gs) {
-            const double vp = V[p * n + i], vq = V[q * n + i];
-            V[p * n + i] = c * vp - s * vq;
-            V[q * n + i] = s * vp + c * vq;
-          }
-          if (gl == 0) rotated = 1;
-        }
-      }
-      __syncthreads();
-    }
-    if (!rotated) break;
-  }
-  for (int col = t; col < ell; col += 1024) {
-    double s = 0.0;
-    for (int i = 0; i < ell; ++i) s += W[col * ell + i] * W[col * ell + i];
-    nrm[col] = sqrt(s);
-  }
-  __syncthreads();
-  for (int a = t; a < ell; a += 1024) {
-    int rnk = 0;
-    for (int b = 0; b < ell; ++b)
-      if (nrm[b] > nrm[a] || (nrm[b] == nrm[a] && b < a)) ++rnk;
-    rank_of[a] = rnk;
-    if (!isfinite(nrm[a])) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_NONFINITE);
-  }
-  __syncthreads();
-  for (int a = t; a < ell; a += 1024) sig[rank_of[a]] = nrm[a];
-  for (int e = t; e < ell * ell; e += 1024) {
-    const int i = e / ell, a = e % ell;
-    Vr[i * ell + rank_of[a]] = V[a * n + i];
-    Ur[i * ell + rank_of[a]] = nrm[a] > 0.0 ? W[a * ell + i] / nrm[a] : 0.0;
-  }
-}
-
 // ---------------------------------------------------------------- skinny product out = X M diag(scale)
-// X rows x ell (ldx), M ell x kout (ldm, f64), out rows x kout (ldo).  32 rows per
-// block, 8 threads per row.
+// X rows x ell (ldx), M ell x kout (ldm, f64), out rows x kout (ldo).  TS_ROWS rows
+// per block (large inputs: 128 for f32, 64 for f64; short inputs: 32); thread
+// (row, part) accumulates KH outputs in registers, every M row is a broadcast
+// LDS read reused for all of them.
 template <typename T>
+constexpr int ts_rows() { return sizeof(T) == 8 ? 64 : 128; }
+
+template <typename T, int KB, int TS_ROWS>
 __global__ void __launch_bounds__(256) k_tsmm(const T *__restrict__ X, int64_t rows, int ell, int64_t ldx,
                                               const double *__restrict__ M, int ldm, int kout,
                                               const double *__restrict__ scale, T *__restrict__ out,
                                               int64_t ldo) {
+  constexpr int TPR = 256 / TS_ROWS;
+  constexpr int KH = KB / TPR;
   extern __shared__ double dyn[];
-  T *Ms = reinterpret_cast<T *>(dyn);                              // ell x kout
-  T *Xs = Ms + ((ell * kout + 1) & ~1);                            // 32 x ell
-  for (int e = threadIdx.x; e < ell * kout; e += 256) {
-    const int i = e / kout, c = e % kout;
-    Ms[e] = (T)(M[i * ldm + c] * (scale ? scale[c] : 1.0));
+  T *Ms = reinterpret_cast<T *>(dyn);                    // ell x KB (zero padded)
+  T *Xs = Ms + ell * KB;                                 // TS_ROWS x (ell + 1)
+  const int ldxs = ell + 1;
+  for (int e = threadIdx.x; e < ell * KB; e += 256) {
+    const int i = e / KB, c = e - (e / KB) * KB;
+    Ms[e] = (c < kout) ? (T)(M[i * ldm + c] * (scale ? scale[c] : 1.0)) : T(0);
   }
-  const int64_t r0 = (int64_t)blockIdx.x * 32;
-  for (int e = threadIdx.x; e < 32 * ell; e += 256) {
-    const int rr = e / ell, c = e % ell;
+  const int64_t r0 = (int64_t)blockIdx.x * TS_ROWS;
+  for (int rr = threadIdx.x >> 6; rr < TS_ROWS; rr += 4) {
     const int64_t r = r0 + rr;
-    Xs[e] = r < rows ? X[r * ldx + c] : T(0);
+    for (int c = threadIdx.x & 63; c < ell; c += 64) Xs[rr * ldxs + c] = r < rows ? X[r * ldx + c] : T(0);
   }
   __syncthreads();
-  const int rr = threadIdx.x >> 3, cl = threadIdx.x & 7;
+  const int rr = threadIdx.x / TPR, half = threadIdx.x % TPR;
   const int64_t r = r0 + rr;
+  T acc[KH];
+#pragma unroll
+  for (int u = 0; u < KH; ++u) acc[u] = 0;
+  const T *mrow = Ms + half * KH;
+  for (int q = 0; q < ell; ++q) {
+    const T xv = Xs[rr * ldxs + q];
+#pragma unroll
+    for (int u = 0; u < KH; ++u) acc[u] = fma(xv, mrow[q * KB + u], acc[u]);
+  }
   if (r >= rows) return;
-  for (int c = cl; c < kout; c += 8) {
-    T s = 0;
-    for (int q = 0; q < ell; ++q) s = fma(Xs[rr * ell + q], Ms[q * kout + c], s);
-    out[r * ldo + c] = s;
+#pragma unroll
+  for (int u = 0; u < KH; ++u) {
+    const int c = half * KH + u;
+    if (c < kout) out[r * ldo + c] = acc[u];
   }
 }
 
@@ -652,31 +564,45 @@ __global__ void __launch_bounds__(256) k_sign_fix(T *__restrict__ U, int64_t m, 
     for (int64_t i = threadIdx.x; i < m; i += 256) U[i * k + j] = -U[i * k + j];
 }
 
+int gram_parts(int64_t rows) { return (int)std::min<int64_t>(std::max<int64_t>(1, (rows + 63) / 64), 32); }
+
+template <typename T, int CW>
+void launch_apply(hipStream_t st, int nparts, size_t lds, const T *Y, int64_t rows, int ell, double *Rinv, T *Q,
+                  int64_t rpb, double *part, int *dflags, int cond, unsigned *counter, double *R, int gram_cond) {
+  allow_lds(k_apply<T, CW>, lds);
+  hipLaunchKernelGGL((k_apply<T, CW>), dim3(nparts), dim3(256), lds, st, Y, rows, ell, (int64_t)ell, Rinv, Q,
+                     (int64_t)ell, rpb, part, dflags, cond, counter, R, gram_cond);
+}
+
+// CholeskyQR2 in 3 launches (+1 after a shifted first pass):
+//   [Gram(Y) -> chol]  [Q1 = Y R1^-1, Gram(Q1) -> chol]  [Q = Q1 R2^-1 (, Gram(Q) -> chol)]  [(Q = Q R3^-1)]
+// The factorizations run in the workgroup that finishes its Gram partial last.
 template <typename T>
 int cholqr2_typed(hipStream_t st, const T *Y, int64_t rows, int ell, T *Q, void *ws, int *dflags) {
   // ws layout: part (nparts*ell*ell f64) | R (ell^2) | Rinv (ell^2) | Q1 (rows*ell T)
-  const int nparts = (int)std::min<int64_t>(std::max<int64_t>(1, (rows + 63) / 64), 240);
+  const int nparts = gram_parts(rows);
   const int64_t rpb = ((rows + nparts - 1) / nparts + GCH - 1) / GCH * GCH;
   double *part = reinterpret_cast<double *>(ws);
   double *R = part + (size_t)nparts * ell * ell;
   double *Rinv = R + ell * ell;
   T *Q1 = reinterpret_cast<T *>(Rinv + ell * ell);
+  unsigned *counter = reinterpret_cast<unsigned *>(dflags + FLAGW_TICKET);
+  const int ellp = (ell + 3) & ~3;
   const size_t chol_lds = (size_t)(ell * ell + ell) * sizeof(double);
-  const size_t apply_lds = (size_t)(ell * ell + GCH * ((ell + 3) & ~3)) * sizeof(double);
-  allow_lds(k_chol, chol_lds);
-  allow_lds(k_apply<T>, apply_lds);
-  hipLaunchKernelGGL(k_gram_part<T>, dim3(nparts), dim3(256), 0, st, Y, rows, ell, (int64_t)ell, rpb, part,
-                     dflags, 0);
-  hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), chol_lds, st, part, nparts, ell, rows, R, Rinv, dflags, 0);
-  hipLaunchKernelGGL(k_apply<T>, dim3(nparts), dim3(256), apply_lds, st, Y, rows, ell, (int64_t)ell, Rinv, Q1,
-                     (int64_t)ell, rpb, part, dflags, 0);
-  hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), chol_lds, st, part, nparts, ell, rows, R, Rinv, dflags, 0);
-  hipLaunchKernelGGL(k_apply<T>, dim3(nparts), dim3(256), apply_lds, st, Q1, rows, ell, (int64_t)ell, Rinv, Q,
-                     (int64_t)ell, rpb, part, dflags, 0);
-  // third pass only after a shifted first pass
-  hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), chol_lds, st, part, nparts, ell, rows, R, Rinv, dflags, 1);
-  hipLaunchKernelGGL(k_apply<T>, dim3(nparts), dim3(256), apply_lds, st, Q, rows, ell, (int64_t)ell, Rinv, Q,
-                     (int64_t)ell, rpb, (double *)nullptr, dflags, 1);
+  const size_t gram_lds = std::max<size_t>(chol_lds, (size_t)GCH * ellp * sizeof(double));
+  const size_t apply_lds = std::max<size_t>(chol_lds, (size_t)(ell * ell + GCH * ellp) * sizeof(double));
+  auto apply = [&](const T *src, T *dst, double *prt, int cond, unsigned *ctr, int gcond) {
+    if (ell <= 64)
+      launch_apply<T, 64>(st, nparts, apply_lds, src, rows, ell, Rinv, dst, rpb, prt, dflags, cond, ctr, R, gcond);
+    else
+      launch_apply<T, 128>(st, nparts, apply_lds, src, rows, ell, Rinv, dst, rpb, prt, dflags, cond, ctr, R, gcond);
+  };
+  allow_lds(k_gram_chol<T>, gram_lds);
+  hipLaunchKernelGGL(k_gram_chol<T>, dim3(nparts), dim3(256), gram_lds, st, Y, rows, ell, (int64_t)ell, rpb, part,
+                     counter, R, Rinv, dflags);
+  apply(Y, Q1, part, 0, counter, 0);
+  apply(Q1, Q, part, 0, counter, 1);     // third factorization only after a shifted first pass
+  apply(Q, Q, nullptr, 1, nullptr, 0);   // third application only after a shifted first pass
   DSK_TRY(hipGetLastError());
   return 0;
 }
@@ -684,7 +610,7 @@ int cholqr2_typed(hipStream_t st, const T *Y, int64_t rows, int ell, T *Q, void 
 }  // namespace
 
 size_t cholqr2_ws_bytes(int64_t rows, int ell) {
-  const int nparts = (int)std::min<int64_t>(std::max<int64_t>(1, (rows + 63) / 64), 240);
+  const int nparts = gram_parts(rows);
   return ((size_t)nparts * ell * ell + 2 * (size_t)ell * ell) * sizeof(double) + (size_t)rows * ell * sizeof(double) +
          1024;
 }
@@ -718,47 +644,40 @@ int launch_gram(hipStream_t st, const void *X, int f64, int64_t rows, int ell, d
   return 0;
 }
 
-int launch_jacobi_eig_parts(hipStream_t st, const double *part, int nparts, int ell, double *lam, double *V,
-                            int *dflags) {
-  if (ell < 1 || ell > ELL_MAX) return -1;
-  const int n = (ell + 1) & ~1;
-  const size_t lds = ((size_t)n * (n + 1) / 2 + (size_t)n * n) * sizeof(double);
-  allow_lds(k_jacobi_eig, lds);
-  hipLaunchKernelGGL(k_jacobi_eig, dim3(1), dim3(1024), lds, st, part, nparts, ell, lam, V, dflags);
-  DSK_TRY(hipGetLastError());
-  return 0;
+template <typename T, int KB, int TS_ROWS>
+void tsmm_r(hipStream_t st, const T *X, int64_t rows, int ell, int64_t ldx, const double *M, int ldm, int kout,
+            const double *colscale, T *out, int64_t ldo) {
+  const unsigned blocks = (unsigned)((rows + TS_ROWS - 1) / TS_ROWS);
+  const size_t lds = ((size_t)ell * KB + (size_t)TS_ROWS * (ell + 1)) * sizeof(T);
+  allow_lds(k_tsmm<T, KB, TS_ROWS>, lds);
+  hipLaunchKernelGGL((k_tsmm<T, KB, TS_ROWS>), dim3(blocks), dim3(256), lds, st, X, rows, ell, ldx, M, ldm, kout,
+                     colscale, out, ldo);
 }
 
-int launch_jacobi_eig(hipStream_t st, const double *G, int ell, double *lam, double *V, int *dflags) {
-  return launch_jacobi_eig_parts(st, G, 1, ell, lam, V, dflags);
+template <typename T, int KB>
+void tsmm_t(hipStream_t st, const T *X, int64_t rows, int ell, int64_t ldx, const double *M, int ldm, int kout,
+            const double *colscale, T *out, int64_t ldo) {
+  // short inputs: 32-row blocks so that more workgroups share the work
+  if (rows < 64 * 256) tsmm_r<T, KB, 32>(st, X, rows, ell, ldx, M, ldm, kout, colscale, out, ldo);
+  else tsmm_r<T, KB, ts_rows<T>()>(st, X, rows, ell, ldx, M, ldm, kout, colscale, out, ldo);
 }
 
-int launch_jacobi_svd(hipStream_t st, const double *Rm, int ell, double *sig, double *Vr, double *Ur, int *dflags) {
-  if (ell < 1 || ell > 100) return -1;
-  const int n = (ell + 1) & ~1;
-  const size_t lds = ((size_t)n * ell + (size_t)n * n) * sizeof(double);
-  allow_lds(k_jacobi_svd, lds);
-  hipLaunchKernelGGL(k_jacobi_svd, dim3(1), dim3(1024), lds, st, Rm, ell, sig, Vr, Ur, dflags);
+template <typename T>
+int tsmm_any(hipStream_t st, const T *X, int64_t rows, int ell, int64_t ldx, const double *M, int ldm, int kout,
+             const double *colscale, T *out, int64_t ldo) {
+  if (kout <= 16) tsmm_t<T, 16>(st, X, rows, ell, ldx, M, ldm, kout, colscale, out, ldo);
+  else if (kout <= 32) tsmm_t<T, 32>(st, X, rows, ell, ldx, M, ldm, kout, colscale, out, ldo);
+  else if (kout <= 64) tsmm_t<T, 64>(st, X, rows, ell, ldx, M, ldm, kout, colscale, out, ldo);
+  else if (kout <= 128) tsmm_t<T, 128>(st, X, rows, ell, ldx, M, ldm, kout, colscale, out, ldo);
+  else return -1;
   DSK_TRY(hipGetLastError());
   return 0;
 }
 
 int launch_tsmm(hipStream_t st, const void *X, int f64, int64_t rows, int ell, int64_t ldx, const double *M, int ldm,
                 int kout, const double *colscale, void *out, int64_t ldo) {
-  const unsigned blocks = (unsigned)((rows + 31) / 32);
-  if (f64) {
-    const size_t lds = ((size_t)((ell * kout + 1) & ~1) + 32 * (size_t)ell) * sizeof(double);
-    allow_lds(k_tsmm<double>, lds);
-    hipLaunchKernelGGL(k_tsmm<double>, dim3(blocks), dim3(256), lds, st, (const double *)X, rows, ell, ldx, M, ldm,
-                       kout, colscale, (double *)out, ldo);
-  } else {
-    const size_t lds = ((size_t)((ell * kout + 1) & ~1) + 32 * (size_t)ell) * sizeof(float);
-    allow_lds(k_tsmm<float>, lds);
-    hipLaunchKernelGGL(k_tsmm<float>, dim3(blocks), dim3(256), lds, st, (const float *)X, rows, ell, ldx, M, ldm,
-                       kout, colscale, (float *)out, ldo);
-  }
-  DSK_TRY(hipGetLastError());
-  return 0;
+  if (f64) return tsmm_any<double>(st, (const double *)X, rows, ell, ldx, M, ldm, kout, colscale, (double *)out, ldo);
+  return tsmm_any<float>(st, (const float *)X, rows, ell, ldx, M, ldm, kout, colscale, (float *)out, ldo);
 }
 
 int launch_sign_fix(hipStream_t st, void *U, int f64, int64_t m, int k, double *sign) {
