@@ -125,6 +125,7 @@ def main():
 
     svd_ms = {qq: timed(lambda qq=qq: dsketch.sketch_svd(A, k, R, q=qq, mode=a.mode)) for qq in (0, 1, 2)}
     id_ms = timed(lambda: dsketch.sketch_id(A, k, R, q=0, skeleton_rows=True))
+    sweeps = {qq: dsketch.sketch_svd(A, k, R, q=qq, mode=a.mode, want_info=True)[3]["core_sweeps"] for qq in (0, 1, 2)}
 
     b_svd, b_id = algorithmic_bytes(m, n, s, k, q)
     step_bytes = b_svd + b_id
@@ -176,6 +177,7 @@ def main():
         "cpu_baseline": cpu,
         "breakdown_ms": {"svd_q0": round(svd_ms[0], 4), "svd_q1": round(svd_ms[1], 4), "svd_q2": round(svd_ms[2], 4),
                          "id_q0": round(id_ms, 4)},
+        "core_sweeps": {f"q{qq}": sweeps[qq] for qq in (0, 1, 2)},
     }
     print(json.dumps(rec), flush=True)
 

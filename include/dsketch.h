@@ -99,6 +99,8 @@ typedef struct {       /* host struct, filled when passed */
   double normA_fro2;   /* ||A||_F^2 (sketch_svd only) */
   double normB_fro2;   /* ||Q^T A||_F^2 (sketch_svd only): projection error^2 = normA - normB */
   double sigma_tail;   /* sigma_{k+1} of B = Q^T A when ell > k, else 0 */
+  int32_t core_sweeps; /* Jacobi sweeps of the ell x ell core factorization (sketch_svd) */
+  int32_t reserved;    /* 0 */
 } dsk_info;
 
 /* Fill *o with the defaults listed above. */

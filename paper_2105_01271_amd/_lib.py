@@ -60,6 +60,8 @@ class Info(ctypes.Structure):
         ("normA_fro2", ctypes.c_double),
         ("normB_fro2", ctypes.c_double),
         ("sigma_tail", ctypes.c_double),
+        ("core_sweeps", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 

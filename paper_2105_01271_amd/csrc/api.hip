@@ -88,13 +88,15 @@ struct Finish {
 
 int read_info(dsk_handle *h, const double *dinfo, dsk_info *info, int ell) {
   if (!info) return 0;
-  int flags = 0;
+  int words[FLAGW_COUNT] = {0, 0, 0, 0};
   double vals[3] = {0, 0, 0};
-  DSK_TRY(hipMemcpyAsync(&flags, h->dflags, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  DSK_TRY(hipMemcpyAsync(words, h->dflags, sizeof(words), hipMemcpyDeviceToHost, h->stream));
   if (dinfo) DSK_TRY(hipMemcpyAsync(vals, dinfo, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   DSK_TRY(hipStreamSynchronize(h->stream));
   info->ell = ell;
-  info->flags = flags;
+  info->flags = words[FLAGW_BITS];
+  info->core_sweeps = words[FLAGW_SWEEPS];
+  info->reserved = 0;
   info->normA_fro2 = vals[2];
   info->normB_fro2 = vals[0];
   info->sigma_tail = vals[1];
@@ -314,8 +316,9 @@ int dsk_sketch_svd(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64
     sws_b = std::max(sws_b, stream_ws_bytes(f64 ? DSK_F64 : DSK_F32, L, n, k, od.mode));
     char *sws = c.take<char>(sws_b);
     float *Mv = c.take<float>((size_t)L * k);
-    const int nparts = (int)std::min<int64_t>(128, std::max<int64_t>(1, (n + 255) / 256));
+    const int nparts = (int)std::min<int64_t>(256, std::max<int64_t>(1, (n + 255) / 256));
     double *part = c.take<double>((size_t)nparts * L * L);
+    double *GB = c.take<double>((size_t)L * L);
     double *lam = c.take<double>(L);
     double *UB = c.take<double>((size_t)L * L);
     double *Ur = c.take<double>((size_t)L * L);
@@ -357,9 +360,8 @@ int dsk_sketch_svd(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64
       DSK_RET(launch_stream(st, A, dtype, m, n, lda, Q, f64, L, Bt, L, od.mode, sws, h->cu_count));
     }
     if (!f64) {
-      DSK_RET(launch_gram(st, Bt, 0, n, L, nullptr, part, nparts));
-      // off-diagonal mass <= 1e-12 ||G||_F: eigenvectors far below f32 resolution
-      DSK_RET(launch_jacobi_eig_parts(st, part, nparts, L, lam, UB, h->dflags, 1e-24));
+      DSK_RET(launch_gram(st, Bt, 0, n, L, GB, part, nparts));
+      DSK_RET(launch_core_eig(st, GB, L, lam, UB, h->dflags));
       DSK_RET(launch_tsmm(st, Q, 0, m, L, L, UB, L, k, nullptr, U, k));
       DSK_RET(launch_sign_fix(st, U, 0, m, k, sign));
       hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, st, lam, 1, L, k, sign, 1, S, colscale, dinfo,

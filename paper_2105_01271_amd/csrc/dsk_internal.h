@@ -20,8 +20,9 @@
   } while (0)
 
 // Device-side status words: [0] DSK_FLAG_* bits, [1] workgroup ticket counter of
-// the fused reduce-and-factor kernels (returns to 0 after every launch).
-enum { FLAGW_BITS = 0, FLAGW_TICKET = 1, FLAGW_COUNT = 4 };
+// the fused reduce-and-factor kernels (returns to 0 after every launch), [2]
+// Jacobi sweeps of the last core factorization.
+enum { FLAGW_BITS = 0, FLAGW_TICKET = 1, FLAGW_SWEEPS = 2, FLAGW_COUNT = 4 };
 
 struct dsk_handle {
   int device;
@@ -93,8 +94,7 @@ int launch_hhqr(hipStream_t st, double *X, int64_t rows, int ell, double *Q, dou
 int launch_gram(hipStream_t st, const void *X, int f64, int64_t rows, int ell, double *G,
                 double *part, int nparts);
 // jacobi.hip
-int launch_jacobi_eig_parts(hipStream_t st, const double *part, int nparts, int ell, double *lam, double *V,
-                            int *dflags, double tol2_rel);
+int launch_core_eig(hipStream_t st, const double *G, int ell, double *lam, double *U, int *dflags);
 int launch_jacobi_svd(hipStream_t st, const double *Rm, int ell, double *sig, double *Vr,
                       double *Ur, int *dflags);
 int launch_tsmm(hipStream_t st, const void *X, int f64, int64_t rows, int ell, int64_t ldx,

@@ -1,36 +1,37 @@
 // Small dense eigen / SVD cores of SVD(B), B = Q^T A (Alg. 2, "SVD(B)" step):
 //
-//  * k_jacobi_eig: two-sided cyclic Jacobi on the ell x ell FP64 Gram
-//    G_B = B B^T (F32 / BF16 / F16 paths): eigenvalues lambda_j = sigma_j^2
-//    and eigenvectors U_B.  Round-robin (circle) ordering: n/2 disjoint
-//    rotations per round, n-1 rounds per sweep.  Every thread owns a fixed
-//    set of 2x2 blocks of G (pairs of pairs) and of (row, pair) entries of V,
-//    decoded once before the sweeps, so a round is: rotation angles (n/2
-//    threads) -> barrier -> in-place block updates -> barrier.  G is kept
-//    packed (upper triangle) and V row-major, both in LDS (ell <= 112).
-//  * k_jacobi_svd: one-sided (Hestenes) Jacobi on an ell x ell triangular
-//    factor R (FP64 path, B^T = Q_B R): no squaring of the singular values.
+//  * k_core_eig (F32 / BF16 / F16 paths): eigenpairs of the ell x ell FP64
+//    Gram G_B = B B^T.  G_B + delta I (delta a few hundred ulps of tr G_B,
+//    which moves no eigenvector and is subtracted from every eigenvalue at the
+//    end) is factored by Cholesky, G_B + delta I = P L L^T P^T; one-sided
+//    (Hestenes) Jacobi then orthogonalises the columns of L, L V = W, so the
+//    left singular vectors of L -- the eigenvectors of G_B -- are the
+//    normalised columns of W and no rotation is accumulated.  ell <= 64: one
+//    wave factors in registers (P = I); wider: the workgroup factors in LDS
+//    with diagonal pivoting (the QR-with-column-pivoting preconditioner of
+//    one-sided Jacobi, Drmac and Veselic 2008).  Pair sums use DPP row
+//    reductions, rotation angles refined hardware reciprocals.
+//  * k_jacobi_svd (FP64 path): one-sided Jacobi on an ell x ell triangular
+//    factor R (B^T = Q_B R): no squaring of the singular values.
+// Both use round-robin (circle) ordering: n/2 disjoint pairs per round, n - 1
+// rounds per sweep, 16 threads per pair.
 #include <algorithm>
 
 #include "dsk_internal.h"
+#include "wavechol.h"
 
 namespace {
 
 constexpr int JNT = 1024;
 constexpr int JELL_MAX = 112;
-constexpr int JNP_MAX = JELL_MAX / 2;
-// per-thread item counts for a size class with at most NMAX rows (NMAX even)
-template <int NMAX>
-constexpr int gi_of() { return ((NMAX / 2) * (NMAX / 2 + 1) / 2 + JNT - 1) / JNT; }   // 2x2 blocks of G
-template <int NMAX>
-constexpr int vi_of() { return (NMAX * (NMAX / 2) + JNT - 1) / JNT; }                  // (row, pair) of V
+constexpr double U64 = 1.1102230246251565e-16;
 
+// position -> player of round r in the circle method (p in [0, n))
 __device__ __forceinline__ int rr_player(int pos, int r, int n) {
-  return pos == 0 ? 0 : ((pos - 1 + r) % (n - 1)) + 1;
-}
-
-__device__ __forceinline__ int pk(int a, int b, int n) {   // packed upper index, a <= b
-  return a * n - ((a * (a - 1)) >> 1) + (b - a);
+  if (pos == 0) return 0;
+  int x = pos - 1 + r;
+  if (x >= n - 1) x -= n - 1;
+  return x + 1;
 }
 
 template <int NT>
@@ -50,195 +51,214 @@ __device__ double jblock_sum(double v, double *scratch) {
   return scratch[NT / 64];
 }
 
-template <int NMAX>
-__global__ void __launch_bounds__(JNT) k_jacobi_eig(const double *__restrict__ part, int nparts, int ell,
-                                                    double tol2_rel, double *__restrict__ lam,
-                                                    double *__restrict__ Vout, int *__restrict__ dflags) {
-  extern __shared__ double dyn[];
-  const int n = (ell + 1) & ~1;    // one zero row/column pads an odd size
-  const int np = n / 2;
-  const int npk = n * (n + 1) / 2;
-  double *Gp = dyn;
-  double *V = dyn + npk;           // n x n row-major
-  __shared__ double rc[JNP_MAX], rs[JNP_MAX];
-  __shared__ int pp[JNP_MAX], pq[JNP_MAX];
-  __shared__ double red[JNT / 64 + 1];
-  __shared__ int rank_of[JELL_MAX + 2];
+// Rotation (c, s) that makes columns p, q orthogonal, given alpha = |w_p|^2,
+// beta = |w_q|^2, gamma = w_p . w_q (Rutishauser's formulas), with refined
+// hardware reciprocals: c^2 + s^2 = 1 to working precision for any t.
+__device__ __forceinline__ void jrot(double al, double be, double ga, double &c, double &s) {
+  const double zeta = (be - al) * wc::rcp_nr(2.0 * ga);
+  double tt;
+  if (fabs(zeta) > 1e150) {
+    tt = 0.5 * wc::rcp_nr(zeta);
+  } else {
+    const double w = fma(zeta, zeta, 1.0);
+    tt = (zeta >= 0.0 ? 1.0 : -1.0) * wc::rcp_nr(fabs(zeta) + w * wc::rsq_nr(w));
+  }
+  c = wc::rsq_nr(fma(tt, tt, 1.0));
+  s = tt * c;
+}
+
+// ell > 64: Cholesky with diagonal pivoting of G + delta I by the whole
+// workgroup (G in LDS, row stride ldg; right-looking, row j of the trailing
+// matrix read unscaled so that the column scaling and the update share a
+// phase), then X = L column-major in place (X(r, c) at c * ldg + r; columns from
+// a non-positive pivot on are zero).  perm receives the pivot order.
+template <int NT>
+__device__ void pivoted_chol_lds(double *G, int ell, int ldg, double delta, int *perm, int *pivsh, double *pivd) {
   const int t = threadIdx.x;
-  constexpr int GI = gi_of<NMAX>();
-  constexpr int VI = vi_of<NMAX>();
-
-  for (int e = t; e < npk; e += JNT) Gp[e] = 0.0;
-  for (int e = t; e < n * n; e += JNT) V[e] = 0.0;
+  for (int i = t; i < ell; i += NT) G[i * ldg + i] += delta;
   __syncthreads();
-  double fro = 0.0;
-  const int nup = ell * (ell + 1) / 2;
-  for (int u = t; u < nup; u += JNT) {
-    int a = 0, rem = u;
-    while (rem >= ell - a) { rem -= ell - a; ++a; }
-    const int b = a + rem;
-    const int64_t e = (int64_t)a * ell + b;
-    const int64_t st = (int64_t)ell * ell;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;   // fixed association: deterministic
-    int p = 0;
-    for (; p + 3 < nparts; p += 4) {
-      s0 += part[p * st + e];
-      s1 += part[(p + 1) * st + e];
-      s2 += part[(p + 2) * st + e];
-      s3 += part[(p + 3) * st + e];
-    }
-    for (; p < nparts; ++p) s0 += part[p * st + e];
-    const double s = (s0 + s1) + (s2 + s3);
-    Gp[pk(a, b, n)] = s;
-    fro += (a == b ? 1.0 : 2.0) * s * s;
-  }
-  for (int a = t; a < n; a += JNT) V[a * n + a] = 1.0;
-  fro = jblock_sum<JNT>(fro, red);
-  if (!isfinite(fro) && t == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_NONFINITE);
 
-  // fixed per-thread work lists
-  const int nblk = np * (np + 1) / 2;
-  int gP1[GI], gP2[GI];
+  int jstop = ell;
+  for (int j = 0; j < ell; ++j) {
+    if (t < 64) {
+      double bv = -1.0;
+      int bi = ell;
+      for (int i = j + t; i < ell; i += 64) {
+        const double v = G[i * ldg + i];
+        if (v > bv) { bv = v; bi = i; }
+      }
 #pragma unroll
-  for (int u = 0; u < GI; ++u) {
-    const int e = t + JNT * u;
-    gP1[u] = -1;
-    gP2[u] = -1;
-    if (e < nblk) {
-      int P1 = 0, rem = e;
-      while (rem >= np - P1) { rem -= np - P1; ++P1; }
-      gP1[u] = P1;
-      gP2[u] = P1 + rem;
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bv, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+      }
+      if (t == 0) { *pivsh = bi; *pivd = bv; }
+    }
+    __syncthreads();
+    const int p = *pivsh;
+    const double d = *pivd;
+    if (!(d > 0.0) || !isfinite(d)) { jstop = j; break; }
+    if (p != j) {
+      for (int e = t; e < ell; e += NT) {
+        if (e != j && e != p) {
+          double a = G[j * ldg + e]; G[j * ldg + e] = G[p * ldg + e]; G[p * ldg + e] = a;
+          a = G[e * ldg + j]; G[e * ldg + j] = G[e * ldg + p]; G[e * ldg + p] = a;
+        }
+      }
+      if (t == 0) {
+        const double a = G[j * ldg + j]; G[j * ldg + j] = G[p * ldg + p]; G[p * ldg + p] = a;
+        const int pi = perm[j]; perm[j] = perm[p]; perm[p] = pi;
+      }
+      __syncthreads();
+    }
+    const double piv = sqrt(d), dinv = 1.0 / d, pinv = 1.0 / piv;
+    for (int i = j + 1 + (t >> 5); i < ell; i += 32) {
+      const double gji = G[j * ldg + i] * dinv;
+      for (int c = j + 1 + (t & 31); c < ell; c += 32) G[i * ldg + c] = fma(-gji, G[j * ldg + c], G[i * ldg + c]);
+    }
+    for (int i = j + 1 + t; i < ell; i += NT) G[i * ldg + j] = G[j * ldg + i] * pinv;
+    if (t == 0) G[j * ldg + j] = piv;
+    __syncthreads();
+  }
+  // ---- X = L, column-major in place: X(r, c) at c * ldg + r; columns from the
+  // stopping pivot on are zero
+  for (int e = t; e < ell * ell; e += NT) {
+    const int r = e / ell, c = e - (e / ell) * ell;
+    if (r > c) {
+      const double v = (c < jstop) ? G[r * ldg + c] : 0.0;
+      G[c * ldg + r] = v;
+      G[r * ldg + c] = 0.0;
+    } else if (r == c && c >= jstop) {
+      G[r * ldg + c] = 0.0;
     }
   }
-  int va[VI], vP[VI];
-#pragma unroll
-  for (int u = 0; u < VI; ++u) {
-    const int e = t + JNT * u;
-    va[u] = -1;
-    vP[u] = 0;
-    if (e < n * np) {
-      va[u] = e / np;
-      vP[u] = e - va[u] * np;
-    }
-  }
+  __syncthreads();
+}
 
-  const double tol2 = tol2_rel * fro;
+// G_in: ell x ell row-major FP64 Gram.  Outputs, descending: lam (ell eigenvalues,
+// clipped at 0) and Uout (ell x ell row-major, column j = eigenvector j; zero
+// where the factor has no column).  dflags[FLAGW_SWEEPS] = sweeps used.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_core_eig(const double *__restrict__ G_in, int ell,
+                                                  double *__restrict__ lam, double *__restrict__ Uout,
+                                                  int *__restrict__ dflags) {
+  extern __shared__ double dyn[];
+  const int ldg = ell | 1;           // odd row stride: conflict-free column walks
+  const int n = (ell + 1) & ~1;      // even size; an odd ell gets one zero column
+  const int np = n / 2;
+  double *G = dyn;                   // ell x ldg, later X column-major (n columns)
+  __shared__ int perm[JELL_MAX + 2];
+  __shared__ int rank_of[JELL_MAX + 2];
+  __shared__ double nrm2[JELL_MAX + 2];
+  __shared__ double red[JNT / 64 + 1];
+  __shared__ int pivsh;
+  __shared__ double pivd;
+  __shared__ int rotated;
+  const int t = threadIdx.x;
+  for (int e = t; e < n * ldg; e += NT) G[e] = 0.0;
+  __syncthreads();
+  for (int e = t; e < ell * ell; e += NT) {
+    const int i = e / ell, c = e - (e / ell) * ell;
+    G[i * ldg + c] = G_in[e];
+  }
+  for (int i = t; i < n; i += NT) perm[i] = i;
+  __syncthreads();
+  double tr = 0.0;
+  for (int i = t; i < ell; i += NT) tr += G[i * ldg + i];
+  tr = jblock_sum<NT>(tr, red);
+  if (!isfinite(tr) && t == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_NONFINITE);
+  const double delta = 16.0 * (ell + 1024) * U64 * fabs(tr);
+  if constexpr (NT == 512) {
+    // ell <= 64, one wave: register Cholesky of G + delta I, then X = L column-major over G
+    double *Lb = dyn + n * ldg;
+    double *col = Lb + 64 * wc::LDL;
+    double *dinv = col + 64;
+    __shared__ int okw;
+    if (t < 64) {
+      const bool ok = wc::chol64(G, ldg, ell, delta, 0.0, Lb, dinv, col);
+      if (t == 0) okw = ok ? 1 : 0;
+    }
+    __syncthreads();
+    if (!okw && t == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_NONFINITE);
+    for (int e = t; e < n * ldg; e += NT) {
+      const int c = e / ldg, r = e - (e / ldg) * ldg;
+      G[e] = (okw && c < ell && r < ell && r >= c) ? Lb[r * wc::LDL + c] : 0.0;
+    }
+    __syncthreads();
+  } else {
+    pivoted_chol_lds<NT>(G, ell, ldg, delta, perm, &pivsh, &pivd);
+  }
+  // ---- one-sided Jacobi on the columns of X
+  const int grp = t >> 4, gl = t & 15;
+  const double tolj = 4.0 * ell * U64;
+  int sweeps = 0;
   for (int sweep = 0; sweep < 40; ++sweep) {
-    // off-diagonal mass over the round-0 block decomposition (covers each pair once)
-    double off = 0.0;
-#pragma unroll
-    for (int u = 0; u < GI; ++u) {
-      if (gP1[u] < 0) continue;
-      int p1 = rr_player(gP1[u], 0, n), q1 = rr_player(n - 1 - gP1[u], 0, n);
-      int p2 = rr_player(gP2[u], 0, n), q2 = rr_player(n - 1 - gP2[u], 0, n);
-      if (gP1[u] == gP2[u]) {
-        const double x = Gp[pk(min(p1, q1), max(p1, q1), n)];
-        off += 2.0 * x * x;
-      } else {
-        const double a = Gp[pk(min(p1, p2), max(p1, p2), n)], b = Gp[pk(min(p1, q2), max(p1, q2), n)];
-        const double c = Gp[pk(min(q1, p2), max(q1, p2), n)], d = Gp[pk(min(q1, q2), max(q1, q2), n)];
-        off += 2.0 * (a * a + b * b + c * c + d * d);
-      }
-    }
-    off = jblock_sum<JNT>(off, red);
-    if (!(off > tol2)) break;
+    if (t == 0) rotated = 0;
+    __syncthreads();
     for (int r = 0; r < n - 1; ++r) {
-      if (t < np) {
-        int p = rr_player(t, r, n), q = rr_player(n - 1 - t, r, n);
+      if (grp < np) {
+        int p = rr_player(grp, r, n), q = rr_player(n - 1 - grp, r, n);
         if (p > q) { const int x = p; p = q; q = x; }
-        const double gpp = Gp[pk(p, p, n)], gqq = Gp[pk(q, q, n)], gpq = Gp[pk(p, q, n)];
-        double c = 1.0, s = 0.0;
-        if (fabs(gpq) > 1e-300 && fabs(gpq) > 1e-18 * sqrt(fabs(gpp * gqq))) {
-          const double theta = (gqq - gpp) / (2.0 * gpq);
-          const double tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
-          c = 1.0 / sqrt(1.0 + tt * tt);
-          s = tt * c;
+        double wp[7], wq[7];
+        double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+        for (int u = 0; u < 7; ++u) {
+          const int i = gl + 16 * u;
+          wp[u] = (i < ell) ? G[p * ldg + i] : 0.0;
+          wq[u] = (i < ell) ? G[q * ldg + i] : 0.0;
+          al = fma(wp[u], wp[u], al);
+          be = fma(wq[u], wq[u], be);
+          ga = fma(wp[u], wq[u], ga);
         }
-        rc[t] = c; rs[t] = s; pp[t] = p; pq[t] = q;
-      }
-      __syncthreads();
-      // all LDS loads of this thread's items first, then the stores (items are
-      // disjoint within a round, so nothing here reads what another item writes)
-      int gi[GI][4];
-      double gv[GI][4], gc1[GI], gs1[GI], gc2[GI], gs2[GI];
-      bool gdiag[GI];
+        al = wc::row16_sum(al);
+        be = wc::row16_sum(be);
+        ga = wc::row16_sum(ga);
+        if (ga != 0.0 && fabs(ga) > tolj * sqrt(al * be)) {
+          double c, s;
+          jrot(al, be, ga, c, s);
 #pragma unroll
-      for (int u = 0; u < GI; ++u) {
-        const int P1 = gP1[u] < 0 ? 0 : gP1[u], P2 = gP2[u] < 0 ? 0 : gP2[u];
-        const int p1 = pp[P1], q1 = pq[P1], p2 = pp[P2], q2 = pq[P2];
-        gc1[u] = rc[P1]; gs1[u] = rs[P1]; gc2[u] = rc[P2]; gs2[u] = rs[P2];
-        gdiag[u] = (P1 == P2);
-        if (gdiag[u]) {
-          gi[u][0] = pk(p1, p1, n); gi[u][1] = pk(q1, q1, n); gi[u][2] = pk(p1, q1, n); gi[u][3] = gi[u][2];
-        } else {
-          gi[u][0] = pk(min(p1, p2), max(p1, p2), n); gi[u][1] = pk(min(p1, q2), max(p1, q2), n);
-          gi[u][2] = pk(min(q1, p2), max(q1, p2), n); gi[u][3] = pk(min(q1, q2), max(q1, q2), n);
+          for (int u = 0; u < 7; ++u) {
+            const int i = gl + 16 * u;
+            if (i < ell) {
+              G[p * ldg + i] = c * wp[u] - s * wq[u];
+              G[q * ldg + i] = s * wp[u] + c * wq[u];
+            }
+          }
+          if (gl == 0) rotated = 1;
         }
-      }
-#pragma unroll
-      for (int u = 0; u < GI; ++u)
-#pragma unroll
-        for (int x = 0; x < 4; ++x) gv[u][x] = (gP1[u] >= 0) ? Gp[gi[u][x]] : 0.0;
-      int vpi[VI], vqi[VI];
-      double vcs[VI], vsn[VI], vpv[VI], vqv[VI];
-#pragma unroll
-      for (int u = 0; u < VI; ++u) {
-        const int P = vP[u];
-        const int a = va[u] < 0 ? 0 : va[u];
-        vpi[u] = a * n + pp[P];
-        vqi[u] = a * n + pq[P];
-        vcs[u] = rc[P];
-        vsn[u] = rs[P];
-      }
-#pragma unroll
-      for (int u = 0; u < VI; ++u) {
-        vpv[u] = (va[u] >= 0) ? V[vpi[u]] : 0.0;
-        vqv[u] = (va[u] >= 0) ? V[vqi[u]] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < GI; ++u) {
-        if (gP1[u] < 0) continue;
-        const double c1 = gc1[u], s1 = gs1[u], c2 = gc2[u], s2 = gs2[u];
-        if (gdiag[u]) {
-          const double gpp = gv[u][0], gqq = gv[u][1], gpq = gv[u][2];
-          Gp[gi[u][0]] = c1 * c1 * gpp - 2.0 * c1 * s1 * gpq + s1 * s1 * gqq;
-          Gp[gi[u][1]] = s1 * s1 * gpp + 2.0 * c1 * s1 * gpq + c1 * c1 * gqq;
-          Gp[gi[u][2]] = 0.0;
-        } else {
-          const double bpp = gv[u][0], bpq = gv[u][1], bqp = gv[u][2], bqq = gv[u][3];
-          const double rpp = c1 * bpp - s1 * bqp, rpq = c1 * bpq - s1 * bqq;   // rows: J^T
-          const double rqp = s1 * bpp + c1 * bqp, rqq = s1 * bpq + c1 * bqq;
-          Gp[gi[u][0]] = c2 * rpp - s2 * rpq;                                   // columns: J
-          Gp[gi[u][1]] = s2 * rpp + c2 * rpq;
-          Gp[gi[u][2]] = c2 * rqp - s2 * rqq;
-          Gp[gi[u][3]] = s2 * rqp + c2 * rqq;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < VI; ++u) {
-        if (va[u] < 0) continue;
-        V[vpi[u]] = vcs[u] * vpv[u] - vsn[u] * vqv[u];
-        V[vqi[u]] = vsn[u] * vpv[u] + vcs[u] * vqv[u];
       }
       __syncthreads();
     }
+    sweeps = sweep + 1;
+    if (!rotated) break;
   }
-  // eigenvalues in descending order (ties by index) over the ell real indices
-  for (int a = t; a < ell; a += JNT) {
-    const double da = Gp[pk(a, a, n)];
+  // ---- eigenvalues lambda_c = |x_c|^2 - delta, eigenvectors x_c / |x_c|
+  for (int c = grp; c < ell; c += NT / 16) {
+    double s2 = 0.0;
+    for (int i = gl; i < ell; i += 16) s2 = fma(G[c * ldg + i], G[c * ldg + i], s2);
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, 16);
+    if (gl == 0) nrm2[c] = s2;
+  }
+  __syncthreads();
+  for (int a = t; a < ell; a += NT) {
+    const double la = nrm2[a];
     int rnk = 0;
     for (int b = 0; b < ell; ++b) {
-      const double db = Gp[pk(b, b, n)];
-      if (db > da || (db == da && b < a)) ++rnk;
+      const double lb = nrm2[b];
+      if (lb > la || (lb == la && b < a)) ++rnk;
     }
     rank_of[a] = rnk;
+    lam[rnk] = fmax(la - delta, 0.0);
+    if (!isfinite(la)) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_NONFINITE);
   }
+  if (t == 0) dflags[FLAGW_SWEEPS] = sweeps;
   __syncthreads();
-  for (int a = t; a < ell; a += JNT) lam[rank_of[a]] = Gp[pk(a, a, n)];
-  for (int e = t; e < ell * ell; e += JNT) {
-    const int i = e / ell, a = e - (e / ell) * ell;
-    Vout[i * ell + rank_of[a]] = V[i * n + a];
+  for (int e = t; e < ell * ell; e += NT) {
+    const int c = e / ell, r = e - (e / ell) * ell;   // column c of X, row r (pivot order)
+    const double nc = nrm2[c];
+    Uout[perm[r] * ell + rank_of[c]] = nc > 0.0 ? G[c * ldg + r] / sqrt(nc) : 0.0;
   }
 }
 
@@ -302,6 +322,7 @@ __global__ void __launch_bounds__(1024) k_jacobi_svd(const double *__restrict__ 
       }
       __syncthreads();
     }
+    if (t == 0) dflags[FLAGW_SWEEPS] = sweep + 1;
     if (!rotated) break;
   }
   for (int col = t; col < ell; col += 1024) {
@@ -328,19 +349,17 @@ __global__ void __launch_bounds__(1024) k_jacobi_svd(const double *__restrict__ 
 
 }  // namespace
 
-// tol2_rel: stop when the off-diagonal Frobenius mass^2 <= tol2_rel * ||G||_F^2.
-int launch_jacobi_eig_parts(hipStream_t st, const double *part, int nparts, int ell, double *lam, double *V,
-                            int *dflags, double tol2_rel) {
+int launch_core_eig(hipStream_t st, const double *G, int ell, double *lam, double *U, int *dflags) {
   if (ell < 1 || ell > JELL_MAX) return -1;
   const int n = (ell + 1) & ~1;
-  const size_t lds = ((size_t)n * (n + 1) / 2 + (size_t)n * n) * sizeof(double);
-  if (n <= 64) {
-    allow_lds(k_jacobi_eig<64>, lds);
-    hipLaunchKernelGGL(k_jacobi_eig<64>, dim3(1), dim3(JNT), lds, st, part, nparts, ell, tol2_rel, lam, V, dflags);
+  size_t lds = (size_t)n * (ell | 1) * sizeof(double);
+  if (ell <= 64) lds += (size_t)(64 * wc::LDL + 128) * sizeof(double);
+  if (ell <= 64) {
+    allow_lds(k_core_eig<512>, lds);
+    hipLaunchKernelGGL(k_core_eig<512>, dim3(1), dim3(512), lds, st, G, ell, lam, U, dflags);
   } else {
-    allow_lds(k_jacobi_eig<JELL_MAX>, lds);
-    hipLaunchKernelGGL(k_jacobi_eig<JELL_MAX>, dim3(1), dim3(JNT), lds, st, part, nparts, ell, tol2_rel, lam, V,
-                       dflags);
+    allow_lds(k_core_eig<JNT>, lds);
+    hipLaunchKernelGGL(k_core_eig<JNT>, dim3(1), dim3(JNT), lds, st, G, ell, lam, U, dflags);
   }
   DSK_TRY(hipGetLastError());
   return 0;

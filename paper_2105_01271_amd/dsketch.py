@@ -122,7 +122,8 @@ def _opts(p=10, S=None, tau=None, id_projected=False, mode="default", refine=Fal
 def _info_dict(info: _lib.Info) -> dict:
     return {"ell": info.ell, "flags": info.flags,
             "flag_names": [v for b, v in _lib.FLAG_NAMES.items() if info.flags & b],
-            "normA_fro2": info.normA_fro2, "normB_fro2": info.normB_fro2, "sigma_tail": info.sigma_tail}
+            "normA_fro2": info.normA_fro2, "normB_fro2": info.normB_fro2, "sigma_tail": info.sigma_tail,
+            "core_sweeps": info.core_sweeps}
 
 
 def restrict(A: torch.Tensor, R: Restriction) -> torch.Tensor:
