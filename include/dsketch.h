@@ -175,6 +175,94 @@ int dsk_power_iter(dsk_handle *h, const void *Ac, int32_t dtype, int64_t m, int6
                    const void *Q0, int32_t ell, int32_t q, double tau, int32_t reorth, void *Qout);
 
 /*
+ * Batched execution (extension; not in the paper): independent sketch-SVD
+ * problems of different shapes, dtypes and restrictions in one call.
+ */
+typedef struct {
+  const void *A;       /* device m x n, row-major, lda */
+  int32_t dtype;       /* DSK_F64 / F32 / BF16 / F16 */
+  int64_t m, n, lda;
+  int32_t k, q;        /* rank and power steps, as in dsk_sketch_svd */
+  dsk_restriction R;   /* by value; its device arrays must stay valid for the call (and for graph replays) */
+  void *U;             /* device m x k, work dtype */
+  double *S;           /* device k */
+  void *V;             /* device n x k, work dtype */
+} dsk_problem;
+
+enum { DSK_BATCH_GRAPH = 1 };   /* capture the batch into a HIP graph on first use, replay afterwards */
+
+/*
+ * dsk_sketch_svd_batched -- dsk_sketch_svd (Alg. 2 + Alg. 7) for nprob problems.
+ * The problems run concurrently on up to 8 worker streams owned by the handle
+ * (longest-processing-time assignment on m*n), forked from and joined back
+ * into the handle's stream.  With DSK_BATCH_GRAPH the launch sequence of a
+ * given batch description (every field of every problem, the options, the
+ * stream) is captured into a HIP graph on its first call (which also runs it)
+ * and replayed with one graph launch on later calls; up to 16 graphs are kept.
+ * Results are identical to nprob separate dsk_sketch_svd calls.
+ * Arguments: h=1, nprob=2 (>= 1), probs=3 (host array), o=4 (host, may be NULL; shared),
+ *   flags=5 (0 or DSK_BATCH_GRAPH), nworkers=6 (host int, may be NULL: workers used).
+ * Errors: -1..-5 as numbered; -(1000 + i) when problem i fails the checks of
+ *   dsk_sketch_svd; DSK_ERR_* (HIP).  No per-problem dsk_info is produced.
+ */
+int dsk_sketch_svd_batched(dsk_handle *h, int32_t nprob, const dsk_problem *probs, const dsk_opts *o, int32_t flags,
+                           int32_t *nworkers);
+
+/*
+ * dsk_autotune -- time the K-split candidates of the projection B^T = A^T Q
+ * (the one full pass over A) for this (dtype, mode, m, n, ell) on A itself,
+ * and keep the fastest in a process-wide table that every later launch of that
+ * shape uses.  Synchronises the handle's stream.
+ * Arguments: h=1, A=2, dtype=3 (F32 / BF16 / F16), m=4, n=5, lda=6, ell=7 (1..112),
+ *   mode=8 (DSK_MODE_*), nsplit=9 (host int, may be NULL), ms=10 (host float, may be NULL:
+ *   time of one projection with the chosen split).
+ */
+int dsk_autotune(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t ell,
+                 int32_t mode, int32_t *nsplit, float *ms);
+
+/*
+ * Learned linear restriction (extension; not in the paper).  R->kind ==
+ * DSK_R_LEARNED: two 5x5 stride-2 zero-padded linear convolutions of every
+ * row viewed as an ny x nx image, 1 -> C channels -> 1, no bias, no
+ * activation (ny, nx multiples of 4, 1 <= C <= 32), so A_c = A D with s =
+ * (ny/4)(nx/4) and the D of Sec. 2 replaced by the conv.  Weights: device
+ * FP32, w1 [C][5][5] and w2 [C][5][5]; FP32 arithmetic.  dsk_restrict,
+ * dsk_sketch_svd and dsk_sketch_id accept it like any other restriction.
+ *
+ * dsk_conv_restrict_bwd -- weight gradients of <gAc, A_c(w)>:
+ *   gw1, gw2 (device FP32, C x 25 each) = d/dw1, d/dw2 of sum(gAc .* conv(A)).
+ * Arguments: h=1, A=2, dtype=3, m=4, n=5, lda=6, R=7 (learned), gAc=8 (device
+ *   m x s FP32 row-major), gw1=9, gw2=10.
+ */
+int dsk_conv_restrict_bwd(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                          const dsk_restriction *R, const float *gAc, float *gw1, float *gw2);
+
+/*
+ * dsk_learned_loss_grad -- training objective of the learned restriction: the
+ * sketch error of Thm 3.2 in the Frobenius norm, normalised,
+ *   L = ||A - Q Q^T A||_F^2 / ||A||_F^2,
+ * with Q the ell-wide orthonormal block of the SVD path built from A_c = conv(A)
+ * (nested direct-injection start block, q power steps with re-orthonormalisation,
+ * Alg. 7), and its weight gradients (every QR factor R held constant: L depends
+ * on Q only through its span).  Coarse algebra in FP64.
+ * Arguments: h=1, A=2, dtype=3, m=4, n=5, lda=6, R=7 (learned), ell=8 (1..min(s, m, 112)),
+ *   q=9 (0..8), loss=10 (host double), gw1=11, gw2=12 (device FP32, C x 25).
+ * Synchronises the handle's stream (the loss is returned on the host).
+ */
+int dsk_learned_loss_grad(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                          const dsk_restriction *R, int32_t ell, int32_t q, double *loss, float *gw1, float *gw2);
+
+/*
+ * dsk_adam_step -- one Adam update (Kingma and Ba) of count FP32 parameters on
+ * the device: m1 = b1 m1 + (1 - b1) g, m2 = b2 m2 + (1 - b2) g^2,
+ * p -= lr (m1 / (1 - b1^t)) / (sqrt(m2 / (1 - b2^t)) + eps).
+ * Arguments: h=1, param=2, grad=3, m1=4, m2=5 (device FP32), count=6, lr=7, beta1=8,
+ *   beta2=9, eps=10, step=11 (t >= 1).
+ */
+int dsk_adam_step(dsk_handle *h, float *param, const float *grad, float *m1, float *m2, int64_t count, float lr,
+                  float beta1, float beta2, float eps, int32_t step);
+
+/*
  * Event timing of the projection kernel B^T = A^T Q (the dominant pass), for
  * benchmarks.  While enabled, dsk_sketch_svd and dsk_project bracket that one
  * kernel with two hipEvents recorded on the handle's stream (up to 4096 launches).

@@ -19,8 +19,10 @@ LIB_PATH = os.path.join(HERE, "libdsketch.so")
 EXPORTED = (
     "dsk_opts_default", "dsk_create", "dsk_destroy", "dsk_set_stream", "dsk_restrict",
     "dsk_project", "dsk_sketch_svd", "dsk_sketch_id", "dsk_power_iter", "dsk_status_string",
-    "dsk_timing_enable", "dsk_timing_read",
+    "dsk_timing_enable", "dsk_timing_read", "dsk_conv_restrict_bwd", "dsk_learned_loss_grad",
+    "dsk_adam_step", "dsk_sketch_svd_batched", "dsk_autotune",
 )
+DSK_BATCH_GRAPH = 1
 
 DSK_F64, DSK_F32, DSK_BF16, DSK_F16 = 0, 1, 2, 3
 DSK_R_INDEX, DSK_R_NN, DSK_R_GLOBAL, DSK_R_LEARNED = 0, 1, 2, 3
@@ -38,6 +40,19 @@ class Restriction(ctypes.Structure):
         ("channels", ctypes.c_int32),
         ("w1", ctypes.c_void_p),
         ("w2", ctypes.c_void_p),
+    ]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("A", ctypes.c_void_p),
+        ("dtype", ctypes.c_int32),
+        ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("lda", ctypes.c_int64),
+        ("k", ctypes.c_int32), ("q", ctypes.c_int32),
+        ("R", Restriction),
+        ("U", ctypes.c_void_p),
+        ("S", ctypes.c_void_p),
+        ("V", ctypes.c_void_p),
     ]
 
 
@@ -96,9 +111,17 @@ def load():
         lib.dsk_status_string.restype = ctypes.c_char_p
         lib.dsk_timing_enable.argtypes = [vp, ctypes.c_int]
         lib.dsk_timing_read.argtypes = [vp, P(ctypes.c_int), P(ctypes.c_double)]
+        lib.dsk_conv_restrict_bwd.argtypes = [vp, vp, i32, i64, i64, i64, P(Restriction), vp, vp, vp]
+        lib.dsk_learned_loss_grad.argtypes = [vp, vp, i32, i64, i64, i64, P(Restriction), i32, i32, P(dbl),
+                                              vp, vp]
+        f32 = ctypes.c_float
+        lib.dsk_adam_step.argtypes = [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, i32]
+        lib.dsk_sketch_svd_batched.argtypes = [vp, i32, P(Problem), P(Opts), i32, P(i32)]
+        lib.dsk_autotune.argtypes = [vp, vp, i32, i64, i64, i64, i32, i32, P(i32), P(f32)]
         for name in ("dsk_create", "dsk_destroy", "dsk_set_stream", "dsk_restrict", "dsk_project",
                      "dsk_sketch_svd", "dsk_sketch_id", "dsk_power_iter", "dsk_timing_enable",
-                     "dsk_timing_read"):
+                     "dsk_timing_read", "dsk_conv_restrict_bwd", "dsk_learned_loss_grad", "dsk_adam_step",
+                     "dsk_sketch_svd_batched", "dsk_autotune"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
         return lib

@@ -76,8 +76,11 @@ int64_t coarse_size(const dsk_restriction *R, int64_t n) {
     case DSK_R_GLOBAL:
       if (R->ny < 1 || R->nx < 1 || (int64_t)R->ny * R->nx != n || R->sy < 1 || R->sx < 1) return -1;
       return (int64_t)((R->ny + R->sy - 1) / R->sy) * ((R->nx + R->sx - 1) / R->sx);
+    case DSK_R_LEARNED:
+      if (!conv_shape_ok(n, R->ny, R->nx, R->channels) || !R->w1 || !R->w2) return -1;
+      return (int64_t)(R->ny / 4) * (R->nx / 4);
     default:
-      return -1;   // learned restriction: dsk_conv_restrict_fwd
+      return -1;
   }
 }
 
@@ -114,6 +117,15 @@ int orth(dsk_handle *h, const void *Y, int f64, int64_t rows, int ell, void *Q, 
 }
 
 }  // namespace
+
+void allow_lds_raw(const void *kernel, size_t bytes) {
+  static std::mutex mu;
+  static std::unordered_map<const void *, size_t> granted;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t &g = granted[kernel];
+  if (bytes <= g) return;
+  if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess) g = bytes;
+}
 
 int arena_reserve(dsk_handle *h, size_t bytes) {
   if (bytes <= h->arena_bytes) return 0;
@@ -170,6 +182,7 @@ int dsk_destroy(dsk_handle *h) {
   if (!h) return -1;
   hipSetDevice(h->device);
   hipStreamSynchronize(h->stream);
+  destroy_workers(h);
   if (h->arena) (void)hipFree(h->arena);
   if (h->dflags) (void)hipFree(h->dflags);
   if (h->tev) {
@@ -269,10 +282,12 @@ int dsk_timing_read(dsk_handle *h, int *count, double *total_ms) {
   return 0;
 }
 
-int dsk_sketch_svd(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,
-                   const dsk_restriction *R, int32_t q, const dsk_opts *o, void *U, double *S, void *V,
-                   dsk_info *info) {
-  if (!h) return -1;
+}  // extern "C"
+
+// Argument checks of dsk_sketch_svd (codes are its argument numbers); fills the
+// effective options, the coarse size s and the range-finder width L.
+int svd_check(const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k, const dsk_restriction *R,
+              int32_t q, const dsk_opts *o, void *U, double *S, void *V, dsk_opts *odp, int64_t *s_out, int *L_out) {
   if (!A) return -2;
   if (!valid_dtype(dtype)) return -3;
   if (m < 1) return -4;
@@ -293,11 +308,20 @@ int dsk_sketch_svd(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64
   if (!U) return -11;
   if (!S) return -12;
   if (!V) return -13;
-  DSK_TRY(hipSetDevice(h->device));
+  *odp = od;
+  *s_out = s;
+  *L_out = (int)ell;
+  return 0;
+}
+
+// The sketch-SVD launch sequence on h's stream and arena.  With need != NULL
+// only the arena size is computed (nothing is allocated or enqueued).
+int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,
+            const dsk_restriction *R, int32_t q, const dsk_opts &od, int64_t s, int L, void *U, double *S, void *V,
+            dsk_info *info, size_t *need) {
   hipStream_t st = h->stream;
   const int f64 = dtype == DSK_F64;
   const size_t we = f64 ? 8 : 4;
-  const int L = (int)ell;
   const int64_t rmax = std::max<int64_t>(std::max<int64_t>(m, s), n);
   // ---- workspace
   Carve c{nullptr, 0, 0, true};
@@ -329,6 +353,10 @@ int dsk_sketch_svd(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64
     double *dinfo = c.take<double>(4);
     double *fpart = c.take<double>(1024);
     if (pass == 0) {
+      if (need) {
+        *need = c.off;
+        return 0;
+      }
       DSK_RET(arena_reserve(h, c.off));
       c.base = h->arena;
       c.cap = h->arena_bytes;
@@ -385,6 +413,20 @@ int dsk_sketch_svd(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64
     return read_info(h, dinfo, info, L);
   }
   return 0;
+}
+
+extern "C" {
+
+int dsk_sketch_svd(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,
+                   const dsk_restriction *R, int32_t q, const dsk_opts *o, void *U, double *S, void *V,
+                   dsk_info *info) {
+  if (!h) return -1;
+  dsk_opts od;
+  int64_t s = 0;
+  int L = 0;
+  DSK_RET(svd_check(A, dtype, m, n, lda, k, R, q, o, U, S, V, &od, &s, &L));
+  DSK_TRY(hipSetDevice(h->device));
+  return svd_run(h, A, dtype, m, n, lda, k, R, q, od, s, L, U, S, V, info, nullptr);
 }
 
 int dsk_sketch_id(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,

@@ -1,0 +1,243 @@
+// Batched execution of independent sketch-SVD problems (extension; not in the
+// paper) and the projection autotuner.
+//
+// A batch of ragged problems is spread over up to DSK_MAX_WORKERS worker
+// sub-handles, each with its own stream, arena and status words, balanced by
+// the longest-processing-time rule on m*n.  The handle's stream forks to the
+// workers through an event and joins them back, so the batch is ordered like
+// any single call on that stream.  With DSK_BATCH_GRAPH the whole fork/join
+// launch sequence is captured once into a HIP graph (after an eager run that
+// sizes every arena and sets every kernel attribute) and replayed by a single
+// hipGraphLaunch on later calls with the same batch description (pointers
+// included, since graph nodes keep their arguments).
+#include <algorithm>
+#include <numeric>
+
+#include "dsk_internal.h"
+
+namespace {
+
+constexpr int MAX_WORKERS = 8;
+constexpr size_t GRAPH_CACHE = 16;
+
+__global__ void k_zero_words(int *f) {
+  if (threadIdx.x < FLAGW_COUNT) f[threadIdx.x] = 0;
+}
+
+int make_worker(dsk_handle *h, dsk_handle **out) {
+  dsk_handle *w = new dsk_handle();
+  w->device = h->device;
+  w->cu_count = h->cu_count;
+  w->max_lds = h->max_lds;
+  if (hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete w;
+    return DSK_ERR_BASE + (int)hipErrorOutOfMemory;
+  }
+  if (hipMalloc(&w->dflags, 256) != hipSuccess) {
+    (void)hipStreamDestroy(w->stream);
+    delete w;
+    return DSK_ERR_BASE + (int)hipErrorOutOfMemory;
+  }
+  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, w->stream, w->dflags);
+  DSK_TRY(hipGetLastError());
+  *out = w;
+  return 0;
+}
+
+int ensure_workers(dsk_handle *h, int nw) {
+  while ((int)h->workers.size() < nw) {
+    dsk_handle *w = nullptr;
+    DSK_RET(make_worker(h, &w));
+    h->workers.push_back(w);
+  }
+  while ((int)h->wev.size() < 1 + nw) {
+    hipEvent_t e;
+    DSK_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    h->wev.push_back(e);
+  }
+  return 0;
+}
+
+uint64_t mix(uint64_t hsh, uint64_t v) {
+  hsh ^= v + 0x9e3779b97f4a7c15ull + (hsh << 6) + (hsh >> 2);
+  return hsh;
+}
+
+template <typename T>
+uint64_t mix_bytes(uint64_t hsh, const T &x) {
+  const unsigned char *p = reinterpret_cast<const unsigned char *>(&x);
+  for (size_t i = 0; i < sizeof(T); ++i) hsh = mix(hsh, p[i]);
+  return hsh;
+}
+
+struct Prepared {
+  dsk_opts od;
+  int64_t s;
+  int L;
+};
+
+// Enqueue the fork from `origin`, every worker's problems, and the join back
+// into `origin`.
+int run_all(dsk_handle *h, hipStream_t origin, int nw, const std::vector<std::vector<int>> &lists,
+            const dsk_problem *probs, const std::vector<Prepared> &prep) {
+  DSK_TRY(hipEventRecord(h->wev[0], origin));
+  for (int w = 0; w < nw; ++w) {
+    dsk_handle *wk = h->workers[w];
+    DSK_TRY(hipStreamWaitEvent(wk->stream, h->wev[0], 0));
+    for (int i : lists[w]) {
+      const dsk_problem &p = probs[i];
+      DSK_RET(svd_run(wk, p.A, p.dtype, p.m, p.n, p.lda, p.k, &p.R, p.q, prep[i].od, prep[i].s, prep[i].L, p.U, p.S,
+                      p.V, nullptr, nullptr));
+    }
+    DSK_TRY(hipEventRecord(h->wev[1 + w], wk->stream));
+    DSK_TRY(hipStreamWaitEvent(origin, h->wev[1 + w], 0));
+  }
+  return 0;
+}
+
+}  // namespace
+
+void destroy_workers(dsk_handle *h) {
+  for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+  h->graphs.clear();
+  h->graph_order.clear();
+  for (dsk_handle *w : h->workers) {
+    (void)hipStreamSynchronize(w->stream);
+    if (w->arena) (void)hipFree(w->arena);
+    if (w->dflags) (void)hipFree(w->dflags);
+    (void)hipStreamDestroy(w->stream);
+    delete w;
+  }
+  h->workers.clear();
+  for (hipEvent_t e : h->wev) (void)hipEventDestroy(e);
+  h->wev.clear();
+  if (h->capst) (void)hipStreamDestroy(h->capst);
+  h->capst = nullptr;
+}
+
+extern "C" {
+
+int dsk_sketch_svd_batched(dsk_handle *h, int32_t nprob, const dsk_problem *probs, const dsk_opts *o, int32_t flags,
+                           int32_t *nworkers) {
+  if (!h) return -1;
+  if (nprob < 1) return -2;
+  if (!probs) return -3;
+  if (flags & ~DSK_BATCH_GRAPH) return -5;
+  std::vector<Prepared> prep(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    const dsk_problem &p = probs[i];
+    const int r = svd_check(p.A, p.dtype, p.m, p.n, p.lda, p.k, &p.R, p.q, o, p.U, p.S, p.V, &prep[i].od, &prep[i].s,
+                            &prep[i].L);
+    if (r) return -1000 - i;
+  }
+  DSK_TRY(hipSetDevice(h->device));
+  const int nw = std::min<int>(nprob, MAX_WORKERS);
+  DSK_RET(ensure_workers(h, nw));
+  // longest processing time first: biggest m*n to the least loaded worker
+  std::vector<int> order(nprob);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return probs[a].m * probs[a].n > probs[b].m * probs[b].n;
+  });
+  std::vector<std::vector<int>> lists(nw);
+  std::vector<double> load(nw, 0.0);
+  for (int i : order) {
+    const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    lists[w].push_back(i);
+    load[w] += (double)probs[i].m * (double)probs[i].n;
+  }
+  // size every worker's arena before anything is enqueued (and before a capture)
+  for (int w = 0; w < nw; ++w) {
+    size_t need = 0;
+    for (int i : lists[w]) {
+      const dsk_problem &p = probs[i];
+      size_t sz = 0;
+      DSK_RET(svd_run(h->workers[w], p.A, p.dtype, p.m, p.n, p.lda, p.k, &p.R, p.q, prep[i].od, prep[i].s,
+                      prep[i].L, p.U, p.S, p.V, nullptr, &sz));
+      need = std::max(need, sz);
+    }
+    DSK_RET(arena_reserve(h->workers[w], need));
+  }
+  if (nworkers) *nworkers = nw;
+  if (!(flags & DSK_BATCH_GRAPH)) return run_all(h, h->stream, nw, lists, probs, prep);
+
+  uint64_t key = mix(0, (uint64_t)nprob);
+  for (int i = 0; i < nprob; ++i) {
+    key = mix_bytes(key, probs[i]);
+    key = mix_bytes(key, prep[i].od);
+  }
+  key = mix(key, (uint64_t)(uintptr_t)h->stream);
+  for (int w = 0; w < nw; ++w) key = mix(key, (uint64_t)(uintptr_t)h->workers[w]->arena);
+  auto it = h->graphs.find(key);
+  if (it != h->graphs.end()) {
+    DSK_TRY(hipGraphLaunch(it->second, h->stream));
+    return 0;
+  }
+  // first call with this description: eager run (results), then capture for
+  // replays on a stream of the handle's own (never the legacy NULL stream)
+  DSK_RET(run_all(h, h->stream, nw, lists, probs, prep));
+  if (!h->capst) DSK_TRY(hipStreamCreateWithFlags(&h->capst, hipStreamNonBlocking));
+  DSK_TRY(hipStreamBeginCapture(h->capst, hipStreamCaptureModeThreadLocal));
+  const int rc = run_all(h, h->capst, nw, lists, probs, prep);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(h->capst, &graph);
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (ec != hipSuccess) return DSK_ERR_BASE + (int)ec;
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) return DSK_ERR_BASE + (int)ei;
+  if (h->graph_order.size() >= GRAPH_CACHE) {
+    const uint64_t old = h->graph_order.front();
+    h->graph_order.erase(h->graph_order.begin());
+    auto o2 = h->graphs.find(old);
+    if (o2 != h->graphs.end()) {
+      (void)hipGraphExecDestroy(o2->second);
+      h->graphs.erase(o2);
+    }
+  }
+  h->graphs[key] = exec;
+  h->graph_order.push_back(key);
+  return 0;
+}
+
+int dsk_autotune(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t ell,
+                 int32_t mode, int32_t *nsplit, float *ms) {
+  if (!h) return -1;
+  if (!A) return -2;
+  if (dtype < DSK_F32 || dtype > DSK_F16) return -3;
+  if (m < 1) return -4;
+  if (n < 1) return -5;
+  if (lda < n) return -6;
+  if (ell < 1 || ell > 112) return -7;
+  if (mode < 0 || mode > DSK_MODE_SPLIT6) return -8;
+  DSK_TRY(hipSetDevice(h->device));
+  Carve c{nullptr, 0, 0, true};
+  for (int pass = 0; pass < 2; ++pass) {
+    c.off = 0;
+    float *Y = c.take<float>((size_t)m * ell);
+    float *out = c.take<float>((size_t)n * ell);
+    char *ws = c.take<char>(stream_ws_bytes(dtype, m, n, ell, mode));
+    if (pass == 0) {
+      DSK_RET(arena_reserve(h, c.off));
+      c.base = h->arena;
+      c.cap = h->arena_bytes;
+      c.dry = false;
+      continue;
+    }
+    // a fixed, finite right-hand side: only the timing matters
+    DSK_TRY(hipMemsetAsync(Y, 0, (size_t)m * ell * sizeof(float), h->stream));
+    int best = 1;
+    float bms = 0.f;
+    DSK_RET(stream_autotune(h->stream, A, dtype, m, n, lda, ell, mode, ws, Y, out, h->cu_count, &best, &bms));
+    if (nsplit) *nsplit = best;
+    if (ms) *ms = bms;
+    return 0;
+  }
+  return 0;
+}
+
+}  // extern "C"

@@ -5,6 +5,10 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
 #include "../../include/dsketch.h"
 
 #define DSK_ERR_BASE 100
@@ -36,6 +40,13 @@ struct dsk_handle {
   int timing;
   int tcount;
   hipEvent_t *tev;    // 2 * TIMING_CAP events
+  // batched execution: worker sub-handles (own stream, arena and status words),
+  // fork/join events, and the cache of instantiated graphs keyed by batch contents
+  std::vector<dsk_handle *> workers;
+  std::vector<hipEvent_t> wev;        // [0] fork, [1 + w] join of worker w
+  hipStream_t capst = nullptr;        // capture origin (the caller's stream may be the legacy NULL stream)
+  std::unordered_map<uint64_t, hipGraphExec_t> graphs;
+  std::vector<uint64_t> graph_order;
 };
 
 constexpr int TIMING_CAP = 4096;
@@ -66,14 +77,24 @@ struct Carve {
 };
 
 int arena_reserve(dsk_handle *h, size_t bytes);
+void destroy_workers(dsk_handle *h);   // batch.hip
 
-// Kernels whose dynamic LDS exceeds 64 KB must opt in (gfx950 offers 160 KB per workgroup).
+// Kernels whose dynamic LDS exceeds 64 KB must opt in (gfx950 offers 160 KB per
+// workgroup).  The largest size granted so far is remembered per kernel, so the
+// attribute call is made once per growth (never again while a stream is being
+// captured into a graph for sizes already granted).
+void allow_lds_raw(const void *kernel, size_t bytes);
 template <typename K>
 inline void allow_lds(K kernel, size_t bytes) {
-  if (bytes > 65536)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)bytes);
+  if (bytes > 65536) allow_lds_raw(reinterpret_cast<const void *>(kernel), bytes);
 }
+
+// api.hip: the sketch-SVD sequence, shared with the batched entry point
+int svd_check(const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k, const dsk_restriction *R,
+              int32_t q, const dsk_opts *o, void *U, double *S, void *V, dsk_opts *odp, int64_t *s_out, int *L_out);
+int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,
+            const dsk_restriction *R, int32_t q, const dsk_opts &od, int64_t s, int L, void *U, double *S, void *V,
+            dsk_info *info, size_t *need);
 
 // ---------------------------------------------------------------- launchers
 // restrict.hip
@@ -85,6 +106,15 @@ int launch_gather_rows(hipStream_t st, const void *A, int dtype, int64_t m, int6
                        const int64_t *rows, int k, void *out);
 int launch_convert(hipStream_t st, const void *src, int src_f64, void *dst, int dst_f64, int64_t count);
 int launch_transpose(hipStream_t st, const void *src, int f64, int64_t rows, int64_t cols, void *dst);
+
+// conv.hip (learned linear restriction)
+int conv_shape_ok(int64_t n, int ny, int nx, int C);
+int launch_conv_fwd(hipStream_t st, const void *A, int dtype, int64_t m, int64_t lda, int ny, int nx, int C,
+                    const float *w1, const float *w2, int out_f64, void *Ac, int64_t ldc);
+size_t conv_bwd_ws_bytes(int64_t m, int ny, int nx, int C);
+int launch_conv_bwd(hipStream_t st, const void *A, int dtype, int64_t m, int64_t lda, int ny, int nx, int C,
+                    const float *w1, const float *w2, const void *gAc, int g_f64, int64_t ldg, float *gw1,
+                    float *gw2, void *ws);
 
 // smallmat.hip (tall-skinny orthonormalisation, small factorizations)
 size_t cholqr2_ws_bytes(int64_t rows, int ell);
@@ -110,6 +140,11 @@ int launch_stream(hipStream_t st, const void *X, int dtype, int64_t K, int64_t N
                   int cu_count, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 int launch_stream_nn(hipStream_t st, const void *X, int dtype, int64_t M, int64_t K, int64_t ldx,
                      const void *Y, int ell, void *out, int64_t ldo, int mode, void *ws, int cu_count);
+// autotuner of the TN projection's K-split for one (dtype/mode, K, N, ell) shape:
+// times the candidates on X with scratch Y (K x ell f32) and out (N x ell f32),
+// records the fastest in the process-wide table the launchers consult.
+int stream_autotune(hipStream_t st, const void *X, int dtype, int64_t K, int64_t N, int64_t ldx, int ell, int mode,
+                    void *ws, void *Y, void *out, int cu_count, int *best_ns, float *best_ms);
 
 // cpqr.hip (row ID)
 int launch_cpqr(hipStream_t st, double *W, int64_t m, int64_t s, int k, double *nu0, double *nu1,
@@ -120,7 +155,7 @@ int launch_id_solve(hipStream_t st, const double *Rk, const int64_t *piv, const 
 // gemm64.hip (small FP64 GEMM for the full-sketch ID power block)
 int launch_gemm64(hipStream_t st, int transA, int transB, int64_t M, int64_t N, int64_t K,
                   double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
-                  double *C, int64_t ldc);
+                  double *C, int64_t ldc, double beta = 0.0);
 
 // device helpers
 __device__ __forceinline__ float bf16_bits_to_f32(unsigned short b) {

@@ -1,6 +1,7 @@
-// FP64 GEMM C = alpha op(A) op(B) for the full-sketch power block of the row
-// ID, W_q = (tau A_c A_c^T)^q A_c (C-PWR without re-orthonormalisation,
-// Alg. 7 applied to the coarse sketch itself).  64x64 output tiles, 16-deep K
+// FP64 GEMM C = alpha op(A) op(B) + beta C: the full-sketch power block of the
+// row ID, W_q = (tau A_c A_c^T)^q A_c (C-PWR without re-orthonormalisation,
+// Alg. 7 applied to the coarse sketch itself), and the coarse-sketch products
+// of the learned restriction's loss gradient.  64x64 output tiles, 16-deep K
 // tiles in LDS, 4x4 register blocking, f64 FMA on the vector units.
 #include "dsk_internal.h"
 
@@ -9,8 +10,8 @@ namespace {
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256) k_gemm64(int64_t M, int64_t N, int64_t K, double alpha,
                                                 const double *__restrict__ A, int64_t lda,
-                                                const double *__restrict__ B, int64_t ldb, double *__restrict__ C,
-                                                int64_t ldc) {
+                                                const double *__restrict__ B, int64_t ldb, double beta,
+                                                double *__restrict__ C, int64_t ldc) {
   constexpr int BM = 64, BN = 64, BK = 16;
   __shared__ double As[BK][BM + 1];
   __shared__ double Bs[BK][BN + 1];
@@ -56,7 +57,7 @@ __global__ void __launch_bounds__(256) k_gemm64(int64_t M, int64_t N, int64_t K,
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t j = n0 + tx + 16 * v;
-      if (j < N) C[i * ldc + j] = alpha * acc[u][v];
+      if (j < N) C[i * ldc + j] = alpha * acc[u][v] + (beta != 0.0 ? beta * C[i * ldc + j] : 0.0);
     }
   }
 }
@@ -64,16 +65,16 @@ __global__ void __launch_bounds__(256) k_gemm64(int64_t M, int64_t N, int64_t K,
 }  // namespace
 
 int launch_gemm64(hipStream_t st, int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha,
-                  const double *A, int64_t lda, const double *B, int64_t ldb, double *C, int64_t ldc) {
+                  const double *A, int64_t lda, const double *B, int64_t ldb, double *C, int64_t ldc, double beta) {
   dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64));
   if (!transA && !transB)
-    hipLaunchKernelGGL((k_gemm64<false, false>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, C, ldc);
+    hipLaunchKernelGGL((k_gemm64<false, false>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
   else if (!transA && transB)
-    hipLaunchKernelGGL((k_gemm64<false, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, C, ldc);
+    hipLaunchKernelGGL((k_gemm64<false, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
   else if (transA && !transB)
-    hipLaunchKernelGGL((k_gemm64<true, false>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, C, ldc);
+    hipLaunchKernelGGL((k_gemm64<true, false>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
   else
-    hipLaunchKernelGGL((k_gemm64<true, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, C, ldc);
+    hipLaunchKernelGGL((k_gemm64<true, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
   DSK_TRY(hipGetLastError());
   return 0;
 }

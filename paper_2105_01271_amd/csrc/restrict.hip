@@ -219,6 +219,10 @@ __global__ void k_sum_parts(const double *__restrict__ part, int nparts, double 
 
 int launch_restrict(hipStream_t st, const void *A, int dtype, int64_t m, int64_t n, int64_t lda,
                     const dsk_restriction *R, int64_t s, int work_f64, void *Ac, void *AcT, int *dflags) {
+  if (R->kind == DSK_R_LEARNED) {
+    if (AcT) return -1;
+    return launch_conv_fwd(st, A, dtype, m, lda, R->ny, R->nx, R->channels, R->w1, R->w2, work_f64, Ac, s);
+  }
   Grid2 g{};
   if (R->kind == DSK_R_NN || R->kind == DSK_R_GLOBAL) {
     g.ny = R->ny; g.nx = R->nx; g.sy = R->sy; g.sx = R->sx;

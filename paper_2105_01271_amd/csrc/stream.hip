@@ -29,6 +29,9 @@
 // FP64 path: VALU kernel with LDS tiles (f64 FMA), same TN/NN forms.
 #include <algorithm>
 
+#include <map>
+#include <tuple>
+
 #include "dsk_internal.h"
 
 namespace {
@@ -411,6 +414,22 @@ __global__ void k_split_reduce(const T *__restrict__ part, int nsplit, int64_t N
 }
 
 // ---------------------------------------------------------------- dispatch helpers
+// Process-wide table of autotuned K-splits of the MFMA stream kernels, keyed by
+// (mode, NN, K, N, ell); filled by stream_autotune, read by every launch.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int64_t, int64_t, int>, int> g_tune;
+
+int tuned_ns(int md, bool nn, int64_t K, int64_t N, int ell) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tune.find(std::make_tuple(md, (int)nn, K, N, ell));
+  return it == g_tune.end() ? 0 : it->second;
+}
+
+void set_tuned_ns(int md, bool nn, int64_t K, int64_t N, int ell, int ns) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune[std::make_tuple(md, (int)nn, K, N, ell)] = ns;
+}
+
 struct Plan {
   int nsplit;
   int kb_per_split;
@@ -534,6 +553,12 @@ int stream_any(hipStream_t st, bool nn, const void *X, int dtype, int64_t K, int
   }
   DSK_TRY(hipGetLastError());
   Plan p = plan_split(K, N, 16 * jt, 32, cu_count, 4);
+  if (const int tn = tuned_ns(md, nn, K, N, ell); tn > 0) {
+    // an autotuned split, within the partial buffers stream_ws_bytes provides (nkb / 4)
+    const int64_t ns = std::max<int64_t>(1, std::min<int64_t>(tn, std::max<int64_t>(1, nkb / 4)));
+    p.kb_per_split = (int)((nkb + ns - 1) / ns);
+    p.nsplit = (int)((nkb + p.kb_per_split - 1) / p.kb_per_split);
+  }
   float *dst = reinterpret_cast<float *>(out);
   int64_t ldd = ldo;
   if (p.nsplit > 1) { dst = reinterpret_cast<float *>(w + yp_bytes); ldd = ell; }
@@ -599,4 +624,40 @@ int launch_stream(hipStream_t st, const void *X, int dtype, int64_t K, int64_t N
 int launch_stream_nn(hipStream_t st, const void *X, int dtype, int64_t M, int64_t K, int64_t ldx, const void *Y,
                      int ell, void *out, int64_t ldo, int mode, void *ws, int cu_count) {
   return stream_any(st, true, X, dtype, K, M, ldx, Y, ell, out, ldo, mode, ws, cu_count, nullptr, nullptr);
+}
+
+int stream_autotune(hipStream_t st, const void *X, int dtype, int64_t K, int64_t N, int64_t ldx, int ell, int mode,
+                    void *ws, void *Y, void *out, int cu_count, int *best_ns, float *best_ms) {
+  if (dtype == DSK_F64 || ell < 1 || ell > 128) return -1;
+  const int md = mode_of(dtype, mode);
+  const int64_t nkb = (K + 31) / 32;
+  const int64_t cap = std::max<int64_t>(1, nkb / 4);
+  hipEvent_t e0, e1;
+  DSK_TRY(hipEventCreate(&e0));
+  DSK_TRY(hipEventCreate(&e1));
+  int best = 1;
+  float bms = 1e30f;
+  int rc = 0;
+  for (int ns : {1, 2, 3, 4, 6, 8, 12, 16}) {
+    if (ns > cap) break;
+    set_tuned_ns(md, false, K, N, ell, ns);
+    rc = stream_any(st, false, X, dtype, K, N, ldx, Y, ell, out, ell, mode, ws, cu_count, nullptr, nullptr);
+    if (rc) break;
+    if ((rc = (int)hipEventRecord(e0, st)) != 0) { rc += DSK_ERR_BASE; break; }
+    for (int r = 0; r < 3 && !rc; ++r)
+      rc = stream_any(st, false, X, dtype, K, N, ldx, Y, ell, out, ell, mode, ws, cu_count, nullptr, nullptr);
+    if (rc) break;
+    if ((rc = (int)hipEventRecord(e1, st)) != 0) { rc += DSK_ERR_BASE; break; }
+    if ((rc = (int)hipEventSynchronize(e1)) != 0) { rc += DSK_ERR_BASE; break; }
+    float ms = 0.f;
+    if ((rc = (int)hipEventElapsedTime(&ms, e0, e1)) != 0) { rc += DSK_ERR_BASE; break; }
+    ms /= 3.f;
+    if (ms < bms) { bms = ms; best = ns; }
+  }
+  set_tuned_ns(md, false, K, N, ell, best);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (best_ns) *best_ns = best;
+  if (best_ms) *best_ms = bms;
+  return rc;
 }

@@ -59,7 +59,8 @@ def _check_matrix(A: torch.Tensor):
 class Restriction:
     """Host description of the sketch D of A_c = A D (paper Sec. 2).
 
-    kind: "index" (direct injection / Gram sub-sample), "nn", "global".
+    kind: "index" (direct injection / Gram sub-sample), "nn", "global",
+    "learned" (two 5x5 stride-2 linear conv layers, w1 and w2 of shape (C, 5, 5)).
     """
     kind: str
     index: torch.Tensor | None = None      # device int64 (s,)
@@ -67,6 +68,8 @@ class Restriction:
     nx: int = 0
     sy: int = 1
     sx: int = 1
+    w1: torch.Tensor | None = None         # learned: device float32 (C, 5, 5)
+    w2: torch.Tensor | None = None         # learned: device float32 (C, 5, 5)
 
     @staticmethod
     def di_grid(ny: int, nx: int, sy: int, sx: int, device="cuda") -> "Restriction":
@@ -89,18 +92,34 @@ class Restriction:
     def global_(ny, nx, sy, sx) -> "Restriction":
         return Restriction("global", None, ny, nx, sy, sx)
 
+    @staticmethod
+    def learned(ny, nx, w1: torch.Tensor, w2: torch.Tensor) -> "Restriction":
+        """Learned linear conv restriction (ny/4 x nx/4 coarse values per row)."""
+        w1 = w1.detach().to(torch.float32).contiguous()
+        w2 = w2.detach().to(torch.float32).contiguous()
+        if w1.shape != w2.shape or w1.dim() != 3 or tuple(w1.shape[1:]) != (5, 5) or not w1.is_cuda:
+            raise ValueError("w1, w2 must be device tensors of shape (C, 5, 5)")
+        return Restriction("learned", None, ny, nx, 4, 4, w1, w2)
+
     def coarse_size(self) -> int:
         if self.kind == "index":
             return int(self.index.numel())
+        if self.kind == "learned":
+            return (self.ny // 4) * (self.nx // 4)
         return (-(-self.ny // self.sy)) * (-(-self.nx // self.sx))
 
     def to_c(self) -> _lib.Restriction:
         r = _lib.Restriction()
-        r.kind = {"index": _lib.DSK_R_INDEX, "nn": _lib.DSK_R_NN, "global": _lib.DSK_R_GLOBAL}[self.kind]
+        r.kind = {"index": _lib.DSK_R_INDEX, "nn": _lib.DSK_R_NN, "global": _lib.DSK_R_GLOBAL,
+                  "learned": _lib.DSK_R_LEARNED}[self.kind]
         if self.kind == "index":
             r.s = int(self.index.numel())
             r.index = self.index.data_ptr()
         r.ny, r.nx, r.sy, r.sx = self.ny, self.nx, self.sy, self.sx
+        if self.kind == "learned":
+            r.channels = int(self.w1.shape[0])
+            r.w1 = self.w1.data_ptr()
+            r.w2 = self.w2.data_ptr()
         return r
 
 
@@ -226,3 +245,131 @@ def power_iter(Ac: torch.Tensor, Q0: torch.Tensor, q: int, tau: float = 1.0, reo
                             float(tau), int(bool(reorth)), _ptr(Qout))
     _lib.check("dsk_power_iter", st)
     return Qout
+
+
+def conv_restrict_bwd(A: torch.Tensor, R: Restriction, gAc: torch.Tensor):
+    """Weight gradients (gw1, gw2) of sum(gAc * restrict(A, R)) for a learned R (dsk_conv_restrict_bwd)."""
+    _check_matrix(A)
+    lib = _lib.load()
+    m, n = A.shape
+    gAc = gAc.contiguous()
+    if gAc.dtype != torch.float32 or tuple(gAc.shape) != (m, R.coarse_size()):
+        raise ValueError("gAc must be float32 of shape (m, s)")
+    gw1 = torch.empty_like(R.w1)
+    gw2 = torch.empty_like(R.w2)
+    rc = R.to_c()
+    _lib.check("dsk_conv_restrict_bwd", lib.dsk_conv_restrict_bwd(
+        _handle(A.device), _ptr(A), _DT[A.dtype], m, n, A.stride(0), ctypes.byref(rc), _ptr(gAc), _ptr(gw1),
+        _ptr(gw2)))
+    return gw1, gw2
+
+
+def learned_loss_grad(A: torch.Tensor, R: Restriction, ell: int, q: int = 0):
+    """Projection loss ||A - Q Q^T A||_F^2 / ||A||_F^2 of the learned sketch and its weight
+    gradients (dsk_learned_loss_grad).  Returns (loss: float, gw1, gw2)."""
+    _check_matrix(A)
+    lib = _lib.load()
+    m, n = A.shape
+    gw1 = torch.empty_like(R.w1)
+    gw2 = torch.empty_like(R.w2)
+    loss = ctypes.c_double()
+    rc = R.to_c()
+    _lib.check("dsk_learned_loss_grad", lib.dsk_learned_loss_grad(
+        _handle(A.device), _ptr(A), _DT[A.dtype], m, n, A.stride(0), ctypes.byref(rc), int(ell), int(q),
+        ctypes.byref(loss), _ptr(gw1), _ptr(gw2)))
+    return loss.value, gw1, gw2
+
+
+def adam_step(param: torch.Tensor, grad: torch.Tensor, m1: torch.Tensor, m2: torch.Tensor, step: int,
+              lr: float = 1e-2, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    """One in-place Adam update of a float32 device tensor (dsk_adam_step)."""
+    lib = _lib.load()
+    for t in (param, grad, m1, m2):
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != param.numel():
+            raise ValueError("adam_step needs contiguous float32 tensors of equal size")
+    _lib.check("dsk_adam_step", lib.dsk_adam_step(_handle(param.device), _ptr(param), _ptr(grad), _ptr(m1), _ptr(m2),
+                                                  param.numel(), float(lr), float(beta1), float(beta2), float(eps),
+                                                  int(step)))
+
+
+def sketch_svd_batched(problems, p: int = 10, mode="default", graph: bool = False):
+    """dsk_sketch_svd for a list of (A, k, R, q) problems in one call (dsk_sketch_svd_batched):
+    concurrent worker streams, optionally captured into a HIP graph and replayed on later calls
+    with the same tensors.  Returns [(U, S, V), ...]."""
+    lib = _lib.load()
+    if not problems:
+        return []
+    dev = problems[0][0].device
+    arr = (_lib.Problem * len(problems))()
+    outs = []
+    keep = []
+    for i, (A, k, R, q) in enumerate(problems):
+        _check_matrix(A)
+        m, n = A.shape
+        wd = _work_dtype(A.dtype)
+        U = torch.empty((m, k), dtype=wd, device=dev)
+        Sv = torch.empty((k,), dtype=torch.float64, device=dev)
+        V = torch.empty((n, k), dtype=wd, device=dev)
+        pr = arr[i]
+        pr.A, pr.dtype, pr.m, pr.n, pr.lda = _ptr(A), _DT[A.dtype], m, n, A.stride(0)
+        pr.k, pr.q = int(k), int(q)
+        pr.R = R.to_c()
+        pr.U, pr.S, pr.V = _ptr(U), _ptr(Sv), _ptr(V)
+        outs.append((U, Sv, V))
+        keep.append(R)
+    o = _opts(p=p, mode=mode)
+    nw = ctypes.c_int32()
+    st = lib.dsk_sketch_svd_batched(_handle(dev), len(problems), arr, ctypes.byref(o),
+                                    _lib.DSK_BATCH_GRAPH if graph else 0, ctypes.byref(nw))
+    _lib.check("dsk_sketch_svd_batched", st)
+    return outs
+
+
+class BatchedSVD:
+    """A fixed batch whose outputs are allocated once, so that repeated calls replay
+    one captured HIP graph (dsk_sketch_svd_batched with DSK_BATCH_GRAPH)."""
+
+    def __init__(self, problems, p: int = 10, mode="default"):
+        self._lib = _lib.load()
+        self.dev = problems[0][0].device
+        self.arr = (_lib.Problem * len(problems))()
+        self.outs = []
+        self._keep = []
+        for i, (A, k, R, q) in enumerate(problems):
+            _check_matrix(A)
+            m, n = A.shape
+            wd = _work_dtype(A.dtype)
+            U = torch.empty((m, k), dtype=wd, device=self.dev)
+            Sv = torch.empty((k,), dtype=torch.float64, device=self.dev)
+            V = torch.empty((n, k), dtype=wd, device=self.dev)
+            pr = self.arr[i]
+            pr.A, pr.dtype, pr.m, pr.n, pr.lda = _ptr(A), _DT[A.dtype], m, n, A.stride(0)
+            pr.k, pr.q = int(k), int(q)
+            pr.R = R.to_c()
+            pr.U, pr.S, pr.V = _ptr(U), _ptr(Sv), _ptr(V)
+            self.outs.append((U, Sv, V))
+            self._keep.append((A, R))
+        self.opts = _opts(p=p, mode=mode)
+        self.nworkers = 0
+
+    def __call__(self, graph: bool = True):
+        nw = ctypes.c_int32()
+        st = self._lib.dsk_sketch_svd_batched(_handle(self.dev), len(self.outs), self.arr, ctypes.byref(self.opts),
+                                              _lib.DSK_BATCH_GRAPH if graph else 0, ctypes.byref(nw))
+        _lib.check("dsk_sketch_svd_batched", st)
+        self.nworkers = nw.value
+        return self.outs
+
+
+def autotune(A: torch.Tensor, ell: int, mode="default"):
+    """Tune the K-split of the projection B^T = A^T Q for A's shape (dsk_autotune).
+    Returns (nsplit, milliseconds per projection)."""
+    _check_matrix(A)
+    lib = _lib.load()
+    m, n = A.shape
+    ns = ctypes.c_int32()
+    ms = ctypes.c_float()
+    _lib.check("dsk_autotune", lib.dsk_autotune(_handle(A.device), _ptr(A), _DT[A.dtype], m, n, A.stride(0), int(ell),
+                                                _MODES[mode] if isinstance(mode, str) else int(mode),
+                                                ctypes.byref(ns), ctypes.byref(ms)))
+    return ns.value, ms.value

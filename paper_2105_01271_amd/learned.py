@@ -1,0 +1,54 @@
+"""Training loop of the learned linear restriction (extension; not in the paper).
+
+The restriction is two 5x5 stride-2 linear convolutions (1 -> C -> 1 channels)
+that map an ny x nx snapshot to ny/4 x nx/4 coarse values, A_c = A D with D
+the conv (Sec. 2 with a learned D).  It is trained to shrink the sketch error
+that Thm 3.2 bounds, L = ||A - Q Q^T A||_F^2 / ||A||_F^2, with Q the ell-wide
+block of the SVD path (start block + q coarse power steps, Alg. 7).  Every
+step runs in the library: the loss and its weight gradients
+(dsk_learned_loss_grad) and the Adam update (dsk_adam_step); this module only
+draws minibatches and loops.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import dsketch
+
+
+def direct_injection_weights(C: int, noise: float = 0.0, seed: int = 0, device="cuda"):
+    """Weights whose conv equals direct injection on the (4, 4) sub-grid:
+    centre taps of channel 0 set to one (plus optional seeded noise elsewhere)."""
+    rng = np.random.default_rng(seed)
+    w1 = noise * rng.standard_normal((C, 5, 5))
+    w2 = noise * rng.standard_normal((C, 5, 5))
+    w1[0, 2, 2] = 1.0
+    w2[0, 2, 2] = 1.0
+    return (torch.from_numpy(w1).to(torch.float32).to(device), torch.from_numpy(w2).to(torch.float32).to(device))
+
+
+def train(A: torch.Tensor, ny: int, nx: int, C: int = 16, ell: int = 60, q: int = 0, steps: int = 100,
+          batch: int = 500, lr: float = 2e-3, seed: int = 0, w1=None, w2=None, log=None):
+    """Adam on the projection loss over random row minibatches of A (rows = snapshots).
+    Returns (w1, w2, history of minibatch losses)."""
+    if w1 is None or w2 is None:
+        w1, w2 = direct_injection_weights(C, noise=1e-3, seed=seed, device=A.device)
+    w1 = w1.clone().contiguous()
+    w2 = w2.clone().contiguous()
+    m1a, m2a = torch.zeros_like(w1), torch.zeros_like(w1)
+    m1b, m2b = torch.zeros_like(w2), torch.zeros_like(w2)
+    rng = np.random.default_rng(seed)
+    hist = []
+    m = A.shape[0]
+    for t in range(1, steps + 1):
+        rows = np.sort(rng.choice(m, size=min(batch, m), replace=False))
+        Ab = A[torch.from_numpy(rows).to(A.device)].contiguous()
+        R = dsketch.Restriction.learned(ny, nx, w1, w2)
+        loss, g1, g2 = dsketch.learned_loss_grad(Ab, R, ell, q)
+        dsketch.adam_step(w1, g1, m1a, m2a, t, lr=lr)
+        dsketch.adam_step(w2, g2, m1b, m2b, t, lr=lr)
+        hist.append(loss)
+        if log is not None:
+            log(t, loss)
+    return w1, w2, hist

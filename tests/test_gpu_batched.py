@@ -1,0 +1,112 @@
+"""Batched ragged sketch SVDs (extension): concurrent worker streams, HIP graph
+capture and replay, and the projection autotuner.
+
+* every instance of a batch equals the same instance run alone (bitwise: the
+  per-instance launch sequence and its reductions are deterministic), and a
+  few instances are checked against the FP64 oracle at the FP32 tolerance;
+* graph replays, separated by the program's own eager work that clears the
+  outputs, reproduce the eager results bitwise on every replay;
+* an autotuned K-split leaves the projection within its tolerance.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import restrict as ores
+from oracle import sketch as osk
+from paper_2105_01271_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+
+
+def dsk():
+    from paper_2105_01271_amd import dsketch
+    return dsketch
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _batch(count, mmax=400, grids=(32, 64), seed=2000):
+    """Ragged instances with the recipe of the batched workload, scaled down:
+    m ~ U[100, mmax], grid from `grids`, k ~ U[10, 40], factor 2 or 4, heat or
+    advection-diffusion family."""
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng(seed + i)
+        m = int(rng.integers(100, mmax + 1))
+        N = int(rng.choice(grids))
+        k = int(rng.integers(10, 41))
+        f = int(rng.choice([2, 4]))
+        if rng.random() < 0.5:
+            A = synth.heat_exact(m, N, N, seed + i, rate=0.05, r=min(m, 120))
+        else:
+            A = synth.advdiff_exact(m, N, seed + i, r=min(m, 200), noise=1e-3)
+        dtype = torch.float64 if i % 5 == 0 else torch.float32
+        q = int(rng.integers(0, 3))
+        out.append((torch.from_numpy(A).to(dtype).cuda(), k, N, f, q))
+    return out
+
+
+def _problems(batch):
+    return [(A, k, dsk().Restriction.di_grid(N, N, f, f), q) for A, k, N, f, q in batch]
+
+
+def test_batched_equals_single_calls_and_oracle():
+    say("batched vs single")
+    batch = _batch(12)
+    probs = _problems(batch)
+    outs = dsk().sketch_svd_batched(probs)
+    torch.cuda.synchronize()
+    for i, ((A, k, R, q), (U, S, V)) in enumerate(zip(probs, outs)):
+        U1, S1, V1 = dsk().sketch_svd(A, k, R, q=q)
+        assert torch.equal(U, U1) and torch.equal(S, S1) and torch.equal(V, V1), i
+    for i in (0, 3, 7):
+        A, k, N, f, q = batch[i]
+        U, S, V = outs[i]
+        Ao = A.double().cpu().numpy()
+        Uo, So, Vo = osk.tpc_svd(Ao, k, {"kind": "index", "index": ores.di_index_2d(N, N, f, f)}, q=q)
+        err = np.abs(S.cpu().numpy() - So).max() / So[0]
+        say("  instance", i, tuple(A.shape), A.dtype, "sigma err", err)
+        assert err <= (1e-10 if A.dtype == torch.float64 else TOL32)
+
+
+def test_graph_replays_match_eager_results():
+    say("graph replay")
+    batch = _batch(9, seed=3000)
+    probs = _problems(batch)
+    eager = [tuple(t.clone() for t in o) for o in dsk().sketch_svd_batched(probs)]
+    runner = dsk().BatchedSVD(probs)
+    first = runner(graph=True)          # eager run + capture
+    torch.cuda.synchronize()
+    for o, e in zip(first, eager):
+        assert all(torch.equal(a, b) for a, b in zip(o, e))
+    for rep in range(3):
+        for U, S, V in runner.outs:     # the program's own eager work between replays
+            U.zero_()
+            S.zero_()
+            V.zero_()
+        torch.cuda.synchronize()
+        outs = runner(graph=True)       # graph replay
+        torch.cuda.synchronize()
+        for i, (o, e) in enumerate(zip(outs, eager)):
+            assert all(torch.equal(a, b) for a, b in zip(o, e)), (rep, i)
+    say("  workers", runner.nworkers)
+
+
+def test_autotuned_split_keeps_projection_accuracy():
+    say("autotune")
+    rng = np.random.default_rng(4)
+    m, n, ell = 1000, 16384, 60
+    A = torch.from_numpy(rng.standard_normal((m, n))).float().cuda()
+    ns, ms = dsk().autotune(A, ell)
+    say("  chosen split", ns, "ms", ms)
+    assert ns >= 1 and ms > 0
+    Q = torch.from_numpy(rng.standard_normal((m, ell))).float().cuda()
+    Bt = dsk().project(A, Q)
+    ref = A.double().cpu().numpy().T @ Q.double().cpu().numpy()
+    scale = np.sqrt((A.double().cpu().numpy() ** 2).sum(0)).max() * np.sqrt((Q.double().cpu().numpy() ** 2).sum(0)).max()
+    assert np.abs(Bt.double().cpu().numpy() - ref).max() <= 1e-6 * scale
