@@ -4,7 +4,8 @@
 
 One step = one rank-k sketch SVD (TPC-SVD with q = 1 coarse power step,
 Alg. 2 + Alg. 7) plus one rank-k row ID (TPC-ID, Alg. 4, q = 0, with the
-skeleton rows) of the same snapshot matrix, inputs resident in HBM.
+skeleton rows) of the same snapshot matrix, inputs resident in HBM, issued as
+one dsk_sketch_svd_id call (the ID overlaps the SVD on a second stream).
 Workload: 1000 time steps x 256x256 grid (n = 65536), FP32, advection-diffusion
 Fourier modes with sigma_j = j^-0.5 plus 1e-3 relative Gaussian noise, direct
 injection every 4th grid point per axis (s = 4096), k = 50, l = 60.
@@ -135,9 +136,8 @@ def main():
     ell = min(k + 10, s, m)
 
     def step():
-        U, S, V = dsketch.sketch_svd(A, k, R, q=q, mode=a.mode)
-        I, P, rows = dsketch.sketch_id(A, k, R, q=0, skeleton_rows=True)
-        return U, S, V, I, P, rows
+        # one call: the row ID runs on a worker stream concurrently with the SVD
+        return dsketch.sketch_svd_id(A, k, R, q_svd=q, q_id=0, skeleton_rows=True, mode=a.mode)
 
     for _ in range(a.warmup):
         step()

@@ -209,6 +209,20 @@ int dsk_sketch_svd_batched(dsk_handle *h, int32_t nprob, const dsk_problem *prob
                            int32_t *nworkers);
 
 /*
+ * dsk_sketch_svd_id -- dsk_sketch_svd (TPC-SVD + C-PWR, Alg. 2 and Alg. 7) and
+ * dsk_sketch_id (TPC-ID, Alg. 4) of the same matrix in one call: the row ID runs
+ * on a worker stream of the handle, concurrently with the SVD on the handle's
+ * stream, and joins back before the call's work ends on the handle's stream.
+ * Outputs are identical to the two separate calls.
+ * Arguments: h=1, A=2, dtype=3, m=4, n=5, lda=6, k=7, R=8, q_svd=9, q_id=10, o=11 (host, may be NULL),
+ *   U=12, S=13, V=14 (as in dsk_sketch_svd), skel=15, P=16, skel_rows=17 (as in dsk_sketch_id),
+ *   info_svd=18, info_id=19 (host, may be NULL).
+ */
+int dsk_sketch_svd_id(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,
+                      const dsk_restriction *R, int32_t q_svd, int32_t q_id, const dsk_opts *o, void *U, double *S,
+                      void *V, int64_t *skel, double *P, void *skel_rows, dsk_info *info_svd, dsk_info *info_id);
+
+/*
  * dsk_autotune -- time the K-split candidates of the projection B^T = A^T Q
  * (the one full pass over A) for this (dtype, mode, m, n, ell) on A itself,
  * and keep the fastest in a process-wide table that every later launch of that

@@ -20,7 +20,7 @@ EXPORTED = (
     "dsk_opts_default", "dsk_create", "dsk_destroy", "dsk_set_stream", "dsk_restrict",
     "dsk_project", "dsk_sketch_svd", "dsk_sketch_id", "dsk_power_iter", "dsk_status_string",
     "dsk_timing_enable", "dsk_timing_read", "dsk_conv_restrict_bwd", "dsk_learned_loss_grad",
-    "dsk_adam_step", "dsk_sketch_svd_batched", "dsk_autotune",
+    "dsk_adam_step", "dsk_sketch_svd_batched", "dsk_autotune", "dsk_sketch_svd_id",
 )
 DSK_BATCH_GRAPH = 1
 
@@ -118,10 +118,12 @@ def load():
         lib.dsk_adam_step.argtypes = [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, i32]
         lib.dsk_sketch_svd_batched.argtypes = [vp, i32, P(Problem), P(Opts), i32, P(i32)]
         lib.dsk_autotune.argtypes = [vp, vp, i32, i64, i64, i64, i32, i32, P(i32), P(f32)]
+        lib.dsk_sketch_svd_id.argtypes = [vp, vp, i32, i64, i64, i64, i32, P(Restriction), i32, i32, P(Opts),
+                                          vp, vp, vp, vp, vp, vp, P(Info), P(Info)]
         for name in ("dsk_create", "dsk_destroy", "dsk_set_stream", "dsk_restrict", "dsk_project",
                      "dsk_sketch_svd", "dsk_sketch_id", "dsk_power_iter", "dsk_timing_enable",
                      "dsk_timing_read", "dsk_conv_restrict_bwd", "dsk_learned_loss_grad", "dsk_adam_step",
-                     "dsk_sketch_svd_batched", "dsk_autotune"):
+                     "dsk_sketch_svd_batched", "dsk_autotune", "dsk_sketch_svd_id"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
         return lib

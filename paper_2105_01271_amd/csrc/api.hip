@@ -107,13 +107,16 @@ int read_info(dsk_handle *h, const double *dinfo, dsk_info *info, int ell) {
 }
 
 // Orthonormalise a rows x ell block in place-ish: Q = orth(Y).  f64 uses
-// Householder (tmp: rows*ell f64 scratch, R: ell^2), f32 uses CholeskyQR2.
-int orth(dsk_handle *h, const void *Y, int f64, int64_t rows, int ell, void *Q, void *tmp, void *cws, double *R) {
+// Householder (tmp: rows*ell f64 scratch, R: ell^2), f32 uses CholeskyQR2, or
+// a single CholeskyQR pass when span_only (a basis of span(Y) whose
+// orthogonality only needs to keep the next product well conditioned).
+int orth(dsk_handle *h, const void *Y, int f64, int64_t rows, int ell, void *Q, void *tmp, void *cws, double *R,
+         bool span_only = false) {
   if (f64) {
     DSK_RET(launch_convert(h->stream, Y, 1, tmp, 1, rows * ell));
     return launch_hhqr(h->stream, (double *)tmp, rows, ell, (double *)Q, R, h->dflags);
   }
-  return launch_cholqr2(h->stream, Y, 0, rows, ell, Q, cws, h->dflags, R);
+  return launch_cholqr2(h->stream, Y, 0, rows, ell, Q, cws, h->dflags, R, span_only ? 1 : 2);
 }
 
 }  // namespace
@@ -126,6 +129,8 @@ void allow_lds_raw(const void *kernel, size_t bytes) {
   if (bytes <= g) return;
   if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess) g = bytes;
 }
+
+int read_info_words(dsk_handle *h, dsk_info *info, int ell) { return read_info(h, nullptr, info, ell); }
 
 int arena_reserve(dsk_handle *h, size_t bytes) {
   if (bytes <= h->arena_bytes) return 0;
@@ -318,7 +323,7 @@ int svd_check(const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, i
 // only the arena size is computed (nothing is allocated or enqueued).
 int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,
             const dsk_restriction *R, int32_t q, const dsk_opts &od, int64_t s, int L, void *U, double *S, void *V,
-            dsk_info *info, size_t *need) {
+            dsk_info *info, size_t *need, const std::function<int()> *after_projection) {
   hipStream_t st = h->stream;
   const int f64 = dtype == DSK_F64;
   const size_t we = f64 ? 8 : 4;
@@ -369,13 +374,15 @@ int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, i
     DSK_RET(launch_restrict(st, A, dtype, m, n, lda, R, s, f64, Ac, nullptr, h->dflags));
     if (od.S) DSK_RET(launch_stream_nn(st, Ac, wdt, m, s, s, od.S, L, Y, L, od.mode, sws, h->cu_count));
     else DSK_RET(launch_select_cols(st, Ac, f64, m, s, s, L, Y));
-    DSK_RET(orth(h, Y, f64, m, L, Q, tmp, cws, Rsm));
+    // intermediate bases of the power iteration only carry a span (one
+    // CholeskyQR pass); the block that B is projected on is orthonormalised fully
+    DSK_RET(orth(h, Y, f64, m, L, Q, tmp, cws, Rsm, q > 0));
     for (int it = 0; it < q; ++it) {
       // Z = A_c^T Q (s x ell), orthonormalised; Q = orth(A_c Z).  tau cancels under re-orthonormalisation.
       DSK_RET(launch_stream(st, Ac, wdt, m, s, s, Q, f64, L, Z, L, od.mode, sws, h->cu_count));
-      DSK_RET(orth(h, Z, f64, s, L, Z, tmp, cws, Rsm));
+      DSK_RET(orth(h, Z, f64, s, L, Z, tmp, cws, Rsm, true));
       DSK_RET(launch_stream_nn(st, Ac, wdt, m, s, s, Z, L, Y, L, od.mode, sws, h->cu_count));
-      DSK_RET(orth(h, Y, f64, m, L, Q, tmp, cws, Rsm));
+      DSK_RET(orth(h, Y, f64, m, L, Q, tmp, cws, Rsm, it + 1 < q));
     }
     // B^T = A^T Q: the single full pass over A
     hipEvent_t e0, e1;
@@ -387,6 +394,7 @@ int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, i
       DSK_RET(launch_convert(st, Y, 0, Q, 0, m * L));
       DSK_RET(launch_stream(st, A, dtype, m, n, lda, Q, f64, L, Bt, L, od.mode, sws, h->cu_count));
     }
+    if (after_projection) DSK_RET((*after_projection)());
     if (!f64) {
       DSK_RET(launch_gram(st, Bt, 0, n, L, GB, part, nparts));
       DSK_RET(launch_core_eig(st, GB, L, lam, UB, h->dflags));
@@ -429,10 +437,12 @@ int dsk_sketch_svd(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64
   return svd_run(h, A, dtype, m, n, lda, k, R, q, od, s, L, U, S, V, info, nullptr);
 }
 
-int dsk_sketch_id(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,
-                  const dsk_restriction *R, int32_t q, const dsk_opts *o, int64_t *skel, double *P, void *skel_rows,
-                  dsk_info *info) {
-  if (!h) return -1;
+}  // extern "C"
+
+// Argument checks of dsk_sketch_id (codes are its argument numbers).
+int id_check(const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k, const dsk_restriction *R,
+             int32_t q, const dsk_opts *o, int64_t *skel, double *P, dsk_opts *odp, int64_t *s_out, int64_t *cols_out,
+             int64_t *ell_out) {
   if (!A) return -2;
   if (!valid_dtype(dtype)) return -3;
   if (m < 1) return -4;
@@ -456,7 +466,17 @@ int dsk_sketch_id(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_
   if (q < 0 || q > 64) return -9;
   if (!skel) return -11;
   if (!P) return -12;
-  DSK_TRY(hipSetDevice(h->device));
+  *odp = od;
+  *s_out = s;
+  *cols_out = cols;
+  *ell_out = ell;
+  return 0;
+}
+
+// The row-ID launch sequence on h's stream and arena (need != NULL: size only).
+int id_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,
+           const dsk_restriction *R, int32_t q, const dsk_opts &od, int64_t s, int64_t cols, int64_t ell,
+           int64_t *skel, double *P, void *skel_rows, dsk_info *info, size_t *need) {
   hipStream_t st = h->stream;
   const double tau = od.tau > 0.0 ? od.tau : (double)n / (double)s;
   Carve c{nullptr, 0, 0, true};
@@ -473,6 +493,10 @@ int dsk_sketch_id(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_
     double *nu1 = c.take<double>(m);
     double *Rk = c.take<double>((size_t)k * m);
     if (pass == 0) {
+      if (need) {
+        *need = c.off;
+        return 0;
+      }
       DSK_RET(arena_reserve(h, c.off));
       c.base = h->arena;
       c.cap = h->arena_bytes;
@@ -516,6 +540,19 @@ int dsk_sketch_id(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_
     return read_info(h, nullptr, info, (int)(od.id_projected ? ell : 0));
   }
   return 0;
+}
+
+extern "C" {
+
+int dsk_sketch_id(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,
+                  const dsk_restriction *R, int32_t q, const dsk_opts *o, int64_t *skel, double *P, void *skel_rows,
+                  dsk_info *info) {
+  if (!h) return -1;
+  dsk_opts od;
+  int64_t s = 0, cols = 0, ell = 0;
+  DSK_RET(id_check(A, dtype, m, n, lda, k, R, q, o, skel, P, &od, &s, &cols, &ell));
+  DSK_TRY(hipSetDevice(h->device));
+  return id_run(h, A, dtype, m, n, lda, k, R, q, od, s, cols, ell, skel, P, skel_rows, info, nullptr);
 }
 
 int dsk_power_iter(dsk_handle *h, const void *Ac, int32_t dtype, int64_t m, int64_t s, int64_t ldc, const void *Q0,

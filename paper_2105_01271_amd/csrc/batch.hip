@@ -1,5 +1,5 @@
 // Batched execution of independent sketch-SVD problems (extension; not in the
-// paper) and the projection autotuner.
+// paper), the combined SVD + row ID call, and the projection autotuner.
 //
 // A batch of ragged problems is spread over up to DSK_MAX_WORKERS worker
 // sub-handles, each with its own stream, arena and status words, balanced by
@@ -201,6 +201,49 @@ int dsk_sketch_svd_batched(dsk_handle *h, int32_t nprob, const dsk_problem *prob
   }
   h->graphs[key] = exec;
   h->graph_order.push_back(key);
+  return 0;
+}
+
+int dsk_sketch_svd_id(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,
+                      const dsk_restriction *R, int32_t q_svd, int32_t q_id, const dsk_opts *o, void *U, double *S,
+                      void *V, int64_t *skel, double *P, void *skel_rows, dsk_info *info_svd, dsk_info *info_id) {
+  if (!h) return -1;
+  dsk_opts osv, oid;
+  int64_t s = 0, cols = 0, ell_id = 0;
+  int L = 0;
+  int r = svd_check(A, dtype, m, n, lda, k, R, q_svd, o, U, S, V, &osv, &s, &L);
+  if (r) {
+    // dsk_sketch_svd numbering -> this entry point's numbering
+    static const int map[14] = {0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -11, -12, -13, -14};
+    return (r <= -1 && r >= -13) ? map[-r] : r;
+  }
+  r = id_check(A, dtype, m, n, lda, k, R, q_id, o, skel, P, &oid, &s, &cols, &ell_id);
+  if (r) {
+    if (r == -9) return -10;
+    if (r == -10) return -11;
+    if (r == -11) return -15;
+    if (r == -12) return -16;
+    return r;
+  }
+  DSK_TRY(hipSetDevice(h->device));
+  DSK_RET(ensure_workers(h, 1));
+  dsk_handle *wk = h->workers[0];
+  size_t need = 0;
+  DSK_RET(id_run(wk, A, dtype, m, n, lda, k, R, q_id, oid, s, cols, ell_id, skel, P, skel_rows, nullptr, &need));
+  DSK_RET(arena_reserve(wk, need));
+  // fork once the SVD's pass over A is enqueued: the row ID (worker stream) then
+  // runs beside the SVD's latency-bound small factorizations, not beside the
+  // bandwidth-bound projection
+  const std::function<int()> fork = [&]() -> int {
+    DSK_TRY(hipEventRecord(h->wev[0], h->stream));
+    DSK_TRY(hipStreamWaitEvent(wk->stream, h->wev[0], 0));
+    DSK_RET(id_run(wk, A, dtype, m, n, lda, k, R, q_id, oid, s, cols, ell_id, skel, P, skel_rows, nullptr, nullptr));
+    DSK_TRY(hipEventRecord(h->wev[1], wk->stream));
+    return 0;
+  };
+  DSK_RET(svd_run(h, A, dtype, m, n, lda, k, R, q_svd, osv, s, L, U, S, V, info_svd, nullptr, &fork));
+  DSK_TRY(hipStreamWaitEvent(h->stream, h->wev[1], 0));
+  if (info_id) DSK_RET(read_info_words(wk, info_id, (int)(oid.id_projected ? ell_id : 0)));
   return 0;
 }
 

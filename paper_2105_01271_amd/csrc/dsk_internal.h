@@ -5,6 +5,7 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <functional>
 #include <mutex>
 #include <unordered_map>
 #include <vector>
@@ -92,9 +93,18 @@ inline void allow_lds(K kernel, size_t bytes) {
 // api.hip: the sketch-SVD sequence, shared with the batched entry point
 int svd_check(const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k, const dsk_restriction *R,
               int32_t q, const dsk_opts *o, void *U, double *S, void *V, dsk_opts *odp, int64_t *s_out, int *L_out);
+// after_projection (may be null) is called once B^T = A^T Q has been enqueued
+// (work forked from the handle's stream at that point starts after it).
 int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,
             const dsk_restriction *R, int32_t q, const dsk_opts &od, int64_t s, int L, void *U, double *S, void *V,
-            dsk_info *info, size_t *need);
+            dsk_info *info, size_t *need, const std::function<int()> *after_projection = nullptr);
+int id_check(const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k, const dsk_restriction *R,
+             int32_t q, const dsk_opts *o, int64_t *skel, double *P, dsk_opts *odp, int64_t *s_out, int64_t *cols_out,
+             int64_t *ell_out);
+int id_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,
+           const dsk_restriction *R, int32_t q, const dsk_opts &od, int64_t s, int64_t cols, int64_t ell,
+           int64_t *skel, double *P, void *skel_rows, dsk_info *info, size_t *need);
+int read_info_words(dsk_handle *h, dsk_info *info, int ell);
 
 // ---------------------------------------------------------------- launchers
 // restrict.hip
@@ -118,8 +128,11 @@ int launch_conv_bwd(hipStream_t st, const void *A, int dtype, int64_t m, int64_t
 
 // smallmat.hip (tall-skinny orthonormalisation, small factorizations)
 size_t cholqr2_ws_bytes(int64_t rows, int ell);
+// passes = 2: CholeskyQR2 (orthonormal to working precision); passes = 1: one
+// CholeskyQR pass, an orthonormal-up-to-kappa^2 u basis of span(Y) (enough
+// where only the span is used, as in the intermediate power steps).
 int launch_cholqr2(hipStream_t st, const void *Y, int f64, int64_t rows, int ell, void *Q,
-                   void *ws, int *dflags, double *Rout);
+                   void *ws, int *dflags, double *Rout, int passes = 2);
 int launch_hhqr(hipStream_t st, double *X, int64_t rows, int ell, double *Q, double *R, int *dflags);
 int launch_gram(hipStream_t st, const void *X, int f64, int64_t rows, int ell, double *G,
                 double *part, int nparts);

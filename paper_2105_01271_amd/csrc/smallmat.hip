@@ -387,12 +387,15 @@ __device__ __forceinline__ void factor_small(int ell, int64_t rows, double *__re
   double tr = 0.0;
   for (int i = 0; i < ell; ++i) tr += G[i * ell + i];
   const bool trok = (tr > 0.0) && isfinite(tr);
-  bool ok = trok && wc::chol64(G, ell, ell, 0.0, 1e-15 * tr, Lb, dinv, col);
-  if (!ok) {
-    if (lane == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_FALLBACK);
-    const double shift = 11.0 * ((double)rows * ell + (double)ell * (ell + 1)) * U64 * tr;
-    ok = trok && wc::chol64(G, ell, ell, shift, 1e-15 * tr, Lb, dinv, col);
+  bool ok = false;
+  // one copy of the unrolled factorization: the retry reuses it with the shift
+#pragma nounroll
+  for (int attempt = 0; attempt < 2 && trok && !ok; ++attempt) {
+    const double shift = attempt ? 11.0 * ((double)rows * ell + (double)ell * (ell + 1)) * U64 * tr : 0.0;
+    ok = wc::chol64(G, ell, ell, shift, 1e-15 * tr, Lb, dinv, col);
+    if (!ok && attempt == 0 && lane == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_FALLBACK);
   }
+  if (!ok && !trok && lane == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_FALLBACK);
   if (!ok) {
     // still failing (non-finite input): identity factor keeps the pipeline finite
     if (lane == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_RANK_DEFICIENT | DSK_FLAG_NONFINITE);
@@ -851,7 +854,7 @@ void launch_apply(hipStream_t st, int nparts, size_t lds, const T *Y, int64_t ro
 // ell <= 64 applies R^{-1} = L^{-T} by row solves; wider blocks multiply by an
 // explicit inverse.
 template <typename T>
-int cholqr2_typed(hipStream_t st, const T *Y, int64_t rows, int ell, T *Q, void *ws, int *dflags) {
+int cholqr2_typed(hipStream_t st, const T *Y, int64_t rows, int ell, T *Q, void *ws, int *dflags, int passes) {
   // ws layout: part (nparts*ell*ell f64) | R (ell^2) | Rinv (ell^2) | Q1 (rows*ell T)
   const int nparts = gram_parts(rows);
   const int64_t rpb = ((rows + nparts - 1) / nparts + GCH - 1) / GCH * GCH;
@@ -884,9 +887,19 @@ int cholqr2_typed(hipStream_t st, const T *Y, int64_t rows, int ell, T *Q, void 
                            rpb, prt, dflags, cond, ctr, gcond);
       }
     };
+    if (passes == 1) {
+      solve(Y, Q, nullptr, 0, nullptr, 0);   // span only: one pass
+      DSK_TRY(hipGetLastError());
+      return 0;
+    }
     solve(Y, Q1, part, 0, counter, 0);
     solve(Q1, Q, part, 0, counter, 1);     // third factorization only after a shifted first pass
     solve(Q, Q, nullptr, 1, nullptr, 0);   // third application only after a shifted first pass
+    DSK_TRY(hipGetLastError());
+    return 0;
+  }
+  if (passes == 1) {
+    launch_apply<T, 128>(st, nparts, apply_lds, Y, rows, ell, Rinv, Q, rpb, nullptr, dflags, 0, nullptr, R, 0);
     DSK_TRY(hipGetLastError());
     return 0;
   }
@@ -906,11 +919,11 @@ size_t cholqr2_ws_bytes(int64_t rows, int ell) {
 }
 
 int launch_cholqr2(hipStream_t st, const void *Y, int f64, int64_t rows, int ell, void *Q, void *ws, int *dflags,
-                   double *Rout) {
+                   double *Rout, int passes) {
   (void)Rout;
-  if (ell < 1 || ell > ELL_MAX) return -1;
-  if (f64) return cholqr2_typed<double>(st, (const double *)Y, rows, ell, (double *)Q, ws, dflags);
-  return cholqr2_typed<float>(st, (const float *)Y, rows, ell, (float *)Q, ws, dflags);
+  if (ell < 1 || ell > ELL_MAX || passes < 1 || passes > 2) return -1;
+  if (f64) return cholqr2_typed<double>(st, (const double *)Y, rows, ell, (double *)Q, ws, dflags, passes);
+  return cholqr2_typed<float>(st, (const float *)Y, rows, ell, (float *)Q, ws, dflags, passes);
 }
 
 int launch_hhqr(hipStream_t st, double *X, int64_t rows, int ell, double *Q, double *R, int *dflags) {

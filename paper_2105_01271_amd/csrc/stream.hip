@@ -197,8 +197,25 @@ __global__ void __launch_bounds__(256) k_stream_mfma(const void *__restrict__ Xv
     for (int jt = 0; jt < JT; ++jt) acc[ct][jt] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   constexpr int NV = nv_of<MODE>();
+  constexpr bool XF32 = MODE == MODE_SPLIT3 || MODE == MODE_F32 || MODE == MODE_SPLIT6;
+  // software pipeline: the X fragment of the next k-block this wave handles is
+  // loaded into registers before the current one is consumed
+  float xn32[XF32 ? JT : 1][8];
+  unsigned short xn16[XF32 ? 1 : JT][8];
+  auto fetch = [&](int kb) {
+    const int64_t kb0 = (int64_t)kb * 32 + 8 * g;
+    if constexpr (XF32) {
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt)
+        load_x_f32<NN>(reinterpret_cast<const float *>(Xv), K, N, ldx, kb0, j0 + 16 * jt + col, xn32[jt]);
+    } else {
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt)
+        load_x_u16<NN>(reinterpret_cast<const unsigned short *>(Xv), K, N, ldx, kb0, j0 + 16 * jt + col, xn16[jt]);
+    }
+  };
+  if (kb_begin + wave < kb_end) fetch(kb_begin + wave);
   for (int kb = kb_begin + wave; kb < kb_end; kb += 4) {
-    const int64_t kbase = (int64_t)kb * 32 + 8 * g;
     uint4 ya[NCT], yb[NCT], yc[NCT];
 #pragma unroll
     for (int ct = 0; ct < NCT; ++ct) {
@@ -207,11 +224,13 @@ __global__ void __launch_bounds__(256) k_stream_mfma(const void *__restrict__ Xv
       yb[ct] = src[64];
       if constexpr (NV == 3) yc[ct] = src[128];
     }
-    if constexpr (MODE == MODE_SPLIT3 || MODE == MODE_F32 || MODE == MODE_SPLIT6) {
-      const float *X = reinterpret_cast<const float *>(Xv);
+    if constexpr (XF32) {
       float xv[JT][8];
 #pragma unroll
-      for (int jt = 0; jt < JT; ++jt) load_x_f32<NN>(X, K, N, ldx, kbase, j0 + 16 * jt + col, xv[jt]);
+      for (int jt = 0; jt < JT; ++jt)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xv[jt][e] = xn32[jt][e];
+      if (kb + 4 < kb_end) fetch(kb + 4);
       if constexpr (MODE == MODE_SPLIT6) {
 #pragma unroll
         for (int jt = 0; jt < JT; ++jt) {
@@ -270,11 +289,15 @@ __global__ void __launch_bounds__(256) k_stream_mfma(const void *__restrict__ Xv
         }
       }
     } else {
-      const unsigned short *X = reinterpret_cast<const unsigned short *>(Xv);
+      unsigned short xc[JT][8];
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xc[jt][e] = xn16[jt][e];
+      if (kb + 4 < kb_end) fetch(kb + 4);
 #pragma unroll
       for (int jt = 0; jt < JT; ++jt) {
-        unsigned short xs[8];
-        load_x_u16<NN>(X, K, N, ldx, kbase, j0 + 16 * jt + col, xs);
+        const unsigned short *xs = xc[jt];
         const uint4 xp = make_uint4((unsigned)xs[0] | ((unsigned)xs[1] << 16), (unsigned)xs[2] | ((unsigned)xs[3] << 16),
                                     (unsigned)xs[4] | ((unsigned)xs[5] << 16), (unsigned)xs[6] | ((unsigned)xs[7] << 16));
 #pragma unroll

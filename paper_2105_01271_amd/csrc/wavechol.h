@@ -63,11 +63,11 @@ __device__ __forceinline__ double row16_sum(double v) {
 
 // Step J of the right-looking register Cholesky: lane i keeps row i of the
 // working matrix in g (compile-time J keeps every register index static); the
-// pivot column travels through LDS (col, 64 doubles).  On success g[c] holds
-// L(i, c) for c <= i; dinv[J] = 1 / L(J, J).
+// pivot column L(:, J) is broadcast lane by lane with v_readlane (no memory
+// round trip on the dependent chain).  On success g[c] holds L(i, c) for
+// c <= i; dinv[J] = 1 / L(J, J).  Rows and columns past ell hold the identity.
 template <int J>
-__device__ __forceinline__ void chol_step(double (&g)[64], int ell, int lane, double thr, bool &ok, double *col,
-                                          double *dinv) {
+__device__ __forceinline__ void chol_step(double (&g)[64], int ell, int lane, double thr, bool &ok, double *dinv) {
   if constexpr (J < 64) {
     if (J < ell && ok) {
       const double d = readlane_f64(g[J], J);
@@ -81,12 +81,12 @@ __device__ __forceinline__ void chol_step(double (&g)[64], int ell, int lane, do
       const double l = lane > J ? g[J] * inv : (lane == J ? piv : 0.0);
       g[J] = l;
       if (lane == 0) dinv[J] = inv;
-      col[lane] = l;
-      wave_lds_sync();
+      double lc[64 - J];
 #pragma unroll
-      for (int c = J + 1; c < 64; ++c) g[c] = fma(-l, col[c], g[c]);
-      wave_lds_sync();
-      chol_step<J + 1>(g, ell, lane, thr, ok, col, dinv);
+      for (int c = J + 1; c < 64; ++c) lc[c - J] = readlane_f64(l, c);
+#pragma unroll
+      for (int c = J + 1; c < 64; ++c) g[c] = fma(-l, lc[c - J], g[c]);
+      chol_step<J + 1>(g, ell, lane, thr, ok, dinv);
     }
   }
 }
@@ -95,7 +95,7 @@ __device__ __forceinline__ void chol_step(double (&g)[64], int ell, int lane, do
 // A: LDS or global, row-major with leading dimension lda.  On success L is
 // written to Lout (LDS, 64 x LDL, row i = L(i, :), zero above the diagonal and
 // identity past ell) and dinv[j] = 1 / L(j, j); returns false at a pivot
-// <= thr (or non-finite).  col: 64-double LDS scratch.
+// <= thr (or non-finite).  col: unused (kept for the LDS layout of callers).
 __device__ __forceinline__ bool chol64(const double *A, int lda, int ell, double shift, double thr, double *Lout,
                                        double *dinv, double *col) {
   const int lane = threadIdx.x & 63;
@@ -104,7 +104,8 @@ __device__ __forceinline__ bool chol64(const double *A, int lda, int ell, double
   for (int c = 0; c < 64; ++c)
     g[c] = (lane < ell && c < ell) ? A[lane * lda + c] + (c == lane ? shift : 0.0) : (c == lane ? 1.0 : 0.0);
   bool ok = true;
-  chol_step<0>(g, ell, lane, thr, ok, col, dinv);
+  (void)col;
+  chol_step<0>(g, ell, lane, thr, ok, dinv);
   if (!ok) return false;
 #pragma unroll
   for (int c = 0; c < 64; ++c) Lout[lane * LDL + c] = c <= lane ? g[c] : 0.0;

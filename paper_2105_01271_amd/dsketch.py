@@ -373,3 +373,29 @@ def autotune(A: torch.Tensor, ell: int, mode="default"):
                                                 _MODES[mode] if isinstance(mode, str) else int(mode),
                                                 ctypes.byref(ns), ctypes.byref(ms)))
     return ns.value, ms.value
+
+
+def sketch_svd_id(A: torch.Tensor, k: int, R: Restriction, q_svd: int = 1, q_id: int = 0, p: int = 10,
+                  skeleton_rows: bool = False, mode="default"):
+    """Sketch SVD and row ID of the same matrix in one call (dsk_sketch_svd_id): the ID runs on a
+    worker stream concurrently with the SVD.  Returns (U, S, V, I, P[, A(I,:)])."""
+    _check_matrix(A)
+    lib = _lib.load()
+    m, n = A.shape
+    wd = _work_dtype(A.dtype)
+    U = torch.empty((m, k), dtype=wd, device=A.device)
+    Sv = torch.empty((k,), dtype=torch.float64, device=A.device)
+    V = torch.empty((n, k), dtype=wd, device=A.device)
+    I = torch.empty((k,), dtype=torch.int64, device=A.device)
+    P = torch.empty((m, k), dtype=torch.float64, device=A.device)
+    rows = torch.empty((k, n), dtype=A.dtype, device=A.device) if skeleton_rows else None
+    o = _opts(p=p, mode=mode)
+    rc = R.to_c()
+    st = lib.dsk_sketch_svd_id(_handle(A.device), _ptr(A), _DT[A.dtype], m, n, A.stride(0), int(k), ctypes.byref(rc),
+                               int(q_svd), int(q_id), ctypes.byref(o), _ptr(U), _ptr(Sv), _ptr(V), _ptr(I), _ptr(P),
+                               _ptr(rows), None, None)
+    _lib.check("dsk_sketch_svd_id", st)
+    out = [U, Sv, V, I, P]
+    if skeleton_rows:
+        out.append(rows)
+    return tuple(out)

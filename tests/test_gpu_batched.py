@@ -110,3 +110,15 @@ def test_autotuned_split_keeps_projection_accuracy():
     ref = A.double().cpu().numpy().T @ Q.double().cpu().numpy()
     scale = np.sqrt((A.double().cpu().numpy() ** 2).sum(0)).max() * np.sqrt((Q.double().cpu().numpy() ** 2).sum(0)).max()
     assert np.abs(Bt.double().cpu().numpy() - ref).max() <= 1e-6 * scale
+
+
+def test_combined_svd_id_equals_separate_calls():
+    say("svd + id in one call")
+    A = torch.from_numpy(synth.advdiff_exact(300, 32, seed=12, r=300)).float().cuda()
+    R = dsk().Restriction.di_grid(32, 32, 2, 2)
+    U, S, V, I, P, rows = dsk().sketch_svd_id(A, 20, R, q_svd=1, q_id=0, skeleton_rows=True)
+    U1, S1, V1 = dsk().sketch_svd(A, 20, R, q=1)
+    I1, P1, rows1 = dsk().sketch_id(A, 20, R, q=0, skeleton_rows=True)
+    torch.cuda.synchronize()
+    for a, b in ((U, U1), (S, S1), (V, V1), (I, I1), (P, P1), (rows, rows1)):
+        assert torch.equal(a, b)
