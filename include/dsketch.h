@@ -67,7 +67,9 @@ enum {
   DSK_FLAG_FALLBACK = 1,        /* a shifted Cholesky-QR fallback was taken */
   DSK_FLAG_RANK_DEFICIENT = 2,  /* a triangular factor had a negligible pivot */
   DSK_FLAG_NONFINITE = 4,       /* NaN/Inf met in a Gram or residual norm */
-  DSK_FLAG_BAD_INDEX = 8        /* an index of the restriction was outside [0, n); column 0 was used */
+  DSK_FLAG_BAD_INDEX = 8,       /* an index of the restriction was outside [0, n); column 0 was used */
+  DSK_FLAG_SYNC_TIMEOUT = 16    /* a workgroup of the persistent pivoted-QR kernel waited past its spin
+                                   limit; the ID outputs of that call are not valid */
 };
 
 typedef struct {
@@ -91,6 +93,9 @@ typedef struct {
                            1 = ID of the ell-wide block (tau A_c A_c^T)^q A_c S */
   int32_t mode;       /* DSK_MODE_* (F32 input only) */
   int32_t refine;     /* 1 = one refinement sweep (second orthonormalisation + re-projection) */
+  int32_t id_per_step; /* sketch_id pivoted QR: 0 = one persistent launch when m <= 4 x (compute units)
+                          and the ID matrix is at most 4096 wide (else one launch per pivot step);
+                          1 = always one launch per pivot step.  Both give bitwise the same result. */
 } dsk_opts;
 
 typedef struct {       /* host struct, filled when passed */

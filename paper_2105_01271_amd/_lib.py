@@ -27,7 +27,7 @@ DSK_BATCH_GRAPH = 1
 DSK_F64, DSK_F32, DSK_BF16, DSK_F16 = 0, 1, 2, 3
 DSK_R_INDEX, DSK_R_NN, DSK_R_GLOBAL, DSK_R_LEARNED = 0, 1, 2, 3
 DSK_MODE_DEFAULT, DSK_MODE_SPLIT3, DSK_MODE_F32, DSK_MODE_SPLIT6 = 0, 1, 2, 3
-FLAG_NAMES = {1: "fallback", 2: "rank_deficient", 4: "nonfinite", 8: "bad_index"}
+FLAG_NAMES = {1: "fallback", 2: "rank_deficient", 4: "nonfinite", 8: "bad_index", 16: "sync_timeout"}
 
 
 class Restriction(ctypes.Structure):
@@ -65,6 +65,7 @@ class Opts(ctypes.Structure):
         ("id_projected", ctypes.c_int32),
         ("mode", ctypes.c_int32),
         ("refine", ctypes.c_int32),
+        ("id_per_step", ctypes.c_int32),
     ]
 
 

@@ -492,6 +492,8 @@ int id_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, in
     double *nu0 = c.take<double>(m);
     double *nu1 = c.take<double>(m);
     double *Rk = c.take<double>((size_t)k * m);
+    const size_t pwsb = od.id_per_step ? 0 : cpqr_persist_ws_bytes(m, cols, h->cu_count);
+    char *pws = pwsb ? c.take<char>(pwsb) : nullptr;
     if (pass == 0) {
       if (need) {
         *need = c.off;
@@ -532,7 +534,7 @@ int id_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, in
     } else {
       Wcur = Ac;
     }
-    DSK_RET(launch_cpqr(st, Wcur, m, cols, k, nu0, nu1, Rk, skel, h->dflags));
+    DSK_RET(launch_cpqr(st, Wcur, m, cols, k, nu0, nu1, Rk, skel, h->dflags, pws, h->cu_count));
     const double *nu_final = ((k - 1) & 1) ? nu0 : nu1;
     DSK_RET(launch_id_solve(st, Rk, skel, nu_final, m, k, P, h->dflags));
     if (skel_rows) DSK_RET(launch_gather_rows(st, A, dtype, m, n, lda, skel, k, skel_rows));

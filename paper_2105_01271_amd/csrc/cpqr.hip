@@ -296,6 +296,259 @@ __global__ void __launch_bounds__(NT) k_cpqr_step_reg(double *__restrict__ W, in
   }
 }
 
+// ---------------------------------------------------------------- persistent variant
+// One launch for all k steps.  Workgroup g owns candidates g*CB .. g*CB+CB-1 and
+// keeps their residual rows in registers for the whole factorization.  Each
+// step has two exchanges between workgroups:
+//   1. every workgroup publishes its best live candidate (norm^2, index) in
+//      its slot and then its step tag; every workgroup waits for all tags and
+//      takes the same global argmax p (ties -> lowest index);
+//   2. the owner of p publishes p's residual row and a row tag; the others
+//      wait for that tag and read the row.
+// Then every workgroup updates its rows exactly as the per-step kernels do
+// (same reductions and FMA order), so pivots, R and the final norms are
+// bitwise those of the per-step path.
+//
+// Ordering without cache maintenance.  Everything another workgroup reads
+// (slots, rows, tags) is written with device-scope relaxed atomic stores,
+// which complete at the device's coherence point, and read with device-scope
+// relaxed atomic loads, which are served from it.  A writer waits for its
+// stores to complete (s_waitcnt 0) and only then stores the tag; a reader
+// issues its data loads only after the loaded tag shows the value it waits
+// for, behind a compiler fence.  So a reader that sees a tag sees the data
+// published before it.  Agent-scope acquire/release fences would give the same
+// order with an L2 writeback or invalidation per workgroup and step, which
+// serialises within each XCD and costs far more than the step itself.
+//
+// Every workgroup must be resident at once: the launcher uses at most one
+// workgroup per compute unit.  Each wait is bounded; past the bound the
+// workgroup raises DSK_FLAG_SYNC_TIMEOUT, sets the shared abort word, and
+// every workgroup leaves.  A workgroup is at most one step ahead of any other,
+// so slots and rows double-buffered by step parity never collide.
+constexpr long long SPIN_LIMIT = 1LL << 22;
+constexpr int TAGW = 32;          // one tag per 256-byte line
+constexpr int RMAX = 256 * 16;    // row buffer length: the widest row the kernel keeps (loads need no bounds branch)
+
+__device__ __forceinline__ long long ld_dev(const long long *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev(const double *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(long long *p, long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// this wave's earlier stores have completed before anything after this point
+__device__ __forceinline__ void stores_done() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+}
+// bounded wait for *tag >= want; false on timeout or when another workgroup aborted
+__device__ __forceinline__ bool wait_tag(const long long *tag, long long want, int *abort_flag) {
+  long long spins = 0;
+  while (ld_dev(tag) < want) {
+    if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || ++spins > SPIN_LIMIT) {
+      atomicOr(abort_flag, 1);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");   // later loads stay after the tag load
+  return true;
+}
+
+template <int SPT, int CB>
+__global__ void __launch_bounds__(NT) k_cpqr_persist(const double *__restrict__ W, int64_t m, int64_t s, int k,
+                                                     double *slot_val, long long *slot_idx, double *rows,
+                                                     long long *tags, long long *rtag, int *abort_flag,
+                                                     double *__restrict__ nu_final, double *__restrict__ Rk,
+                                                     int64_t *__restrict__ piv, int *__restrict__ dflags) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int G = gridDim.x, gid = blockIdx.x;
+  __shared__ double redv[NT / 64][CB];
+  __shared__ double coef[CB];
+  __shared__ double bv[NT / 64];
+  __shared__ long long bi[NT / 64];
+  __shared__ long long p_sh;
+  __shared__ double nup_sh;
+  __shared__ int stop_sh;
+
+  int64_t cand[CB];
+  bool live[CB];
+  double w[CB][SPT];
+  double nu[CB];
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    cand[c] = (int64_t)gid * CB + c;
+    live[c] = cand[c] < m;
+    nu[c] = -1.0;
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) {
+      const int64_t e = t + (int64_t)NT * u;
+      w[c][u] = (live[c] && e < s) ? W[cand[c] * s + e] : 0.0;
+    }
+  }
+  if (t == 0) stop_sh = 0;
+
+  // residual norms of the live rows (wave sums, then waves in order) -> nu,
+  // and this workgroup's best live candidate (ascending index, strict '>')
+  auto norms = [&](double &best, long long &bidx) {
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      double a = 0.0;
+#pragma unroll
+      for (int u = 0; u < SPT; ++u) a = fma(w[c][u], w[c][u], a);
+      a = wsum(a);
+      if (lane == 0) redv[wave][c] = a;
+    }
+    __syncthreads();
+    if (t < CB) {
+      double v = 0.0;
+      for (int ww = 0; ww < NT / 64; ++ww) v += redv[ww][t];
+      coef[t] = v;
+      if (live[t] && !isfinite(v)) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_NONFINITE);
+    }
+    __syncthreads();
+    best = -1.0;
+    bidx = (long long)m;
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      if (!live[c]) continue;
+      nu[c] = coef[c];
+      if (nu[c] > best) { best = nu[c]; bidx = cand[c]; }
+    }
+  };
+
+  double mybest;
+  long long myidx;
+  norms(mybest, myidx);
+  for (int step = 0; step < k; ++step) {
+    const long long want = (long long)step + 1;
+    const int par = step & 1;
+    // ---- exchange 1: best candidate per workgroup, then the global argmax
+    if (t == 0) {
+      st_dev(&slot_val[(int64_t)par * G + gid], mybest);
+      st_dev(&slot_idx[(int64_t)par * G + gid], myidx);
+      stores_done();
+      st_dev(&tags[(int64_t)gid * TAGW], want);
+    }
+    double best = -1.0;
+    long long bidx = (long long)m;
+    for (int g = t; g < G; g += NT) {
+      if (!wait_tag(&tags[(int64_t)g * TAGW], want, abort_flag)) {
+        stop_sh = 1;
+        break;
+      }
+      const double v = ld_dev(&slot_val[(int64_t)par * G + g]);
+      const long long ix = ld_dev(&slot_idx[(int64_t)par * G + g]);
+      if (v > best || (v == best && ix < bidx)) { best = v; bidx = ix; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(best, o, 64);
+      const long long oi = __shfl_xor(bidx, o, 64);
+      if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
+    }
+    if (lane == 0) { bv[wave] = best; bi[wave] = bidx; }
+    __syncthreads();
+    if (t == 0) {
+      double b = bv[0];
+      long long ix = bi[0];
+      for (int ww = 1; ww < NT / 64; ++ww)
+        if (bv[ww] > b || (bv[ww] == b && bi[ww] < ix)) { b = bv[ww]; ix = bi[ww]; }
+      p_sh = ix;
+      nup_sh = b;
+    }
+    __syncthreads();
+    if (stop_sh) break;
+    const long long p = p_sh;
+    const double nup = nup_sh;
+    const double rpp = nup > 0.0 ? sqrt(nup) : 0.0;
+    const double qscale = rpp > 0.0 ? 1.0 / rpp : 0.0;
+    if (gid == 0 && t == 0) {
+      piv[step] = p;
+      if (p < m) Rk[(int64_t)step * m + p] = rpp;
+      if (!(rpp > 0.0)) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_RANK_DEFICIENT);
+    }
+    // ---- exchange 2: the pivot's residual row, from its owner
+    const int owner = (p < m) ? (int)(p / CB) : -1;
+    double *rbuf = rows + (int64_t)par * RMAX;
+    double qv[SPT];
+    if (owner == gid) {
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        if (cand[c] != p) continue;
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+          const int64_t e = t + (int64_t)NT * u;
+          if (e < s) st_dev(&rbuf[e], w[c][u]);
+          qv[u] = w[c][u] * qscale;
+        }
+      }
+      stores_done();
+      __syncthreads();
+      if (t == 0) st_dev(rtag, want);
+    } else if (owner >= 0) {
+      if (t == 0 && !wait_tag(rtag, want, abort_flag)) stop_sh = 1;
+      __syncthreads();
+      if (stop_sh) break;
+#pragma unroll
+      for (int u = 0; u < SPT; ++u) {
+        const int64_t e = t + (int64_t)NT * u;    // < RMAX: in bounds; entries past s are not used
+        const double x = ld_dev(&rbuf[e]);
+        qv[u] = (e < s) ? x * qscale : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < SPT; ++u) qv[u] = 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+      if (cand[c] == p) live[c] = false;
+    // ---- R(step, i) = q . residual_i, residual_i -= R(step, i) q, new norms
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      double a = 0.0;
+#pragma unroll
+      for (int u = 0; u < SPT; ++u) a = fma(qv[u], w[c][u], a);
+      a = wsum(a);
+      if (lane == 0) redv[wave][c] = a;
+    }
+    __syncthreads();
+    if (t < CB) {
+      double v = 0.0;
+      for (int ww = 0; ww < NT / 64; ++ww) v += redv[ww][t];
+      coef[t] = v;
+      if (live[t]) Rk[(int64_t)step * m + cand[t]] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      const double r = coef[c];
+#pragma unroll
+      for (int u = 0; u < SPT; ++u) w[c][u] = fma(-r, qv[u], w[c][u]);
+    }
+    norms(mybest, myidx);
+  }
+  if (stop_sh) {
+    if (t == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_SYNC_TIMEOUT);
+    return;
+  }
+  // final residual norms of unselected candidates (selected: -1), as the per-step path writes
+#pragma unroll
+  for (int c = 0; c < CB; ++c)
+    if (t == c && cand[c] < m) nu_final[cand[c]] = live[c] ? nu[c] : -1.0;
+}
+
+__global__ void k_tags_reset(long long *tags, int n, int *abort_flag) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) tags[i] = 0;
+  if (threadIdx.x == 0) *abort_flag = 0;
+}
+
 // C = R_1^{-1} R_2 by back substitution; P(piv[b], :) = e_b, P(i, :) = C(:, i)^T.
 // One wave per candidate: lane l holds entries a = l and a = l + 64 of the
 // right-hand side; the k substitution steps broadcast x_b by a lane shuffle and
@@ -347,12 +600,44 @@ __global__ void __launch_bounds__(64 * SOLVE_WAVES) k_id_solve(const double *__r
 
 }  // namespace
 
+// Workspace of the persistent variant: slot values and indices (2 G each),
+// two residual rows (2 RMAX), G + 1 tags of one 256-byte line each, the abort word.
+size_t cpqr_persist_ws_bytes(int64_t m, int64_t s, int cu_count) {
+  const int64_t G = (m + 3) / 4;
+  if (s > RMAX || G > cu_count) return 0;
+  return (size_t)2 * G * 8 * 2 + (size_t)2 * RMAX * 8 + (size_t)(G + 1) * TAGW * 8 + 256;
+}
+
 int launch_cpqr(hipStream_t st, double *W, int64_t m, int64_t s, int k, double *nu0, double *nu1, double *Rk,
-                int64_t *piv, int *dflags) {
-  hipLaunchKernelGGL(k_cpqr_norms, dim3((unsigned)m), dim3(NT), 0, st, (const double *)W, m, s, nu0);
-  DSK_TRY(hipGetLastError());
+                int64_t *piv, int *dflags, void *pws, int cu_count) {
   hipLaunchKernelGGL(k_fill0, dim3((unsigned)std::min<int64_t>(((int64_t)k * m + 255) / 256, 4096)), dim3(256), 0, st,
                      Rk, (int64_t)k * m);
+  DSK_TRY(hipGetLastError());
+  if (pws && cpqr_persist_ws_bytes(m, s, cu_count) > 0) {
+    // one launch, at most one workgroup per compute unit; the final norms go
+    // where the per-step path leaves them
+    const int G = (int)((m + 3) / 4);
+    char *w = reinterpret_cast<char *>(pws);
+    long long *tags = reinterpret_cast<long long *>(w);                     // G tags + the row tag
+    long long *rtag = tags + (int64_t)G * TAGW;
+    int *abort_flag = reinterpret_cast<int *>(rtag + TAGW);
+    double *slot_val = reinterpret_cast<double *>(w + (size_t)(G + 1) * TAGW * 8 + 256);
+    long long *slot_idx = reinterpret_cast<long long *>(slot_val + 2 * G);
+    double *rows = reinterpret_cast<double *>(slot_idx + 2 * G);
+    double *nu_final = ((k - 1) & 1) ? nu0 : nu1;
+    hipLaunchKernelGGL(k_tags_reset, dim3(1), dim3(256), 0, st, tags, (G + 1) * TAGW, abort_flag);
+    DSK_TRY(hipGetLastError());
+#define DSK_PERSIST(SPT_)                                                                                      \
+  hipLaunchKernelGGL((k_cpqr_persist<SPT_, 4>), dim3(G), dim3(NT), 0, st, (const double *)W, m, s, k, slot_val, \
+                     slot_idx, rows, tags, rtag, abort_flag, nu_final, Rk, piv, dflags)
+    if (s <= 256 * 4) DSK_PERSIST(4);
+    else if (s <= 256 * 8) DSK_PERSIST(8);
+    else DSK_PERSIST(16);
+#undef DSK_PERSIST
+    DSK_TRY(hipGetLastError());
+    return 0;
+  }
+  hipLaunchKernelGGL(k_cpqr_norms, dim3((unsigned)m), dim3(NT), 0, st, (const double *)W, m, s, nu0);
   DSK_TRY(hipGetLastError());
   const unsigned blocks = (unsigned)((m + CPB - 1) / CPB);
   for (int t = 0; t < k; ++t) {

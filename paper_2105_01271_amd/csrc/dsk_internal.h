@@ -160,8 +160,11 @@ int stream_autotune(hipStream_t st, const void *X, int dtype, int64_t K, int64_t
                     void *ws, void *Y, void *out, int cu_count, int *best_ns, float *best_ms);
 
 // cpqr.hip (row ID)
+// pws: workspace of the persistent one-launch variant (cpqr_persist_ws_bytes;
+// 0 bytes = not applicable for this shape), or nullptr for one launch per step.
+size_t cpqr_persist_ws_bytes(int64_t m, int64_t s, int cu_count);
 int launch_cpqr(hipStream_t st, double *W, int64_t m, int64_t s, int k, double *nu0, double *nu1,
-                double *Rk, int64_t *piv, int *dflags);
+                double *Rk, int64_t *piv, int *dflags, void *pws = nullptr, int cu_count = 0);
 int launch_id_solve(hipStream_t st, const double *Rk, const int64_t *piv, const double *nu_final,
                     int64_t m, int k, double *P, int *dflags);
 

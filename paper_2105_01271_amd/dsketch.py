@@ -123,7 +123,7 @@ class Restriction:
         return r
 
 
-def _opts(p=10, S=None, tau=None, id_projected=False, mode="default", refine=False):
+def _opts(p=10, S=None, tau=None, id_projected=False, mode="default", refine=False, id_per_step=False):
     lib = _lib.load()
     o = _lib.Opts()
     lib.dsk_opts_default(ctypes.byref(o))
@@ -135,6 +135,7 @@ def _opts(p=10, S=None, tau=None, id_projected=False, mode="default", refine=Fal
     o.id_projected = int(bool(id_projected))
     o.mode = _MODES[mode] if isinstance(mode, str) else int(mode)
     o.refine = int(bool(refine))
+    o.id_per_step = int(bool(id_per_step))
     return o
 
 
@@ -194,15 +195,16 @@ def sketch_svd(A: torch.Tensor, k: int, R: Restriction, q: int = 0, p: int = 10,
 
 
 def sketch_id(A: torch.Tensor, k: int, R: Restriction, q: int = 0, p: int = 10, S=None, tau=None,
-              projected=False, skeleton_rows=False, want_info: bool = False):
-    """Rank-k row ID by TPC-ID (dsk_sketch_id).  Returns I (k, int64), P (m x k, f64)[, A(I,:)][, info]."""
+              projected=False, skeleton_rows=False, want_info: bool = False, per_step: bool = False):
+    """Rank-k row ID by TPC-ID (dsk_sketch_id).  Returns I (k, int64), P (m x k, f64)[, A(I,:)][, info].
+    per_step: run the pivoted QR as one launch per pivot step even where one persistent launch fits."""
     _check_matrix(A)
     lib = _lib.load()
     m, n = A.shape
     I = torch.empty((k,), dtype=torch.int64, device=A.device)
     P = torch.empty((m, k), dtype=torch.float64, device=A.device)
     rows = torch.empty((k, n), dtype=A.dtype, device=A.device) if skeleton_rows else None
-    o = _opts(p=p, S=S, tau=tau, id_projected=projected)
+    o = _opts(p=p, S=S, tau=tau, id_projected=projected, id_per_step=per_step)
     rc = R.to_c()
     info = _lib.Info()
     st = lib.dsk_sketch_id(_handle(A.device), _ptr(A), _DT[A.dtype], m, n, A.stride(0), int(k), ctypes.byref(rc),

@@ -89,3 +89,7 @@ def test_fullsize_sketch_id_q0(c2):
     say("  ID error gpu / oracle", e_gpu, e_or)
     assert e_gpu <= e_or * (1 + 1e-6) + 1e-12
     np.testing.assert_array_equal(rows.cpu().numpy(), A.cpu().numpy()[I])
+    # the timed launch configuration (one persistent launch) equals the per-step factorization
+    I1, P1 = dsk().sketch_id(A, 50, R, q=0, per_step=True)
+    np.testing.assert_array_equal(I1.cpu().numpy(), I)
+    np.testing.assert_array_equal(P1.cpu().numpy(), P)

@@ -259,6 +259,26 @@ def test_sketch_id_advdiff_fp32(q, projected):
     assert npre >= 10
 
 
+@pytest.mark.parametrize("m", [1024, 1300])
+def test_sketch_id_row_counts_around_one_launch_limit(m):
+    """Up to one workgroup of 4 candidates per compute unit (m <= 1024 on 256
+    CUs) the factorization runs as one persistent launch; above that, one
+    launch per step.  Both follow the oracle's pivots."""
+    say("id rows", m)
+    A32 = _A(synth.advdiff_exact(m, 32, seed=5, r=300, noise=1e-3), torch.float32)
+    A_np = _up(A32)
+    R = dsk().Restriction.di_grid(32, 32, 2, 2)
+    I, P = dsk().sketch_id(A32, 30, R, q=0)
+    Io, Po, info_o = orid.tpc_id(A_np, 30, {"kind": "index", "index": ores.di_index_2d(32, 32, 2, 2)}, q=0,
+                                 return_all=True)
+    npre = _compare_id(A_np, I, P, Io, Po, info_o, 30)
+    say("  separated prefix", npre)
+    assert npre >= 20
+    # the one-launch and the per-step factorizations take the same arithmetic
+    I1, P1 = dsk().sketch_id(A32, 30, R, q=0, per_step=True)
+    assert torch.equal(I, I1) and torch.equal(P, P1)
+
+
 def test_sketch_id_exact_rank_k():
     say("id rank k")
     A_np = synth.lowrank(60, 16 * 16, 5, seed=3)
