@@ -128,6 +128,11 @@ int launch_conv_bwd(hipStream_t st, const void *A, int dtype, int64_t m, int64_t
 
 // smallmat.hip (tall-skinny orthonormalisation, small factorizations)
 size_t cholqr2_ws_bytes(int64_t rows, int ell);
+// ell <= 64 (cholqr64.hip): MFMA Gram partials, one-workgroup factorization,
+// blocked forward substitution; same contract as launch_cholqr2.
+size_t cholqr64_ws_bytes(int64_t rows, int ell);
+int launch_cholqr64(hipStream_t st, const void *Y, int f64, int64_t rows, int ell, void *Q, void *ws, int *dflags,
+                    int passes);
 // passes = 2: CholeskyQR2 (orthonormal to working precision); passes = 1: one
 // CholeskyQR pass, an orthonormal-up-to-kappa^2 u basis of span(Y) (enough
 // where only the span is used, as in the intermediate power steps).

@@ -7,14 +7,17 @@
 //    (Hestenes) Jacobi then orthogonalises the columns of L, L V = W, so the
 //    left singular vectors of L -- the eigenvectors of G_B -- are the
 //    normalised columns of W and no rotation is accumulated.  ell <= 64: one
-//    wave factors in registers (P = I); wider: the workgroup factors in LDS
+//    wave factors (blocked, P = I); wider: the workgroup factors in LDS
 //    with diagonal pivoting (the QR-with-column-pivoting preconditioner of
-//    one-sided Jacobi, Drmac and Veselic 2008).  Pair sums use DPP row
-//    reductions, rotation angles refined hardware reciprocals.
+//    one-sided Jacobi, Drmac and Veselic 2008).  Pair sums use DPP
+//    reductions, rotation angles refined hardware reciprocals.  The rounds
+//    are bound by instruction issue, so ell <= 64 runs 4 waves (one per SIMD)
+//    with 8 lanes per pair, and columns are padded in LDS so that every lane
+//    loads and stores without a bounds branch.
 //  * k_jacobi_svd (FP64 path): one-sided Jacobi on an ell x ell triangular
 //    factor R (B^T = Q_B R): no squaring of the singular values.
 // Both use round-robin (circle) ordering: n/2 disjoint pairs per round, n - 1
-// rounds per sweep, 16 threads per pair.
+// rounds per sweep.
 #include <algorithm>
 
 #include "dsk_internal.h"
@@ -49,6 +52,21 @@ __device__ double jblock_sum(double v, double *scratch) {
   }
   __syncthreads();
   return scratch[NT / 64];
+}
+
+// Sum over each aligned group of G lanes (G = 8 or 16); every lane of the group
+// gets the group's sum.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  if constexpr (G == 16) {
+    return wc::row16_sum(v);
+  } else {
+    static_assert(G == 8, "8 or 16 lanes per pair");
+    v += wc::dpp_f64<0xB1>(v);    // quad xor 1
+    v += wc::dpp_f64<0x4E>(v);    // quad xor 2
+    v += wc::dpp_f64<0x141>(v);   // half-row mirror: lane i + lane 7 - i
+    return v;
+  }
 }
 
 // Rotation (c, s) that makes columns p, q orthogonal, given alpha = |w_p|^2,
@@ -139,12 +157,19 @@ __device__ void pivoted_chol_lds(double *G, int ell, int ldg, double delta, int 
 // G_in: ell x ell row-major FP64 Gram.  Outputs, descending: lam (ell eigenvalues,
 // clipped at 0) and Uout (ell x ell row-major, column j = eigenvector j; zero
 // where the factor has no column).  dflags[FLAGW_SWEEPS] = sweeps used.
+// NT = 256: ell <= 64 (register Cholesky, 8 lanes x 8 entries per pair);
+// NT = 1024: ell <= 112 (pivoted LDS Cholesky, 16 lanes x 7 entries per pair).
+template <int NT>
+constexpr int eig_ldg() { return NT == 256 ? 65 : 113; }   // LDS column stride >= lanes x entries per pair
+
 template <int NT>
 __global__ void __launch_bounds__(NT) k_core_eig(const double *__restrict__ G_in, int ell,
                                                   double *__restrict__ lam, double *__restrict__ Uout,
                                                   int *__restrict__ dflags) {
   extern __shared__ double dyn[];
-  const int ldg = ell | 1;           // odd row stride: conflict-free column walks
+  constexpr int LPP = NT == 256 ? 8 : 16;     // lanes per pair
+  constexpr int EPL = NT == 256 ? 8 : 7;      // entries per lane
+  const int ldg = eig_ldg<NT>();              // odd stride, >= LPP * EPL: padded rows stay zero
   const int n = (ell + 1) & ~1;      // even size; an odd ell gets one zero column
   const int np = n / 2;
   double *G = dyn;                   // ell x ldg, later X column-major (n columns)
@@ -156,7 +181,8 @@ __global__ void __launch_bounds__(NT) k_core_eig(const double *__restrict__ G_in
   __shared__ double pivd;
   __shared__ int rotated;
   const int t = threadIdx.x;
-  for (int e = t; e < n * ldg; e += NT) G[e] = 0.0;
+  const int grows = NT == 256 ? 64 : n;   // the 64-row blocked Cholesky reads padded rows
+  for (int e = t; e < grows * ldg; e += NT) G[e] = 0.0;
   __syncthreads();
   for (int e = t; e < ell * ell; e += NT) {
     const int i = e / ell, c = e - (e / ell) * ell;
@@ -169,14 +195,15 @@ __global__ void __launch_bounds__(NT) k_core_eig(const double *__restrict__ G_in
   tr = jblock_sum<NT>(tr, red);
   if (!isfinite(tr) && t == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_NONFINITE);
   const double delta = 16.0 * (ell + 1024) * U64 * fabs(tr);
-  if constexpr (NT == 512) {
+  if constexpr (NT == 256) {
     // ell <= 64, one wave: register Cholesky of G + delta I, then X = L column-major over G
-    double *Lb = dyn + n * ldg;
-    double *col = Lb + 64 * wc::LDL;
-    double *dinv = col + 64;
+    double *Lb = dyn + 64 * ldg;
+    double *dinv = Lb + 64 * wc::LDL;
     __shared__ int okw;
+    for (int i = t; i < ell; i += NT) G[i * ldg + i] += delta;
+    __syncthreads();
     if (t < 64) {
-      const bool ok = wc::chol64(G, ldg, ell, delta, 0.0, Lb, dinv, col);
+      const bool ok = wc::chol64_blocked(G, ell, 0.0, Lb, dinv, dinv + 64);
       if (t == 0) okw = ok ? 1 : 0;
     }
     __syncthreads();
@@ -189,43 +216,44 @@ __global__ void __launch_bounds__(NT) k_core_eig(const double *__restrict__ G_in
   } else {
     pivoted_chol_lds<NT>(G, ell, ldg, delta, perm, &pivsh, &pivd);
   }
-  // ---- one-sided Jacobi on the columns of X
-  const int grp = t >> 4, gl = t & 15;
+  // ---- one-sided Jacobi on the columns of X (entries past ell are zero and stay zero)
+  const int pr = t / LPP, pl = t % LPP;
   const double tolj = 4.0 * ell * U64;
+  const double tol2 = tolj * tolj;   // rotate when gamma^2 > tol^2 alpha beta
   int sweeps = 0;
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (t == 0) rotated = 0;
     __syncthreads();
     for (int r = 0; r < n - 1; ++r) {
-      if (grp < np) {
-        int p = rr_player(grp, r, n), q = rr_player(n - 1 - grp, r, n);
+      if (pr < np) {
+        int p = rr_player(pr, r, n), q = rr_player(n - 1 - pr, r, n);
         if (p > q) { const int x = p; p = q; q = x; }
-        double wp[7], wq[7];
+        double *xp = G + p * ldg + pl, *xq = G + q * ldg + pl;
+        double wp[EPL], wq[EPL];
         double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-        for (int u = 0; u < 7; ++u) {
-          const int i = gl + 16 * u;
-          wp[u] = (i < ell) ? G[p * ldg + i] : 0.0;
-          wq[u] = (i < ell) ? G[q * ldg + i] : 0.0;
+        for (int u = 0; u < EPL; ++u) {
+          wp[u] = xp[LPP * u];
+          wq[u] = xq[LPP * u];
+        }
+#pragma unroll
+        for (int u = 0; u < EPL; ++u) {
           al = fma(wp[u], wp[u], al);
           be = fma(wq[u], wq[u], be);
           ga = fma(wp[u], wq[u], ga);
         }
-        al = wc::row16_sum(al);
-        be = wc::row16_sum(be);
-        ga = wc::row16_sum(ga);
-        if (ga != 0.0 && fabs(ga) > tolj * sqrt(al * be)) {
+        al = group_sum<LPP>(al);
+        be = group_sum<LPP>(be);
+        ga = group_sum<LPP>(ga);
+        if (ga != 0.0 && ga * ga > tol2 * (al * be)) {
           double c, s;
           jrot(al, be, ga, c, s);
 #pragma unroll
-          for (int u = 0; u < 7; ++u) {
-            const int i = gl + 16 * u;
-            if (i < ell) {
-              G[p * ldg + i] = c * wp[u] - s * wq[u];
-              G[q * ldg + i] = s * wp[u] + c * wq[u];
-            }
+          for (int u = 0; u < EPL; ++u) {
+            xp[LPP * u] = c * wp[u] - s * wq[u];
+            xq[LPP * u] = s * wp[u] + c * wq[u];
           }
-          if (gl == 0) rotated = 1;
+          if (pl == 0) rotated = 1;
         }
       }
       __syncthreads();
@@ -233,6 +261,7 @@ __global__ void __launch_bounds__(NT) k_core_eig(const double *__restrict__ G_in
     sweeps = sweep + 1;
     if (!rotated) break;
   }
+  const int grp = t >> 4, gl = t & 15;
   // ---- eigenvalues lambda_c = |x_c|^2 - delta, eigenvectors x_c / |x_c|
   for (int c = grp; c < ell; c += NT / 16) {
     double s2 = 0.0;
@@ -352,12 +381,12 @@ __global__ void __launch_bounds__(1024) k_jacobi_svd(const double *__restrict__ 
 int launch_core_eig(hipStream_t st, const double *G, int ell, double *lam, double *U, int *dflags) {
   if (ell < 1 || ell > JELL_MAX) return -1;
   const int n = (ell + 1) & ~1;
-  size_t lds = (size_t)n * (ell | 1) * sizeof(double);
-  if (ell <= 64) lds += (size_t)(64 * wc::LDL + 128) * sizeof(double);
   if (ell <= 64) {
-    allow_lds(k_core_eig<512>, lds);
-    hipLaunchKernelGGL(k_core_eig<512>, dim3(1), dim3(512), lds, st, G, ell, lam, U, dflags);
+    const size_t lds = ((size_t)64 * eig_ldg<256>() + 64 * wc::LDL + 128) * sizeof(double);
+    allow_lds(k_core_eig<256>, lds);
+    hipLaunchKernelGGL(k_core_eig<256>, dim3(1), dim3(256), lds, st, G, ell, lam, U, dflags);
   } else {
+    const size_t lds = (size_t)std::max(n, ell) * eig_ldg<JNT>() * sizeof(double);
     allow_lds(k_core_eig<JNT>, lds);
     hipLaunchKernelGGL(k_core_eig<JNT>, dim3(1), dim3(JNT), lds, st, G, ell, lam, U, dflags);
   }

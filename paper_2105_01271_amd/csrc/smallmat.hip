@@ -13,7 +13,6 @@
 #include <algorithm>
 
 #include "dsk_internal.h"
-#include "wavechol.h"
 
 namespace {
 
@@ -370,62 +369,6 @@ __device__ void chol_body(const double *__restrict__ part, int nparts, int ell, 
     for (int c = t & 63; c < ell; c += 64) Rinv[i * ell + c] = (c >= i) ? G[c * ell + i] : 0.0;
 }
 
-// ell <= 64: one wave factors the summed Gram (LDS, ell x ell) G = L L^T,
-// retrying once with the shift on breakdown, and writes L (Lg, ell x ell
-// row-major, zero above the diagonal) and dg = 1 / diag(L).  No inverse is
-// formed: the apply step solves with L row by row.  dyn: G | L rows (64 x 65,
-// over G) | column buffer (64) | pivot reciprocals (64).
-constexpr int CW_LDS_DOUBLES = 64 * wc::LDL + 128;
-
-__device__ __forceinline__ void factor_small(int ell, int64_t rows, double *__restrict__ Lg, double *__restrict__ dg,
-                                             int *__restrict__ dflags, double *dyn) {
-  const int lane = threadIdx.x;
-  const double *G = dyn;
-  double *Lb = dyn;
-  double *col = dyn + 64 * wc::LDL;
-  double *dinv = col + 64;
-  double tr = 0.0;
-  for (int i = 0; i < ell; ++i) tr += G[i * ell + i];
-  const bool trok = (tr > 0.0) && isfinite(tr);
-  bool ok = false;
-  // one copy of the unrolled factorization: the retry reuses it with the shift
-#pragma nounroll
-  for (int attempt = 0; attempt < 2 && trok && !ok; ++attempt) {
-    const double shift = attempt ? 11.0 * ((double)rows * ell + (double)ell * (ell + 1)) * U64 * tr : 0.0;
-    ok = wc::chol64(G, ell, ell, shift, 1e-15 * tr, Lb, dinv, col);
-    if (!ok && attempt == 0 && lane == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_FALLBACK);
-  }
-  if (!ok && !trok && lane == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_FALLBACK);
-  if (!ok) {
-    // still failing (non-finite input): identity factor keeps the pipeline finite
-    if (lane == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_RANK_DEFICIENT | DSK_FLAG_NONFINITE);
-    for (int e = lane; e < ell * ell; e += 64) Lg[e] = (e / ell == e % ell) ? 1.0 : 0.0;
-    for (int i = lane; i < ell; i += 64) dg[i] = 1.0;
-    return;
-  }
-  for (int e = lane; e < ell * ell; e += 64) {
-    const int i = e / ell, c = e - (e / ell) * ell;
-    Lg[e] = Lb[i * wc::LDL + c];
-  }
-  for (int i = lane; i < ell; i += 64) dg[i] = dinv[i];
-}
-
-// Sum the partials, then factor.  ell <= 64: one wave, output L in Rinv and
-// 1 / diag(L) in R; ell > 64: the whole workgroup, output R and R^{-1}.
-// SMALL_ONLY: the caller guarantees ell <= 64 (keeps the large path out of its code).
-template <bool SMALL_ONLY>
-__device__ __forceinline__ void factor_parts(const double *__restrict__ part, int nparts, int ell, int64_t rows,
-                                             double *__restrict__ R, double *__restrict__ Rinv,
-                                             int *__restrict__ dflags, double *dyn) {
-  if (!SMALL_ONLY && ell > 64) {
-    chol_body(part, nparts, ell, rows, R, Rinv, dflags, dyn);
-    return;
-  }
-  sum_parts_lds(part, nparts, ell * ell, dyn);
-  __syncthreads();
-  if (threadIdx.x < 64) factor_small(ell, rows, Rinv, R, dflags, dyn);
-}
-
 __global__ void __launch_bounds__(256) k_chol(const double *__restrict__ part, int nparts, int ell, int64_t rows,
                                               double *__restrict__ R, double *__restrict__ Rinv,
                                               int *__restrict__ dflags, int cond) {
@@ -478,7 +421,7 @@ __global__ void __launch_bounds__(256) k_gram_chol(const T *__restrict__ X, int6
     __syncthreads();
   }
   gram_store(g, slots, ell, part + (int64_t)blockIdx.x * ell * ell);
-  if (last_block_done(counter)) factor_parts<false>(part, gridDim.x, ell, rows, R, Rinv, dflags, dyn);
+  if (last_block_done(counter)) chol_body(part, gridDim.x, ell, rows, R, Rinv, dflags, dyn);
 }
 
 // ---------------------------------------------------------------- Q = Y Rinv (+ Gram partials of Q)
@@ -551,126 +494,6 @@ __global__ void __launch_bounds__(256) k_apply(const T *__restrict__ Y, int64_t 
     __syncthreads();   // LDS (Rs, sh) is reused by the factorization
     if (last_block_done(counter)) chol_body(part, gridDim.x, ell, rows, R, Rinv, dflags, dyn);
   }
-}
-
-// ---------------------------------------------------------------- Q = Y L^{-T} by row solves (ell <= 64)
-// Right-looking forward substitution of one row: L x = y (y, x in registers).
-template <int C, int NMAX>
-__device__ __forceinline__ void solve_row(double (&x)[64], int ell, const double *Ls, const double *dv) {
-  if constexpr (C < NMAX) {
-    if (C < ell) {
-      const double v = x[C] * dv[C];
-      x[C] = v;
-#pragma unroll
-      for (int r = C + 1; r < NMAX; ++r) x[r] = fma(-Ls[r * wc::LDL + C], v, x[r]);
-      solve_row<C + 1, NMAX>(x, ell, Ls, dv);
-    }
-  }
-}
-
-// Every thread solves one row of a staged chunk (CH rows: 256 for f32, 128 for
-// f64); the chunk is then written out coalesced and, with part != nullptr,
-// accumulated into this workgroup's Gram partial of the rounded output (one
-// 4x4 block per thread and row group, as in k_gram_rows).  With a counter the
-// last workgroup factors the summed Gram (L into Lg, 1 / diag into dg; all
-// workgroups have read Lg, dg by then).  cond / gram_cond as in k_apply.
-template <typename T, int NMAX>
-__global__ void __launch_bounds__(256) k_apply_solve(const T *__restrict__ Y, int64_t rows, int ell,
-                                                     double *__restrict__ Lg, double *__restrict__ dg,
-                                                     T *__restrict__ Q, int64_t rows_per_blk,
-                                                     double *__restrict__ part, int *__restrict__ dflags, int cond,
-                                                     unsigned *__restrict__ counter, int gram_cond) {
-  const bool fallback = (dflags[FLAGW_BITS] & DSK_FLAG_FALLBACK) != 0;
-  if (cond && !fallback) return;
-  if (gram_cond && !fallback) {
-    part = nullptr;
-    counter = nullptr;
-  }
-  constexpr int CH = sizeof(T) == 4 ? 256 : 128;
-  constexpr int LDY = 65;
-  extern __shared__ double dyn[];
-  double *Ls = dyn;                          // 64 x LDL
-  double *dv = Ls + 64 * wc::LDL;            // 64
-  T *sh = reinterpret_cast<T *>(dv + 64);    // CH x LDY
-  const int t = threadIdx.x;
-  for (int e = t; e < 64 * wc::LDL; e += 256) {
-    const int r = e / wc::LDL, c = e - (e / wc::LDL) * wc::LDL;
-    Ls[e] = (r < ell && c < ell) ? Lg[r * ell + c] : 0.0;
-  }
-  for (int i = t; i < 64; i += 256) dv[i] = i < ell ? dg[i] : 1.0;
-  const int ellp = (ell + 3) & ~3, nb = ellp / 4, npairs = nb * (nb + 1) / 2;
-  const int RG = 256 / npairs;
-  const int rg = t / npairs, pid = t - rg * npairs;
-  const bool on = rg < RG;
-  int bi = 0, bj = 0;
-  if (on) pair_of(pid, nb, bi, bj);
-  double acc[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) acc[e] = 0.0;
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
-  const int64_t r1 = std::min<int64_t>(rows, r0 + rows_per_blk);
-  for (int64_t c0 = r0; c0 < r1; c0 += CH) {
-    const int nr = (int)std::min<int64_t>(CH, r1 - c0);
-    __syncthreads();
-    for (int e = t; e < CH * ell; e += 256) {
-      const int rr = e / ell, c = e - (e / ell) * ell;
-      sh[rr * LDY + c] = rr < nr ? Y[(c0 + rr) * ell + c] : T(0);
-    }
-    __syncthreads();
-    if (t < nr) {
-      double x[64];
-#pragma unroll
-      for (int c = 0; c < 64; ++c) x[c] = c < ell ? (double)sh[t * LDY + c] : 0.0;
-      solve_row<0, NMAX>(x, ell, Ls, dv);
-#pragma unroll
-      for (int c = 0; c < 64; ++c)
-        if (c < ell) sh[t * LDY + c] = (T)x[c];
-    }
-    __syncthreads();
-    for (int e = t; e < nr * ell; e += 256) {
-      const int rr = e / ell, c = e - (e / ell) * ell;
-      Q[(c0 + rr) * ell + c] = sh[rr * LDY + c];
-    }
-    if (part && on) {
-      for (int r = rg; r < nr; r += RG) {
-        const T *row = sh + r * LDY;
-        double xs[4], ys[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          xs[a] = 4 * bi + a < ell ? (double)row[4 * bi + a] : 0.0;
-          ys[a] = 4 * bj + a < ell ? (double)row[4 * bj + a] : 0.0;
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) acc[a * 4 + b] = fma(xs[a], ys[b], acc[a * 4 + b]);
-      }
-    }
-  }
-  if (!part) return;
-  // combine the row groups in a fixed order (LDS reused), then publish
-  __syncthreads();
-  double *comb = dyn;
-  if (on && rg > 0) {
-#pragma unroll
-    for (int e = 0; e < 16; ++e) comb[((rg - 1) * npairs + pid) * 16 + e] = acc[e];
-  }
-  __syncthreads();
-  if (on && rg == 0) {
-    for (int g = 1; g < RG; ++g)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc[e] += comb[((g - 1) * npairs + pid) * 16 + e];
-    gram_store_u(acc, bi, bj, true, ell, part + (int64_t)blockIdx.x * ell * ell);
-  }
-  if (counter) {
-    __syncthreads();
-    if (last_block_done(counter)) factor_parts<true>(part, gridDim.x, ell, rows, dg, Lg, dflags, dyn);
-  }
-}
-
-template <typename T>
-constexpr size_t apply_solve_lds() {
-  return (64 * wc::LDL + 64) * sizeof(double) + (size_t)(sizeof(T) == 4 ? 256 : 128) * 65 * sizeof(T);
 }
 
 // ---------------------------------------------------------------- Householder QR (one block)
@@ -851,10 +674,11 @@ void launch_apply(hipStream_t st, int nparts, size_t lds, const T *Y, int64_t ro
 // CholeskyQR2 in 3 launches (+1 after a shifted first pass):
 //   [Gram(Y) -> chol]  [Q1 = Y R1^-1, Gram(Q1) -> chol]  [Q = Q1 R2^-1 (, Gram(Q) -> chol)]  [(Q = Q R3^-1)]
 // The factorizations run in the workgroup that finishes its Gram partial last.
-// ell <= 64 applies R^{-1} = L^{-T} by row solves; wider blocks multiply by an
-// explicit inverse.
+// Blocks at most 64 wide take the MFMA path of cholqr64.hip; wider blocks
+// multiply by an explicit inverse.
 template <typename T>
 int cholqr2_typed(hipStream_t st, const T *Y, int64_t rows, int ell, T *Q, void *ws, int *dflags, int passes) {
+  if (ell <= 64) return launch_cholqr64(st, Y, sizeof(T) == 8, rows, ell, Q, ws, dflags, passes);
   // ws layout: part (nparts*ell*ell f64) | R (ell^2) | Rinv (ell^2) | Q1 (rows*ell T)
   const int nparts = gram_parts(rows);
   const int64_t rpb = ((rows + nparts - 1) / nparts + GCH - 1) / GCH * GCH;
@@ -864,7 +688,7 @@ int cholqr2_typed(hipStream_t st, const T *Y, int64_t rows, int ell, T *Q, void 
   T *Q1 = reinterpret_cast<T *>(Rinv + ell * ell);
   unsigned *counter = reinterpret_cast<unsigned *>(dflags + FLAGW_TICKET);
   const int ellp = (ell + 3) & ~3;
-  const size_t chol_lds = (size_t)std::max(ell * ell + ell, ell <= 64 ? CW_LDS_DOUBLES : 0) * sizeof(double);
+  const size_t chol_lds = (size_t)(ell * ell + ell) * sizeof(double);
   const size_t gram_lds = std::max<size_t>(chol_lds, (size_t)GCH * ellp * sizeof(double));
   const size_t apply_lds = std::max<size_t>(chol_lds, (size_t)(ell * ell + GCH * ellp) * sizeof(double));
   auto apply = [&](const T *src, T *dst, double *prt, int cond, unsigned *ctr, int gcond) {
@@ -873,31 +697,6 @@ int cholqr2_typed(hipStream_t st, const T *Y, int64_t rows, int ell, T *Q, void 
   allow_lds(k_gram_chol<T>, gram_lds);
   hipLaunchKernelGGL(k_gram_chol<T>, dim3(nparts), dim3(256), gram_lds, st, Y, rows, ell, (int64_t)ell, rpb, part,
                      counter, R, Rinv, dflags);
-  if (ell <= 64) {
-    // L in Rinv, 1 / diag(L) in R: Q = Y L^{-T} by row solves
-    const size_t lds = std::max<size_t>(apply_solve_lds<T>(), chol_lds);
-    auto solve = [&](const T *src, T *dst, double *prt, int cond, unsigned *ctr, int gcond) {
-      if (ell <= 32) {
-        allow_lds(k_apply_solve<T, 32>, lds);
-        hipLaunchKernelGGL((k_apply_solve<T, 32>), dim3(nparts), dim3(256), lds, st, src, rows, ell, Rinv, R, dst,
-                           rpb, prt, dflags, cond, ctr, gcond);
-      } else {
-        allow_lds(k_apply_solve<T, 64>, lds);
-        hipLaunchKernelGGL((k_apply_solve<T, 64>), dim3(nparts), dim3(256), lds, st, src, rows, ell, Rinv, R, dst,
-                           rpb, prt, dflags, cond, ctr, gcond);
-      }
-    };
-    if (passes == 1) {
-      solve(Y, Q, nullptr, 0, nullptr, 0);   // span only: one pass
-      DSK_TRY(hipGetLastError());
-      return 0;
-    }
-    solve(Y, Q1, part, 0, counter, 0);
-    solve(Q1, Q, part, 0, counter, 1);     // third factorization only after a shifted first pass
-    solve(Q, Q, nullptr, 1, nullptr, 0);   // third application only after a shifted first pass
-    DSK_TRY(hipGetLastError());
-    return 0;
-  }
   if (passes == 1) {
     launch_apply<T, 128>(st, nparts, apply_lds, Y, rows, ell, Rinv, Q, rpb, nullptr, dflags, 0, nullptr, R, 0);
     DSK_TRY(hipGetLastError());
@@ -913,6 +712,7 @@ int cholqr2_typed(hipStream_t st, const T *Y, int64_t rows, int ell, T *Q, void 
 }  // namespace
 
 size_t cholqr2_ws_bytes(int64_t rows, int ell) {
+  if (ell <= 64) return cholqr64_ws_bytes(rows, ell);
   const int nparts = gram_parts(rows);
   return ((size_t)nparts * ell * ell + 2 * (size_t)ell * ell) * sizeof(double) + (size_t)rows * ell * sizeof(double) +
          1024;

@@ -1,7 +1,7 @@
 // One-wave building blocks shared by the small factorizations: lane-uniform
 // reads, wave-local LDS ordering, refined hardware reciprocal / reciprocal
-// square root, 16-lane DPP sums, and a register-resident Cholesky of an
-// ell x ell (ell <= 64) symmetric positive definite matrix.
+// square root, 16-lane DPP sums, the FP64 16 x 16 x 4 MFMA, and a blocked
+// Cholesky of an ell x ell (ell <= 64) symmetric positive definite matrix.
 #pragma once
 
 #include "dsk_internal.h"
@@ -61,57 +61,78 @@ __device__ __forceinline__ double row16_sum(double v) {
   return v;
 }
 
-// Step J of the right-looking register Cholesky: lane i keeps row i of the
-// working matrix in g (compile-time J keeps every register index static); the
-// pivot column L(:, J) is broadcast lane by lane with v_readlane (no memory
-// round trip on the dependent chain).  On success g[c] holds L(i, c) for
-// c <= i; dinv[J] = 1 / L(J, J).  Rows and columns past ell hold the identity.
-template <int J>
-__device__ __forceinline__ void chol_step(double (&g)[64], int ell, int lane, double thr, bool &ok, double *dinv) {
-  if constexpr (J < 64) {
-    if (J < ell && ok) {
-      const double d = readlane_f64(g[J], J);
-      if (!(d > thr) || !isfinite(d)) {
-        ok = false;
-        return;
-      }
-      const double inv = rsq_nr(d), piv = d * inv;
-      // lanes below the pivot get L(i, J); the pivot lane's own update only
-      // touches its (unused) upper triangle
-      const double l = lane > J ? g[J] * inv : (lane == J ? piv : 0.0);
-      g[J] = l;
-      if (lane == 0) dinv[J] = inv;
-      double lc[64 - J];
-#pragma unroll
-      for (int c = J + 1; c < 64; ++c) lc[c - J] = readlane_f64(l, c);
-#pragma unroll
-      for (int c = J + 1; c < 64; ++c) g[c] = fma(-l, lc[c - J], g[c]);
-      chol_step<J + 1>(g, ell, lane, thr, ok, dinv);
-    }
-  }
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// D = A B + C for 16 x 16 FP64 tiles, k = 4: A(i, k) in lane i + 16 k, B(k, j) in
+// lane j + 16 k, D(i, j) in lane j + 16 (i mod 4), register i / 4.
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Cholesky of S = A + shift I by the calling wave (lanes 0..63), ell <= 64.
-// A: LDS or global, row-major with leading dimension lda.  On success L is
-// written to Lout (LDS, 64 x LDL, row i = L(i, :), zero above the diagonal and
-// identity past ell) and dinv[j] = 1 / L(j, j); returns false at a pivot
-// <= thr (or non-finite).  col: unused (kept for the LDS layout of callers).
-__device__ __forceinline__ bool chol64(const double *A, int lda, int ell, double shift, double thr, double *Lout,
-                                       double *dinv, double *col) {
-  const int lane = threadIdx.x & 63;
-  double g[64];
-#pragma unroll
-  for (int c = 0; c < 64; ++c)
-    g[c] = (lane < ell && c < ell) ? A[lane * lda + c] + (c == lane ? shift : 0.0) : (c == lane ? 1.0 : 0.0);
+// Cholesky of the lower triangle of A (LDS, 64 x LDL, the shift already added;
+// rows and columns past ell zero), ell <= 64, by the calling wave, no
+// barriers: four 16-column panels, each factored in registers, then the
+// trailing tiles A_IJ -= L_IK L_JK^T (K < J <= I) on MFMA.  In a panel step
+// lane i keeps row i; the pivot column goes to every lane through one LDS
+// write and uniform-address reads (colb: 64 doubles of LDS), the pivot itself
+// by v_readlane, and the update A(i, c) -= A(i, p) A(c, p) / d needs no square
+// root, so only 1 / d is on the chain from one pivot to the next.  Branch-free
+// steps (a padded column p >= ell is an identity column).  A is overwritten.
+// L goes to Lf (LDS, 64 x LDL, zero above the diagonal, identity past ell),
+// dinv[j] = 1 / L(j, j).  Returns false at a pivot <= thr or non-finite.
+__device__ __forceinline__ bool chol64_blocked(double *A, int ell, double thr, double *Lf, double *dinv,
+                                               double *colb) {
+  const int i = threadIdx.x & 63;
   bool ok = true;
-  (void)col;
-  chol_step<0>(g, ell, lane, thr, ok, dinv);
-  if (!ok) return false;
+  double mydinv = 1.0;
+  for (int K = 0; K < 4; ++K) {
+    const int c0 = 16 * K;
+    double g[16];
 #pragma unroll
-  for (int c = 0; c < 64; ++c) Lout[lane * LDL + c] = c <= lane ? g[c] : 0.0;
-  if (lane >= ell) dinv[lane] = 1.0;
+    for (int j = 0; j < 16; ++j) g[j] = A[i * LDL + c0 + j];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int p = c0 + j;
+      const bool live = p < ell;
+      const double dp = readlane_f64(g[j], p);
+      colb[i] = g[j];
+      wave_lds_sync();
+      // uniform-address reads; colb is only 8-byte aligned (the dynamic LDS base
+      // follows the static segment), so no wider access is assumed
+      double lc[16];
+#pragma unroll
+      for (int c = j + 1; c < 16; ++c) lc[c] = colb[c0 + c];
+      const double d = live ? dp : 1.0;
+      ok = ok && (!live || (d > thr && isfinite(d)));
+      const double inv = rcp_nr(d), rs = rsq_nr(d);
+      const double ti = g[j] * inv;
+#pragma unroll
+      for (int c = j + 1; c < 16; ++c) g[c] = fma(-ti, lc[c], g[c]);
+      g[j] = live ? (i > p ? g[j] * rs : (i == p ? d * rs : 0.0)) : (i == p ? 1.0 : 0.0);
+      mydinv = (i == p) ? (live ? rs : 1.0) : mydinv;
+      wave_lds_sync();   // colb is rewritten by the next step
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) Lf[i * LDL + c0 + j] = (i >= c0 + j) ? g[j] : 0.0;
+    wave_lds_sync();
+    // A(i, k) = L(16 I + i, c0 + k) in lane i + 16 k, B(k, j) = L(16 J + j, c0 + k) in lane j + 16 k
+    for (int I = K + 1; I < 4; ++I)
+      for (int J = K + 1; J <= I; ++J) {
+        d4 c;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) c[v] = A[(16 * I + (i >> 4) + 4 * v) * LDL + 16 * J + (i & 15)];
+#pragma unroll
+        for (int k4 = 0; k4 < 4; ++k4)
+          c = mfma(-Lf[(16 * I + (i & 15)) * LDL + c0 + 4 * k4 + (i >> 4)],
+                   Lf[(16 * J + (i & 15)) * LDL + c0 + 4 * k4 + (i >> 4)], c);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) A[(16 * I + (i >> 4) + 4 * v) * LDL + 16 * J + (i & 15)] = c[v];
+      }
+    wave_lds_sync();
+  }
+  dinv[i] = mydinv;
   wave_lds_sync();
-  return true;
+  return ok;
 }
 
 }  // namespace wc
