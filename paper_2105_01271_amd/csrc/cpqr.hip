@@ -4,8 +4,9 @@
 // W is m x s, row-major, FP64: row i of W is column i of X = W^T, the i-th
 // candidate (time step).  The factorization is right-looking modified
 // Gram-Schmidt with column pivoting, FP64 throughout:
-//   step t: p = argmax over unselected i of nu_i = ||residual_i||^2
-//           (exact ties -> lowest index), q = residual_p / ||residual_p||,
+//   step t: p = argmax over unselected i of nu_i = ||residual_i||^2, in the
+//           order of nu_rank (nu truncated to 34 mantissa bits, ties -> lowest
+//           index), q = residual_p / ||residual_p||,
 //           for every unselected i:  R[t, i] = q . residual_i,
 //           residual_i -= R[t, i] q,  nu_i = ||residual_i||^2 recomputed from
 //           the updated residual (no norm downdating).
@@ -19,6 +20,7 @@
 // it.  Selected candidates carry nu = -1.
 #include <algorithm>
 
+#include "devsync.h"
 #include "dsk_internal.h"
 
 namespace {
@@ -30,6 +32,15 @@ __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
+}
+
+// Pivot order of a candidate with residual norm^2 v (larger wins): v truncated
+// to 34 mantissa bits, so candidates closer than 2^-34 relative rank equal and
+// the lower index wins; selected (negative) or NaN candidates rank 0 and never
+// win.  Both the per-step and the persistent factorization use it.
+__device__ __forceinline__ unsigned long long nu_rank(double v) {
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(v) & 0x7FFFFFFFFFFFFFFFull;
+  return (v >= 0.0) ? (bits >> 18) + 1ull : 0ull;
 }
 
 // zero fill by a kernel (keeps the sequence capturable in a graph)
@@ -62,29 +73,29 @@ __global__ void __launch_bounds__(NT) k_cpqr_step(double *__restrict__ W, int64_
                                                   double *__restrict__ Rk, int64_t *__restrict__ piv,
                                                   int *__restrict__ dflags) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  __shared__ double bv[NT / 64];
+  __shared__ unsigned long long bv[NT / 64];
   __shared__ int64_t bi[NT / 64];
   __shared__ int64_t p_sh;
   __shared__ double red[NT / 64][CPB];
   __shared__ double coef[CPB];
 
-  // ---- argmax of nu_in over unselected candidates (ties -> lowest index)
-  double best = -1.0;
+  // ---- pivot: maximum of nu_rank over unselected candidates (ties -> lowest index)
+  unsigned long long best = 0;
   int64_t bidx = m;
   for (int64_t i = t; i < m; i += NT) {
-    const double v = nu_in[i];
-    if (v > best) { best = v; bidx = i; }   // ascending i: strict '>' keeps the lowest index
+    const unsigned long long r = nu_rank(nu_in[i]);
+    if (r > best) { best = r; bidx = i; }   // ascending i: strict '>' keeps the lowest index
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
-    const double ov = __shfl_xor(best, o, 64);
+    const unsigned long long ov = (unsigned long long)__shfl_xor((long long)best, o, 64);
     const int64_t oi = __shfl_xor(bidx, o, 64);
     if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
   }
   if (lane == 0) { bv[wave] = best; bi[wave] = bidx; }
   __syncthreads();
   if (t == 0) {
-    double b = bv[0];
+    unsigned long long b = bv[0];
     int64_t ix = bi[0];
     for (int w = 1; w < NT / 64; ++w)
       if (bv[w] > b || (bv[w] == b && bi[w] < ix)) { b = bv[w]; ix = bi[w]; }
@@ -180,7 +191,7 @@ __global__ void __launch_bounds__(NT) k_cpqr_step_reg(double *__restrict__ W, in
                                                       double *__restrict__ Rk, int64_t *__restrict__ piv,
                                                       int *__restrict__ dflags) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  __shared__ double bv[NT / 64];
+  __shared__ unsigned long long bv[NT / 64];
   __shared__ int64_t bi[NT / 64];
   __shared__ int64_t p_sh;
   __shared__ double red[NT / 64][CB];
@@ -201,23 +212,23 @@ __global__ void __launch_bounds__(NT) k_cpqr_step_reg(double *__restrict__ W, in
     }
   }
 
-  // ---- argmax of nu_in over unselected candidates (ties -> lowest index)
-  double best = -1.0;
+  // ---- pivot: maximum of nu_rank over unselected candidates (ties -> lowest index)
+  unsigned long long best = 0;
   int64_t bidx = m;
   for (int64_t i = t; i < m; i += NT) {
-    const double v = nu_in[i];
-    if (v > best) { best = v; bidx = i; }
+    const unsigned long long r = nu_rank(nu_in[i]);
+    if (r > best) { best = r; bidx = i; }   // ascending i: strict '>' keeps the lowest index
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
-    const double ov = __shfl_xor(best, o, 64);
+    const unsigned long long ov = (unsigned long long)__shfl_xor((long long)best, o, 64);
     const int64_t oi = __shfl_xor(bidx, o, 64);
     if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
   }
   if (lane == 0) { bv[wave] = best; bi[wave] = bidx; }
   __syncthreads();
   if (t == 0) {
-    double b = bv[0];
+    unsigned long long b = bv[0];
     int64_t ix = bi[0];
     for (int ww = 1; ww < NT / 64; ++ww)
       if (bv[ww] > b || (bv[ww] == b && bi[ww] < ix)) { b = bv[ww]; ix = bi[ww]; }
@@ -298,83 +309,66 @@ __global__ void __launch_bounds__(NT) k_cpqr_step_reg(double *__restrict__ W, in
 
 // ---------------------------------------------------------------- persistent variant
 // One launch for all k steps.  Workgroup g owns candidates g*CB .. g*CB+CB-1 and
-// keeps their residual rows in registers for the whole factorization.  Each
-// step has two exchanges between workgroups:
-//   1. every workgroup publishes its best live candidate (norm^2, index) in
-//      its slot and then its step tag; every workgroup waits for all tags and
-//      takes the same global argmax p (ties -> lowest index);
-//   2. the owner of p publishes p's residual row and a row tag; the others
-//      wait for that tag and read the row.
-// Then every workgroup updates its rows exactly as the per-step kernels do
-// (same reductions and FMA order), so pivots, R and the final norms are
-// bitwise those of the per-step path.
+// keeps their residual rows in registers for the whole factorization.  After
+// the norms of a step, every workgroup publishes, in the buffers of the step's
+// parity, its best live candidate's residual row with the exact norm^2, then
+// one 64-bit word: pivot rank (46 bits), inverted index (11 bits), step marker
+// (7 bits).  Every workgroup polls all words of the step, takes the same
+// maximum (the pivot p), reads p's row from its owner's buffer and updates its
+// own rows exactly as the per-step kernels do (same reductions and FMA order),
+// so pivots, R and the final norms are bitwise those of the per-step path.
+// Each step has one exchange: the word carries the argmax data, and the pivot
+// row is already published when its word is seen.
 //
-// Ordering without cache maintenance.  Everything another workgroup reads
-// (slots, rows, tags) is written with device-scope relaxed atomic stores,
-// which complete at the device's coherence point, and read with device-scope
-// relaxed atomic loads, which are served from it.  A writer waits for its
-// stores to complete (s_waitcnt 0) and only then stores the tag; a reader
-// issues its data loads only after the loaded tag shows the value it waits
-// for, behind a compiler fence.  So a reader that sees a tag sees the data
-// published before it.  Agent-scope acquire/release fences would give the same
-// order with an L2 writeback or invalidation per workgroup and step, which
-// serialises within each XCD and costs far more than the step itself.
+// Ordering without cache maintenance (devsync.h): rows, norms and words are
+// device-coherent relaxed atomic stores and loads; a workgroup's row stores
+// complete (s_waitcnt 0) before its word is stored, and a reader loads a row
+// only after it has seen the word of that step.
 //
 // Every workgroup must be resident at once: the launcher uses at most one
-// workgroup per compute unit.  Each wait is bounded; past the bound the
-// workgroup raises DSK_FLAG_SYNC_TIMEOUT, sets the shared abort word, and
-// every workgroup leaves.  A workgroup is at most one step ahead of any other,
-// so slots and rows double-buffered by step parity never collide.
+// workgroup per compute unit.  A workgroup is at most one step ahead of any
+// other, so the two parities never collide (a buffer of parity t & 1 is
+// rewritten at step t + 2 only after every workgroup has published step
+// t + 1, i.e. has finished reading step t).  Each wait is bounded; past the
+// bound the workgroup raises DSK_FLAG_SYNC_TIMEOUT, sets the shared abort word,
+// and every workgroup leaves.
 constexpr long long SPIN_LIMIT = 1LL << 22;
-constexpr int TAGW = 32;          // one tag per 256-byte line
-constexpr int RMAX = 256 * 16;    // row buffer length: the widest row the kernel keeps (loads need no bounds branch)
+constexpr int TAGW = 32;              // one word per 256-byte line
+constexpr int RMAX = 256 * 16;        // widest row kept in registers (loads need no bounds branch)
+constexpr int RSTRIDE = RMAX + 32;    // a published row, its exact norm^2 at [RMAX], padding
 
-__device__ __forceinline__ long long ld_dev(const long long *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ unsigned long long pack_word(unsigned long long rank, long long idx, int marker) {
+  return (rank << 18) | ((unsigned long long)(~idx & 0x7FF) << 7) | (unsigned long long)(marker & 0x7F);
 }
-__device__ __forceinline__ double ld_dev(const double *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_dev(long long *p, long long v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_dev(double *p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-// this wave's earlier stores have completed before anything after this point
-__device__ __forceinline__ void stores_done() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_s_waitcnt(0);
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-}
-// bounded wait for *tag >= want; false on timeout or when another workgroup aborted
-__device__ __forceinline__ bool wait_tag(const long long *tag, long long want, int *abort_flag) {
+
+// bounded wait for the word of the current step (marker); 0 on timeout or abort
+__device__ __forceinline__ bool wait_word(const unsigned long long *wp, int marker, int *abort_flag,
+                                          unsigned long long &word) {
   long long spins = 0;
-  while (ld_dev(tag) < want) {
+  for (;;) {
+    word = (unsigned long long)ds::ld_dev(reinterpret_cast<const long long *>(wp));
+    if ((int)(word & 0x7F) == (marker & 0x7F)) break;
     if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || ++spins > SPIN_LIMIT) {
       atomicOr(abort_flag, 1);
       return false;
     }
     __builtin_amdgcn_s_sleep(2);
   }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");   // later loads stay after the tag load
+  ds::after_flag();
   return true;
 }
 
 template <int SPT, int CB>
 __global__ void __launch_bounds__(NT) k_cpqr_persist(const double *__restrict__ W, int64_t m, int64_t s, int k,
-                                                     double *slot_val, long long *slot_idx, double *rows,
-                                                     long long *tags, long long *rtag, int *abort_flag,
+                                                     unsigned long long *words, double *rows, int *abort_flag,
                                                      double *__restrict__ nu_final, double *__restrict__ Rk,
                                                      int64_t *__restrict__ piv, int *__restrict__ dflags) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int G = gridDim.x, gid = blockIdx.x;
   __shared__ double redv[NT / 64][CB];
   __shared__ double coef[CB];
-  __shared__ double bv[NT / 64];
-  __shared__ long long bi[NT / 64];
-  __shared__ long long p_sh;
-  __shared__ double nup_sh;
+  __shared__ unsigned long long bk[NT / 64];
+  __shared__ unsigned long long key_sh;
   __shared__ int stop_sh;
 
   int64_t cand[CB];
@@ -394,9 +388,9 @@ __global__ void __launch_bounds__(NT) k_cpqr_persist(const double *__restrict__ 
   }
   if (t == 0) stop_sh = 0;
 
-  // residual norms of the live rows (wave sums, then waves in order) -> nu,
-  // and this workgroup's best live candidate (ascending index, strict '>')
-  auto norms = [&](double &best, long long &bidx) {
+  // residual norms of the live rows (wave sums, then waves in order) -> nu, and
+  // this workgroup's best live candidate in pivot order
+  auto norms = [&](unsigned long long &brank, int &bc) {
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
       double a = 0.0;
@@ -413,98 +407,87 @@ __global__ void __launch_bounds__(NT) k_cpqr_persist(const double *__restrict__ 
       if (live[t] && !isfinite(v)) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_NONFINITE);
     }
     __syncthreads();
-    best = -1.0;
-    bidx = (long long)m;
+    brank = 0;
+    bc = -1;
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
       if (!live[c]) continue;
       nu[c] = coef[c];
-      if (nu[c] > best) { best = nu[c]; bidx = cand[c]; }
+      const unsigned long long r = nu_rank(nu[c]);
+      if (r > brank) { brank = r; bc = c; }   // ascending candidates: ties keep the lower index
     }
   };
 
-  double mybest;
-  long long myidx;
-  norms(mybest, myidx);
+  unsigned long long myrank;
+  int mybc;
+  norms(myrank, mybc);
   for (int step = 0; step < k; ++step) {
-    const long long want = (long long)step + 1;
     const int par = step & 1;
-    // ---- exchange 1: best candidate per workgroup, then the global argmax
-    if (t == 0) {
-      st_dev(&slot_val[(int64_t)par * G + gid], mybest);
-      st_dev(&slot_idx[(int64_t)par * G + gid], myidx);
-      stores_done();
-      st_dev(&tags[(int64_t)gid * TAGW], want);
+    // ---- publish: best row and its exact norm^2, then the word
+    double *mine = rows + ((int64_t)par * G + gid) * RSTRIDE;
+    if (mybc >= 0) {
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        if (c != mybc) continue;
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) ds::st_dev(&mine[t + NT * u], w[c][u]);
+        if (t == 0) ds::st_dev(&mine[RMAX], nu[c]);
+      }
     }
-    double best = -1.0;
-    long long bidx = (long long)m;
+    ds::stores_done();
+    __syncthreads();
+    if (t == 0) {
+      const long long myidx = mybc >= 0 ? cand[mybc] : (long long)m;
+      ds::st_dev(reinterpret_cast<long long *>(&words[((int64_t)par * G + gid) * TAGW]),
+                 (long long)pack_word(myrank, myidx, step + 1));
+    }
+    // ---- every word of this step; maximum of (rank, inverted index)
+    unsigned long long best = 0;
     for (int g = t; g < G; g += NT) {
-      if (!wait_tag(&tags[(int64_t)g * TAGW], want, abort_flag)) {
+      unsigned long long wd;
+      if (!wait_word(&words[((int64_t)par * G + g) * TAGW], step + 1, abort_flag, wd)) {
         stop_sh = 1;
         break;
       }
-      const double v = ld_dev(&slot_val[(int64_t)par * G + g]);
-      const long long ix = ld_dev(&slot_idx[(int64_t)par * G + g]);
-      if (v > best || (v == best && ix < bidx)) { best = v; bidx = ix; }
+      best = max(best, wd >> 7);
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(best, o, 64);
-      const long long oi = __shfl_xor(bidx, o, 64);
-      if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
-    }
-    if (lane == 0) { bv[wave] = best; bi[wave] = bidx; }
+    for (int o = 32; o > 0; o >>= 1) best = max(best, (unsigned long long)__shfl_xor((long long)best, o, 64));
+    if (lane == 0) bk[wave] = best;
     __syncthreads();
     if (t == 0) {
-      double b = bv[0];
-      long long ix = bi[0];
-      for (int ww = 1; ww < NT / 64; ++ww)
-        if (bv[ww] > b || (bv[ww] == b && bi[ww] < ix)) { b = bv[ww]; ix = bi[ww]; }
-      p_sh = ix;
-      nup_sh = b;
+      unsigned long long b = bk[0];
+      for (int ww = 1; ww < NT / 64; ++ww) b = max(b, bk[ww]);
+      key_sh = b;
     }
     __syncthreads();
     if (stop_sh) break;
-    const long long p = p_sh;
-    const double nup = nup_sh;
+    const unsigned long long key = key_sh;
+    const long long p = (key >> 11) ? (long long)(~key & 0x7FF) : (long long)m;
+    const int owner = (p < m) ? (int)(p / CB) : -1;
+    // ---- the pivot's residual row and exact norm^2 from its owner's buffer
+    double qv[SPT];
+    double nup = 0.0;
+    if (owner >= 0) {
+      const double *src = rows + ((int64_t)par * G + owner) * RSTRIDE;
+#pragma unroll
+      for (int u = 0; u < SPT; ++u) qv[u] = ds::ld_dev(&src[t + NT * u]);
+      nup = ds::ld_dev(&src[RMAX]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < SPT; ++u) qv[u] = 0.0;
+    }
     const double rpp = nup > 0.0 ? sqrt(nup) : 0.0;
     const double qscale = rpp > 0.0 ? 1.0 / rpp : 0.0;
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) {
+      const int64_t e = t + (int64_t)NT * u;
+      qv[u] = (e < s) ? qv[u] * qscale : 0.0;
+    }
     if (gid == 0 && t == 0) {
       piv[step] = p;
       if (p < m) Rk[(int64_t)step * m + p] = rpp;
       if (!(rpp > 0.0)) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_RANK_DEFICIENT);
-    }
-    // ---- exchange 2: the pivot's residual row, from its owner
-    const int owner = (p < m) ? (int)(p / CB) : -1;
-    double *rbuf = rows + (int64_t)par * RMAX;
-    double qv[SPT];
-    if (owner == gid) {
-#pragma unroll
-      for (int c = 0; c < CB; ++c) {
-        if (cand[c] != p) continue;
-#pragma unroll
-        for (int u = 0; u < SPT; ++u) {
-          const int64_t e = t + (int64_t)NT * u;
-          if (e < s) st_dev(&rbuf[e], w[c][u]);
-          qv[u] = w[c][u] * qscale;
-        }
-      }
-      stores_done();
-      __syncthreads();
-      if (t == 0) st_dev(rtag, want);
-    } else if (owner >= 0) {
-      if (t == 0 && !wait_tag(rtag, want, abort_flag)) stop_sh = 1;
-      __syncthreads();
-      if (stop_sh) break;
-#pragma unroll
-      for (int u = 0; u < SPT; ++u) {
-        const int64_t e = t + (int64_t)NT * u;    // < RMAX: in bounds; entries past s are not used
-        const double x = ld_dev(&rbuf[e]);
-        qv[u] = (e < s) ? x * qscale : 0.0;
-      }
-    } else {
-#pragma unroll
-      for (int u = 0; u < SPT; ++u) qv[u] = 0.0;
     }
 #pragma unroll
     for (int c = 0; c < CB; ++c)
@@ -532,7 +515,7 @@ __global__ void __launch_bounds__(NT) k_cpqr_persist(const double *__restrict__ 
 #pragma unroll
       for (int u = 0; u < SPT; ++u) w[c][u] = fma(-r, qv[u], w[c][u]);
     }
-    norms(mybest, myidx);
+    norms(myrank, mybc);
   }
   if (stop_sh) {
     if (t == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_SYNC_TIMEOUT);
@@ -544,8 +527,8 @@ __global__ void __launch_bounds__(NT) k_cpqr_persist(const double *__restrict__ 
     if (t == c && cand[c] < m) nu_final[cand[c]] = live[c] ? nu[c] : -1.0;
 }
 
-__global__ void k_tags_reset(long long *tags, int n, int *abort_flag) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) tags[i] = 0;
+__global__ void k_words_reset(unsigned long long *words, int n, int *abort_flag) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) words[i] = 0;
   if (threadIdx.x == 0) *abort_flag = 0;
 }
 
@@ -600,12 +583,12 @@ __global__ void __launch_bounds__(64 * SOLVE_WAVES) k_id_solve(const double *__r
 
 }  // namespace
 
-// Workspace of the persistent variant: slot values and indices (2 G each),
-// two residual rows (2 RMAX), G + 1 tags of one 256-byte line each, the abort word.
+// Workspace of the persistent variant: 2 G words of one 256-byte line each,
+// 2 G published rows (RSTRIDE doubles each), the abort word.
 size_t cpqr_persist_ws_bytes(int64_t m, int64_t s, int cu_count) {
   const int64_t G = (m + 3) / 4;
-  if (s > RMAX || G > cu_count) return 0;
-  return (size_t)2 * G * 8 * 2 + (size_t)2 * RMAX * 8 + (size_t)(G + 1) * TAGW * 8 + 256;
+  if (s > RMAX || G > cu_count || m > 2048) return 0;
+  return (size_t)2 * G * TAGW * 8 + (size_t)2 * G * RSTRIDE * 8 + 256;
 }
 
 int launch_cpqr(hipStream_t st, double *W, int64_t m, int64_t s, int k, double *nu0, double *nu1, double *Rk,
@@ -618,18 +601,15 @@ int launch_cpqr(hipStream_t st, double *W, int64_t m, int64_t s, int k, double *
     // where the per-step path leaves them
     const int G = (int)((m + 3) / 4);
     char *w = reinterpret_cast<char *>(pws);
-    long long *tags = reinterpret_cast<long long *>(w);                     // G tags + the row tag
-    long long *rtag = tags + (int64_t)G * TAGW;
-    int *abort_flag = reinterpret_cast<int *>(rtag + TAGW);
-    double *slot_val = reinterpret_cast<double *>(w + (size_t)(G + 1) * TAGW * 8 + 256);
-    long long *slot_idx = reinterpret_cast<long long *>(slot_val + 2 * G);
-    double *rows = reinterpret_cast<double *>(slot_idx + 2 * G);
+    unsigned long long *words = reinterpret_cast<unsigned long long *>(w);
+    double *rows = reinterpret_cast<double *>(w + (size_t)2 * G * TAGW * 8);
+    int *abort_flag = reinterpret_cast<int *>(rows + (size_t)2 * G * RSTRIDE);
     double *nu_final = ((k - 1) & 1) ? nu0 : nu1;
-    hipLaunchKernelGGL(k_tags_reset, dim3(1), dim3(256), 0, st, tags, (G + 1) * TAGW, abort_flag);
+    hipLaunchKernelGGL(k_words_reset, dim3(1), dim3(256), 0, st, words, 2 * G * TAGW, abort_flag);
     DSK_TRY(hipGetLastError());
 #define DSK_PERSIST(SPT_)                                                                                      \
-  hipLaunchKernelGGL((k_cpqr_persist<SPT_, 4>), dim3(G), dim3(NT), 0, st, (const double *)W, m, s, k, slot_val, \
-                     slot_idx, rows, tags, rtag, abort_flag, nu_final, Rk, piv, dflags)
+  hipLaunchKernelGGL((k_cpqr_persist<SPT_, 4>), dim3(G), dim3(NT), 0, st, (const double *)W, m, s, k, words, rows, \
+                     abort_flag, nu_final, Rk, piv, dflags)
     if (s <= 256 * 4) DSK_PERSIST(4);
     else if (s <= 256 * 8) DSK_PERSIST(8);
     else DSK_PERSIST(16);
