@@ -180,6 +180,8 @@ __global__ void __launch_bounds__(NT) k_core_eig(const double *__restrict__ G_in
   __shared__ int pivsh;
   __shared__ double pivd;
   __shared__ int rotated;
+  __shared__ int bigrot;
+  __shared__ int okw;
   const int t = threadIdx.x;
   const int grows = NT == 256 ? 64 : n;   // the 64-row blocked Cholesky reads padded rows
   for (int e = t; e < grows * ldg; e += NT) G[e] = 0.0;
@@ -199,7 +201,6 @@ __global__ void __launch_bounds__(NT) k_core_eig(const double *__restrict__ G_in
     // ell <= 64, one wave: register Cholesky of G + delta I, then X = L column-major over G
     double *Lb = dyn + 64 * ldg;
     double *dinv = Lb + 64 * wc::LDL;
-    __shared__ int okw;
     for (int i = t; i < ell; i += NT) G[i * ldg + i] += delta;
     __syncthreads();
     if (t < 64) {
@@ -208,19 +209,85 @@ __global__ void __launch_bounds__(NT) k_core_eig(const double *__restrict__ G_in
     }
     __syncthreads();
     if (!okw && t == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_NONFINITE);
-    for (int e = t; e < n * ldg; e += NT) {
-      const int c = e / ldg, r = e - (e / ldg) * ldg;
-      G[e] = (okw && c < ell && r < ell && r >= c) ? Lb[r * wc::LDL + c] : 0.0;
-    }
-    __syncthreads();
   } else {
     pivoted_chol_lds<NT>(G, ell, ldg, delta, perm, &pivsh, &pivd);
   }
-  // ---- one-sided Jacobi on the columns of X (entries past ell are zero and stay zero)
-  const int pr = t / LPP, pl = t % LPP;
   const double tolj = 4.0 * ell * U64;
   const double tol2 = tolj * tolj;   // rotate when gamma^2 > tol^2 alpha beta
   int sweeps = 0;
+  double *X = G;                     // columns of the factor, stride ldx
+  int ldx = ldg;
+  if constexpr (NT == 256) {
+    // ell <= 64: X = L column-major in a 16-byte aligned static array with
+    // contiguous 64-entry columns; each pair's 8 lanes move a column with four
+    // 16-byte accesses, which cover every LDS bank once (no conflicts between
+    // the pairs of a wave, whichever columns they hold)
+    __shared__ __align__(16) double Xc[64 * 64];
+    {
+      const double *Lb = dyn + 64 * ldg;
+      for (int e = t; e < 64 * 64; e += NT) {
+        const int c = e >> 6, r = e & 63;
+        Xc[e] = (okw && c < ell && r < ell && r >= c) ? Lb[r * wc::LDL + c] : 0.0;
+      }
+    }
+    __syncthreads();
+    const int pr = t >> 3, pl = t & 7;
+    // Convergence is quadratic: once a sweep's rotations all have |cos| <= 1e-7
+    // (gamma^2 <= 1e-14 alpha beta), the next sweep would leave every pair below
+    // about 1e-14 and change nothing the outputs resolve, so it is not run.
+    const double big2 = 1e-14;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+      if (t == 0) { rotated = 0; bigrot = 0; }
+      __syncthreads();
+      for (int r = 0; r < n - 1; ++r) {
+        if (pr < np) {
+          int p = rr_player(pr, r, n), q = rr_player(n - 1 - pr, r, n);
+          if (p > q) { const int x = p; p = q; q = x; }
+          double2 *xp = reinterpret_cast<double2 *>(Xc + p * 64) + pl;   // entries 2 pl + 16 u, +1
+          double2 *xq = reinterpret_cast<double2 *>(Xc + q * 64) + pl;
+          double2 wp[4], wq[4];
+          double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            wp[u] = xp[8 * u];
+            wq[u] = xq[8 * u];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            al = fma(wp[u].x, wp[u].x, al);
+            be = fma(wq[u].x, wq[u].x, be);
+            ga = fma(wp[u].x, wq[u].x, ga);
+            al = fma(wp[u].y, wp[u].y, al);
+            be = fma(wq[u].y, wq[u].y, be);
+            ga = fma(wp[u].y, wq[u].y, ga);
+          }
+          al = group_sum<8>(al);
+          be = group_sum<8>(be);
+          ga = group_sum<8>(ga);
+          if (ga != 0.0 && ga * ga > tol2 * (al * be)) {
+            double c, s;
+            jrot(al, be, ga, c, s);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              xp[8 * u] = make_double2(c * wp[u].x - s * wq[u].x, c * wp[u].y - s * wq[u].y);
+              xq[8 * u] = make_double2(s * wp[u].x + c * wq[u].x, s * wp[u].y + c * wq[u].y);
+            }
+            if (pl == 0) {
+              rotated = 1;
+              if (ga * ga > big2 * (al * be)) bigrot = 1;
+            }
+          }
+        }
+        __syncthreads();
+      }
+      sweeps = sweep + 1;
+      if (!rotated || !bigrot) break;
+    }
+    X = Xc;
+    ldx = 64;
+  } else {
+  // ---- one-sided Jacobi on the columns of X (entries past ell are zero and stay zero)
+  const int pr = t / LPP, pl = t % LPP;
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (t == 0) rotated = 0;
     __syncthreads();
@@ -261,11 +328,12 @@ __global__ void __launch_bounds__(NT) k_core_eig(const double *__restrict__ G_in
     sweeps = sweep + 1;
     if (!rotated) break;
   }
+  }
   const int grp = t >> 4, gl = t & 15;
   // ---- eigenvalues lambda_c = |x_c|^2 - delta, eigenvectors x_c / |x_c|
   for (int c = grp; c < ell; c += NT / 16) {
     double s2 = 0.0;
-    for (int i = gl; i < ell; i += 16) s2 = fma(G[c * ldg + i], G[c * ldg + i], s2);
+    for (int i = gl; i < ell; i += 16) s2 = fma(X[c * ldx + i], X[c * ldx + i], s2);
 #pragma unroll
     for (int o = 8; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, 16);
     if (gl == 0) nrm2[c] = s2;
@@ -287,7 +355,7 @@ __global__ void __launch_bounds__(NT) k_core_eig(const double *__restrict__ G_in
   for (int e = t; e < ell * ell; e += NT) {
     const int c = e / ell, r = e - (e / ell) * ell;   // column c of X, row r (pivot order)
     const double nc = nrm2[c];
-    Uout[perm[r] * ell + rank_of[c]] = nc > 0.0 ? G[c * ldg + r] / sqrt(nc) : 0.0;
+    Uout[perm[r] * ell + rank_of[c]] = nc > 0.0 ? X[c * ldx + r] / sqrt(nc) : 0.0;
   }
 }
 
