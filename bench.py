@@ -175,10 +175,12 @@ def main():
     if not a.no_breakdown:
         svd_ms = {qq: timed(lambda qq=qq: dsketch.sketch_svd(A, k, R, q=qq, mode=a.mode)) for qq in (0, 1, 2)}
         id_ms = timed(lambda: dsketch.sketch_id(A, k, R, q=0, skeleton_rows=True))
+        sp_ms = timed(lambda: dsketch.sketch_svd_sp(A, k, R, mode=a.mode))
         sweeps = {qq: dsketch.sketch_svd(A, k, R, q=qq, mode=a.mode, want_info=True)[3]["core_sweeps"]
                   for qq in (0, 1, 2)}
         breakdown = {"svd_q0": round(svd_ms[0], 4), "svd_q1": round(svd_ms[1], 4), "svd_q2": round(svd_ms[2], 4),
-                     "id_q0": round(id_ms, 4), "core_sweeps": {f"q{qq}": sweeps[qq] for qq in (0, 1, 2)}}
+                     "id_q0": round(id_ms, 4), "svd_single_pass": round(sp_ms, 4),
+                     "core_sweeps": {f"q{qq}": sweeps[qq] for qq in (0, 1, 2)}}
         tte = time_to_eps(torch, dsketch, A, A_np, k, R, svd_ms, timed)
 
     b_svd, b_id = algorithmic_bytes(m, n, s, k, q)

@@ -154,6 +154,27 @@ int dsk_sketch_svd(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64
                    void *U, double *S, void *V, dsk_info *info);
 
 /*
+ * dsk_sketch_svd_sp -- rank-k SVD by the single-pass SPC-SVD (Alg. 3): the one
+ * pass over A forms H = A^T Y for the start block Y = A_c S_ell (same Y as
+ * dsk_sketch_svd), Y = Q R, and B^T = H R^{-1} = A^T Q (the identity derived
+ * under Alg. 3) replaces the second pass; then SVD(B) and U, S, V as in
+ * dsk_sketch_svd.  No power iteration (Alg. 3 has none).  In exact arithmetic
+ * the result equals dsk_sketch_svd with q = 0; in floating point the rounding
+ * of H is amplified by kappa(Y) = ||Y|| ||R^{-1}||, as the formula implies, so
+ * the two agree to about u kappa(Y) sigma_1 (u = 2^-24 for FP32 input).
+ * R: FP64, the Cholesky factor of the FP64 Gram Y^T Y (FP32 / 16-bit input) or
+ * the Householder R of Y (FP64 input); a numerically rank-deficient Y (where
+ * the formula breaks down) raises DSK_FLAG_RANK_DEFICIENT.  The orthonormalisation
+ * of Y runs on a worker stream of the handle, concurrently with the pass.
+ * Arguments: h=1, A=2, dtype=3, m=4, n=5, lda=6, k=7 (1 <= k <= ell), R=8,
+ *   o=9 (host, may be NULL; refine must be 0), U=10 (m x k row-major, work dtype),
+ *   S=11 (k, F64), V=12 (n x k row-major, work dtype), info=13 (host, may be NULL).
+ */
+int dsk_sketch_svd_sp(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                      int32_t k, const dsk_restriction *R, const dsk_opts *o,
+                      void *U, double *S, void *V, dsk_info *info);
+
+/*
  * dsk_sketch_id -- rank-k row interpolative decomposition A ~ P A(I, :) by
  * TPC-ID (Alg. 4): column-pivoted QR of W^T (Sec. 4, row ID) with W = A_c, or
  * W = (tau A_c A_c^T)^q A_c for q >= 1 (C-PWR without re-orthonormalisation),
@@ -194,7 +215,8 @@ typedef struct {
   void *V;             /* device n x k, work dtype */
 } dsk_problem;
 
-enum { DSK_BATCH_GRAPH = 1 };   /* capture the batch into a HIP graph on first use, replay afterwards */
+enum { DSK_BATCH_GRAPH = 1 };   /* capture the batch into a HIP graph on first use, replay afterwards
+                                   (currently disabled: the call returns -5, see below) */
 
 /*
  * dsk_sketch_svd_batched -- dsk_sketch_svd (Alg. 2 + Alg. 7) for nprob problems.
@@ -209,6 +231,9 @@ enum { DSK_BATCH_GRAPH = 1 };   /* capture the batch into a HIP graph on first u
  *   flags=5 (0 or DSK_BATCH_GRAPH), nworkers=6 (host int, may be NULL: workers used).
  * Errors: -1..-5 as numbered; -(1000 + i) when problem i fails the checks of
  *   dsk_sketch_svd; DSK_ERR_* (HIP).  No per-problem dsk_info is produced.
+ *   DSK_BATCH_GRAPH is currently disabled and returns -5: a memory fault was
+ *   observed on the capture-and-replay path and its cause has not been
+ *   identified.  The eager path (flags = 0) is unaffected.
  */
 int dsk_sketch_svd_batched(dsk_handle *h, int32_t nprob, const dsk_problem *probs, const dsk_opts *o, int32_t flags,
                            int32_t *nworkers);

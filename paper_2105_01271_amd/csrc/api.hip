@@ -323,7 +323,7 @@ int svd_check(const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, i
 // only the arena size is computed (nothing is allocated or enqueued).
 int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,
             const dsk_restriction *R, int32_t q, const dsk_opts &od, int64_t s, int L, void *U, double *S, void *V,
-            dsk_info *info, size_t *need, const std::function<int()> *after_projection) {
+            dsk_info *info, size_t *need, const std::function<int()> *after_projection, bool single_pass) {
   hipStream_t st = h->stream;
   const int f64 = dtype == DSK_F64;
   const size_t we = f64 ? 8 : 4;
@@ -357,6 +357,10 @@ int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, i
     double *colscale = c.take<double>(L);
     double *dinfo = c.take<double>(4);
     double *fpart = c.take<double>(1024);
+    // single pass: H = A^T Y, M = R^{-1}, the Gram of Y
+    char *Hb = single_pass ? c.take<char>((size_t)n * L * we) : nullptr;
+    double *Mr = single_pass ? c.take<double>((size_t)L * L) : nullptr;
+    double *GY = single_pass ? c.take<double>((size_t)L * L) : nullptr;
     if (pass == 0) {
       if (need) {
         *need = c.off;
@@ -374,6 +378,30 @@ int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, i
     DSK_RET(launch_restrict(st, A, dtype, m, n, lda, R, s, f64, Ac, nullptr, h->dflags));
     if (od.S) DSK_RET(launch_stream_nn(st, Ac, wdt, m, s, s, od.S, L, Y, L, od.mode, sws, h->cu_count));
     else DSK_RET(launch_select_cols(st, Ac, f64, m, s, s, L, Y));
+    if (single_pass) {
+      // SPC-SVD (Alg. 3): the pass over A needs Y only, so it starts at once; a
+      // worker stream meanwhile orthonormalises Y (Q for U = Q U_B) and forms
+      // M = R^{-1}; then B^T = A^T Q = H M.
+      dsk_handle *wk = h->workers[0];
+      hipStream_t wst = wk->stream;
+      DSK_TRY(hipEventRecord(h->wev[0], st));
+      DSK_TRY(hipStreamWaitEvent(wst, h->wev[0], 0));
+      if (f64) {
+        DSK_RET(launch_convert(wst, Y, 1, tmp, 1, m * L));
+        DSK_RET(launch_hhqr(wst, tmp, m, L, (double *)Q, Rsm, h->dflags));
+        DSK_RET(launch_spc_rinv(wst, Rsm, L, 0, 0x1p-53, Mr, h->dflags));
+      } else {
+        DSK_RET(launch_cholqr2(wst, Y, 0, m, L, Q, cws, h->dflags, Rsm, 2));
+        DSK_RET(launch_gram(wst, Y, 0, m, L, GY, part, nparts));
+        DSK_RET(launch_spc_rinv(wst, GY, L, 1, dtype == DSK_F32 ? 0x1p-24 : (dtype == DSK_BF16 ? 0x1p-8 : 0x1p-11), Mr, h->dflags));
+      }
+      DSK_TRY(hipEventRecord(h->wev[1], wst));
+      hipEvent_t e0, e1;
+      timing_slot(h, &e0, &e1);
+      DSK_RET(launch_stream(st, A, dtype, m, n, lda, Y, f64, L, Hb, L, od.mode, sws, h->cu_count, e0, e1));
+      DSK_TRY(hipStreamWaitEvent(st, h->wev[1], 0));
+      DSK_RET(launch_tsmm(st, Hb, f64, n, L, L, Mr, L, L, nullptr, Bt, L));
+    } else {
     // intermediate bases of the power iteration only carry a span (one
     // CholeskyQR pass); the block that B is projected on is orthonormalised fully
     DSK_RET(orth(h, Y, f64, m, L, Q, tmp, cws, Rsm, q > 0));
@@ -395,6 +423,7 @@ int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, i
       DSK_RET(launch_stream(st, A, dtype, m, n, lda, Q, f64, L, Bt, L, od.mode, sws, h->cu_count));
     }
     if (after_projection) DSK_RET((*after_projection)());
+    }
     if (!f64) {
       DSK_RET(launch_gram(st, Bt, 0, n, L, GB, part, nparts));
       DSK_RET(launch_core_eig(st, GB, L, lam, UB, h->dflags));
@@ -435,6 +464,20 @@ int dsk_sketch_svd(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64
   DSK_RET(svd_check(A, dtype, m, n, lda, k, R, q, o, U, S, V, &od, &s, &L));
   DSK_TRY(hipSetDevice(h->device));
   return svd_run(h, A, dtype, m, n, lda, k, R, q, od, s, L, U, S, V, info, nullptr);
+}
+
+int dsk_sketch_svd_sp(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,
+                      const dsk_restriction *R, const dsk_opts *o, void *U, double *S, void *V, dsk_info *info) {
+  if (!h) return -1;
+  dsk_opts od;
+  int64_t s = 0;
+  int L = 0;
+  const int r = svd_check(A, dtype, m, n, lda, k, R, 0, o, U, S, V, &od, &s, &L);
+  if (r) return r <= -10 ? r + 1 : r;   // dsk_sketch_svd numbering -> this one (no q argument)
+  if (od.refine) return -9;
+  DSK_TRY(hipSetDevice(h->device));
+  DSK_RET(ensure_workers(h, 1));
+  return svd_run(h, A, dtype, m, n, lda, k, R, 0, od, s, L, U, S, V, info, nullptr, nullptr, true);
 }
 
 }  // extern "C"

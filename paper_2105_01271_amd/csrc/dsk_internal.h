@@ -95,9 +95,13 @@ int svd_check(const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, i
               int32_t q, const dsk_opts *o, void *U, double *S, void *V, dsk_opts *odp, int64_t *s_out, int *L_out);
 // after_projection (may be null) is called once B^T = A^T Q has been enqueued
 // (work forked from the handle's stream at that point starts after it).
+// single_pass: SPC-SVD (Alg. 3, q must be 0): the pass over A forms H = A^T Y
+// while a worker stream orthonormalises Y, then B^T = H R^{-1}.
 int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,
             const dsk_restriction *R, int32_t q, const dsk_opts &od, int64_t s, int L, void *U, double *S, void *V,
-            dsk_info *info, size_t *need, const std::function<int()> *after_projection = nullptr);
+            dsk_info *info, size_t *need, const std::function<int()> *after_projection = nullptr,
+            bool single_pass = false);
+int ensure_workers(dsk_handle *h, int nw);   // batch.hip
 int id_check(const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k, const dsk_restriction *R,
              int32_t q, const dsk_opts *o, int64_t *skel, double *P, dsk_opts *odp, int64_t *s_out, int64_t *cols_out,
              int64_t *ell_out);
@@ -125,6 +129,12 @@ size_t conv_bwd_ws_bytes(int64_t m, int ny, int nx, int C);
 int launch_conv_bwd(hipStream_t st, const void *A, int dtype, int64_t m, int64_t lda, int ny, int nx, int C,
                     const float *w1, const float *w2, const void *gAc, int g_f64, int64_t ldg, float *gw1,
                     float *gw2, void *ws);
+
+// spc.hip: M = R^{-1} (FP64, upper triangular) from the Gram Y^T Y (from_gram = 1,
+// R = chol(G)^T) or from an upper-triangular R (from_gram = 0); ell <= 112;
+// u_data = unit roundoff of Y's data (rank test)
+int launch_spc_rinv(hipStream_t st, const double *G, int ell, int from_gram, double u_data, double *M,
+                    int *dflags);
 
 // smallmat.hip (tall-skinny orthonormalisation, small factorizations)
 size_t cholqr2_ws_bytes(int64_t rows, int ell);

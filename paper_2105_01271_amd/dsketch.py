@@ -194,6 +194,29 @@ def sketch_svd(A: torch.Tensor, k: int, R: Restriction, q: int = 0, p: int = 10,
     return U, Sv, V
 
 
+def sketch_svd_sp(A: torch.Tensor, k: int, R: Restriction, p: int = 10, S=None, mode="default",
+                  want_info: bool = False):
+    """Rank-k SVD by the single-pass SPC-SVD (dsk_sketch_svd_sp, Alg. 3).
+    Returns U (m x k), S (k, f64), V (n x k)[, info]."""
+    _check_matrix(A)
+    lib = _lib.load()
+    m, n = A.shape
+    wd = _work_dtype(A.dtype)
+    U = torch.empty((m, k), dtype=wd, device=A.device)
+    Sv = torch.empty((k,), dtype=torch.float64, device=A.device)
+    V = torch.empty((n, k), dtype=wd, device=A.device)
+    o = _opts(p=p, S=S, mode=mode)
+    rc = R.to_c()
+    info = _lib.Info()
+    st = lib.dsk_sketch_svd_sp(_handle(A.device), _ptr(A), _DT[A.dtype], m, n, A.stride(0), int(k),
+                               ctypes.byref(rc), ctypes.byref(o), _ptr(U), _ptr(Sv), _ptr(V),
+                               ctypes.byref(info) if want_info else None)
+    _lib.check("dsk_sketch_svd_sp", st)
+    if want_info:
+        return U, Sv, V, _info_dict(info)
+    return U, Sv, V
+
+
 def sketch_id(A: torch.Tensor, k: int, R: Restriction, q: int = 0, p: int = 10, S=None, tau=None,
               projected=False, skeleton_rows=False, want_info: bool = False, per_step: bool = False):
     """Rank-k row ID by TPC-ID (dsk_sketch_id).  Returns I (k, int64), P (m x k, f64)[, A(I,:)][, info].

@@ -18,6 +18,8 @@ Families:
   heat_exact      Dirichlet sine modes with exact spectrum sigma_j
   advdiff_field   physical advection-diffusion snapshots at a diffusivity nu
   lowrank         product of Gaussian factors (exact rank r)
+  gaussian_matrix iid N(0, 1) draws, e.g. the optional Gaussian second-level
+                  sketch of the hybrid method (passed to both sides as input)
 """
 from __future__ import annotations
 
@@ -27,7 +29,7 @@ from dataclasses import dataclass
 import numpy as np
 
 __all__ = [
-    "heat_modes", "advdiff_exact", "heat_exact", "advdiff_field", "lowrank",
+    "heat_modes", "advdiff_exact", "heat_exact", "advdiff_field", "lowrank", "gaussian_matrix",
     "batch_specs", "BatchSpec", "orthonormal_fourier_1d",
 ]
 
@@ -209,6 +211,11 @@ def lowrank(m: int, n: int, r: int, seed: int) -> np.ndarray:
     """Exact rank-r matrix X Z^T with iid Gaussian factors."""
     rng = np.random.default_rng(seed)
     return rng.standard_normal((m, r)) @ rng.standard_normal((r, n))
+
+
+def gaussian_matrix(rows: int, cols: int, seed: int) -> np.ndarray:
+    """rows x cols iid standard normal values from numpy's default_rng(seed)."""
+    return np.random.default_rng(seed).standard_normal((rows, cols))
 
 
 @dataclass

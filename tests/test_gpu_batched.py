@@ -74,6 +74,18 @@ def test_batched_equals_single_calls_and_oracle():
         assert err <= (1e-10 if A.dtype == torch.float64 else TOL32)
 
 
+def test_graph_flag_is_rejected_while_disabled():
+    # the capture-and-replay path is switched off: the flag is refused before anything is enqueued
+    say("graph flag rejected")
+    batch = _batch(2, seed=3100)
+    runner = dsk().BatchedSVD(_problems(batch))
+    with pytest.raises(dsk()._lib.DskError) as e:
+        runner(graph=True)
+    assert e.value.status == -5
+
+
+@pytest.mark.skip(reason="graph capture and replay is disabled (DSK_BATCH_GRAPH returns -5): this test ended in "
+                         "a GPU memory fault on some runs and the cause has not been identified")
 def test_graph_replays_match_eager_results():
     say("graph replay")
     batch = _batch(9, seed=3000)
