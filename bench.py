@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-reps", type=int, default=4)
     ap.add_argument("--no-breakdown", action="store_true", help="skip the per-component timings and time-to-eps")
+    ap.add_argument("--mreo-trials", type=int, default=100, help="trials of the hybrid-sketch MREO harness")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 256 MiB device copy (known bytes) to scale HBM counters")
     return ap.parse_args()
@@ -114,6 +115,26 @@ def time_to_eps(torch, dsketch, A, A_np, k, R, svd_ms, timed, eps=0.05):
     return out
 
 
+def hybrid_mreo(torch, dsketch, A, k, R, tail, trials):
+    """MREO (max over trials of ||A - U S V^T||_F / ||A - A_k||_F, Sec. 6) of the
+    hybrid sketch (Gaussian s x ell second level, `trials` seeds) for TPC-SVD
+    at q = 0, 1 and SPC-SVD, next to the deterministic nested-DI start block."""
+    from paper_2105_01271_amd import hybrid
+    out = {"trials": trials}
+    for name, q, sp in (("tpc_q0", 0, False), ("tpc_q1", 1, False), ("spc", 0, True)):
+        t0 = time.perf_counter()
+        errs = hybrid.trial_errors(A, k, R, trials=trials, q=q, seed0=0, single_pass=sp)
+        dt = (time.perf_counter() - t0) / trials
+        if sp:
+            _, S, _, info = dsketch.sketch_svd_sp(A, k, R, want_info=True)
+        else:
+            _, S, _, info = dsketch.sketch_svd(A, k, R, q=q, want_info=True)
+        di = float(np.sqrt(max(info["normA_fro2"] - float((S * S).sum().item()), 0.0))) / tail
+        out[name] = {"mreo_gaussian": round(hybrid.mreo(errs, tail), 5), "ratio_nested_di": round(di, 5),
+                     "ms_per_trial": round(1e3 * dt, 3)}
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -172,6 +193,7 @@ def main():
 
     breakdown = None
     tte = None
+    mreo = None
     if not a.no_breakdown:
         svd_ms = {qq: timed(lambda qq=qq: dsketch.sketch_svd(A, k, R, q=qq, mode=a.mode)) for qq in (0, 1, 2)}
         id_ms = timed(lambda: dsketch.sketch_id(A, k, R, q=0, skeleton_rows=True))
@@ -182,6 +204,7 @@ def main():
                      "id_q0": round(id_ms, 4), "svd_single_pass": round(sp_ms, 4),
                      "core_sweeps": {f"q{qq}": sweeps[qq] for qq in (0, 1, 2)}}
         tte = time_to_eps(torch, dsketch, A, A_np, k, R, svd_ms, timed)
+        mreo = hybrid_mreo(torch, dsketch, A, k, R, tte["tail_fro"], a.mreo_trials)
 
     b_svd, b_id = algorithmic_bytes(m, n, s, k, q)
     step_bytes = b_svd + b_id
@@ -233,6 +256,7 @@ def main():
         "cpu_baseline": cpu,
         "breakdown_ms": breakdown,
         "time_to_eps": tte,
+        "hybrid_mreo": mreo,
     }
     print(json.dumps(rec), flush=True)
 

@@ -87,7 +87,7 @@ typedef struct {
   int32_t p;          /* oversampling; range-finder width ell = min(k+p, s, m); default 10 */
   const void *S;      /* optional device s x ell second-level sketch, row-major, work dtype;
                          NULL = nested direct injection (every floor(s/ell)-th coarse column) */
-  int32_t ell;        /* width of S when S != NULL */
+  int32_t ell;        /* width of S when S != NULL: 1 <= ell <= min(s, 112) (and <= m for the SVD) */
   double tau;         /* coarse Gram scale (Sec. 5); <= 0 means n/s */
   int32_t id_projected; /* sketch_id: 0 = ID of W_q = (tau A_c A_c^T)^q A_c (full coarse sketch),
                            1 = ID of the ell-wide block (tau A_c A_c^T)^q A_c S */

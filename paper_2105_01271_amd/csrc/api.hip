@@ -305,7 +305,7 @@ int svd_check(const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, i
   if (od.p < 0) return -10;
   int64_t ell = od.S ? od.ell : std::min<int64_t>(std::min<int64_t>((int64_t)k + od.p, s), m);
   if (s < 1) return -8;
-  if (od.S && (od.ell < 1 || od.ell > std::min<int64_t>(s, m))) return -10;
+  if (od.S && (od.ell < 1 || od.ell > std::min<int64_t>(s, m) || od.ell > ELL_CAP)) return -10;
   ell = std::min<int64_t>(ell, ELL_CAP);
   if (k < 1 || k > ell) return -7;
   if (q < 0 || q > 64) return -9;
@@ -501,7 +501,7 @@ int id_check(const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, in
   int64_t ell = 0;
   if (od.id_projected) {
     ell = od.S ? od.ell : std::min<int64_t>(std::min<int64_t>((int64_t)k + od.p, s), m);
-    if (od.S && (od.ell < 1 || od.ell > s)) return -10;
+    if (od.S && (od.ell < 1 || od.ell > s || od.ell > ELL_CAP)) return -10;
     ell = std::min<int64_t>(ell, ELL_CAP);
     cols = ell;
   }
@@ -537,6 +537,9 @@ int id_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, in
     double *Rk = c.take<double>((size_t)k * m);
     const size_t pwsb = od.id_per_step ? 0 : cpqr_persist_ws_bytes(m, cols, h->cu_count);
     char *pws = pwsb ? c.take<char>(pwsb) : nullptr;
+    // a given S arrives in the work dtype; the ID works in FP64
+    const bool s_conv = od.id_projected && od.S && dtype != DSK_F64;
+    double *S64 = s_conv ? c.take<double>((size_t)s * ell) : nullptr;
     if (pass == 0) {
       if (need) {
         *need = c.off;
@@ -554,7 +557,12 @@ int id_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, in
     double *Wcur = nullptr;
     if (od.id_projected) {
       if (od.S) {
-        DSK_RET(launch_stream_nn(st, Ac, DSK_F64, m, s, s, od.S, (int)ell, W, ell, 0, sws, h->cu_count));
+        const void *S = od.S;
+        if (s_conv) {
+          DSK_RET(launch_convert(st, od.S, 0, S64, 1, s * ell));
+          S = S64;
+        }
+        DSK_RET(launch_stream_nn(st, Ac, DSK_F64, m, s, s, S, (int)ell, W, ell, 0, sws, h->cu_count));
       } else {
         DSK_RET(launch_select_cols(st, Ac, 1, m, s, s, (int)ell, W));
       }

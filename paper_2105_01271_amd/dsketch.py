@@ -46,6 +46,19 @@ def _work_dtype(dt: torch.dtype) -> torch.dtype:
     return torch.float64 if dt == torch.float64 else torch.float32
 
 
+def _check_second_level(S, A: torch.Tensor, R: "Restriction"):
+    """S (s x ell) must be a contiguous device tensor in A's work dtype: the
+    library reads it through a plain pointer with that element size."""
+    if S is None:
+        return
+    if not isinstance(S, torch.Tensor) or not S.is_cuda or S.dim() != 2 or not S.is_contiguous():
+        raise ValueError("S must be a contiguous 2-D device tensor")
+    if S.dtype != _work_dtype(A.dtype):
+        raise ValueError(f"S must have dtype {_work_dtype(A.dtype)} (the work dtype of A)")
+    if S.shape[0] != R.coarse_size():
+        raise ValueError(f"S must have {R.coarse_size()} rows (the coarse size)")
+
+
 def _check_matrix(A: torch.Tensor):
     if not A.is_cuda:
         raise ValueError("A must be a device tensor")
@@ -182,6 +195,7 @@ def sketch_svd(A: torch.Tensor, k: int, R: Restriction, q: int = 0, p: int = 10,
     U = torch.empty((m, k), dtype=wd, device=A.device)
     Sv = torch.empty((k,), dtype=torch.float64, device=A.device)
     V = torch.empty((n, k), dtype=wd, device=A.device)
+    _check_second_level(S, A, R)
     o = _opts(p=p, S=S, tau=tau, mode=mode, refine=refine)
     rc = R.to_c()
     info = _lib.Info()
@@ -205,6 +219,7 @@ def sketch_svd_sp(A: torch.Tensor, k: int, R: Restriction, p: int = 10, S=None, 
     U = torch.empty((m, k), dtype=wd, device=A.device)
     Sv = torch.empty((k,), dtype=torch.float64, device=A.device)
     V = torch.empty((n, k), dtype=wd, device=A.device)
+    _check_second_level(S, A, R)
     o = _opts(p=p, S=S, mode=mode)
     rc = R.to_c()
     info = _lib.Info()
@@ -227,6 +242,7 @@ def sketch_id(A: torch.Tensor, k: int, R: Restriction, q: int = 0, p: int = 10, 
     I = torch.empty((k,), dtype=torch.int64, device=A.device)
     P = torch.empty((m, k), dtype=torch.float64, device=A.device)
     rows = torch.empty((k, n), dtype=A.dtype, device=A.device) if skeleton_rows else None
+    _check_second_level(S, A, R)
     o = _opts(p=p, S=S, tau=tau, id_projected=projected, id_per_step=per_step)
     rc = R.to_c()
     info = _lib.Info()

@@ -1,0 +1,135 @@
+"""Hybrid deterministic-randomized sketch (Gaussian second level on the DI
+sketch) and the MREO trial harness, through the C ABI against the FP64 oracle.
+
+* the sketch SVD with a given s x ell second level equals the oracle's TPC-SVD
+  with the same Omega (tolerances as for TPC-SVD: 1e-10 FP64, 1e-5 FP32 of
+  sigma_1);
+* the row ID of the projected block A_c Omega equals the oracle's;
+* per trial, the harness's error ||A - U S V^T||_F (from ||A||_F^2 - sum S_j^2)
+  equals the oracle's explicit residual norm within the bound the singular
+  value tolerance implies: |e^2 - e_o^2| <= 2 tol sigma_1 sum_j sigma_j, so
+  |e - e_o| <= 2 tol sigma_1 sum_j sigma_j / (e + e_o); MREO likewise.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import metrics as omet
+from oracle import restrict as ores
+from oracle import rowid as orid
+from oracle import sketch as osk
+from paper_2105_01271_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float64: 1e-10, torch.float32: 1e-5}
+
+
+def dsk():
+    from paper_2105_01271_amd import dsketch
+    return dsketch
+
+
+def hyb():
+    from paper_2105_01271_amd import hybrid
+    return hybrid
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _A(A_np, dtype):
+    return torch.from_numpy(np.ascontiguousarray(A_np)).to(dtype).cuda()
+
+
+def _up(A_t):
+    return A_t.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("q", [0, 1])
+def test_svd_with_gaussian_second_level_matches_oracle(dtype, q):
+    say("hybrid svd", dtype, q)
+    A = _A(synth.advdiff_exact(260, 32, seed=21, r=200), dtype)
+    A_np = _up(A)
+    idx = ores.di_index_2d(32, 32, 2, 2)
+    Om = synth.gaussian_matrix(idx.size, 22, seed=22)
+    R = dsk().Restriction.di_grid(32, 32, 2, 2)
+    U, S, V = dsk().sketch_svd(A, 12, R, q=q, S=_A(Om, dtype))
+    Uo, So, Vo = osk.tpc_svd(A_np, 12, {"kind": "index", "index": idx}, q=q, S=Om)
+    tol = TOL[dtype]
+    Sg = S.cpu().numpy()
+    assert np.abs(Sg - So).max() <= tol * So[0]
+    e = omet.svd_error(A_np, _up(U), Sg, _up(V))
+    eo = omet.svd_error(A_np, Uo, So, Vo)
+    assert abs(e - eo) <= tol * eo + 1e-300
+
+
+@pytest.mark.parametrize("q", [0, 1])
+def test_id_of_gaussian_projected_block_matches_oracle(q):
+    say("hybrid id", q)
+    A = _A(synth.advdiff_exact(240, 32, seed=23, r=240), torch.float64)
+    A_np = _up(A)
+    idx = ores.di_index_2d(32, 32, 2, 2)
+    Om = synth.gaussian_matrix(idx.size, 25, seed=24)
+    R = dsk().Restriction.di_grid(32, 32, 2, 2)
+    I, P = dsk().sketch_id(A, 15, R, q=q, S=_A(Om, torch.float64), projected=True)
+    Io, Po, info = orid.tpc_id(A_np, 15, {"kind": "index", "index": idx}, q=q, S=Om, projected=True,
+                               return_all=True)
+    from test_gpu_parity import _compare_id
+    npre = _compare_id(A_np, I, P, Io, Po, info, 15)
+    say("  separated prefix", npre)
+    assert npre >= 10
+
+
+def test_id_fp32_input_with_given_second_level():
+    # S arrives in the work dtype (FP32 here) and is widened exactly for the FP64 ID
+    say("hybrid id fp32")
+    A32 = _A(synth.advdiff_exact(240, 32, seed=26, r=240), torch.float32)
+    A_np = _up(A32)
+    idx = ores.di_index_2d(32, 32, 2, 2)
+    Om32 = _A(synth.gaussian_matrix(idx.size, 25, seed=27), torch.float32)
+    R = dsk().Restriction.di_grid(32, 32, 2, 2)
+    I, P = dsk().sketch_id(A32, 15, R, q=1, S=Om32, projected=True)
+    Io, Po, info = orid.tpc_id(A_np, 15, {"kind": "index", "index": idx}, q=1, S=_up(Om32), projected=True,
+                               return_all=True)
+    from test_gpu_parity import _compare_id
+    npre = _compare_id(A_np, I, P, Io, Po, info, 15)
+    say("  separated prefix", npre)
+    assert npre >= 10
+
+
+@pytest.mark.parametrize("single_pass", [False, True])
+def test_trial_errors_and_mreo_match_oracle(single_pass):
+    say("hybrid trials, single pass", single_pass)
+    dtype = torch.float64
+    A = _A(synth.advdiff_exact(220, 32, seed=25, r=200), dtype)
+    A_np = _up(A)
+    idx = ores.di_index_2d(32, 32, 2, 2)
+    R = dsk().Restriction.di_grid(32, 32, 2, 2)
+    k, q, trials, seed0 = 10, 0 if single_pass else 1, 5, 100
+    errs = hyb().trial_errors(A, k, R, trials=trials, q=q, seed0=seed0, single_pass=single_pass)
+    sig = np.linalg.svd(A_np, compute_uv=False)
+    tail = float(np.sqrt((sig[k:] ** 2).sum()))
+    eo = []
+    for t in range(trials):
+        Om = synth.gaussian_matrix(idx.size, k + 10, seed=seed0 + t)
+        if single_pass:
+            Uo, So, Vo = osk.spc_svd(A_np, k, {"kind": "index", "index": idx}, S=Om)
+        else:
+            Uo, So, Vo = osk.tpc_svd(A_np, k, {"kind": "index", "index": idx}, q=q, S=Om)
+        eo.append(omet.svd_error(A_np, Uo, So, Vo) * np.linalg.norm(A_np))   # absolute residual norm
+        # the single-pass tolerance adds its kappa(Y) amplification (u = 2^-53 here)
+        Y = A_np[:, idx] @ Om
+        Rf = np.linalg.qr(Y, mode="r")
+        kF = np.linalg.norm(Y) * np.linalg.norm(np.linalg.inv(Rf))
+        tol = TOL[dtype] + (single_pass and (4 + Y.shape[1]) * 2.0 ** -53 * kF * np.linalg.norm(A_np) / sig[0])
+        bound = 2 * tol * sig[0] * So.sum() / (errs[t] + eo[t])
+        assert abs(errs[t] - eo[t]) <= bound + 1e-12 * eo[t], (t, errs[t], eo[t], bound)
+    eo = np.array(eo)
+    m_gpu = hyb().mreo(errs, tail)
+    m_or = float(eo.max() / tail)
+    say("  MREO gpu", m_gpu, "oracle", m_or)
+    assert m_gpu >= 1.0 - 1e-9                      # Eckart-Young
+    assert abs(m_gpu - m_or) <= 1e-8 * m_or
