@@ -182,6 +182,24 @@ def spc_id_err(A: np.ndarray, R: dict, mc: int, tau_bounds=(1e-6, 1e6), Ac=None)
     return float(res.fun), float(np.exp(res.x))
 
 
+def spc_id_err_curve(A: np.ndarray, R: dict, mc: int, taus, Ac=None) -> np.ndarray:
+    """SPC-ID-ERR (Alg. 6) evaluated at given scales:
+    eps_hat(tau) = c * lambda_max(B_f B_f^T - tau B_c B_c^T), c = m // mc, with
+    B_f and B_c the rows i of A and A_c for which (i + 1) mod c == 0 (the rows
+    Alg. 6 keeps while it streams A)."""
+    A = np.asarray(A, dtype=np.float64)
+    if Ac is None:
+        Ac = _restrict.apply(A, R)
+    m = A.shape[0]
+    c = m // mc
+    J = np.array([i for i in range(m) if (i + 1) % c == 0])
+    Bf = A[J]
+    Bc = Ac[J]
+    Gf = Bf @ Bf.T
+    Gc = Bc @ Bc.T
+    return np.array([c * np.linalg.eigvalsh(Gf - t * Gc)[-1] for t in np.asarray(taus, dtype=np.float64)])
+
+
 def eps_tau(A: np.ndarray, Ac: np.ndarray, tau: float) -> float:
     """epsilon(tau) = lambda_max(A_f A_f^T - tau A_c A_c^T) (Sec. 4)."""
     return float(np.linalg.eigvalsh(A @ A.T - tau * (Ac @ Ac.T))[-1])

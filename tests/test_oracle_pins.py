@@ -312,6 +312,32 @@ def test_spc_id_err_full_sampling_equals_eps_tau():
         assert rowid.eps_tau(A, Ac, t) >= est - 1e-9 * abs(est)
 
 
+def test_spc_id_err_curve_pins():
+    # tau = 0: c times the largest squared singular value of the kept rows B_f
+    A = synth.heat_modes(30, 8, seed=9, nu=0.002) + 1e-2 * np.random.default_rng(5).standard_normal((30, 64))
+    R = _di(8, 8, 2, 2)
+    Ac = restrict.apply(A, R)
+    mc = 10
+    c = 30 // mc
+    keep = [i for i in range(30) if (i + 1) % c == 0]
+    e0 = rowid.spc_id_err_curve(A, R, mc, [0.0])[0]
+    assert abs(e0 - c * np.linalg.svd(A[keep], compute_uv=False)[0] ** 2) <= 1e-12 * e0
+    # every row kept (mc = m): the definition of eps(tau) on the full matrices
+    taus = [0.1, 1.0, 4.0, 16.0]
+    full = rowid.spc_id_err_curve(A, R, 30, taus)
+    for t, v in zip(taus, full):
+        assert abs(v - rowid.eps_tau(A, Ac, t)) <= 1e-10 * max(abs(v), 1.0)
+    # B_c B_c^T is positive semidefinite: non-increasing in tau, within Weyl's bounds
+    curve = rowid.spc_id_err_curve(A, R, mc, np.linspace(0.0, 20.0, 41))
+    assert np.all(np.diff(curve) <= 1e-10 * np.abs(curve).max())
+    Gf = A[keep] @ A[keep].T
+    Gc = Ac[keep] @ Ac[keep].T
+    lf = np.linalg.eigvalsh(Gf)[-1]
+    lc = np.linalg.eigvalsh(Gc)
+    for t, v in zip(np.linspace(0.0, 20.0, 41), curve):
+        assert c * (lf - t * lc[-1]) - 1e-9 * lf <= v <= c * (lf - t * lc[0]) + 1e-9 * lf
+
+
 # ------------------------------------------------------------------ learned restriction
 
 def test_projection_loss_gradient_finite_difference():
