@@ -162,10 +162,12 @@ int dsk_sketch_svd(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64
  * the result equals dsk_sketch_svd with q = 0; in floating point the rounding
  * of H is amplified by kappa(Y) = ||Y|| ||R^{-1}||, as the formula implies, so
  * the two agree to about u kappa(Y) sigma_1 (u = 2^-24 for FP32 input).
- * R: FP64, the Cholesky factor of the FP64 Gram Y^T Y (FP32 / 16-bit input) or
- * the Householder R of Y (FP64 input); a numerically rank-deficient Y (where
- * the formula breaks down) raises DSK_FLAG_RANK_DEFICIENT.  The orthonormalisation
- * of Y runs on a worker stream of the handle, concurrently with the pass.
+ * R: FP64, the Cholesky factor of the FP64 Gram Y^T Y with Q = Y R^{-1} (FP32 /
+ * 16-bit input; one CholeskyQR pass, and B^T = H R^{-1} by the same blocked
+ * substitution) or the Householder R of Y (FP64 input).  A numerically
+ * rank-deficient Y (where the formula breaks down) raises DSK_FLAG_FALLBACK
+ * (shifted factor) or DSK_FLAG_RANK_DEFICIENT.  The orthonormalisation of Y runs
+ * on a worker stream of the handle, concurrently with the pass.
  * Arguments: h=1, A=2, dtype=3, m=4, n=5, lda=6, k=7 (1 <= k <= ell), R=8,
  *   o=9 (host, may be NULL; refine must be 0), U=10 (m x k row-major, work dtype),
  *   S=11 (k, F64), V=12 (n x k row-major, work dtype), info=13 (host, may be NULL).
@@ -173,6 +175,26 @@ int dsk_sketch_svd(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64
 int dsk_sketch_svd_sp(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                       int32_t k, const dsk_restriction *R, const dsk_opts *o,
                       void *U, double *S, void *V, dsk_info *info);
+
+/*
+ * dsk_spc_id_err -- the single-pass error estimate of SPC-ID (SPC-ID-ERR,
+ * Alg. 6) at given scales tau:
+ *   eps[i] = c lambda_max(B_f B_f^T - taus[i] B_c B_c^T),  c = floor(m / mc),
+ * where B_f holds the rows i of A with (i + 1) mod c == 0 (floor(m / c) rows,
+ * the rows Alg. 6 keeps while streaming A) and B_c = B_f D their coarse rows;
+ * with every row kept (mc = m) this is eps(tau) of the SPC-ID bound (Sec. 4).
+ * Alg. 6 writes a minimum over tau; lambda_max(B_f B_f^T - tau B_c B_c^T) is
+ * non-increasing in tau (B_c B_c^T is positive semidefinite), so the scales
+ * are chosen by the caller and the minimum over them is eps's minimum.
+ * Grams in FP64 from the stored values; eigenvalues by the core eigensolver on
+ * the positive semidefinite shift M + ||M||_F I (absolute error about
+ * 1e-12 c (|tr M| + r ||M||_F)).
+ * Arguments: h=1, A=2, dtype=3, m=4, n=5, lda=6, R=7, mc=8 (1 <= mc <= m, with
+ *   floor(m / floor(m / mc)) <= 112 kept rows), taus=9 (device F64, ntau values),
+ *   ntau=10 (1..1024), eps=11 (device F64, ntau).
+ */
+int dsk_spc_id_err(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                   const dsk_restriction *R, int32_t mc, const double *taus, int32_t ntau, double *eps);
 
 /*
  * dsk_sketch_id -- rank-k row interpolative decomposition A ~ P A(I, :) by

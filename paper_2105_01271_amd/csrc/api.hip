@@ -386,10 +386,15 @@ int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, i
       hipStream_t wst = wk->stream;
       DSK_TRY(hipEventRecord(h->wev[0], st));
       DSK_TRY(hipStreamWaitEvent(wst, h->wev[0], 0));
+      // FP32 / 16-bit, ell <= 64: one CholeskyQR pass, Y^T Y = L L^T (FP64),
+      // Q = Y L^{-T}; then B^T = H L^{-T} by the same blocked substitution
+      const bool chol_tiles = !f64 && L <= 64;
       if (f64) {
         DSK_RET(launch_convert(wst, Y, 1, tmp, 1, m * L));
         DSK_RET(launch_hhqr(wst, tmp, m, L, (double *)Q, Rsm, h->dflags));
         DSK_RET(launch_spc_rinv(wst, Rsm, L, 0, 0x1p-53, Mr, h->dflags));
+      } else if (chol_tiles) {
+        DSK_RET(launch_cholqr64(wst, Y, 0, m, L, Q, cws, h->dflags, 1));
       } else {
         DSK_RET(launch_cholqr2(wst, Y, 0, m, L, Q, cws, h->dflags, Rsm, 2));
         DSK_RET(launch_gram(wst, Y, 0, m, L, GY, part, nparts));
@@ -400,7 +405,8 @@ int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, i
       timing_slot(h, &e0, &e1);
       DSK_RET(launch_stream(st, A, dtype, m, n, lda, Y, f64, L, Hb, L, od.mode, sws, h->cu_count, e0, e1));
       DSK_TRY(hipStreamWaitEvent(st, h->wev[1], 0));
-      DSK_RET(launch_tsmm(st, Hb, f64, n, L, L, Mr, L, L, nullptr, Bt, L));
+      if (chol_tiles) DSK_RET(launch_cholqr64_apply(st, Hb, 0, n, L, cws, Bt, h->dflags));
+      else DSK_RET(launch_tsmm(st, Hb, f64, n, L, L, Mr, L, L, nullptr, Bt, L));
     } else {
     // intermediate bases of the power iteration only carry a span (one
     // CholeskyQR pass); the block that B is projected on is orthonormalised fully
@@ -464,6 +470,57 @@ int dsk_sketch_svd(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64
   DSK_RET(svd_check(A, dtype, m, n, lda, k, R, q, o, U, S, V, &od, &s, &L));
   DSK_TRY(hipSetDevice(h->device));
   return svd_run(h, A, dtype, m, n, lda, k, R, q, od, s, L, U, S, V, info, nullptr);
+}
+
+int dsk_spc_id_err(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                   const dsk_restriction *R, int32_t mc, const double *taus, int32_t ntau, double *eps) {
+  if (!h) return -1;
+  if (!A) return -2;
+  if (!valid_dtype(dtype)) return -3;
+  if (m < 1) return -4;
+  if (n < 1) return -5;
+  if (lda < n) return -6;
+  const int64_t s = coarse_size(R, n);
+  if (s < 1) return -7;
+  if (mc < 1 || mc > m) return -8;
+  const int64_t c = m / mc;         // keep rows i with (i + 1) mod c == 0
+  const int64_t r = m / c;
+  if (r > 112) return -8;
+  if (!taus) return -9;
+  if (ntau < 1 || ntau > 1024) return -10;
+  if (!eps) return -11;
+  DSK_TRY(hipSetDevice(h->device));
+  hipStream_t st = h->stream;
+  const size_t esz = dtype == DSK_F64 ? 8 : (dtype == DSK_F32 ? 4 : 2);
+  const int nparts = std::max(spc_err_parts(n), spc_err_parts(s));
+  Carve cv{nullptr, 0, 0, true};
+  for (int pass = 0; pass < 2; ++pass) {
+    cv.off = 0;
+    double *Bc = cv.take<double>((size_t)r * s);
+    double *part = cv.take<double>((size_t)nparts * r * r);
+    double *Gf = cv.take<double>((size_t)r * r);
+    double *Gc = cv.take<double>((size_t)r * r);
+    double *Mb = cv.take<double>((size_t)ntau * r * r);
+    double *sig = cv.take<double>(ntau);
+    double *lam = cv.take<double>((size_t)ntau * r);
+    double *Ub = cv.take<double>((size_t)ntau * r * r);
+    if (pass == 0) {
+      DSK_RET(arena_reserve(h, cv.off));
+      cv.base = h->arena;
+      cv.cap = h->arena_bytes;
+      cv.dry = false;
+      continue;
+    }
+    hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, st, h->dflags);
+    // the kept rows: a strided view of A (first row c - 1, row stride c lda)
+    const void *Ak = reinterpret_cast<const char *>(A) + (size_t)(c - 1) * lda * esz;
+    const int64_t ldk = c * lda;
+    DSK_RET(launch_restrict(st, Ak, dtype, r, n, ldk, R, s, 1, Bc, nullptr, h->dflags));
+    DSK_RET(launch_row_gram(st, Ak, dtype, (int)r, n, ldk, part, Gf));
+    DSK_RET(launch_row_gram(st, Bc, DSK_F64, (int)r, s, s, part, Gc));
+    DSK_RET(launch_eps_curve(st, Gf, Gc, (int)r, taus, ntau, (double)c, Mb, sig, lam, Ub, eps, h->dflags));
+  }
+  return 0;
 }
 
 int dsk_sketch_svd_sp(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,

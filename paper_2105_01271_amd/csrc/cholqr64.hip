@@ -360,6 +360,26 @@ int cholqr64_typed(hipStream_t st, const T *Y, int64_t rows, int ell, T *Q, void
 
 }  // namespace
 
+int launch_cholqr64_apply(hipStream_t st, const void *X, int f64, int64_t rows, int ell, const void *ws, void *out,
+                          int *dflags) {
+  if (ell < 1 || ell > 64 || rows < 1) return -1;
+  // the factor tiles the last factorization on ws left (after the Gram partials)
+  double *Mf = const_cast<double *>(reinterpret_cast<const double *>(ws)) + (size_t)PMAX * PART;
+  const unsigned grid = (unsigned)((rows + RPW - 1) / RPW);
+  const size_t lds = (size_t)POOL_LDS * sizeof(double);
+  if (f64) {
+    allow_pool(k_cq_apply<double>);
+    hipLaunchKernelGGL(k_cq_apply<double>, dim3(grid), dim3(256), lds, st, (const double *)X, rows, ell, Mf,
+                       (double *)out, (int64_t)RPW, (double *)nullptr, (unsigned *)nullptr, dflags, 0, 0);
+  } else {
+    allow_pool(k_cq_apply<float>);
+    hipLaunchKernelGGL(k_cq_apply<float>, dim3(grid), dim3(256), lds, st, (const float *)X, rows, ell, Mf,
+                       (float *)out, (int64_t)RPW, (double *)nullptr, (unsigned *)nullptr, dflags, 0, 0);
+  }
+  DSK_TRY(hipGetLastError());
+  return 0;
+}
+
 size_t cholqr64_ws_bytes(int64_t rows, int ell) {
   return ((size_t)PMAX * PART + PART) * sizeof(double) + (size_t)rows * ell * sizeof(double) + 256;
 }

@@ -143,6 +143,10 @@ size_t cholqr2_ws_bytes(int64_t rows, int ell);
 size_t cholqr64_ws_bytes(int64_t rows, int ell);
 int launch_cholqr64(hipStream_t st, const void *Y, int f64, int64_t rows, int ell, void *Q, void *ws, int *dflags,
                     int passes);
+// out = X L^{-T} (rows x ell, one 64-row chunk per workgroup) with the factor L that
+// the last launch_cholqr64 on ws computed (with passes = 1: Y^T Y = L L^T)
+int launch_cholqr64_apply(hipStream_t st, const void *X, int f64, int64_t rows, int ell, const void *ws, void *out,
+                          int *dflags);
 // passes = 2: CholeskyQR2 (orthonormal to working precision); passes = 1: one
 // CholeskyQR pass, an orthonormal-up-to-kappa^2 u basis of span(Y) (enough
 // where only the span is used, as in the intermediate power steps).
@@ -153,6 +157,17 @@ int launch_gram(hipStream_t st, const void *X, int f64, int64_t rows, int ell, d
                 double *part, int nparts);
 // jacobi.hip
 int launch_core_eig(hipStream_t st, const double *G, int ell, double *lam, double *U, int *dflags);
+// count independent ell x ell matrices (consecutive), one workgroup each
+int launch_core_eig_batched(hipStream_t st, const double *G, int ell, double *lam, double *U, int *dflags,
+                            int count);
+// spcerr.hip: row Gram G = X X^T (r <= 112 rows of length ncols, row stride ldx) in FP64;
+// part: spc_err_parts(ncols) * r^2 doubles
+int spc_err_parts(int64_t ncols);
+int launch_row_gram(hipStream_t st, const void *X, int dtype, int r, int64_t ncols, int64_t ldx, double *part,
+                    double *G);
+// eps[i] = c lambda_max(Gf - taus[i] Gc) for i < ntau (Mb: ntau r^2, sig: ntau, lam: ntau r, Ub: ntau r^2)
+int launch_eps_curve(hipStream_t st, const double *Gf, const double *Gc, int r, const double *taus, int ntau,
+                     double c, double *Mb, double *sig, double *lam, double *Ub, double *eps, int *dflags);
 int launch_jacobi_svd(hipStream_t st, const double *Rm, int ell, double *sig, double *Vr,
                       double *Ur, int *dflags);
 int launch_tsmm(hipStream_t st, const void *X, int f64, int64_t rows, int ell, int64_t ldx,

@@ -232,6 +232,20 @@ def sketch_svd_sp(A: torch.Tensor, k: int, R: Restriction, p: int = 10, S=None, 
     return U, Sv, V
 
 
+def spc_id_err(A: torch.Tensor, R: Restriction, mc: int, taus) -> torch.Tensor:
+    """SPC-ID-ERR (dsk_spc_id_err, Alg. 6) at the given scales: eps_hat(tau) for
+    each tau (float64 device tensor)."""
+    _check_matrix(A)
+    lib = _lib.load()
+    m, n = A.shape
+    t = torch.as_tensor(taus, dtype=torch.float64).to(A.device).contiguous()
+    eps = torch.empty_like(t)
+    rc = R.to_c()
+    _lib.check("dsk_spc_id_err", lib.dsk_spc_id_err(_handle(A.device), _ptr(A), _DT[A.dtype], m, n, A.stride(0),
+                                                    ctypes.byref(rc), int(mc), _ptr(t), int(t.numel()), _ptr(eps)))
+    return eps
+
+
 def sketch_id(A: torch.Tensor, k: int, R: Restriction, q: int = 0, p: int = 10, S=None, tau=None,
               projected=False, skeleton_rows=False, want_info: bool = False, per_step: bool = False):
     """Rank-k row ID by TPC-ID (dsk_sketch_id).  Returns I (k, int64), P (m x k, f64)[, A(I,:)][, info].
