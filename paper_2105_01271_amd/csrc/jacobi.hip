@@ -285,7 +285,9 @@ __global__ void __launch_bounds__(NT) k_core_eig(const double *__restrict__ G_in
         __syncthreads();
       }
       sweeps = sweep + 1;
-      if (!rotated || !bigrot) break;
+      const bool stop = !rotated || !bigrot;
+      __syncthreads();   // every thread has read the flags before thread 0 clears them
+      if (stop) break;
     }
     X = Xc;
     ldx = 64;
@@ -330,7 +332,9 @@ __global__ void __launch_bounds__(NT) k_core_eig(const double *__restrict__ G_in
       __syncthreads();
     }
     sweeps = sweep + 1;
-    if (!rotated) break;
+    const bool stop = !rotated;
+    __syncthreads();   // every thread has read the flag before thread 0 clears it
+    if (stop) break;
   }
   }
   const int grp = t >> 4, gl = t & 15;
@@ -424,7 +428,9 @@ __global__ void __launch_bounds__(1024) k_jacobi_svd(const double *__restrict__ 
       __syncthreads();
     }
     if (t == 0) dflags[FLAGW_SWEEPS] = sweep + 1;
-    if (!rotated) break;
+    const bool stop = !rotated;
+    __syncthreads();   // every thread has read the flag before thread 0 clears it
+    if (stop) break;
   }
   for (int col = t; col < ell; col += 1024) {
     double s = 0.0;
