@@ -1,0 +1,190 @@
+// Calls the C ABI of the host-emulated library on host buffers.  Built with
+// AddressSanitizer, any out-of-bounds access of a kernel (device buffers and
+// LDS) aborts the run with a report; a missing barrier shows up as a deadlock.
+// Modes: "quick" (one configuration per path), "svd", "batch", "all".
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <random>
+#include <string>
+#include <vector>
+#include "dsketch.h"
+
+static std::vector<double> make_A(int64_t m, int N, int r, unsigned seed, double noise) {
+  // sum of r smooth separable modes with decaying weights plus noise
+  std::mt19937_64 g(seed);
+  std::normal_distribution<double> nd(0.0, 1.0);
+  const int64_t n = (int64_t)N * N;
+  std::vector<double> A(m * n, 0.0);
+  for (int q = 0; q < r; ++q) {
+    const double w = 1.0 / std::sqrt(1.0 + q);
+    const int kx = 1 + q % 7, ky = 1 + q / 7;
+    const double ph = nd(g);
+    std::vector<double> tt(m);
+    for (int64_t i = 0; i < m; ++i) tt[i] = nd(g);
+    for (int64_t i = 0; i < m; ++i)
+      for (int y = 0; y < N; ++y)
+        for (int x = 0; x < N; ++x)
+          A[i * n + y * N + x] += w * tt[i] * std::cos(6.283185307 * (kx * x + ky * y) / N + ph);
+  }
+  for (auto &v : A) v += noise * nd(g);
+  return A;
+}
+
+static std::vector<int64_t> di_index(int N, int f) {
+  std::vector<int64_t> idx;
+  for (int y = 0; y < N; y += f)
+    for (int x = 0; x < N; x += f) idx.push_back((int64_t)y * N + x);
+  return idx;
+}
+
+
+static int check(const char *what, int rc) {
+  printf("%-44s rc=%d\n", what, rc);
+  fflush(stdout);
+  return rc;
+}
+
+int main(int argc, char **argv) {
+  const std::string which = argc > 1 ? argv[1] : "quick";
+  const bool quick = which == "quick";
+  dsk_handle *h = nullptr;
+  if (dsk_create(&h, 0, nullptr)) return 1;
+  dsk_opts o;
+  dsk_opts_default(&o);
+  auto want = [&](const char *w) { return which == "all" || quick || which == w; };
+
+  // ---- sketch SVD, FP32 and FP64, q = 0..2, ell = 30 and 60
+  for (int f64 = 0; f64 < 2; ++f64)
+    for (int cfg = 0; cfg < (quick ? 1 : 2) && want("svd"); ++cfg) {
+      const int64_t m = cfg ? 300 : 200;
+      const int N = 32, fct = cfg ? 2 : 4, k = cfg ? 50 : 20;
+      const int64_t n = (int64_t)N * N;
+      auto A64 = make_A(m, N, 40, 7 + cfg, 1e-3);
+      std::vector<float> A32(A64.begin(), A64.end());
+      auto idx = di_index(N, fct);
+      int64_t *didx = nullptr;
+      double *dA = nullptr;
+      void *dAv = nullptr;
+      dsk_restriction R{};
+      R.kind = DSK_R_INDEX;
+      R.s = (int64_t)idx.size();
+      R.index = idx.data();
+      R.ny = R.nx = N;
+      R.sy = R.sx = fct;
+      (void)didx;
+      (void)dA;
+      dAv = f64 ? (void *)A64.data() : (void *)A32.data();
+      const size_t we = f64 ? 8 : 4;
+      std::vector<char> U(m * k * we), V(n * k * we);
+      std::vector<double> S(k);
+      for (int q = 0; q < (quick ? (f64 ? 1 : 2) : 3); ++q) {
+        dsk_info info{};
+        char nm[128];
+        snprintf(nm, sizeof nm, "svd f64=%d cfg=%d q=%d", f64, cfg, q);
+        check(nm, dsk_sketch_svd(h, dAv, f64 ? DSK_F64 : DSK_F32, m, n, n, k, &R, q, &o, U.data(), S.data(),
+                                 V.data(), &info));
+        printf("   S0 %.10g S%d %.10g flags %d sweeps %d\n", S[0], k - 1, S[k - 1], info.flags, info.core_sweeps);
+      }
+      // row ID and the combined call
+      if (want("svd") && !(quick && f64)) {
+        std::vector<int64_t> I(k);
+        std::vector<double> P(m * k);
+        std::vector<char> rows(k * n * we);
+        dsk_info ii{};
+        check("id q=0", dsk_sketch_id(h, dAv, f64 ? DSK_F64 : DSK_F32, m, n, n, k, &R, 0, &o, I.data(), P.data(),
+                                      rows.data(), &ii));
+        printf("   I0 %lld I1 %lld flags %d\n", (long long)I[0], (long long)I[1], ii.flags);
+        dsk_info a{}, b{};
+        check("svd_id q=1", dsk_sketch_svd_id(h, dAv, f64 ? DSK_F64 : DSK_F32, m, n, n, k, &R, 1, 0, &o, U.data(),
+                                               S.data(), V.data(), I.data(), P.data(), rows.data(), &a, &b));
+        check("svd single pass", dsk_sketch_svd_sp(h, dAv, f64 ? DSK_F64 : DSK_F32, m, n, n, k, &R, &o, U.data(),
+                                                   S.data(), V.data(), &a));
+        printf("   S0 %.10g flags %d\n", S[0], a.flags);
+        std::vector<double> taus = {0.0, 1.0, 4.0, 16.0}, eps(4);
+        check("spc_id_err", dsk_spc_id_err(h, dAv, f64 ? DSK_F64 : DSK_F32, m, n, n, &R, (int)(m / 10), taus.data(), 4,
+                                           eps.data()));
+        printf("   eps %.6g %.6g %.6g %.6g\n", eps[0], eps[1], eps[2], eps[3]);
+      }
+    }
+
+  // ---- batched ragged instances (eager), shapes of the batched tests
+  if (want("batch")) {
+    struct Inst { int64_t m; int N, k, f, f64, q; };
+    std::vector<Inst> ins = {{331, 32, 18, 2, 1, 2}, {199, 64, 22, 4, 0, 1}, {238, 32, 11, 4, 0, 2},
+                             {386, 32, 12, 4, 0, 1}, {198, 64, 19, 4, 0, 0}, {273, 32, 37, 4, 1, 0},
+                             {144, 32, 16, 2, 0, 2}, {388, 32, 14, 4, 0, 0}, {338, 64, 11, 4, 0, 1}};
+    std::vector<std::vector<double>> A64s;
+    std::vector<std::vector<float>> A32s;
+    std::vector<std::vector<int64_t>> idxs;
+    std::vector<std::vector<char>> Us, Vs;
+    std::vector<std::vector<double>> Ss;
+    std::vector<dsk_problem> pr;
+    if (quick) ins.resize(3);
+    for (size_t i = 0; i < ins.size(); ++i) {
+      const Inst &t = ins[i];
+      A64s.push_back(make_A(t.m, t.N, 30, 100 + (unsigned)i, 1e-3));
+      A32s.emplace_back(A64s.back().begin(), A64s.back().end());
+      idxs.push_back(di_index(t.N, t.f));
+    }
+    for (size_t i = 0; i < ins.size(); ++i) {
+      const Inst &t = ins[i];
+      const int64_t n = (int64_t)t.N * t.N;
+      const size_t we = t.f64 ? 8 : 4;
+      Us.emplace_back(t.m * t.k * we);
+      Vs.emplace_back(n * t.k * we);
+      Ss.emplace_back(t.k);
+      dsk_problem p{};
+      p.A = t.f64 ? (const void *)A64s[i].data() : (const void *)A32s[i].data();
+      p.dtype = t.f64 ? DSK_F64 : DSK_F32;
+      p.m = t.m;
+      p.n = n;
+      p.lda = n;
+      p.k = t.k;
+      p.q = t.q;
+      p.R.kind = DSK_R_INDEX;
+      p.R.s = (int64_t)idxs[i].size();
+      p.R.index = idxs[i].data();
+      p.U = Us.back().data();
+      p.S = Ss.back().data();
+      p.V = Vs.back().data();
+      pr.push_back(p);
+    }
+    int nw = 0;
+    check("batched eager", dsk_sketch_svd_batched(h, (int)pr.size(), pr.data(), &o, 0, &nw));
+    printf("   workers %d S0 %.8g\n", nw, Ss[0][0]);
+    // graph path: fresh outputs, first call = eager run + capture, then replays after clearing the outputs
+    std::vector<std::vector<char>> U2, V2;
+    std::vector<std::vector<double>> S2;
+    std::vector<dsk_problem> pr2 = pr;
+    for (size_t i = 0; i < pr.size(); ++i) {
+      U2.emplace_back(Us[i].size());
+      V2.emplace_back(Vs[i].size());
+      S2.emplace_back(Ss[i].size());
+      pr2[i].U = U2.back().data();
+      pr2[i].S = S2.back().data();
+      pr2[i].V = V2.back().data();
+    }
+    const int rg = check("batched graph (first call; -5 while graph replay is disabled)", dsk_sketch_svd_batched(h, (int)pr2.size(), pr2.data(), &o,
+                                                                             DSK_BATCH_GRAPH, &nw));
+    if (rg == 0) {
+      for (int rep = 0; rep < 3; ++rep) {
+        for (size_t i = 0; i < pr.size(); ++i) {
+          memset(U2[i].data(), 0, U2[i].size());
+          memset(V2[i].data(), 0, V2[i].size());
+          memset(S2[i].data(), 0, S2[i].size() * 8);
+        }
+        check("batched graph replay", dsk_sketch_svd_batched(h, (int)pr2.size(), pr2.data(), &o, DSK_BATCH_GRAPH, &nw));
+        int bad = 0;
+        for (size_t i = 0; i < pr.size(); ++i)
+          bad += memcmp(U2[i].data(), Us[i].data(), Us[i].size()) != 0 || memcmp(V2[i].data(), Vs[i].data(), Vs[i].size()) != 0 ||
+                 memcmp(S2[i].data(), Ss[i].data(), Ss[i].size() * 8) != 0;
+        printf("   replay %d: %d instances differ from the eager results\n", rep, bad);
+      }
+    }
+  }
+  dsk_destroy(h);
+  printf("done\n");
+  return 0;
+}
