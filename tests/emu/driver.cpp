@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 #include "dsketch.h"
+#include <cstdint>
 
 static std::vector<double> make_A(int64_t m, int N, int r, unsigned seed, double noise) {
   // sum of r smooth separable modes with decaying weights plus noise
@@ -183,6 +184,113 @@ int main(int argc, char **argv) {
         printf("   replay %d: %d instances differ from the eager results\n", rep, bad);
       }
     }
+  }
+  // ---- wide range finder (ell = 110), 16-bit storage with refinement, stencil restrictions, projected ID
+  if (which == "all" || which == "more") {
+    const int64_t m = 300;
+    const int N = 32;
+    const int64_t n = (int64_t)N * N;
+    auto A64 = make_A(m, N, 60, 21, 1e-3);
+    std::vector<float> A32(A64.begin(), A64.end());
+    std::vector<uint16_t> Abf(m * n), Ah(m * n);
+    for (int64_t i = 0; i < m * n; ++i) {
+      const __bf16 b = (__bf16)A32[i];
+      const _Float16 hv = (_Float16)A32[i];
+      memcpy(&Abf[i], &b, 2);
+      memcpy(&Ah[i], &hv, 2);
+    }
+    auto idx2 = di_index(N, 2);
+    dsk_restriction R{};
+    R.kind = DSK_R_INDEX;
+    R.s = (int64_t)idx2.size();
+    R.index = idx2.data();
+    const int k = 100;
+    std::vector<float> U(m * k), V(n * k);
+    std::vector<double> S(k);
+    dsk_info info{};
+    check("svd wide ell=110 q=1", dsk_sketch_svd(h, A32.data(), DSK_F32, m, n, n, k, &R, 1, &o, U.data(), S.data(),
+                                                 V.data(), &info));
+    printf("   ell %d S0 %.10g S99 %.6g flags %d\n", info.ell, S[0], S[99], info.flags);
+    const int k2 = 20;
+    dsk_opts orf = o;
+    orf.refine = 1;
+    check("svd bf16 q=1 refine", dsk_sketch_svd(h, Abf.data(), DSK_BF16, m, n, n, k2, &R, 1, &orf, U.data(),
+                                                S.data(), V.data(), &info));
+    printf("   S0 %.10g flags %d\n", S[0], info.flags);
+    check("svd f16 q=0", dsk_sketch_svd(h, Ah.data(), DSK_F16, m, n, n, k2, &R, 0, &o, U.data(), S.data(), V.data(),
+                                        &info));
+    printf("   S0 %.10g flags %d\n", S[0], info.flags);
+    for (int kind : {DSK_R_NN, DSK_R_GLOBAL}) {
+      dsk_restriction Rs{};
+      Rs.kind = kind;
+      Rs.ny = Rs.nx = N;
+      Rs.sy = Rs.sx = 4;
+      check(kind == DSK_R_NN ? "svd nn q=1" : "svd global q=1",
+            dsk_sketch_svd(h, A64.data(), DSK_F64, m, n, n, k2, &Rs, 1, &o, U.data(), S.data(), V.data(), &info));
+      std::vector<int64_t> I(k2);
+      std::vector<double> P(m * k2);
+      check(kind == DSK_R_NN ? "id nn q=1" : "id global q=1",
+            dsk_sketch_id(h, A64.data(), DSK_F64, m, n, n, k2, &Rs, 1, &o, I.data(), P.data(), nullptr, &info));
+    }
+    // projected ID with a given FP32 second level (widened to FP64 inside)
+    std::vector<float> Om(idx2.size() * 30);
+    std::mt19937_64 g(5);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    for (auto &v : Om) v = (float)nd(g);
+    dsk_opts op = o;
+    op.S = Om.data();
+    op.ell = 30;
+    op.id_projected = 1;
+    std::vector<int64_t> I(k2);
+    std::vector<double> P(m * k2);
+    check("id projected given S q=1", dsk_sketch_id(h, A32.data(), DSK_F32, m, n, n, k2, &R, 1, &op, I.data(), P.data(),
+                                                    nullptr, &info));
+    check("svd given S q=1", dsk_sketch_svd(h, A32.data(), DSK_F32, m, n, n, k2, &R, 1, &op, U.data(), S.data(),
+                                            V.data(), &info));
+    // restriction, projection and power iteration alone
+    std::vector<float> Ac(m * idx2.size()), Q(m * 30), Bt(n * 30), Qo(m * 30);
+    for (auto &v : Q) v = (float)nd(g);
+    check("restrict", dsk_restrict(h, A32.data(), DSK_F32, m, n, n, &R, Ac.data()));
+    check("project", dsk_project(h, A32.data(), DSK_F32, m, n, n, Q.data(), 30, Bt.data(), DSK_MODE_DEFAULT));
+    check("power_iter q=2", dsk_power_iter(h, Ac.data(), DSK_F32, m, (int64_t)idx2.size(), (int64_t)idx2.size(),
+                                           Q.data(), 30, 2, 1.0, 1, Qo.data()));
+    // learned restriction: forward, backward, loss gradient, Adam
+    const int C = 4;
+    std::vector<float> w1(C * 25), w2(C * 25), gw1(C * 25), gw2(C * 25), m1(C * 25, 0.f), m2(C * 25, 0.f);
+    for (auto &v : w1) v = (float)(0.2 * nd(g));
+    for (auto &v : w2) v = (float)(0.2 * nd(g));
+    dsk_restriction Rl{};
+    Rl.kind = DSK_R_LEARNED;
+    Rl.ny = Rl.nx = N;
+    Rl.channels = C;
+    Rl.w1 = w1.data();
+    Rl.w2 = w2.data();
+    const int64_t sl = (N / 4) * (N / 4);
+    std::vector<float> Acl(m * sl), gAc(m * sl);
+    for (auto &v : gAc) v = (float)nd(g);
+    check("learned restrict", dsk_restrict(h, A32.data(), DSK_F32, m, n, n, &Rl, Acl.data()));
+    check("learned conv bwd", dsk_conv_restrict_bwd(h, A32.data(), DSK_F32, m, n, n, &Rl, gAc.data(), gw1.data(),
+                                                    gw2.data()));
+    double loss = 0.0;
+    check("learned loss grad ell=20 q=1", dsk_learned_loss_grad(h, A32.data(), DSK_F32, m, n, n, &Rl, 20, 1, &loss,
+                                                                 gw1.data(), gw2.data()));
+    printf("   loss %.8g\n", loss);
+    check("adam step", dsk_adam_step(h, w1.data(), gw1.data(), m1.data(), m2.data(), C * 25, 1e-3f, 0.9f, 0.999f,
+                                     1e-8f, 1));
+    check("learned svd q=1", dsk_sketch_svd(h, A32.data(), DSK_F32, m, n, n, k2, &Rl, 1, &o, U.data(), S.data(),
+                                            V.data(), &info));
+    // documented argument errors (checked on the host before anything is enqueued)
+    const int e1 = dsk_sketch_svd(h, nullptr, DSK_F32, m, n, n, k2, &R, 1, &o, U.data(), S.data(), V.data(), nullptr);
+    const int e2 = dsk_sketch_svd(h, A32.data(), 9, m, n, n, k2, &R, 1, &o, U.data(), S.data(), V.data(), nullptr);
+    const int e3 = dsk_sketch_svd(h, A32.data(), DSK_F32, m, n, n - 1, k2, &R, 1, &o, U.data(), S.data(), V.data(),
+                                  nullptr);
+    const int e4 = dsk_sketch_svd(h, A32.data(), DSK_F32, m, n, n, 0, &R, 1, &o, U.data(), S.data(), V.data(), nullptr);
+    const int e5 = dsk_sketch_id(h, A32.data(), DSK_F32, m, n, n, k2, &R, 0, &o, nullptr, P.data(), nullptr, nullptr);
+    const int e6 = dsk_sketch_svd_sp(h, A32.data(), DSK_F32, m, n, n, k2, &R, &orf, U.data(), S.data(), V.data(),
+                                     nullptr);
+    const int ok = e1 == -2 && e2 == -3 && e3 == -6 && e4 == -7 && e5 == -11 && e6 == -9;
+    printf("%-44s rc=%d\n", "argument errors as documented", ok ? 0 : 1);
+    if (!ok) printf("   codes %d %d %d %d %d %d\n", e1, e2, e3, e4, e5, e6);
   }
   dsk_destroy(h);
   printf("done\n");

@@ -60,3 +60,22 @@ def test_kernels_run_clean_under_host_emulation():
     # single-pass SVD equals the two-pass one at q = 0 (Alg. 3 vs Alg. 2)
     sp = float(re.search(r"svd single pass.*\n\s+S0 ([\d.eE+-]+)", r.stdout).group(1))
     assert abs(sp - s32[0]) <= 1e-5 * s32[0], (sp, s32)
+
+
+@pytest.mark.skipif(os.environ.get("DSK_EMU_FULL") != "1", reason="the extended host emulation runs about 4 minutes; "
+                    "set DSK_EMU_FULL=1")
+def test_remaining_paths_run_clean_under_host_emulation():
+    """ell = 110 (wide CholeskyQR and eigensolver kernels), BF16 storage with the
+    refinement sweep, FP16, stencil restrictions (SVD and ID), the projected ID
+    and the SVD with a given second-level sketch, the restriction, projection
+    and power iteration entry points, the learned restriction (forward,
+    backward, loss gradient, Adam, SVD) and the documented argument errors."""
+    exe = _build()
+    r = subprocess.run([exe, "more"], capture_output=True, text=True, timeout=1800)
+    out = r.stdout + r.stderr
+    assert r.returncode == 0, out[-4000:]
+    assert "ERROR: AddressSanitizer" not in out and "SIMT FATAL" not in out, out[-4000:]
+    assert out.rstrip().endswith("done"), out[-2000:]
+    rcs = re.findall(r"^(.*?)\s+rc=(-?\d+)$", r.stdout, re.M)
+    assert len(rcs) >= 18, r.stdout
+    assert all(int(rc) == 0 for _, rc in rcs), rcs
