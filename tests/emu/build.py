@@ -59,6 +59,11 @@ def build(verbose: bool = False) -> str:
         s = open(p).read()
         # dynamic LDS: a heap buffer of exactly the launch's size
         s = re.sub(r"extern __shared__ (\w+) (\w+)\[\];", r"\1 *\2 = (\1 *)simt::dyn_lds();", s)
+        if os.path.basename(p) == "cpqr.hip":
+            # workgroups of the one-launch factorization run together: one copy of
+            # each static LDS variable per resident block
+            s = re.sub(r"__shared__ ((?:unsigned )?(?:long long|\w+)) (\w+)((?:\[[^\]]+\])*);",
+                       r"static \1 \2__b[64]\3; auto &\2 = \2__b[simt::block_linear()];", s)
         dst = os.path.join(gen, os.path.basename(p).replace(".hip", ".cpp"))
         open(dst, "w").write(f'#line 1 "{p}"\n' + s)
         srcs.append(dst)

@@ -1,7 +1,10 @@
 // Calls the C ABI of the host-emulated library on host buffers.  Built with
 // AddressSanitizer, any out-of-bounds access of a kernel (device buffers and
 // LDS) aborts the run with a report; a missing barrier shows up as a deadlock.
-// Modes: "quick" (one configuration per path), "svd", "batch", "all".
+// Modes: "quick" (one configuration per path), "svd", "batch", "more", "persist"
+// ("persist-quick": its two smaller cases), "all".  "persist" runs the one-launch pivoted QR (its workgroups waiting on
+// each other's published words) with all blocks of the launch resident together,
+// and compares it bitwise with the per-step factorization.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -11,6 +14,10 @@
 #include <vector>
 #include "dsketch.h"
 #include <cstdint>
+
+namespace simt {
+extern long long g_resident_launches;
+}
 
 static std::vector<double> make_A(int64_t m, int N, int r, unsigned seed, double noise) {
   // sum of r smooth separable modes with decaying weights plus noise
@@ -50,6 +57,9 @@ static int check(const char *what, int rc) {
 int main(int argc, char **argv) {
   const std::string which = argc > 1 ? argv[1] : "quick";
   const bool quick = which == "quick";
+  // enough emulated compute units for the one-launch factorization (m <= 4 x units)
+  const bool persist = which == "persist" || which == "persist-quick";
+  if (persist) setenv("SIMT_CU", "48", 1);
   dsk_handle *h = nullptr;
   if (dsk_create(&h, 0, nullptr)) return 1;
   dsk_opts o;
@@ -291,6 +301,47 @@ int main(int argc, char **argv) {
     const int ok = e1 == -2 && e2 == -3 && e3 == -6 && e4 == -7 && e5 == -11 && e6 == -9;
     printf("%-44s rc=%d\n", "argument errors as documented", ok ? 0 : 1);
     if (!ok) printf("   codes %d %d %d %d %d %d\n", e1, e2, e3, e4, e5, e6);
+  }
+  // ---- one-launch pivoted QR against the per-step one, bitwise
+  if (persist) {
+    struct Cfg { int64_t m; int N, f, k, f64; };
+    // s = 64, 256 (registers 4 per thread), 1024 (ragged: 4 per thread, last
+    // slots empty), 4096 (16 per thread); m with an incomplete last workgroup
+    std::vector<Cfg> cfgs = {{61, 32, 4, 20, 0}, {37, 64, 1, 30, 1}, {96, 32, 2, 40, 1}, {190, 64, 2, 50, 0}};
+    if (which == "persist-quick") cfgs.resize(2);
+    for (const Cfg &c : cfgs) {
+      const int64_t n = (int64_t)c.N * c.N;
+      auto A64 = make_A(c.m, c.N, 30, 300 + (unsigned)c.m, 1e-3);
+      std::vector<float> A32(A64.begin(), A64.end());
+      void *Av = c.f64 ? (void *)A64.data() : (void *)A32.data();
+      auto idx = di_index(c.N, c.f);
+      dsk_restriction R{};
+      R.kind = DSK_R_INDEX;
+      R.s = (int64_t)idx.size();
+      R.index = idx.data();
+      R.ny = R.nx = c.N;
+      R.sy = R.sx = c.f;
+      std::vector<int64_t> I[2];
+      std::vector<double> P[2];
+      dsk_info inf[2]{};
+      long long res[2];
+      for (int ps = 0; ps < 2; ++ps) {
+        const long long before = simt::g_resident_launches;
+        dsk_opts oo = o;
+        oo.id_per_step = ps;
+        I[ps].assign(c.k, -1);
+        P[ps].assign(c.m * c.k, 0.0);
+        char nm[128];
+        snprintf(nm, sizeof nm, "id m=%lld s=%lld k=%d f64=%d %s", (long long)c.m, (long long)R.s, c.k, c.f64,
+                 ps ? "per-step" : "one launch");
+        check(nm, dsk_sketch_id(h, Av, c.f64 ? DSK_F64 : DSK_F32, c.m, n, n, c.k, &R, 0, &oo, I[ps].data(),
+                                P[ps].data(), nullptr, &inf[ps]));
+        res[ps] = simt::g_resident_launches - before;
+      }
+      const bool same = I[0] == I[1] && memcmp(P[0].data(), P[1].data(), P[0].size() * 8) == 0;
+      printf("   I0 %lld I%d %lld flags %d %d resident launches %lld %lld same %d\n", (long long)I[0][0], c.k - 1,
+             (long long)I[0][c.k - 1], inf[0].flags, inf[1].flags, res[0], res[1], same ? 1 : 0);
+    }
   }
   dsk_destroy(h);
   printf("done\n");

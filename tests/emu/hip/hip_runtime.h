@@ -33,6 +33,8 @@ void block_sync();
 void group_sync(int size);                 // barrier among the aligned group of `size` lanes of this thread
 uint64_t *slots();                          // per-block exchange slots: 1024 threads x 8 words
 void *dyn_lds();
+int block_linear();                         // resident-block index of this thread (per-block static LDS)
+void yield();                               // a spin-wait iteration: let the other threads run
 [[noreturn]] void die(const char *msg);
 void launch_impl(const char *name, dim3 grid, dim3 block, size_t lds, void *stream, std::function<void()> body);
 template <typename T>
@@ -109,7 +111,7 @@ inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int rm, int b
 #define __builtin_amdgcn_wave_barrier() simt::group_sync(64)
 #define __builtin_amdgcn_fence(order, scope) __atomic_thread_fence(order)
 #define __builtin_amdgcn_s_waitcnt(x) ((void)0)
-#define __builtin_amdgcn_s_sleep(x) ((void)0)
+#define __builtin_amdgcn_s_sleep(x) simt::yield()
 inline double __builtin_amdgcn_rcp(double x) { return 1.0 / x; }
 inline float __builtin_amdgcn_rcpf(float x) { return 1.0f / x; }
 inline double __builtin_amdgcn_rsq(double x) { return 1.0 / sqrt(x); }

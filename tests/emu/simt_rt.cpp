@@ -46,6 +46,7 @@ thread_local Ctx ctx;
 
 static std::string g_kernel;
 constexpr size_t STACK = 512 * 1024;
+constexpr int MAXB = 64;   // resident blocks of a launch whose workgroups run together
 
 enum { READY = 0, BLOCKED = 1, DONE = 2 };
 struct Fiber {
@@ -55,7 +56,8 @@ struct Fiber {
   int where = 0;   // 1 block barrier, 10 + lg group barrier
   Ctx c;
 };
-static Fiber g_fib[1024];
+static Fiber g_fib[MAXB * 256];   // a sequential launch uses up to 1024 of them
+static int g_fib_blk[MAXB * 256];
 static void *g_sched_sp = nullptr;
 static const void *g_main_bottom = nullptr;
 static size_t g_main_size = 0;
@@ -64,13 +66,17 @@ static const std::function<void()> *g_body = nullptr;
 
 struct Bar {
   int n = 0, count = 0;
-  int waiters[1024];
-  int nw = 0;
+  std::vector<int> waiters;
 };
-static Bar g_block;
-static Bar g_groups[7][1024];
-static uint64_t g_slots[1024 * 8];
-static void *g_dyn = nullptr;
+// per resident block: barriers, exchange slots, dynamic LDS
+struct BlockState {
+  Bar block;
+  Bar groups[7][1024];
+  uint64_t slots[1024 * 8];
+  void *dyn = nullptr;
+};
+static BlockState *g_bs[MAXB];
+static int g_cur_blk = 0;
 
 static void to_sched() {
   void *fake = nullptr;
@@ -82,26 +88,34 @@ static void to_sched() {
 static void bar_wait(Bar &b, int where) {
   if (++b.count == b.n) {
     b.count = 0;
-    for (int i = 0; i < b.nw; ++i) g_fib[b.waiters[i]].state = READY;
-    b.nw = 0;
+    for (int w : b.waiters) g_fib[w].state = READY;
+    b.waiters.clear();
     return;   // the last to arrive continues
   }
-  b.waiters[b.nw++] = g_cur;
+  b.waiters.push_back(g_cur);
   g_fib[g_cur].state = BLOCKED;
   g_fib[g_cur].where = where;
   to_sched();
   g_fib[g_cur].where = 0;
 }
 
-void block_sync() { bar_wait(g_block, 1); }
+void block_sync() { bar_wait(g_bs[g_cur_blk]->block, 1); }
 void group_sync(int size) {
   int lg = 0;
   while ((1 << lg) < size) ++lg;
   if ((1 << lg) != size || lg > 6) die("group size");
-  bar_wait(g_groups[lg][ctx.flat >> lg], 10 + lg);
+  bar_wait(g_bs[g_cur_blk]->groups[lg][ctx.flat >> lg], 10 + lg);
 }
-uint64_t *slots() { return g_slots; }
-void *dyn_lds() { return g_dyn; }
+uint64_t *slots() { return g_bs[g_cur_blk]->slots; }
+void *dyn_lds() { return g_bs[g_cur_blk]->dyn; }
+int block_linear() { return g_cur_blk; }
+// a spin-wait iteration: let every other fiber run before this one continues
+void yield() {
+  g_fib[g_cur].state = READY;
+  g_fib[g_cur].where = 2;
+  to_sched();
+  g_fib[g_cur].where = 0;
+}
 
 static void fiber_entry() {
   __sanitizer_finish_switch_fiber(nullptr, &g_main_bottom, &g_main_size);
@@ -124,73 +138,97 @@ static void dump_states() {
     if (cnt[i]) fprintf(stderr, "   %s %d: %d threads (e.g. thread %d)\n", i == 31 ? "finished" : "waiting at", i, cnt[i], ex[i]);
 }
 
-static void run_block(dim3 b, dim3 g, dim3 bd) {
-  const int n = (int)(bd.x * bd.y * bd.z);
+// run the blocks listed in `blocks` as one set of fibers (concurrently when
+// there are several: a launch whose workgroups wait on each other)
+static void run_blocks(const std::vector<dim3> &blocks, dim3 g, dim3 bd, size_t lds) {
+  const int per = (int)(bd.x * bd.y * bd.z);
+  const int nb = (int)blocks.size();
+  if (nb > MAXB || (nb > 1 && per > 256)) die("too many resident blocks");
+  for (int bi = 0; bi < nb; ++bi) {
+    if (!g_bs[bi]) g_bs[bi] = new BlockState();
+    BlockState &B = *g_bs[bi];
+    B.block.n = per;
+    B.block.count = 0;
+    B.block.waiters.clear();
+    for (int lg = 0; lg <= 6; ++lg)
+      for (int gi = 0; gi < per >> lg; ++gi) {
+        B.groups[lg][gi].n = 1 << lg;
+        B.groups[lg][gi].count = 0;
+        B.groups[lg][gi].waiters.clear();
+      }
+    B.dyn = malloc(lds ? lds : 1);
+  }
+  const int n = nb * per;
   g_n = n;
-  for (int t = 0; t < n; ++t) {
-    Fiber &f = g_fib[t];
-    if (!f.stack) f.stack = (char *)malloc(STACK);
-    // initial frame: 6 callee-saved registers, then the entry address for `ret`
-    uintptr_t top = ((uintptr_t)(f.stack + STACK)) & ~(uintptr_t)15;
+  for (int f = 0; f < n; ++f) {
+    const int bi = f / per, t = f % per;
+    Fiber &fb = g_fib[f];
+    if (!fb.stack) fb.stack = (char *)malloc(STACK);
+    uintptr_t top = ((uintptr_t)(fb.stack + STACK)) & ~(uintptr_t)15;
     void **sp = (void **)top;
     *--sp = nullptr;                          // fake return address of fiber_entry
     *--sp = (void *)&fiber_entry;
     for (int r = 0; r < 6; ++r) *--sp = nullptr;
-    f.sp = sp;
-    f.state = READY;
-    f.where = 0;
-    f.c.bid = b;
-    f.c.gdim = g;
-    f.c.bdim = bd;
-    f.c.flat = t;
-    f.c.tid = dim3(t % bd.x, (t / bd.x) % bd.y, t / (bd.x * bd.y));
+    fb.sp = sp;
+    fb.state = READY;
+    fb.where = 0;
+    fb.c.bid = blocks[bi];
+    fb.c.gdim = g;
+    fb.c.bdim = bd;
+    fb.c.flat = t;
+    fb.c.tid = dim3(t % bd.x, (t / bd.x) % bd.y, t / (bd.x * bd.y));
+    g_fib_blk[f] = bi;
   }
   for (;;) {
     bool any = false, all_done = true;
-    for (int t = 0; t < n; ++t) {
-      if (g_fib[t].state != DONE) all_done = false;
-      if (g_fib[t].state != READY) continue;
+    for (int f = 0; f < n; ++f) {
+      if (g_fib[f].state != DONE) all_done = false;
+      if (g_fib[f].state != READY) continue;
       any = true;
-      g_cur = t;
-      ctx = g_fib[t].c;
+      g_cur = f;
+      g_cur_blk = g_fib_blk[f];
+      ctx = g_fib[f].c;
       void *fake = nullptr;
-      __sanitizer_start_switch_fiber(&fake, g_fib[t].stack, STACK);
-      simt_swap(&g_sched_sp, g_fib[t].sp);
+      __sanitizer_start_switch_fiber(&fake, g_fib[f].stack, STACK);
+      simt_swap(&g_sched_sp, g_fib[f].sp);
       __sanitizer_finish_switch_fiber(fake, nullptr, nullptr);
-      g_fib[t].c = ctx;
+      g_fib[f].c = ctx;
     }
     if (all_done) break;
     if (!any) {
-      fprintf(stderr, "SIMT: deadlock in %s, block (%u, %u)\n", g_kernel.c_str(), b.x, b.y);
+      fprintf(stderr, "SIMT: deadlock in %s, block (%u, %u)\n", g_kernel.c_str(), blocks[0].x, blocks[0].y);
       dump_states();
       die("deadlock");
     }
   }
-  for (int t = 0; t < n; ++t) ASAN_UNPOISON_MEMORY_REGION(g_fib[t].stack, STACK);
+  for (int f = 0; f < n; ++f) ASAN_UNPOISON_MEMORY_REGION(g_fib[f].stack, STACK);
+  for (int bi = 0; bi < nb; ++bi) {
+    free(g_bs[bi]->dyn);
+    g_bs[bi]->dyn = nullptr;
+  }
+  g_cur_blk = 0;
 }
 
 long long g_launches = 0;
+long long g_resident_launches = 0;   // launches run with all blocks resident together
 
 void launch_exec(const char *name, dim3 grid, dim3 block, size_t lds, const std::function<void()> &body) {
   const int n = (int)(block.x * block.y * block.z);
   if (n < 1 || n > 1024 || (n % 64) != 0) die("block size");
   g_kernel = name;
-  g_block.n = n;
-  g_block.count = 0;
-  g_block.nw = 0;
-  for (int lg = 0; lg <= 6; ++lg)
-    for (int gi = 0; gi < n >> lg; ++gi) {
-      g_groups[lg][gi].n = 1 << lg;
-      g_groups[lg][gi].count = 0;
-      g_groups[lg][gi].nw = 0;
-    }
-  void *dyn = malloc(lds ? lds : 1);
-  g_dyn = dyn;
   g_body = &body;
-  for (unsigned by = 0; by < grid.y; ++by)
-    for (unsigned bx = 0; bx < grid.x; ++bx) run_block(dim3(bx, by, 0), grid, block);
-  free(dyn);
-  g_dyn = nullptr;
+  // workgroups that wait on each other run as one set of fibers
+  const bool together = strstr(name, "k_cpqr_persist") != nullptr;
+  if (together) {
+    std::vector<dim3> all;
+    for (unsigned by = 0; by < grid.y; ++by)
+      for (unsigned bx = 0; bx < grid.x; ++bx) all.push_back(dim3(bx, by, 0));
+    run_blocks(all, grid, block, lds);
+    ++g_resident_launches;
+  } else {
+    for (unsigned by = 0; by < grid.y; ++by)
+      for (unsigned bx = 0; bx < grid.x; ++bx) run_blocks({dim3(bx, by, 0)}, grid, block, lds);
+  }
   ++g_launches;
 }
 }  // namespace simt
@@ -294,7 +332,8 @@ hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned) {
 }
 hipError_t hipSetDevice(int) { return hipSuccess; }
 hipError_t hipDeviceGetAttribute(int *v, hipDeviceAttribute_t a, int) {
-  *v = a == hipDeviceAttributeMultiprocessorCount ? 4 : 163840;
+  const char *cu = getenv("SIMT_CU");
+  *v = a == hipDeviceAttributeMultiprocessorCount ? (cu ? atoi(cu) : 4) : 163840;
   return hipSuccess;
 }
 hipError_t hipFuncSetAttribute(const void *, hipFuncAttribute, int v) { return v <= 163840 ? hipSuccess : hipErrorInvalidValue; }

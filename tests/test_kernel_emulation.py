@@ -5,7 +5,8 @@ shim (each GPU thread a fiber scheduled until it blocks at a barrier; wave
 shuffles, readlane, DPP and MFMA emulated by per-group exchange; dynamic LDS a
 heap buffer of exactly the launch's size) and runs the C ABI on host buffers:
 the sketch SVD (FP32 at q = 0, 1 and FP64), the row ID, the combined call,
-the single-pass SVD, SPC-ID-ERR and a batch.  Any out-of-bounds access to a
+the single-pass SVD, SPC-ID-ERR, a batch and the one-launch pivoted QR (its
+workgroups resident together).  Any out-of-bounds access to a
 device buffer or to LDS aborts with an AddressSanitizer report; a missing
 barrier shows up as a deadlock with a per-thread state dump.  The emulated
 results also have to agree across precisions and algorithms.
@@ -79,3 +80,38 @@ def test_remaining_paths_run_clean_under_host_emulation():
     rcs = re.findall(r"^(.*?)\s+rc=(-?\d+)$", r.stdout, re.M)
     assert len(rcs) >= 18, r.stdout
     assert all(int(rc) == 0 for _, rc in rcs), rcs
+
+
+def _persist_run(mode):
+    exe = _build()
+    r = subprocess.run([exe, mode], capture_output=True, text=True, timeout=1800)
+    out = r.stdout + r.stderr
+    assert r.returncode == 0, out[-4000:]
+    assert "ERROR: AddressSanitizer" not in out and "SIMT FATAL" not in out, out[-4000:]
+    assert out.rstrip().endswith("done"), out[-2000:]
+    rcs = re.findall(r"^(.*?)\s+rc=(-?\d+)$", r.stdout, re.M)
+    assert rcs and all(int(rc) == 0 for _, rc in rcs), rcs
+    res = re.findall(r"flags (\d+) (\d+) resident launches (\d+) (\d+) same (\d)", r.stdout)
+    assert res, r.stdout
+    for f0, f1, n0, n1, same in res:
+        # the one-launch factorization ran (all its workgroups resident together),
+        # raised no flag (a timed-out wait would), and equals the per-step one bitwise
+        assert (int(n0), int(n1)) == (1, 0), res
+        assert int(f0) == 0 and int(f1) == 0, res
+        assert same == "1", res
+    return len(res)
+
+
+def test_one_launch_pivoted_qr_equals_per_step_under_host_emulation():
+    """The one-launch pivoted QR of the row ID, whose workgroups wait on each
+    other's published words, run with every workgroup of the launch resident
+    (a spin-wait iteration yields to the other threads): no out-of-bounds
+    access, no deadlock, and pivots and P equal the per-step factorization's
+    bit for bit (s = 64 and 4096, m with an incomplete last workgroup)."""
+    assert _persist_run("persist-quick") == 2
+
+
+@pytest.mark.skipif(os.environ.get("DSK_EMU_FULL") != "1", reason="about three minutes; set DSK_EMU_FULL=1")
+def test_one_launch_pivoted_qr_all_widths_under_host_emulation():
+    """As above, adding s = 256 (FP64) and s = 1024 with 48 workgroups."""
+    assert _persist_run("persist") == 4
