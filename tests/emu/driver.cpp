@@ -2,10 +2,14 @@
 // AddressSanitizer, any out-of-bounds access of a kernel (device buffers and
 // LDS) aborts the run with a report; a missing barrier shows up as a deadlock.
 // Modes: "quick" (one configuration per path), "svd", "batch", "more", "persist"
-// ("persist-quick": its two smaller cases), "all".  "persist" runs the one-launch pivoted QR (its workgroups waiting on
+// ("persist-quick": its two smaller cases), "streams" ("streams-quick": one small
+// case each, nine small batch problems), "all".  SIMT_STREAMS=defer:<order> runs
+// the streams' work in another interleaving (see simt_rt.cpp).  "persist" runs the one-launch pivoted QR (its workgroups waiting on
 // each other's published words) with all blocks of the launch resident together,
 // and compares it bitwise with the per-step factorization.
 #include <cmath>
+#include <initializer_list>
+#include <utility>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -17,6 +21,17 @@
 
 namespace simt {
 extern long long g_resident_launches;
+void sync_all();   // run every queued stream item (deferred streams)
+}
+
+// FNV-1a over a set of output buffers
+static unsigned long long fnv(std::initializer_list<std::pair<const void *, size_t>> bufs) {
+  unsigned long long hsh = 1469598103934665603ull;
+  for (const auto &b : bufs) {
+    const unsigned char *p = (const unsigned char *)b.first;
+    for (size_t i = 0; i < b.second; ++i) hsh = (hsh ^ p[i]) * 1099511628211ull;
+  }
+  return hsh;
 }
 
 static std::vector<double> make_A(int64_t m, int N, int r, unsigned seed, double noise) {
@@ -49,6 +64,7 @@ static std::vector<int64_t> di_index(int N, int f) {
 
 
 static int check(const char *what, int rc) {
+  simt::sync_all();
   printf("%-44s rc=%d\n", what, rc);
   fflush(stdout);
   return rc;
@@ -302,6 +318,93 @@ int main(int argc, char **argv) {
     printf("%-44s rc=%d\n", "argument errors as documented", ok ? 0 : 1);
     if (!ok) printf("   codes %d %d %d %d %d %d\n", e1, e2, e3, e4, e5, e6);
   }
+  // ---- entry points that run work on several streams (the combined call, the
+  // single-pass SVD in each of its three worker paths, a batch over 8 workers):
+  // a hash of every output, to compare runs under different stream interleavings
+  const bool streams = which == "streams" || which == "streams-quick";
+  if (streams) {
+    struct Cfg { int64_t m; int N, f, k, f64; };
+    std::vector<Cfg> cfgs = {{200, 32, 4, 20, 0}, {150, 32, 4, 20, 1}, {180, 32, 2, 60, 0}};
+    if (which == "streams-quick") cfgs = {{120, 32, 4, 12, 0}};
+    for (const Cfg &c : cfgs) {
+      const int64_t n = (int64_t)c.N * c.N;
+      auto A64 = make_A(c.m, c.N, 40, 500 + (unsigned)c.m, 1e-3);
+      std::vector<float> A32(A64.begin(), A64.end());
+      void *Av = c.f64 ? (void *)A64.data() : (void *)A32.data();
+      const size_t we = c.f64 ? 8 : 4;
+      auto idx = di_index(c.N, c.f);
+      dsk_restriction R{};
+      R.kind = DSK_R_INDEX;
+      R.s = (int64_t)idx.size();
+      R.index = idx.data();
+      R.ny = R.nx = c.N;
+      R.sy = R.sx = c.f;
+      std::vector<char> U(c.m * c.k * we), V(n * c.k * we), rows(c.k * n * we);
+      std::vector<double> S(c.k), P(c.m * c.k);
+      std::vector<int64_t> I(c.k);
+      dsk_info a{}, b{};
+      char nm[128];
+      snprintf(nm, sizeof nm, "svd_id m=%lld k=%d f64=%d", (long long)c.m, c.k, c.f64);
+      check(nm, dsk_sketch_svd_id(h, Av, c.f64 ? DSK_F64 : DSK_F32, c.m, n, n, c.k, &R, 1, 0, &o, U.data(), S.data(),
+                                  V.data(), I.data(), P.data(), rows.data(), &a, &b));
+      printf("   hash %016llx flags %d %d\n", fnv({{U.data(), U.size()}, {S.data(), S.size() * 8}, {V.data(), V.size()},
+                                                {I.data(), I.size() * 8}, {P.data(), P.size() * 8},
+                                                {rows.data(), rows.size()}}), a.flags, b.flags);
+      snprintf(nm, sizeof nm, "svd single pass m=%lld k=%d f64=%d", (long long)c.m, c.k, c.f64);
+      check(nm, dsk_sketch_svd_sp(h, Av, c.f64 ? DSK_F64 : DSK_F32, c.m, n, n, c.k, &R, &o, U.data(), S.data(),
+                                  V.data(), &a));
+      printf("   hash %016llx flags %d\n", fnv({{U.data(), U.size()}, {S.data(), S.size() * 8}, {V.data(), V.size()}}),
+             a.flags);
+    }
+  }
+  if (streams) {
+    struct Inst { int64_t m; int N, k, f, f64, q; };
+    std::vector<Inst> ins = {{231, 32, 18, 2, 1, 2}, {199, 64, 22, 4, 0, 1}, {138, 32, 11, 4, 0, 2},
+                             {186, 32, 12, 4, 0, 1}, {198, 64, 19, 4, 0, 0}, {173, 32, 37, 4, 1, 0},
+                             {144, 32, 16, 2, 0, 2}, {188, 32, 14, 4, 0, 0}, {138, 64, 11, 4, 0, 1}};
+    if (which == "streams-quick")   // nine small problems: still eight workers
+      for (size_t i = 0; i < ins.size(); ++i) ins[i] = {70 + 7 * (int64_t)i, 16, 6 + (int)(i % 4), 2, (int)(i % 4 == 0), (int)(i % 3)};
+    std::vector<std::vector<double>> A64s, Ss;
+    std::vector<std::vector<float>> A32s;
+    std::vector<std::vector<int64_t>> idxs;
+    std::vector<std::vector<char>> Us, Vs;
+    std::vector<dsk_problem> pr;
+    for (size_t i = 0; i < ins.size(); ++i) {
+      const Inst &t = ins[i];
+      const int64_t n = (int64_t)t.N * t.N;
+      const size_t we = t.f64 ? 8 : 4;
+      A64s.push_back(make_A(t.m, t.N, 30, 700 + (unsigned)i, 1e-3));
+      A32s.emplace_back(A64s.back().begin(), A64s.back().end());
+      idxs.push_back(di_index(t.N, t.f));
+      Us.emplace_back(t.m * t.k * we);
+      Vs.emplace_back(n * t.k * we);
+      Ss.emplace_back(t.k);
+    }
+    for (size_t i = 0; i < ins.size(); ++i) {
+      const Inst &t = ins[i];
+      dsk_problem p{};
+      p.A = t.f64 ? (const void *)A64s[i].data() : (const void *)A32s[i].data();
+      p.dtype = t.f64 ? DSK_F64 : DSK_F32;
+      p.m = t.m;
+      p.n = (int64_t)t.N * t.N;
+      p.lda = p.n;
+      p.k = t.k;
+      p.q = t.q;
+      p.R.kind = DSK_R_INDEX;
+      p.R.s = (int64_t)idxs[i].size();
+      p.R.index = idxs[i].data();
+      p.U = Us[i].data();
+      p.S = Ss[i].data();
+      p.V = Vs[i].data();
+      pr.push_back(p);
+    }
+    int nw = 0;
+    check("batched eager, 9 problems", dsk_sketch_svd_batched(h, (int)pr.size(), pr.data(), &o, 0, &nw));
+    for (size_t i = 0; i < ins.size(); ++i)
+      printf("   hash %016llx problem %zu workers %d\n",
+             fnv({{Us[i].data(), Us[i].size()}, {Ss[i].data(), Ss[i].size() * 8}, {Vs[i].data(), Vs[i].size()}}), i, nw);
+  }
+
   // ---- one-launch pivoted QR against the per-step one, bitwise
   if (persist) {
     struct Cfg { int64_t m; int N, f, k, f64; };

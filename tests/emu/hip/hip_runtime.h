@@ -35,6 +35,7 @@ uint64_t *slots();                          // per-block exchange slots: 1024 th
 void *dyn_lds();
 int block_linear();                         // resident-block index of this thread (per-block static LDS)
 void yield();                               // a spin-wait iteration: let the other threads run
+void sync_all();                            // deferred streams: run every queued item
 [[noreturn]] void die(const char *msg);
 void launch_impl(const char *name, dim3 grid, dim3 block, size_t lds, void *stream, std::function<void()> body);
 template <typename T>

@@ -33,6 +33,9 @@ simt_swap:
 .size simt_swap, .-simt_swap
 )");
 
+#include <algorithm>
+#include <deque>
+#include <random>
 #include <string>
 
 namespace simt {
@@ -247,12 +250,25 @@ struct ihipGraph {
 struct ihipGraphExec {
   std::vector<Op> ops;
 };
+// A queued stream item: an operation, or a wait for another stream to have
+// completed `pos` items (hipStreamWaitEvent).
+struct Item {
+  bool wait = false;
+  Op op;
+  ihipStream_t *src = nullptr;
+  long long pos = 0;
+};
 struct ihipStream_t {
   bool capturing = false;
   ihipGraph *g = nullptr;
+  int id = 0;
+  std::deque<Item> q;
+  long long issued = 0, done = 0;
 };
 struct ihipEvent_t {
   ihipGraph *g = nullptr;
+  ihipStream_t *src = nullptr;   // deferred streams: the stream and item count it marks
+  long long pos = 0;
 };
 
 static void run_op(const Op &o) {
@@ -260,19 +276,102 @@ static void run_op(const Op &o) {
   else simt::launch_exec(o.name.c_str(), o.grid, o.block, o.lds, o.body);
 }
 
+// Streams run operations as they are enqueued, in host issue order, unless
+// SIMT_STREAMS=defer:<order>: then every stream queues its work (waits on
+// events included) and the queues advance only when the host synchronises,
+// one item at a time from a stream chosen among those whose front item can
+// run: order 0 the stream created first, 1 the one created last, any other
+// value a seeded random choice.  Work on different streams that is not
+// ordered by events then runs in different interleavings, and a race between
+// streams changes the results.
+static int g_defer = -1;
+static long long g_order = 0;
+static std::mt19937_64 g_rng;
+static std::vector<ihipStream_t *> g_streams;
+static ihipStream_t g_null_stream;
+static int g_stream_ids = 0;
+
+static long long g_items = 0, g_choices = 0, g_switches = 0;   // deferred streams: items run, steps with a
+static ihipStream_t *g_last = nullptr;                          // choice of stream, changes of stream
+static void report() {
+  fprintf(stderr, "SIMT streams: %lld items, %lld with a choice of stream, %lld stream changes\n", g_items, g_choices,
+          g_switches);
+}
+
+static bool deferred() {
+  if (g_defer < 0) {
+    const char *e = getenv("SIMT_STREAMS");
+    g_defer = (e && strncmp(e, "defer", 5) == 0) ? 1 : 0;
+    if (g_defer && e[5] == ':') g_order = atoll(e + 6);
+    g_rng.seed((uint64_t)g_order);
+    g_streams.push_back(&g_null_stream);
+    if (g_defer) atexit(report);
+  }
+  return g_defer == 1;
+}
+static ihipStream_t *stream_of(hipStream_t s) { return s ? s : &g_null_stream; }
+
+static bool front_ready(const ihipStream_t *x) {
+  if (x->q.empty()) return false;
+  const Item &f = x->q.front();
+  return !f.wait || f.src->done >= f.pos;
+}
+
+static void drain(const std::function<bool()> &satisfied) {
+  while (!satisfied()) {
+    std::vector<ihipStream_t *> r;
+    for (ihipStream_t *x : g_streams)
+      if (front_ready(x)) r.push_back(x);
+    if (r.empty()) simt::die("streams deadlocked (a wait that no queued work satisfies)");
+    ihipStream_t *x = g_order == 0 ? r.front() : g_order == 1 ? r.back() : r[g_rng() % r.size()];
+    g_items += 1;
+    if (r.size() > 1) g_choices += 1;
+    if (x != g_last) g_switches += 1;
+    g_last = x;
+    Item it = std::move(x->q.front());
+    x->q.pop_front();
+    if (!it.wait) run_op(it.op);
+    x->done += 1;
+  }
+}
+static void drain_all() {
+  drain([] {
+    for (ihipStream_t *x : g_streams)
+      if (!x->q.empty()) return false;
+    return true;
+  });
+}
+namespace simt {
+void sync_all() {
+  if (deferred()) drain_all();
+}
+}  // namespace simt
+
+static void submit(hipStream_t st, Op o) {
+  ihipStream_t *s = st;
+  if (s && s->capturing) {
+    s->g->ops.push_back(std::move(o));
+    return;
+  }
+  if (!deferred()) {
+    run_op(o);
+    return;
+  }
+  ihipStream_t *x = stream_of(st);
+  Item it;
+  it.op = std::move(o);
+  x->q.push_back(std::move(it));
+  x->issued += 1;
+}
+
 namespace simt {
 void launch_impl(const char *name, dim3 grid, dim3 block, size_t lds, void *stream, std::function<void()> body) {
-  ihipStream_t *s = (ihipStream_t *)stream;
-  Op o{name, grid, block, lds, std::move(body)};
-  if (s && s->capturing) s->g->ops.push_back(std::move(o));
-  else run_op(o);
+  submit((hipStream_t)stream, Op{name, grid, block, lds, std::move(body)});
 }
 }  // namespace simt
 
 static void host_op(hipStream_t s, std::function<void()> f) {
-  Op o{"host", dim3(), dim3(), (size_t)-1, std::move(f)};
-  if (s && s->capturing) s->g->ops.push_back(std::move(o));
-  else run_op(o);
+  submit(s, Op{"host", dim3(), dim3(), (size_t)-1, std::move(f)});
 }
 
 hipError_t hipMalloc(void **p, size_t n) {
@@ -283,6 +382,7 @@ hipError_t hipMalloc(void **p, size_t n) {
   return hipSuccess;
 }
 hipError_t hipFree(void *p) {
+  simt::sync_all();   // hipFree waits for the device
   free(p);
   return hipSuccess;
 }
@@ -294,13 +394,27 @@ hipError_t hipMemsetAsync(void *d, int v, size_t n, hipStream_t st) {
   host_op(st, [=] { memset(d, v, n); });
   return hipSuccess;
 }
-hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
-hipError_t hipDeviceSynchronize() { return hipSuccess; }
+hipError_t hipStreamSynchronize(hipStream_t s) {
+  if (deferred()) {
+    ihipStream_t *x = stream_of(s);
+    drain([x] { return x->q.empty(); });
+  }
+  return hipSuccess;
+}
+hipError_t hipDeviceSynchronize() {
+  simt::sync_all();
+  return hipSuccess;
+}
 hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned) {
+  deferred();
   *s = new ihipStream_t();
+  (*s)->id = ++g_stream_ids;
+  g_streams.push_back(*s);
   return hipSuccess;
 }
 hipError_t hipStreamDestroy(hipStream_t s) {
+  if (deferred()) drain([s] { return s->q.empty(); });
+  g_streams.erase(std::remove(g_streams.begin(), g_streams.end(), s), g_streams.end());
   delete s;
   return hipSuccess;
 }
@@ -315,18 +429,38 @@ hipError_t hipEventDestroy(hipEvent_t e) {
 }
 hipError_t hipEventRecord(hipEvent_t e, hipStream_t s) {
   e->g = (s && s->capturing) ? s->g : nullptr;
+  e->src = nullptr;
+  if (!e->g && deferred()) {
+    e->src = stream_of(s);
+    e->pos = e->src->issued;
+  }
   return hipSuccess;
 }
 hipError_t hipEventElapsedTime(float *ms, hipEvent_t, hipEvent_t) {
   *ms = 0.f;
   return hipSuccess;
 }
-hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
+hipError_t hipEventSynchronize(hipEvent_t e) {
+  if (deferred() && e->src) {
+    ihipStream_t *x = e->src;
+    const long long pos = e->pos;
+    drain([x, pos] { return x->done >= pos; });
+  }
+  return hipSuccess;
+}
 hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned) {
   if (e->g && s && !s->capturing) {
     s->capturing = true;
     s->g = e->g;
     e->g->joined.push_back(s);
+  } else if (deferred() && e->src && !(s && s->capturing)) {
+    ihipStream_t *x = stream_of(s);
+    Item it;
+    it.wait = true;
+    it.src = e->src;
+    it.pos = e->pos;
+    x->q.push_back(std::move(it));
+    x->issued += 1;
   }
   return hipSuccess;
 }
@@ -359,8 +493,8 @@ hipError_t hipGraphInstantiate(hipGraphExec_t *x, hipGraph_t g, void *, char *, 
   *x = new ihipGraphExec{g->ops};
   return hipSuccess;
 }
-hipError_t hipGraphLaunch(hipGraphExec_t x, hipStream_t) {
-  for (const Op &o : x->ops) run_op(o);
+hipError_t hipGraphLaunch(hipGraphExec_t x, hipStream_t s) {
+  for (const Op &o : x->ops) submit(s, o);
   return hipSuccess;
 }
 hipError_t hipGraphDestroy(hipGraph_t g) {

@@ -9,7 +9,9 @@ the single-pass SVD, SPC-ID-ERR, a batch and the one-launch pivoted QR (its
 workgroups resident together).  Any out-of-bounds access to a
 device buffer or to LDS aborts with an AddressSanitizer report; a missing
 barrier shows up as a deadlock with a per-thread state dump.  The emulated
-results also have to agree across precisions and algorithms.
+results also have to agree across precisions and algorithms, and the entry
+points that run work on several streams have to give the same bits in every
+interleaving of their streams' queued work.
 """
 import importlib.util
 import os
@@ -115,3 +117,62 @@ def test_one_launch_pivoted_qr_equals_per_step_under_host_emulation():
 def test_one_launch_pivoted_qr_all_widths_under_host_emulation():
     """As above, adding s = 256 (FP64) and s = 1024 with 48 workgroups."""
     assert _persist_run("persist") == 4
+
+
+def _streams_runs(mode, orders):
+    """Run `mode` with immediate streams and with each deferred order, in
+    parallel processes; return {order: stdout}."""
+    exe = _build()
+    procs = {}
+    for order in [None, *orders]:
+        env = dict(os.environ)
+        env.pop("SIMT_STREAMS", None)
+        if order is not None:
+            env["SIMT_STREAMS"] = f"defer:{order}"
+        procs[order] = subprocess.Popen([exe, mode], stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True,
+                                        env=env)
+    outs = {}
+    for order, p in procs.items():
+        so, se = p.communicate(timeout=1800)
+        out = so + se
+        assert p.returncode == 0, (order, out[-4000:])
+        assert "ERROR: AddressSanitizer" not in out and "SIMT FATAL" not in out, (order, out[-4000:])
+        assert so.rstrip().endswith("done"), (order, out[-2000:])
+        rcs = re.findall(r"^(.*?)\s+rc=(-?\d+)$", so, re.M)
+        assert rcs and all(int(rc) == 0 for _, rc in rcs), (order, rcs)
+        if order is not None:
+            st = re.search(r"SIMT streams: (\d+) items, (\d+) with a choice of stream", se)
+            assert st and int(st.group(2)) > 0, (order, se[-2000:])
+        outs[order] = so
+    return outs
+
+
+def _hashes(so):
+    return re.findall(r"hash ([0-9a-f]{16}) (.*)$", so, re.M)
+
+
+def test_multi_stream_entry_points_are_interleaving_independent():
+    """The combined SVD + ID call (row ID on a worker stream), the single-pass
+    SVD (Q and R on a worker stream beside the pass over A) and a batch over
+    eight worker streams, run with each stream's work queued and the queues
+    advanced in three different interleavings (main stream first, workers
+    first, seeded random): every output is bitwise the same as in issue
+    order, so no work on one stream reads or overwrites what another stream
+    has not ordered by an event.  (Removing the single-pass join changes the
+    outputs under the main-stream-first order.)"""
+    outs = _streams_runs("streams-quick", [0, 1, 9001])
+    ref = _hashes(outs[None])
+    assert len(ref) == 11, outs[None]
+    for order, so in outs.items():
+        assert _hashes(so) == ref, order
+
+
+@pytest.mark.skipif(os.environ.get("DSK_EMU_FULL") != "1", reason="about three minutes; set DSK_EMU_FULL=1")
+def test_multi_stream_entry_points_all_paths_interleaving_independent():
+    """As above on FP32 and FP64 and on the single-pass path with ell > 64, and
+    the batch at the batched test's sizes."""
+    outs = _streams_runs("streams", [0, 1, 12345, 777])
+    ref = _hashes(outs[None])
+    assert len(ref) == 15, outs[None]
+    for order, so in outs.items():
+        assert _hashes(so) == ref, order
