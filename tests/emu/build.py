@@ -71,7 +71,8 @@ def build(verbose: bool = False) -> str:
         open(os.path.join(gen, os.path.basename(p)), "w").write(
             open(p).read().replace('"../../include/dsketch.h"', '"dsketch.h"'))
     srcs += [os.path.join(HERE, "simt_rt.cpp"), os.path.join(HERE, "driver.cpp")]
-    flags = ["-std=c++17", "-O1", "-g", "-fsanitize=address", "-fno-omit-frame-pointer", "-I", HERE, "-I", gen,
+    flags = ["-std=c++17", "-O1", "-g", "-fsanitize=address,alignment", "-fno-sanitize-recover=alignment",
+             "-fno-omit-frame-pointer", "-I", HERE, "-I", gen,
              "-I", os.path.join(ROOT, "include"), "-Wno-unused-result", "-Wno-unknown-attributes",
              "-Wno-ignored-attributes", "-w"]
 
@@ -84,7 +85,8 @@ def build(verbose: bool = False) -> str:
 
     with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 4)) as ex:
         objs = list(ex.map(comp, srcs))
-    r = subprocess.run([cxx, "-fsanitize=address", "-pthread", *objs, "-o", exe], capture_output=True, text=True)
+    r = subprocess.run([cxx, "-fsanitize=address,alignment", "-pthread", *objs, "-o", exe], capture_output=True,
+                       text=True)
     if r.returncode:
         raise RuntimeError(f"host emulation link failed:\n{r.stderr[-3000:]}")
     if verbose:

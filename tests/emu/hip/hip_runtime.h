@@ -223,10 +223,49 @@ inline double __longlong_as_double(long long l) { double r; memcpy(&r, &l, 8); r
 inline float __uint_as_float(unsigned u) { float r; memcpy(&r, &u, 4); return r; }
 inline unsigned __float_as_uint(float f) { unsigned r; memcpy(&r, &f, 4); return r; }
 
-struct uint4 { unsigned x, y, z, w; };
-struct float4 { float x, y, z, w; };
-struct double2 { double x, y; };
-struct uint2 { unsigned x, y; };
+// HIP's vector types are aligned to their size; so are these, and their
+// copies and assignments go member by member, so that the alignment sanitizer
+// reports every load or store through a misaligned vector pointer (as a
+// 16-byte LDS access at an 8-byte boundary would be on the device)
+#define SIMT_VEC4(T, E, A)                                                             \
+  struct alignas(A) T {                                                                \
+    E x, y, z, w;                                                                      \
+    T() = default;                                                                     \
+    constexpr T(E a, E b, E c, E d) : x(a), y(b), z(c), w(d) {}                        \
+    T(const T &o) : x(o.x), y(o.y), z(o.z), w(o.w) {}                                  \
+    T &operator=(const T &o) {                                                         \
+      x = o.x;                                                                         \
+      y = o.y;                                                                         \
+      z = o.z;                                                                         \
+      w = o.w;                                                                         \
+      return *this;                                                                    \
+    }                                                                                  \
+  };
+#define SIMT_VEC2(T, E, A)                                                             \
+  struct alignas(A) T {                                                                \
+    E x, y;                                                                            \
+    T() = default;                                                                     \
+    constexpr T(E a, E b) : x(a), y(b) {}                                              \
+    T(const T &o) : x(o.x), y(o.y) {}                                                  \
+    T &operator=(const T &o) {                                                         \
+      x = o.x;                                                                         \
+      y = o.y;                                                                         \
+      return *this;                                                                    \
+    }                                                                                  \
+  };
+// bit casts through memcpy (the vector types above are not trivially copyable)
+template <class To, class From>
+inline To simt_bit_cast(const From &f) {
+  static_assert(sizeof(To) == sizeof(From), "bit cast between types of different sizes");
+  To t;
+  memcpy((void *)&t, (const void *)&f, sizeof(To));
+  return t;
+}
+#define __builtin_bit_cast(T, v) simt_bit_cast<T>(v)
+SIMT_VEC4(uint4, unsigned, 16)
+SIMT_VEC4(float4, float, 16)
+SIMT_VEC2(double2, double, 16)
+SIMT_VEC2(uint2, unsigned, 8)
 inline uint4 make_uint4(unsigned a, unsigned b, unsigned c, unsigned d) { return uint4{a, b, c, d}; }
 inline float4 make_float4(float a, float b, float c, float d) { return float4{a, b, c, d}; }
 inline double2 make_double2(double a, double b) { return double2{a, b}; }

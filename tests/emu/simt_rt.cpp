@@ -76,7 +76,8 @@ struct BlockState {
   Bar block;
   Bar groups[7][1024];
   uint64_t slots[1024 * 8];
-  void *dyn = nullptr;
+  void *dyn = nullptr;       // dynamic LDS: 8 bytes past a 16-byte boundary, the weakest
+  void *dyn_raw = nullptr;   // alignment the device gives an `extern __shared__ double[]`
 };
 static BlockState *g_bs[MAXB];
 static int g_cur_blk = 0;
@@ -159,7 +160,10 @@ static void run_blocks(const std::vector<dim3> &blocks, dim3 g, dim3 bd, size_t 
         B.groups[lg][gi].count = 0;
         B.groups[lg][gi].waiters.clear();
       }
-    B.dyn = malloc(lds ? lds : 1);
+    B.dyn_raw = aligned_alloc(16, ((lds + 8) + 15) & ~(size_t)15);
+    B.dyn = (char *)B.dyn_raw + 8;
+    // the bytes past the launch's size are poisoned, so the bound stays exact
+    ASAN_POISON_MEMORY_REGION((char *)B.dyn + lds, (((lds + 8) + 15) & ~(size_t)15) - 8 - lds);
   }
   const int n = nb * per;
   g_n = n;
@@ -206,8 +210,10 @@ static void run_blocks(const std::vector<dim3> &blocks, dim3 g, dim3 bd, size_t 
   }
   for (int f = 0; f < n; ++f) ASAN_UNPOISON_MEMORY_REGION(g_fib[f].stack, STACK);
   for (int bi = 0; bi < nb; ++bi) {
-    free(g_bs[bi]->dyn);
-    g_bs[bi]->dyn = nullptr;
+    const size_t tot = ((lds + 8) + 15) & ~(size_t)15;
+    ASAN_UNPOISON_MEMORY_REGION(g_bs[bi]->dyn_raw, tot);
+    free(g_bs[bi]->dyn_raw);
+    g_bs[bi]->dyn_raw = g_bs[bi]->dyn = nullptr;
   }
   g_cur_blk = 0;
 }
