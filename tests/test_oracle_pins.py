@@ -302,6 +302,75 @@ def test_spc_id_lifting_operator_identity():
     np.testing.assert_array_equal(P[I], np.eye(4))
 
 
+def test_spc_id_exact_lift_closed_form():
+    # A_f = X W with W(:, coarse nodes) = I, so that A_c = A_f D = X (full
+    # column rank): with r = s the lifting operator is A_c^+ A_f = W, and with
+    # k = s the ID is exact, so P_c A_c(I_c, :) T_r reproduces A_f
+    rng = np.random.default_rng(41)
+    N, f, m = 8, 2, 30
+    idx = restrict.di_index_2d(N, N, f, f)
+    s = idx.size
+    X = rng.standard_normal((m, s))
+    W = rng.standard_normal((s, N * N))
+    W[:, idx] = np.eye(s)
+    A = X @ W
+    R = {"kind": "index", "index": idx}
+    I, P, AcI, Tr = rowid.spc_id(A, s, R, r=s)
+    np.testing.assert_allclose(Tr, W, atol=1e-10 * np.abs(W).max())
+    np.testing.assert_allclose(P @ AcI @ Tr, A, atol=1e-9 * np.abs(A).max())
+    # r < s: the operator is X^+ U_r U_r^T X W, whose range misses the trailing
+    # left singular directions of X
+    r = 5
+    I, P, AcI, Tr = rowid.spc_id(A, 4, R, r=r)
+    U, sv, Vt = np.linalg.svd(X, full_matrices=False)
+    ref = (Vt[:r].T / sv[:r]) @ (U[:, :r].T @ A)
+    np.testing.assert_allclose(Tr, ref, atol=1e-10 * np.abs(ref).max())
+
+
+def test_spc_id_full_sampling_reduces_to_row_id():
+    # D = I (every node kept): A_c = A_f, and with r = rank(A_f) the lifting
+    # operator is the projector onto the row space, so SPC-ID returns the row
+    # ID of A_f itself
+    A = synth.lowrank(24, 40, 10, seed=42)
+    rank = np.linalg.matrix_rank(A)
+    assert rank == 10
+    R = {"kind": "index", "index": np.arange(40)}
+    I, P, AcI, Tr = rowid.spc_id(A, 6, R, r=rank)
+    I0, P0, _ = rowid.row_id(A, 6)
+    assert list(I) == list(I0)
+    np.testing.assert_allclose(P @ AcI @ Tr, P0 @ A[I0], atol=1e-9 * np.abs(A).max())
+
+
+def test_spc_id_error_within_theorem_bound():
+    # Thm. 4.1: ||A_f - P_c A_c(I_c, :) T_r||_2 is at most
+    # (eps(tau) + tau sigma_{c,r+1}^2)^{1/2} + ||A_c - P_c A_c(I_c, :)||_2 (tau + eps(tau) sigma_{c,r}^{-2})^{1/2}
+    # for every tau > 0 at which both radicands are non-negative
+    rng = np.random.default_rng(43)
+    for seed, (m, N, f, k, r) in enumerate([(40, 8, 2, 4, 8), (60, 16, 4, 6, 10), (50, 8, 2, 3, 3)]):
+        A = synth.heat_modes(m, N, seed=44 + seed, nu=0.002) + 1e-3 * rng.standard_normal((m, N * N))
+        idx = restrict.di_index_2d(N, N, f, f)
+        R = {"kind": "index", "index": idx}
+        Ac = A[:, idx]
+        I, P, AcI, Tr = rowid.spc_id(A, k, R, r=r)
+        lhs = np.linalg.norm(A - P @ AcI @ Tr, 2)
+        sc = np.linalg.svd(Ac, compute_uv=False)
+        id_err = np.linalg.norm(Ac - P @ AcI, 2)
+        checked = 0
+        for tau in np.logspace(-2, 3, 26) * (N * N / idx.size):
+            e = rowid.eps_tau(A, Ac, tau)
+            a, b = e + tau * sc[r] ** 2, tau + e / sc[r - 1] ** 2
+            if a < 0 or b < 0:
+                continue
+            checked += 1
+            assert lhs <= (math.sqrt(a) + id_err * math.sqrt(b)) * (1 + 1e-9), (seed, tau, lhs)
+        assert checked >= 10
+        # and the bound is not vacuous: its minimum over tau is within a small factor of the error
+        best = min(math.sqrt(max(rowid.eps_tau(A, Ac, t) + t * sc[r] ** 2, 0))
+                   + id_err * math.sqrt(max(t + rowid.eps_tau(A, Ac, t) / sc[r - 1] ** 2, 0))
+                   for t in np.logspace(-2, 3, 26) * (N * N / idx.size))
+        assert best <= 50 * lhs, (seed, best, lhs)
+
+
 def test_spc_id_err_full_sampling_equals_eps_tau():
     A = synth.heat_modes(24, 8, seed=8, nu=0.001)
     R = _di(8, 8, 2, 2)
