@@ -32,9 +32,54 @@ def _build():
     return mod.build()
 
 
-def test_kernels_run_clean_under_host_emulation():
-    exe = _build()
-    r = subprocess.run([exe, "quick"], capture_output=True, text=True, timeout=900)
+# the default emulation runs, started together on first use (each is one
+# single-threaded process) and collected by the tests that read them
+_DEFAULT_RUNS = [("quick", None), ("persist-quick", None), ("streams-quick", None), ("streams-quick", 0),
+                 ("streams-quick", 1), ("streams-quick", 9001)]
+
+
+class _Run:
+    def __init__(self, returncode, stdout, stderr):
+        self.returncode, self.stdout, self.stderr = returncode, stdout, stderr
+
+
+def _spawn(exe, mode, order):
+    env = dict(os.environ)
+    env.pop("SIMT_STREAMS", None)
+    if order is not None:
+        env["SIMT_STREAMS"] = f"defer:{order}"
+    return subprocess.Popen([exe, mode], stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
+
+
+def _collect(p):
+    so, se = p.communicate(timeout=1800)
+    return _Run(p.returncode, so, se)
+
+
+@pytest.fixture(scope="module")
+def emu():
+    procs = {}
+    results = {}
+
+    def get(mode, order=None):
+        if not procs:
+            exe = _build()
+            for key in _DEFAULT_RUNS:
+                procs[key] = _spawn(exe, *key)
+        key = (mode, order)
+        if key not in results:
+            results[key] = _collect(procs[key])
+        return results[key]
+
+    yield get
+    for p in procs.values():   # runs no test collected (a -k selection) end with the module
+        if p.poll() is None:
+            p.kill()
+            p.communicate()
+
+
+def test_kernels_run_clean_under_host_emulation(emu):
+    r = emu("quick")
     out = r.stdout + r.stderr
     assert r.returncode == 0, out[-4000:]
     assert "ERROR: AddressSanitizer" not in out, out[-4000:]
@@ -84,9 +129,7 @@ def test_remaining_paths_run_clean_under_host_emulation():
     assert all(int(rc) == 0 for _, rc in rcs), rcs
 
 
-def _persist_run(mode):
-    exe = _build()
-    r = subprocess.run([exe, mode], capture_output=True, text=True, timeout=1800)
+def _check_persist(r):
     out = r.stdout + r.stderr
     assert r.returncode == 0, out[-4000:]
     assert "ERROR: AddressSanitizer" not in out and "SIMT FATAL" not in out, out[-4000:]
@@ -104,38 +147,31 @@ def _persist_run(mode):
     return len(res)
 
 
-def test_one_launch_pivoted_qr_equals_per_step_under_host_emulation():
+def test_one_launch_pivoted_qr_equals_per_step_under_host_emulation(emu):
     """The one-launch pivoted QR of the row ID, whose workgroups wait on each
     other's published words, run with every workgroup of the launch resident
     (a spin-wait iteration yields to the other threads): no out-of-bounds
     access, no deadlock, and pivots and P equal the per-step factorization's
     bit for bit (s = 64 and 4096, m with an incomplete last workgroup)."""
-    assert _persist_run("persist-quick") == 2
+    assert _check_persist(emu("persist-quick")) == 2
 
 
 @pytest.mark.skipif(os.environ.get("DSK_EMU_FULL") != "1", reason="about three minutes; set DSK_EMU_FULL=1")
 def test_one_launch_pivoted_qr_all_widths_under_host_emulation():
     """As above, adding s = 256 (FP64) and s = 1024 with 48 workgroups."""
-    assert _persist_run("persist") == 4
-
-
-def _streams_runs(mode, orders):
-    """Run `mode` with immediate streams and with each deferred order, in
-    parallel processes; return {order: stdout}."""
     exe = _build()
-    procs = {}
-    for order in [None, *orders]:
-        env = dict(os.environ)
-        env.pop("SIMT_STREAMS", None)
-        if order is not None:
-            env["SIMT_STREAMS"] = f"defer:{order}"
-        procs[order] = subprocess.Popen([exe, mode], stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True,
-                                        env=env)
+    r = subprocess.run([exe, "persist"], capture_output=True, text=True, timeout=1800)
+    assert _check_persist(r) == 4
+
+
+def _check_streams(runs):
+    """runs: {order: _Run} for one mode with immediate streams (None) and with
+    each deferred order; returns {order: stdout}."""
     outs = {}
-    for order, p in procs.items():
-        so, se = p.communicate(timeout=1800)
+    for order, r in runs.items():
+        so, se = r.stdout, r.stderr
         out = so + se
-        assert p.returncode == 0, (order, out[-4000:])
+        assert r.returncode == 0, (order, out[-4000:])
         assert "ERROR: AddressSanitizer" not in out and "SIMT FATAL" not in out, (order, out[-4000:])
         assert so.rstrip().endswith("done"), (order, out[-2000:])
         rcs = re.findall(r"^(.*?)\s+rc=(-?\d+)$", so, re.M)
@@ -151,7 +187,7 @@ def _hashes(so):
     return re.findall(r"hash ([0-9a-f]{16}) (.*)$", so, re.M)
 
 
-def test_multi_stream_entry_points_are_interleaving_independent():
+def test_multi_stream_entry_points_are_interleaving_independent(emu):
     """The combined SVD + ID call (row ID on a worker stream), the single-pass
     SVD (Q and R on a worker stream beside the pass over A) and a batch over
     eight worker streams, run with each stream's work queued and the queues
@@ -160,7 +196,7 @@ def test_multi_stream_entry_points_are_interleaving_independent():
     order, so no work on one stream reads or overwrites what another stream
     has not ordered by an event.  (Removing the single-pass join changes the
     outputs under the main-stream-first order.)"""
-    outs = _streams_runs("streams-quick", [0, 1, 9001])
+    outs = _check_streams({o: emu("streams-quick", o) for o in (None, 0, 1, 9001)})
     ref = _hashes(outs[None])
     assert len(ref) == 11, outs[None]
     for order, so in outs.items():
@@ -171,7 +207,9 @@ def test_multi_stream_entry_points_are_interleaving_independent():
 def test_multi_stream_entry_points_all_paths_interleaving_independent():
     """As above on FP32 and FP64 and on the single-pass path with ell > 64, and
     the batch at the batched test's sizes."""
-    outs = _streams_runs("streams", [0, 1, 12345, 777])
+    exe = _build()
+    procs = {o: _spawn(exe, "streams", o) for o in (None, 0, 1, 12345, 777)}
+    outs = _check_streams({o: _collect(p) for o, p in procs.items()})
     ref = _hashes(outs[None])
     assert len(ref) == 15, outs[None]
     for order, so in outs.items():
