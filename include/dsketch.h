@@ -112,10 +112,17 @@ typedef struct {       /* host struct, filled when passed */
 void dsk_opts_default(dsk_opts *o);
 
 /* Create a handle bound to `device` and `stream` (a hipStream_t; NULL = default stream).
-   *h receives the handle.  Errors: -1 (h NULL), DSK_ERR_* (HIP). */
+   *h receives the handle.  A handle owns a device arena (grown on demand), status
+   words and, once a call needs them, worker streams with arenas of their own; calls
+   on one handle must not overlap (one host thread at a time).
+   Errors: -1 (h NULL), DSK_ERR_* (HIP). */
 int dsk_create(dsk_handle **h, int device, void *stream);
+/* Wait for the handle's stream and worker streams, then free everything the handle
+   owns (arenas, status words, worker streams, events).  Errors: -1 (h NULL). */
 int dsk_destroy(dsk_handle *h);
-/* Rebind the handle's stream. */
+/* Rebind the handle's stream: later calls enqueue on `stream` (a hipStream_t, NULL =
+   default stream).  Work already enqueued stays where it is; ordering the old stream
+   before the new one is the caller's.  Errors: -1 (h NULL). */
 int dsk_set_stream(dsk_handle *h, void *stream);
 
 /*
