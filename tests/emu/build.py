@@ -89,6 +89,9 @@ def build(verbose: bool = False) -> str:
                        text=True)
     if r.returncode:
         raise RuntimeError(f"host emulation link failed:\n{r.stderr[-3000:]}")
+    for old in glob.glob(os.path.join(OUT, "driver_*")):   # earlier builds of other inputs
+        if old != exe:
+            os.remove(old)
     if verbose:
         print("built", exe)
     return exe
