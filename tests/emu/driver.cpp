@@ -2,7 +2,8 @@
 // AddressSanitizer, any out-of-bounds access of a kernel (device buffers and
 // LDS) aborts the run with a report; a missing barrier shows up as a deadlock.
 // Modes: "quick" (one configuration per path), "svd", "batch", "more", "persist"
-// ("persist-quick": its two smaller cases), "streams" ("streams-quick": one small
+// ("persist-quick": its two smaller cases), "files <dir>" (inputs from and outputs
+// to raw files, for comparison with the oracle), "streams" ("streams-quick": one small
 // case each, nine small batch problems), "all".  SIMT_STREAMS=defer:<order> runs
 // the streams' work in another interleaving (see simt_rt.cpp).  "persist" runs the one-launch pivoted QR (its workgroups waiting on
 // each other's published words) with all blocks of the launch resident together,
@@ -62,6 +63,22 @@ static std::vector<int64_t> di_index(int N, int f) {
   return idx;
 }
 
+
+// raw little-endian arrays for the file mode
+template <class T>
+static bool read_bin(const std::string &path, std::vector<T> &v) {
+  FILE *f = fopen(path.c_str(), "rb");
+  if (!f) return false;
+  const size_t got = fread(v.data(), sizeof(T), v.size(), f);
+  fclose(f);
+  return got == v.size();
+}
+static void write_bin(const std::string &path, const void *p, size_t bytes) {
+  FILE *f = fopen(path.c_str(), "wb");
+  if (!f) return;
+  fwrite(p, 1, bytes, f);
+  fclose(f);
+}
 
 static int check(const char *what, int rc) {
   simt::sync_all();
@@ -318,6 +335,63 @@ int main(int argc, char **argv) {
     printf("%-44s rc=%d\n", "argument errors as documented", ok ? 0 : 1);
     if (!ok) printf("   codes %d %d %d %d %d %d\n", e1, e2, e3, e4, e5, e6);
   }
+  // ---- file mode: inputs written by a test (A, the index set, tau values), outputs
+  // of the main entry points written back for comparison with the FP64 oracle
+  if (which == "files" && argc > 2) {
+    const std::string dir = argv[2];
+    long long m = 0, N = 0, f = 0, k = 0, mc = 0, ntau = 0;
+    FILE *pf = fopen((dir + "/dims.txt").c_str(), "r");
+    if (!pf || fscanf(pf, "%lld %lld %lld %lld %lld %lld", &m, &N, &f, &k, &mc, &ntau) != 6) {
+      printf("files: bad dims\n");
+      return 1;
+    }
+    fclose(pf);
+    const int64_t n = N * N;
+    std::vector<double> A64(m * n), taus(ntau);
+    auto idx = di_index((int)N, (int)f);
+    if (!read_bin(dir + "/A.bin", A64) || !read_bin(dir + "/taus.bin", taus)) {
+      printf("files: missing inputs\n");
+      return 1;
+    }
+    std::vector<float> A32(A64.begin(), A64.end());
+    dsk_restriction R{};
+    R.kind = DSK_R_INDEX;
+    R.s = (int64_t)idx.size();
+    R.index = idx.data();
+    R.ny = R.nx = (int)N;
+    R.sy = R.sx = (int)f;
+    std::vector<char> U(m * k * 8), V(n * k * 8);
+    std::vector<double> S(k);
+    auto out = [&](const std::string &tag, size_t we) {
+      write_bin(dir + "/" + tag + "_U.bin", U.data(), m * k * we);
+      write_bin(dir + "/" + tag + "_S.bin", S.data(), k * 8);
+      write_bin(dir + "/" + tag + "_V.bin", V.data(), n * k * we);
+    };
+    for (int q = 0; q < 2; ++q) {
+      char nm[64];
+      snprintf(nm, sizeof nm, "files svd f64 q=%d", q);
+      check(nm, dsk_sketch_svd(h, A64.data(), DSK_F64, m, n, n, (int)k, &R, q, &o, U.data(), S.data(), V.data(),
+                               nullptr));
+      out(q ? "svd64q1" : "svd64q0", 8);
+    }
+    check("files svd f32 q=1", dsk_sketch_svd(h, A32.data(), DSK_F32, m, n, n, (int)k, &R, 1, &o, U.data(), S.data(),
+                                              V.data(), nullptr));
+    out("svd32q1", 4);
+    check("files svd single pass f64", dsk_sketch_svd_sp(h, A64.data(), DSK_F64, m, n, n, (int)k, &R, &o, U.data(),
+                                                         S.data(), V.data(), nullptr));
+    out("sp64", 8);
+    std::vector<int64_t> I(k);
+    std::vector<double> P(m * k);
+    check("files id f64 q=0", dsk_sketch_id(h, A64.data(), DSK_F64, m, n, n, (int)k, &R, 0, &o, I.data(), P.data(),
+                                            nullptr, nullptr));
+    write_bin(dir + "/id64_I.bin", I.data(), k * 8);
+    write_bin(dir + "/id64_P.bin", P.data(), m * k * 8);
+    std::vector<double> eps(ntau);
+    check("files spc_id_err f64", dsk_spc_id_err(h, A64.data(), DSK_F64, m, n, n, &R, (int)mc, taus.data(), (int)ntau,
+                                                 eps.data()));
+    write_bin(dir + "/eps64.bin", eps.data(), ntau * 8);
+  }
+
   // ---- entry points that run work on several streams (the combined call, the
   // single-pass SVD in each of its three worker paths, a batch over 8 workers):
   // a hash of every output, to compare runs under different stream interleavings

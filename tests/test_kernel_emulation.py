@@ -11,7 +11,9 @@ device buffer or to LDS aborts with an AddressSanitizer report; a missing
 barrier shows up as a deadlock with a per-thread state dump.  The emulated
 results also have to agree across precisions and algorithms, and the entry
 points that run work on several streams have to give the same bits in every
-interleaving of their streams' queued work.
+interleaving of their streams' queued work.  On a small seeded input the
+emulated outputs are compared with the FP64 oracle at the GPU parity
+tolerances.
 """
 import importlib.util
 import os
@@ -214,3 +216,82 @@ def test_multi_stream_entry_points_all_paths_interleaving_independent():
     assert len(ref) == 15, outs[None]
     for order, so in outs.items():
         assert _hashes(so) == ref, order
+
+
+def test_emulated_kernels_match_the_oracle(tmp_path):
+    """The HIP path run in host emulation against the FP64 oracle on the same
+    seeded input (120 x 16^2, direct injection 2 x 2, s = 64, k = 10, ell =
+    20), at the GPU parity tests' tolerances: sketch SVD (FP64 q = 0, 1 and
+    FP32 q = 1 against the oracle on the upcast FP32 values), single-pass SVD
+    (with its kappa(Y) term), row ID (pivots and P) and SPC-ID-ERR."""
+    import numpy as np
+
+    from oracle import restrict as ores
+    from oracle import rowid as orid
+    from oracle import sketch as osk
+    from paper_2105_01271_amd import synth
+
+    exe = _build()
+    m, N, f, k, mc = 120, 16, 2, 10, 30
+    rng = np.random.default_rng(61)
+    A = synth.heat_modes(m, N, seed=60, nu=0.002) + 1e-2 * rng.standard_normal((m, N * N))
+    idx = ores.di_index_2d(N, N, f, f)
+    taus = np.array([0.0, 1.0, 4.0, 16.0])
+    (tmp_path / "dims.txt").write_text(f"{m} {N} {f} {k} {mc} {taus.size}\n")
+    A.astype("<f8").tofile(tmp_path / "A.bin")
+    taus.astype("<f8").tofile(tmp_path / "taus.bin")
+    r = subprocess.run([exe, "files", str(tmp_path)], capture_output=True, text=True, timeout=900)
+    out = r.stdout + r.stderr
+    assert r.returncode == 0, out[-4000:]
+    assert "ERROR: AddressSanitizer" not in out and "SIMT FATAL" not in out and "runtime error" not in out, out[-4000:]
+    rcs = re.findall(r"^(.*?)\s+rc=(-?\d+)$", r.stdout, re.M)
+    assert len(rcs) == 6 and all(int(c) == 0 for _, c in rcs), r.stdout
+
+    n = N * N
+    Rd = {"kind": "index", "index": idx}
+
+    def load(tag, dt, shape):
+        return np.fromfile(tmp_path / f"{tag}.bin", dtype=dt).reshape(shape).astype(np.float64)
+
+    def svd_parts(tag, dt):
+        return load(f"{tag}_U", dt, (m, k)), load(f"{tag}_S", "<f8", (k,)), load(f"{tag}_V", dt, (n, k))
+
+    def err(Ax, U, S, V):
+        return np.linalg.norm(Ax - (U * S) @ V.T)
+
+    A32 = A.astype(np.float32).astype(np.float64)
+    for tag, Ax, q, dt, tol in [("svd64q0", A, 0, "<f8", 1e-10), ("svd64q1", A, 1, "<f8", 1e-10),
+                                ("svd32q1", A32, 1, "<f4", 1e-5)]:
+        U, S, V = svd_parts(tag, dt)
+        Uo, So, Vo = osk.tpc_svd(Ax, k, Rd, q=q)
+        assert np.abs(S - So).max() <= tol * So[0], (tag, S, So)
+        eo = err(Ax, Uo, So, Vo)
+        assert abs(err(Ax, U, S, V) - eo) <= tol * max(eo, 1e-13 * So[0]) + tol * So[0] * 1e-3, tag
+        assert np.abs(U.T @ U - np.eye(k)).max() <= 100 * tol, tag
+
+    # single pass (Alg. 3): the TPC tolerance plus (4 + ell) u kappa_F(Y) ||A||_F / sigma_1
+    U, S, V = svd_parts("sp64", "<f8")
+    Uo, So, Vo = osk.spc_svd(A, k, Rd)
+    Ac = A[:, idx]
+    ell = k + 10
+    Y = Ac[:, osk.nested_di_columns(idx.size, ell)]
+    Rf = np.linalg.qr(Y, mode="r")
+    kF = np.linalg.norm(Y) * np.linalg.norm(np.linalg.inv(Rf))
+    tol_sp = 1e-10 + (4 + ell) * 2.0 ** -53 * kF * np.linalg.norm(A) / So[0]
+    assert np.abs(S - So).max() <= tol_sp * So[0], (S, So, tol_sp)
+
+    # row ID (Alg. 4): pivots and coefficients
+    I = np.fromfile(tmp_path / "id64_I.bin", dtype="<i8")
+    P = load("id64_P", "<f8", (m, k))
+    Io, Po = orid.tpc_id(A, k, Rd, q=0)
+    assert list(I) == list(Io), (I, Io)
+    assert np.abs(P - Po).max() <= 1e-8 * max(1.0, np.abs(Po).max()), np.abs(P - Po).max()
+
+    # SPC-ID-ERR (Alg. 6)
+    eps = np.fromfile(tmp_path / "eps64.bin", dtype="<f8")
+    ref = orid.spc_id_err_curve(A, Rd, mc, taus)
+    c = m // mc
+    keep = [i for i in range(m) if (i + 1) % c == 0]
+    Gf, Gc = A[keep] @ A[keep].T, Ac[keep] @ Ac[keep].T
+    tol = np.array([1e-10 * c * (abs(np.trace(Gf - t * Gc)) + len(keep) * np.linalg.norm(Gf - t * Gc)) for t in taus])
+    assert np.all(np.abs(eps - ref) <= tol), (eps, ref, tol)
