@@ -390,6 +390,29 @@ int main(int argc, char **argv) {
     check("files spc_id_err f64", dsk_spc_id_err(h, A64.data(), DSK_F64, m, n, n, &R, (int)mc, taus.data(), (int)ntau,
                                                  eps.data()));
     write_bin(dir + "/eps64.bin", eps.data(), ntau * 8);
+    // the same matrix stored BF16 (bits from the test), q = 1
+    std::vector<uint16_t> Abf(m * n);
+    if (read_bin(dir + "/Abf.bin", Abf)) {
+      check("files svd bf16 q=1", dsk_sketch_svd(h, Abf.data(), DSK_BF16, m, n, n, (int)k, &R, 1, &o, U.data(),
+                                                 S.data(), V.data(), nullptr));
+      out("svdbfq1", 4);
+    }
+    // nearest-neighbour stencil restriction, FP64, q = 1
+    dsk_restriction Rn{};
+    Rn.kind = DSK_R_NN;
+    Rn.ny = Rn.nx = (int)N;
+    Rn.sy = Rn.sx = (int)f;
+    check("files svd nn f64 q=1", dsk_sketch_svd(h, A64.data(), DSK_F64, m, n, n, (int)k, &Rn, 1, &o, U.data(),
+                                                 S.data(), V.data(), nullptr));
+    out("svdnn64q1", 8);
+    // projection B^T = A^T Q, FP32 A and Q (ell = 2k + 3)
+    const int ellp = (int)(2 * k + 3);
+    std::vector<float> Q(m * ellp), Bt(n * ellp);
+    if (read_bin(dir + "/Q.bin", Q)) {
+      check("files project f32", dsk_project(h, A32.data(), DSK_F32, m, n, n, Q.data(), ellp, Bt.data(),
+                                             DSK_MODE_SPLIT6));
+      write_bin(dir + "/proj32.bin", Bt.data(), Bt.size() * 4);
+    }
   }
 
   // ---- entry points that run work on several streams (the combined call, the

@@ -221,9 +221,10 @@ def test_multi_stream_entry_points_all_paths_interleaving_independent():
 def test_emulated_kernels_match_the_oracle(tmp_path):
     """The HIP path run in host emulation against the FP64 oracle on the same
     seeded input (120 x 16^2, direct injection 2 x 2, s = 64, k = 10, ell =
-    20), at the GPU parity tests' tolerances: sketch SVD (FP64 q = 0, 1 and
-    FP32 q = 1 against the oracle on the upcast FP32 values), single-pass SVD
-    (with its kappa(Y) term), row ID (pivots and P) and SPC-ID-ERR."""
+    20), at the GPU parity tests' tolerances: sketch SVD (FP64 q = 0, 1; FP32
+    and BF16 storage q = 1 against the oracle on the upcast stored values; the
+    nearest-neighbour stencil restriction), the projection, the single-pass
+    SVD (with its kappa(Y) term), row ID (pivots and P) and SPC-ID-ERR."""
     import numpy as np
 
     from oracle import restrict as ores
@@ -240,12 +241,20 @@ def test_emulated_kernels_match_the_oracle(tmp_path):
     (tmp_path / "dims.txt").write_text(f"{m} {N} {f} {k} {mc} {taus.size}\n")
     A.astype("<f8").tofile(tmp_path / "A.bin")
     taus.astype("<f8").tofile(tmp_path / "taus.bin")
+    # BF16 storage: round to nearest even on the FP32 bit pattern
+    bits = A.astype(np.float32).view(np.uint32).astype(np.uint64)
+    bf = ((bits + 0x7FFF + ((bits >> 16) & 1)) >> 16).astype("<u2")
+    bf.tofile(tmp_path / "Abf.bin")
+    A_bf = (bf.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    ellp = 2 * k + 3
+    Q = rng.standard_normal((m, ellp)).astype("<f4")
+    Q.tofile(tmp_path / "Q.bin")
     r = subprocess.run([exe, "files", str(tmp_path)], capture_output=True, text=True, timeout=900)
     out = r.stdout + r.stderr
     assert r.returncode == 0, out[-4000:]
     assert "ERROR: AddressSanitizer" not in out and "SIMT FATAL" not in out and "runtime error" not in out, out[-4000:]
     rcs = re.findall(r"^(.*?)\s+rc=(-?\d+)$", r.stdout, re.M)
-    assert len(rcs) == 6 and all(int(c) == 0 for _, c in rcs), r.stdout
+    assert len(rcs) == 9 and all(int(c) == 0 for _, c in rcs), r.stdout
 
     n = N * N
     Rd = {"kind": "index", "index": idx}
@@ -260,14 +269,22 @@ def test_emulated_kernels_match_the_oracle(tmp_path):
         return np.linalg.norm(Ax - (U * S) @ V.T)
 
     A32 = A.astype(np.float32).astype(np.float64)
-    for tag, Ax, q, dt, tol in [("svd64q0", A, 0, "<f8", 1e-10), ("svd64q1", A, 1, "<f8", 1e-10),
-                                ("svd32q1", A32, 1, "<f4", 1e-5)]:
+    Rnn = {"kind": "nn", "ny": N, "nx": N, "sy": f, "sx": f}
+    for tag, Ax, Rx, q, dt, tol in [("svd64q0", A, Rd, 0, "<f8", 1e-10), ("svd64q1", A, Rd, 1, "<f8", 1e-10),
+                                    ("svd32q1", A32, Rd, 1, "<f4", 1e-5), ("svdbfq1", A_bf, Rd, 1, "<f4", 1e-4),
+                                    ("svdnn64q1", A, Rnn, 1, "<f8", 1e-10)]:
         U, S, V = svd_parts(tag, dt)
-        Uo, So, Vo = osk.tpc_svd(Ax, k, Rd, q=q)
+        Uo, So, Vo = osk.tpc_svd(Ax, k, Rx, q=q)
         assert np.abs(S - So).max() <= tol * So[0], (tag, S, So)
         eo = err(Ax, Uo, So, Vo)
         assert abs(err(Ax, U, S, V) - eo) <= tol * max(eo, 1e-13 * So[0]) + tol * So[0] * 1e-3, tag
         assert np.abs(U.T @ U - np.eye(k)).max() <= 100 * tol, tag
+
+    # projection B^T = A^T Q (FP32, three-piece split): the definition in FP64
+    Bt = load("proj32", "<f4", (n, ellp))
+    ref = A32.T @ Q.astype(np.float64)
+    scale = np.sqrt((A32 ** 2).sum(0)).max() * np.sqrt((Q.astype(np.float64) ** 2).sum(0)).max()
+    assert np.abs(Bt - ref).max() <= 1e-6 * scale
 
     # single pass (Alg. 3): the TPC tolerance plus (4 + ell) u kappa_F(Y) ||A||_F / sigma_1
     U, S, V = svd_parts("sp64", "<f8")
