@@ -200,6 +200,28 @@ def spc_id_err_curve(A: np.ndarray, R: dict, mc: int, taus, Ac=None) -> np.ndarr
     return np.array([c * np.linalg.eigvalsh(Gf - t * Gc)[-1] for t in np.asarray(taus, dtype=np.float64)])
 
 
+def spc_rho_curve(A: np.ndarray, R: dict, mc: int, taus, Ac=None) -> np.ndarray:
+    """The subsampled estimate of rho(tau) = ||A_f A_f^T - tau A_c A_c^T||_2
+    (the Gram-mismatch measure of the C-PWR analysis, Sec. 3), formed from the
+    same kept rows as Alg. 6: rho_hat(tau) = c ||B_f B_f^T - tau B_c B_c^T||_2,
+    c = m // mc.  The matrix is symmetric, so its 2-norm is its largest
+    eigenvalue magnitude.  With mc = m it is rho(tau) itself."""
+    A = np.asarray(A, dtype=np.float64)
+    if Ac is None:
+        Ac = _restrict.apply(A, R)
+    m = A.shape[0]
+    c = m // mc
+    J = np.array([i for i in range(m) if (i + 1) % c == 0])
+    Gf = A[J] @ A[J].T
+    Gc = Ac[J] @ Ac[J].T
+    return np.array([c * np.abs(np.linalg.eigvalsh(Gf - t * Gc)).max() for t in np.asarray(taus, dtype=np.float64)])
+
+
+def rho_tau(A: np.ndarray, Ac: np.ndarray, tau: float) -> float:
+    """rho(tau) = ||A_f A_f^T - tau A_c A_c^T||_2 (Sec. 3, C-PWR analysis)."""
+    return float(np.linalg.norm(A @ A.T - tau * (Ac @ Ac.T), 2))
+
+
 def eps_tau(A: np.ndarray, Ac: np.ndarray, tau: float) -> float:
     """epsilon(tau) = lambda_max(A_f A_f^T - tau A_c A_c^T) (Sec. 4)."""
     return float(np.linalg.eigvalsh(A @ A.T - tau * (Ac @ Ac.T))[-1])

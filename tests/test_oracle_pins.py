@@ -371,6 +371,36 @@ def test_spc_id_error_within_theorem_bound():
         assert best <= 50 * lhs, (seed, best, lhs)
 
 
+def test_spc_rho_curve_pins():
+    A = synth.heat_modes(30, 8, seed=19, nu=0.002) + 1e-2 * np.random.default_rng(20).standard_normal((30, 64))
+    R = _di(8, 8, 2, 2)
+    Ac = restrict.apply(A, R)
+    mc = 10
+    c = 30 // mc
+    keep = [i for i in range(30) if (i + 1) % c == 0]
+    sf = np.linalg.svd(A[keep], compute_uv=False)
+    sc = np.linalg.svd(Ac[keep], compute_uv=False)
+    # tau = 0: c sigma_max(B_f)^2; large tau: rho / tau -> c sigma_max(B_c)^2
+    assert abs(rowid.spc_rho_curve(A, R, mc, [0.0])[0] - c * sf[0] ** 2) <= 1e-12 * c * sf[0] ** 2
+    big = 1e8
+    assert abs(rowid.spc_rho_curve(A, R, mc, [big])[0] / big - c * sc[0] ** 2) <= 1e-6 * c * sc[0] ** 2
+    taus = np.linspace(0.0, 40.0, 81)
+    rho = rowid.spc_rho_curve(A, R, mc, taus)
+    eps = rowid.spc_id_err_curve(A, R, mc, taus)
+    # a norm bounds the largest eigenvalue: rho >= |eps_hat|
+    assert np.all(rho >= np.abs(eps) - 1e-10 * rho.max())
+    # Lipschitz in tau with constant c ||B_c B_c^T||_2, and convex (the norm of an affine function)
+    assert np.all(np.abs(np.diff(rho)) <= (taus[1] - taus[0]) * c * sc[0] ** 2 * (1 + 1e-10))
+    assert np.all(rho[:-2] + rho[2:] - 2 * rho[1:-1] >= -1e-9 * rho.max())
+    # every row kept: rho(tau) of the C-PWR analysis, through the singular values of the
+    # Gram mismatch written out from the two data matrices
+    for t in (0.5, 4.0, 16.0):
+        full = rowid.spc_rho_curve(A, R, 30, [t])[0]
+        M = A @ A.T - t * (Ac @ Ac.T)
+        assert abs(full - np.linalg.svd(M, compute_uv=False)[0]) <= 1e-10 * full
+        assert abs(full - rowid.rho_tau(A, Ac, t)) <= 1e-10 * full
+
+
 def test_spc_id_err_full_sampling_equals_eps_tau():
     A = synth.heat_modes(24, 8, seed=8, nu=0.001)
     R = _di(8, 8, 2, 2)
