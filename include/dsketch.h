@@ -196,12 +196,20 @@ int dsk_sketch_svd_sp(dsk_handle *h, const void *A, int32_t dtype, int64_t m, in
  * Grams in FP64 from the stored values; eigenvalues by the core eigensolver on
  * the positive semidefinite shift M + ||M||_F I (absolute error about
  * 1e-12 c (|tr M| + r ||M||_F)).
+ * With rho, the same kept rows also give the estimate of the Gram mismatch
+ * rho(tau) = ||A_f A_f^T - tau A_c A_c^T||_2 of the C-PWR analysis (Sec. 3):
+ *   rho[i] = c ||B_f B_f^T - taus[i] B_c B_c^T||_2 = c max(lambda_max, -lambda_min),
+ * from the same eigenvalues (rho(tau) itself when mc = m).
  * Arguments: h=1, A=2, dtype=3, m=4, n=5, lda=6, R=7, mc=8 (1 <= mc <= m, with
  *   floor(m / floor(m / mc)) <= 112 kept rows), taus=9 (device F64, ntau values),
- *   ntau=10 (1..1024), eps=11 (device F64, ntau).
+ *   ntau=10 (1..1024), eps=11 (device F64, ntau), rho=12 (device F64, ntau; NULL
+ *   when not wanted).
+ * Errors: -1..-7 as for dsk_restrict's arguments 1..7 (-7: restriction invalid),
+ *   -8 mc, -9 taus NULL, -10 ntau, -11 eps NULL.
  */
 int dsk_spc_id_err(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
-                   const dsk_restriction *R, int32_t mc, const double *taus, int32_t ntau, double *eps);
+                   const dsk_restriction *R, int32_t mc, const double *taus, int32_t ntau, double *eps,
+                   double *rho);
 
 /*
  * dsk_sketch_id -- rank-k row interpolative decomposition A ~ P A(I, :) by

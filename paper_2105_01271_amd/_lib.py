@@ -110,7 +110,7 @@ def load():
                                       vp, vp, vp, P(Info)]
         lib.dsk_sketch_svd_sp.argtypes = [vp, vp, i32, i64, i64, i64, i32, P(Restriction), P(Opts),
                                           vp, vp, vp, P(Info)]
-        lib.dsk_spc_id_err.argtypes = [vp, vp, i32, i64, i64, i64, P(Restriction), i32, vp, i32, vp]
+        lib.dsk_spc_id_err.argtypes = [vp, vp, i32, i64, i64, i64, P(Restriction), i32, vp, i32, vp, vp]
         lib.dsk_power_iter.argtypes = [vp, vp, i32, i64, i64, i64, vp, i32, i32, dbl, i32, vp]
         lib.dsk_status_string.argtypes = [ctypes.c_int]
         lib.dsk_status_string.restype = ctypes.c_char_p

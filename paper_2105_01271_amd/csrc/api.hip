@@ -473,7 +473,8 @@ int dsk_sketch_svd(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64
 }
 
 int dsk_spc_id_err(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
-                   const dsk_restriction *R, int32_t mc, const double *taus, int32_t ntau, double *eps) {
+                   const dsk_restriction *R, int32_t mc, const double *taus, int32_t ntau, double *eps,
+                   double *rho) {
   if (!h) return -1;
   if (!A) return -2;
   if (!valid_dtype(dtype)) return -3;
@@ -518,7 +519,7 @@ int dsk_spc_id_err(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64
     DSK_RET(launch_restrict(st, Ak, dtype, r, n, ldk, R, s, 1, Bc, nullptr, h->dflags));
     DSK_RET(launch_row_gram(st, Ak, dtype, (int)r, n, ldk, part, Gf));
     DSK_RET(launch_row_gram(st, Bc, DSK_F64, (int)r, s, s, part, Gc));
-    DSK_RET(launch_eps_curve(st, Gf, Gc, (int)r, taus, ntau, (double)c, Mb, sig, lam, Ub, eps, h->dflags));
+    DSK_RET(launch_eps_curve(st, Gf, Gc, (int)r, taus, ntau, (double)c, Mb, sig, lam, Ub, eps, rho, h->dflags));
   }
   return 0;
 }

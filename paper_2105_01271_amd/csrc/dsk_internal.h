@@ -167,7 +167,8 @@ int launch_row_gram(hipStream_t st, const void *X, int dtype, int r, int64_t nco
                     double *G);
 // eps[i] = c lambda_max(Gf - taus[i] Gc) for i < ntau (Mb: ntau r^2, sig: ntau, lam: ntau r, Ub: ntau r^2)
 int launch_eps_curve(hipStream_t st, const double *Gf, const double *Gc, int r, const double *taus, int ntau,
-                     double c, double *Mb, double *sig, double *lam, double *Ub, double *eps, int *dflags);
+                     double c, double *Mb, double *sig, double *lam, double *Ub, double *eps, double *rho,
+                     int *dflags);
 int launch_jacobi_svd(hipStream_t st, const double *Rm, int ell, double *sig, double *Vr,
                       double *Ur, int *dflags);
 int launch_tsmm(hipStream_t st, const void *X, int f64, int64_t rows, int ell, int64_t ldx,

@@ -138,10 +138,15 @@ __global__ void __launch_bounds__(NT) k_eps_shift(const double *__restrict__ Gf,
   if (t == 0) sig[i] = sigma;
 }
 
+// eps_hat(tau_i) = c lambda_max(M_i); with rho, also c ||M_i||_2 = c max(lambda_max, -lambda_min)
+// (the eigenvalues of M_i + sigma_i I come sorted in descending order)
 __global__ void k_eps_finish(const double *__restrict__ lam, int r, const double *__restrict__ sig, int ntau,
-                             double c, double *__restrict__ eps) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ntau; i += gridDim.x * blockDim.x)
-    eps[i] = c * (lam[(size_t)i * r] - sig[i]);
+                             double c, double *__restrict__ eps, double *__restrict__ rho) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ntau; i += gridDim.x * blockDim.x) {
+    const double top = lam[(size_t)i * r] - sig[i];
+    eps[i] = c * top;
+    if (rho) rho[i] = c * fmax(top, sig[i] - lam[(size_t)i * r + (r - 1)]);
+  }
 }
 
 template <int DT>
@@ -173,12 +178,13 @@ int launch_row_gram(hipStream_t st, const void *X, int dtype, int r, int64_t nco
 }
 
 int launch_eps_curve(hipStream_t st, const double *Gf, const double *Gc, int r, const double *taus, int ntau,
-                     double c, double *Mb, double *sig, double *lam, double *Ub, double *eps, int *dflags) {
+                     double c, double *Mb, double *sig, double *lam, double *Ub, double *eps, double *rho,
+                     int *dflags) {
   if (r < 1 || r > RMAX || ntau < 1) return -1;
   hipLaunchKernelGGL(k_eps_shift, dim3(ntau), dim3(NT), 0, st, Gf, Gc, r, taus, Mb, sig);
   DSK_RET(launch_core_eig_batched(st, Mb, r, lam, Ub, dflags, ntau));
   hipLaunchKernelGGL(k_eps_finish, dim3((ntau + 255) / 256), dim3(256), 0, st, (const double *)lam, r,
-                     (const double *)sig, ntau, c, eps);
+                     (const double *)sig, ntau, c, eps, rho);
   DSK_TRY(hipGetLastError());
   return 0;
 }

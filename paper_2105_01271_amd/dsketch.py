@@ -232,18 +232,21 @@ def sketch_svd_sp(A: torch.Tensor, k: int, R: Restriction, p: int = 10, S=None, 
     return U, Sv, V
 
 
-def spc_id_err(A: torch.Tensor, R: Restriction, mc: int, taus) -> torch.Tensor:
+def spc_id_err(A: torch.Tensor, R: Restriction, mc: int, taus, with_rho: bool = False):
     """SPC-ID-ERR (dsk_spc_id_err, Alg. 6) at the given scales: eps_hat(tau) for
-    each tau (float64 device tensor)."""
+    each tau (float64 device tensor); with_rho=True also returns the estimate of
+    rho(tau) = ||A_f A_f^T - tau A_c A_c^T||_2 from the same kept rows."""
     _check_matrix(A)
     lib = _lib.load()
     m, n = A.shape
     t = torch.as_tensor(taus, dtype=torch.float64).to(A.device).contiguous()
     eps = torch.empty_like(t)
+    rho = torch.empty_like(t) if with_rho else None
     rc = R.to_c()
     _lib.check("dsk_spc_id_err", lib.dsk_spc_id_err(_handle(A.device), _ptr(A), _DT[A.dtype], m, n, A.stride(0),
-                                                    ctypes.byref(rc), int(mc), _ptr(t), int(t.numel()), _ptr(eps)))
-    return eps
+                                                    ctypes.byref(rc), int(mc), _ptr(t), int(t.numel()), _ptr(eps),
+                                                    _ptr(rho)))
+    return (eps, rho) if with_rho else eps
 
 
 def sketch_id(A: torch.Tensor, k: int, R: Restriction, q: int = 0, p: int = 10, S=None, tau=None,

@@ -148,7 +148,7 @@ int main(int argc, char **argv) {
         printf("   S0 %.10g flags %d\n", S[0], a.flags);
         std::vector<double> taus = {0.0, 1.0, 4.0, 16.0}, eps(4);
         check("spc_id_err", dsk_spc_id_err(h, dAv, f64 ? DSK_F64 : DSK_F32, m, n, n, &R, (int)(m / 10), taus.data(), 4,
-                                           eps.data()));
+                                           eps.data(), nullptr));
         printf("   eps %.6g %.6g %.6g %.6g\n", eps[0], eps[1], eps[2], eps[3]);
       }
     }
@@ -386,10 +386,11 @@ int main(int argc, char **argv) {
                                             nullptr, nullptr));
     write_bin(dir + "/id64_I.bin", I.data(), k * 8);
     write_bin(dir + "/id64_P.bin", P.data(), m * k * 8);
-    std::vector<double> eps(ntau);
+    std::vector<double> eps(ntau), rho(ntau);
     check("files spc_id_err f64", dsk_spc_id_err(h, A64.data(), DSK_F64, m, n, n, &R, (int)mc, taus.data(), (int)ntau,
-                                                 eps.data()));
+                                                 eps.data(), rho.data()));
     write_bin(dir + "/eps64.bin", eps.data(), ntau * 8);
+    write_bin(dir + "/rho64.bin", rho.data(), ntau * 8);
     // the same matrix stored BF16 (bits from the test), q = 1
     std::vector<uint16_t> Abf(m * n);
     if (read_bin(dir + "/Abf.bin", Abf)) {

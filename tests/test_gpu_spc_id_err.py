@@ -1,4 +1,5 @@
-"""SPC-ID-ERR (Alg. 6) at given scales through the C ABI against the FP64 oracle.
+"""SPC-ID-ERR (Alg. 6) at given scales through the C ABI against the FP64 oracle,
+with the rho(tau) estimate the same eigenvalues give.
 
 eps_hat(tau) = c lambda_max(B_f B_f^T - tau B_c B_c^T) is evaluated on the
 device from FP64 Grams of the stored values and the core eigensolver applied
@@ -56,12 +57,19 @@ def test_spc_id_err_matches_oracle(dtype, m, N, f, mc):
     idx = ores.di_index_2d(N, N, f, f)
     R = dsk().Restriction.di_grid(N, N, f, f)
     taus = np.concatenate([[0.0], np.logspace(-1, 2, 7) * (N * N / idx.size)])
-    eps = dsk().spc_id_err(A, R, mc, taus).cpu().numpy()
-    ref = orid.spc_id_err_curve(A_np, {"kind": "index", "index": idx}, mc, taus)
+    eps, rho = (t.cpu().numpy() for t in dsk().spc_id_err(A, R, mc, taus, with_rho=True))
+    Rd = {"kind": "index", "index": idx}
+    ref = orid.spc_id_err_curve(A_np, Rd, mc, taus)
     tol = _tol(A_np, A_np[:, idx], mc, taus)
     say("  max |diff| / tol", float(np.max(np.abs(eps - ref) / tol)))
     assert np.all(np.abs(eps - ref) <= tol), (eps, ref, tol)
     assert np.all(np.diff(eps) <= tol[1:])          # non-increasing in tau
+    # rho(tau) estimate from the same eigenvalues: c max(lambda_max, -lambda_min)
+    ref_rho = orid.spc_rho_curve(A_np, Rd, mc, taus)
+    say("  rho max |diff| / tol", float(np.max(np.abs(rho - ref_rho) / tol)))
+    assert np.all(np.abs(rho - ref_rho) <= tol), (rho, ref_rho, tol)
+    # the rho-less call gives the same eps
+    assert np.array_equal(dsk().spc_id_err(A, R, mc, taus).cpu().numpy(), eps)
 
 
 def test_spc_id_err_full_sampling_is_eps_tau():
@@ -71,12 +79,14 @@ def test_spc_id_err_full_sampling_is_eps_tau():
     idx = ores.di_index_2d(8, 8, 2, 2)
     R = dsk().Restriction.di_grid(8, 8, 2, 2)
     taus = [0.5, 2.0, 4.0, 8.0]
-    eps = dsk().spc_id_err(A, R, 40, taus).cpu().numpy()
+    eps, rho = (t.cpu().numpy() for t in dsk().spc_id_err(A, R, 40, taus, with_rho=True))
     Ac = A0[:, idx]
-    for t, e in zip(taus, eps):
+    for t, e, r in zip(taus, eps, rho):
         ref = orid.eps_tau(A0, Ac, t)
         M = A0 @ A0.T - t * Ac @ Ac.T
-        assert abs(e - ref) <= 1e-10 * (abs(np.trace(M)) + 40 * np.linalg.norm(M)), (t, e, ref)
+        tol = 1e-10 * (abs(np.trace(M)) + 40 * np.linalg.norm(M))
+        assert abs(e - ref) <= tol, (t, e, ref)
+        assert abs(r - orid.rho_tau(A0, Ac, t)) <= tol, (t, r)
 
 
 def test_spc_id_err_stencil_restriction():

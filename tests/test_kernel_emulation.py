@@ -224,7 +224,7 @@ def test_emulated_kernels_match_the_oracle(tmp_path):
     20), at the GPU parity tests' tolerances: sketch SVD (FP64 q = 0, 1; FP32
     and BF16 storage q = 1 against the oracle on the upcast stored values; the
     nearest-neighbour stencil restriction), the projection, the single-pass
-    SVD (with its kappa(Y) term), row ID (pivots and P) and SPC-ID-ERR."""
+    SVD (with its kappa(Y) term), row ID (pivots and P) and SPC-ID-ERR with its rho(tau) estimate."""
     import numpy as np
 
     from oracle import restrict as ores
@@ -312,3 +312,6 @@ def test_emulated_kernels_match_the_oracle(tmp_path):
     Gf, Gc = A[keep] @ A[keep].T, Ac[keep] @ Ac[keep].T
     tol = np.array([1e-10 * c * (abs(np.trace(Gf - t * Gc)) + len(keep) * np.linalg.norm(Gf - t * Gc)) for t in taus])
     assert np.all(np.abs(eps - ref) <= tol), (eps, ref, tol)
+    rho = np.fromfile(tmp_path / "rho64.bin", dtype="<f8")
+    ref_rho = orid.spc_rho_curve(A, Rd, mc, taus)
+    assert np.all(np.abs(rho - ref_rho) <= tol), (rho, ref_rho, tol)
