@@ -398,6 +398,23 @@ int main(int argc, char **argv) {
                                                  S.data(), V.data(), nullptr));
       out("svdbfq1", 4);
     }
+    // hybrid sketch: a given s x (k + 6) second level (Gaussian, from the test), FP64,
+    // the SVD at q = 1 and the ID of the projected block at q = 1
+    const int ellg = (int)k + 6;
+    std::vector<double> Om((size_t)R.s * ellg);
+    if (read_bin(dir + "/Om.bin", Om)) {
+      dsk_opts oh = o;
+      oh.S = Om.data();
+      oh.ell = ellg;
+      check("files svd hybrid f64 q=1", dsk_sketch_svd(h, A64.data(), DSK_F64, m, n, n, (int)k, &R, 1, &oh, U.data(),
+                                                       S.data(), V.data(), nullptr));
+      out("hyb64q1", 8);
+      oh.id_projected = 1;
+      check("files id hybrid projected f64 q=1", dsk_sketch_id(h, A64.data(), DSK_F64, m, n, n, (int)k, &R, 1, &oh,
+                                                               I.data(), P.data(), nullptr, nullptr));
+      write_bin(dir + "/hybid_I.bin", I.data(), k * 8);
+      write_bin(dir + "/hybid_P.bin", P.data(), m * k * 8);
+    }
     // nearest-neighbour stencil restriction, FP64, q = 1
     dsk_restriction Rn{};
     Rn.kind = DSK_R_NN;

@@ -223,7 +223,8 @@ def test_emulated_kernels_match_the_oracle(tmp_path):
     seeded input (120 x 16^2, direct injection 2 x 2, s = 64, k = 10, ell =
     20), at the GPU parity tests' tolerances: sketch SVD (FP64 q = 0, 1; FP32
     and BF16 storage q = 1 against the oracle on the upcast stored values; the
-    nearest-neighbour stencil restriction), the projection, the single-pass
+    nearest-neighbour stencil restriction; a Gaussian second level, with the ID
+    of the projected block), the projection, the single-pass
     SVD (with its kappa(Y) term), row ID (pivots and P) and SPC-ID-ERR with its rho(tau) estimate."""
     import numpy as np
 
@@ -249,12 +250,14 @@ def test_emulated_kernels_match_the_oracle(tmp_path):
     ellp = 2 * k + 3
     Q = rng.standard_normal((m, ellp)).astype("<f4")
     Q.tofile(tmp_path / "Q.bin")
+    Om = synth.gaussian_matrix(idx.size, k + 6, seed=62)
+    Om.astype("<f8").tofile(tmp_path / "Om.bin")
     r = subprocess.run([exe, "files", str(tmp_path)], capture_output=True, text=True, timeout=900)
     out = r.stdout + r.stderr
     assert r.returncode == 0, out[-4000:]
     assert "ERROR: AddressSanitizer" not in out and "SIMT FATAL" not in out and "runtime error" not in out, out[-4000:]
     rcs = re.findall(r"^(.*?)\s+rc=(-?\d+)$", r.stdout, re.M)
-    assert len(rcs) == 9 and all(int(c) == 0 for _, c in rcs), r.stdout
+    assert len(rcs) == 11 and all(int(c) == 0 for _, c in rcs), r.stdout
 
     n = N * N
     Rd = {"kind": "index", "index": idx}
@@ -279,6 +282,16 @@ def test_emulated_kernels_match_the_oracle(tmp_path):
         eo = err(Ax, Uo, So, Vo)
         assert abs(err(Ax, U, S, V) - eo) <= tol * max(eo, 1e-13 * So[0]) + tol * So[0] * 1e-3, tag
         assert np.abs(U.T @ U - np.eye(k)).max() <= 100 * tol, tag
+
+    # hybrid sketch (Gaussian second level): SVD and the ID of the projected block
+    U, S, V = svd_parts("hyb64q1", "<f8")
+    Uo, So, Vo = osk.tpc_svd(A, k, Rd, q=1, S=Om)
+    assert np.abs(S - So).max() <= 1e-10 * So[0], (S, So)
+    I = np.fromfile(tmp_path / "hybid_I.bin", dtype="<i8")
+    P = load("hybid_P", "<f8", (m, k))
+    Io, Po = orid.tpc_id(A, k, Rd, q=1, S=Om, projected=True)
+    assert list(I) == list(Io), (I, Io)
+    assert np.abs(P - Po).max() <= 1e-7 * max(1.0, np.abs(Po).max())
 
     # projection B^T = A^T Q (FP32, three-piece split): the definition in FP64
     Bt = load("proj32", "<f4", (n, ellp))
