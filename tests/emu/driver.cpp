@@ -415,6 +415,32 @@ int main(int argc, char **argv) {
       write_bin(dir + "/hybid_I.bin", I.data(), k * 8);
       write_bin(dir + "/hybid_P.bin", P.data(), m * k * 8);
     }
+    // learned conv restriction (4 channels, FP32 A): forward, weight gradients of
+    // <gAc, A_c(w)>, and the training loss with its gradients (ell = 8, q = 1)
+    const int C = 4;
+    const int64_t sl = (N / 4) * (N / 4);
+    std::vector<float> w1(C * 25), w2(C * 25), gAc(m * sl);
+    if (read_bin(dir + "/w1.bin", w1) && read_bin(dir + "/w2.bin", w2) && read_bin(dir + "/gAc.bin", gAc)) {
+      dsk_restriction Rl{};
+      Rl.kind = DSK_R_LEARNED;
+      Rl.ny = Rl.nx = (int)N;
+      Rl.channels = C;
+      Rl.w1 = w1.data();
+      Rl.w2 = w2.data();
+      std::vector<float> Acl(m * sl), g1(C * 25), g2(C * 25);
+      check("files learned restrict", dsk_restrict(h, A32.data(), DSK_F32, m, n, n, &Rl, Acl.data()));
+      write_bin(dir + "/learned_Ac.bin", Acl.data(), Acl.size() * 4);
+      check("files learned conv bwd", dsk_conv_restrict_bwd(h, A32.data(), DSK_F32, m, n, n, &Rl, gAc.data(),
+                                                            g1.data(), g2.data()));
+      write_bin(dir + "/learned_g1.bin", g1.data(), g1.size() * 4);
+      write_bin(dir + "/learned_g2.bin", g2.data(), g2.size() * 4);
+      double loss = 0.0;
+      check("files learned loss grad", dsk_learned_loss_grad(h, A64.data(), DSK_F64, m, n, n, &Rl, 8, 1, &loss,
+                                                              g1.data(), g2.data()));
+      write_bin(dir + "/learned_loss.bin", &loss, 8);
+      write_bin(dir + "/learned_l1.bin", g1.data(), g1.size() * 4);
+      write_bin(dir + "/learned_l2.bin", g2.data(), g2.size() * 4);
+    }
     // nearest-neighbour stencil restriction, FP64, q = 1
     dsk_restriction Rn{};
     Rn.kind = DSK_R_NN;

@@ -224,7 +224,8 @@ def test_emulated_kernels_match_the_oracle(tmp_path):
     20), at the GPU parity tests' tolerances: sketch SVD (FP64 q = 0, 1; FP32
     and BF16 storage q = 1 against the oracle on the upcast stored values; the
     nearest-neighbour stencil restriction; a Gaussian second level, with the ID
-    of the projected block), the projection, the single-pass
+    of the projected block), the learned conv restriction (forward, weight
+    gradients, training loss and its gradients), the projection, the single-pass
     SVD (with its kappa(Y) term), row ID (pivots and P) and SPC-ID-ERR with its rho(tau) estimate."""
     import numpy as np
 
@@ -252,12 +253,21 @@ def test_emulated_kernels_match_the_oracle(tmp_path):
     Q.tofile(tmp_path / "Q.bin")
     Om = synth.gaussian_matrix(idx.size, k + 6, seed=62)
     Om.astype("<f8").tofile(tmp_path / "Om.bin")
+    C, sl = 4, (N // 4) ** 2
+    w1 = (0.2 * rng.standard_normal((C, 5, 5))).astype("<f4")
+    w2 = (0.2 * rng.standard_normal((C, 5, 5))).astype("<f4")
+    w1[0, 2, 2] += 1.0
+    w2[0, 2, 2] += 1.0
+    gAc = rng.standard_normal((m, sl)).astype("<f4")
+    w1.tofile(tmp_path / "w1.bin")
+    w2.tofile(tmp_path / "w2.bin")
+    gAc.tofile(tmp_path / "gAc.bin")
     r = subprocess.run([exe, "files", str(tmp_path)], capture_output=True, text=True, timeout=900)
     out = r.stdout + r.stderr
     assert r.returncode == 0, out[-4000:]
     assert "ERROR: AddressSanitizer" not in out and "SIMT FATAL" not in out and "runtime error" not in out, out[-4000:]
     rcs = re.findall(r"^(.*?)\s+rc=(-?\d+)$", r.stdout, re.M)
-    assert len(rcs) == 11 and all(int(c) == 0 for _, c in rcs), r.stdout
+    assert len(rcs) == 14 and all(int(c) == 0 for _, c in rcs), r.stdout
 
     n = N * N
     Rd = {"kind": "index", "index": idx}
@@ -292,6 +302,24 @@ def test_emulated_kernels_match_the_oracle(tmp_path):
     Io, Po = orid.tpc_id(A, k, Rd, q=1, S=Om, projected=True)
     assert list(I) == list(Io), (I, Io)
     assert np.abs(P - Po).max() <= 1e-7 * max(1.0, np.abs(Po).max())
+
+    # learned conv restriction (the GPU learned tests' tolerances)
+    from oracle import learned as olearn
+    # oracle layout: w1 as C x 1 x 5 x 5 (1 -> C channels), w2 as 1 x C x 5 x 5
+    o1, o2 = w1.astype(np.float64).reshape(C, 1, 5, 5), w2.astype(np.float64).reshape(1, C, 5, 5)
+    Acl = load("learned_Ac", "<f4", (m, sl))
+    ref = ores.conv_restrict(A32, N, N, o1, o2)
+    assert np.abs(Acl - ref).max() <= 2e-6 * np.abs(ref).max()
+    r1, r2 = ores.conv_restrict_bwd(A32, N, N, o1, o2, gAc.astype(np.float64))
+    for tag, rr in (("learned_g1", r1), ("learned_g2", r2)):
+        g = load(tag, "<f4", (C * 25,))
+        assert np.abs(g - rr.reshape(-1)).max() <= 1e-5 * np.abs(rr).max(), tag
+    L, l1, l2 = olearn.learned_loss_and_grad(A, N, N, o1, o2, 8, 1)
+    loss = np.fromfile(tmp_path / "learned_loss.bin", dtype="<f8")[0]
+    assert abs(loss - L) <= 1e-6, (loss, L)
+    for tag, rr in (("learned_l1", l1), ("learned_l2", l2)):
+        g = load(tag, "<f4", (C * 25,))
+        assert np.abs(g - rr.reshape(-1)).max() <= 1e-5 * np.abs(rr).max(), tag
 
     # projection B^T = A^T Q (FP32, three-piece split): the definition in FP64
     Bt = load("proj32", "<f4", (n, ellp))
