@@ -544,6 +544,18 @@ int main(int argc, char **argv) {
     for (size_t i = 0; i < ins.size(); ++i)
       printf("   hash %016llx problem %zu workers %d\n",
              fnv({{Us[i].data(), Us[i].size()}, {Ss[i].data(), Ss[i].size() * 8}, {Vs[i].data(), Vs[i].size()}}), i, nw);
+    // every instance of the batch equals the same problem run alone, bit for bit
+    int differ = 0;
+    for (size_t i = 0; i < ins.size(); ++i) {
+      std::vector<char> U1(Us[i].size()), V1(Vs[i].size());
+      std::vector<double> S1(Ss[i].size());
+      const dsk_problem &p = pr[i];
+      const int rc1 = dsk_sketch_svd(h, p.A, p.dtype, p.m, p.n, p.lda, p.k, &p.R, p.q, &o, U1.data(), S1.data(),
+                                     V1.data(), nullptr);
+      simt::sync_all();
+      differ += rc1 != 0 || U1 != Us[i] || V1 != Vs[i] || S1 != Ss[i];
+    }
+    printf("%-44s rc=%d\n", "batch instances equal single calls", differ);
   }
 
   // ---- one-launch pivoted QR against the per-step one, bitwise
