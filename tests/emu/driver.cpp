@@ -491,6 +491,19 @@ int main(int argc, char **argv) {
       printf("   hash %016llx flags %d %d\n", fnv({{U.data(), U.size()}, {S.data(), S.size() * 8}, {V.data(), V.size()},
                                                 {I.data(), I.size() * 8}, {P.data(), P.size() * 8},
                                                 {rows.data(), rows.size()}}), a.flags, b.flags);
+      {
+        // the combined call equals the two separate calls, bit for bit
+        std::vector<char> U1(U.size()), V1(V.size()), rows1(rows.size());
+        std::vector<double> S1(S.size()), P1(P.size());
+        std::vector<int64_t> I1(I.size());
+        int rc1 = dsk_sketch_svd(h, Av, c.f64 ? DSK_F64 : DSK_F32, c.m, n, n, c.k, &R, 1, &o, U1.data(), S1.data(),
+                                 V1.data(), nullptr);
+        rc1 |= dsk_sketch_id(h, Av, c.f64 ? DSK_F64 : DSK_F32, c.m, n, n, c.k, &R, 0, &o, I1.data(), P1.data(),
+                             rows1.data(), nullptr);
+        simt::sync_all();
+        const int differ = rc1 != 0 || U1 != U || V1 != V || S1 != S || I1 != I || P1 != P || rows1 != rows;
+        printf("%-44s rc=%d\n", "combined call equals separate calls", differ);
+      }
       snprintf(nm, sizeof nm, "svd single pass m=%lld k=%d f64=%d", (long long)c.m, c.k, c.f64);
       check(nm, dsk_sketch_svd_sp(h, Av, c.f64 ? DSK_F64 : DSK_F32, c.m, n, n, c.k, &R, &o, U.data(), S.data(),
                                   V.data(), &a));

@@ -196,13 +196,15 @@ def test_multi_stream_entry_points_are_interleaving_independent(emu):
     advanced in three different interleavings (main stream first, workers
     first, seeded random): every output is bitwise the same as in issue
     order, so no work on one stream reads or overwrites what another stream
-    has not ordered by an event; and every batch instance equals the same
-    problem run alone, bit for bit.  (Removing the single-pass join changes the
+    has not ordered by an event; every batch instance equals the same
+    problem run alone, and the combined call the two separate calls, bit for
+    bit.  (Removing the single-pass join changes the
     outputs under the main-stream-first order.)"""
     outs = _check_streams({o: emu("streams-quick", o) for o in (None, 0, 1, 9001)})
     ref = _hashes(outs[None])
     assert len(ref) == 11, outs[None]
     assert all("batch instances equal single calls" in so for so in outs.values())
+    assert all("combined call equals separate calls" in so for so in outs.values())
     for order, so in outs.items():
         assert _hashes(so) == ref, order
 
