@@ -441,6 +441,32 @@ int main(int argc, char **argv) {
       write_bin(dir + "/learned_l1.bin", g1.data(), g1.size() * 4);
       write_bin(dir + "/learned_l2.bin", g2.data(), g2.size() * 4);
     }
+    // restriction entry point (index and global kinds, FP64) and the C-PWR loop on
+    // the restricted block from a given start (q = 2; raw and re-orthonormalised)
+    {
+      const int64_t s = R.s;
+      std::vector<double> Ac(m * s);
+      check("files restrict index f64", dsk_restrict(h, A64.data(), DSK_F64, m, n, n, &R, Ac.data()));
+      write_bin(dir + "/rest_idx.bin", Ac.data(), Ac.size() * 8);
+      dsk_restriction Rg{};
+      Rg.kind = DSK_R_GLOBAL;
+      Rg.ny = Rg.nx = (int)N;
+      Rg.sy = Rg.sx = (int)f;
+      std::vector<double> Ag(m * s);
+      check("files restrict global f64", dsk_restrict(h, A64.data(), DSK_F64, m, n, n, &Rg, Ag.data()));
+      write_bin(dir + "/rest_glob.bin", Ag.data(), Ag.size() * 8);
+      const int ell0 = 6;
+      std::vector<double> Q0(m * ell0), Qo(m * ell0);
+      if (read_bin(dir + "/Q0.bin", Q0)) {
+        const double tau = (double)n / (double)s;
+        check("files power iter raw q=2", dsk_power_iter(h, Ac.data(), DSK_F64, m, s, s, Q0.data(), ell0, 2, tau, 0,
+                                                          Qo.data()));
+        write_bin(dir + "/pw_raw.bin", Qo.data(), Qo.size() * 8);
+        check("files power iter orth q=2", dsk_power_iter(h, Ac.data(), DSK_F64, m, s, s, Q0.data(), ell0, 2, tau, 1,
+                                                           Qo.data()));
+        write_bin(dir + "/pw_orth.bin", Qo.data(), Qo.size() * 8);
+      }
+    }
     // nearest-neighbour stencil restriction, FP64, q = 1
     dsk_restriction Rn{};
     Rn.kind = DSK_R_NN;

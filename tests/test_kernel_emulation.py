@@ -229,7 +229,8 @@ def test_emulated_kernels_match_the_oracle(tmp_path):
     and BF16 storage q = 1 against the oracle on the upcast stored values; the
     nearest-neighbour stencil restriction; a Gaussian second level, with the ID
     of the projected block), the learned conv restriction (forward, weight
-    gradients, training loss and its gradients), the projection, the single-pass
+    gradients, training loss and its gradients), the restriction and C-PWR
+    entry points, the projection, the single-pass
     SVD (with its kappa(Y) term), row ID (pivots and P) and SPC-ID-ERR with its rho(tau) estimate."""
     import numpy as np
 
@@ -263,6 +264,8 @@ def test_emulated_kernels_match_the_oracle(tmp_path):
     w1[0, 2, 2] += 1.0
     w2[0, 2, 2] += 1.0
     gAc = rng.standard_normal((m, sl)).astype("<f4")
+    Q0 = rng.standard_normal((m, 6))
+    Q0.astype("<f8").tofile(tmp_path / "Q0.bin")
     w1.tofile(tmp_path / "w1.bin")
     w2.tofile(tmp_path / "w2.bin")
     gAc.tofile(tmp_path / "gAc.bin")
@@ -271,7 +274,7 @@ def test_emulated_kernels_match_the_oracle(tmp_path):
     assert r.returncode == 0, out[-4000:]
     assert "ERROR: AddressSanitizer" not in out and "SIMT FATAL" not in out and "runtime error" not in out, out[-4000:]
     rcs = re.findall(r"^(.*?)\s+rc=(-?\d+)$", r.stdout, re.M)
-    assert len(rcs) == 14 and all(int(c) == 0 for _, c in rcs), r.stdout
+    assert len(rcs) == 18 and all(int(c) == 0 for _, c in rcs), r.stdout
 
     n = N * N
     Rd = {"kind": "index", "index": idx}
@@ -306,6 +309,23 @@ def test_emulated_kernels_match_the_oracle(tmp_path):
     Io, Po = orid.tpc_id(A, k, Rd, q=1, S=Om, projected=True)
     assert list(I) == list(Io), (I, Io)
     assert np.abs(P - Po).max() <= 1e-7 * max(1.0, np.abs(Po).max())
+
+    # restriction entry point (a gather is exact; the global average to rounding) and
+    # the C-PWR loop: the raw block (tau A_c A_c^T)^2 Q0, and the span of the
+    # re-orthonormalised one
+    Ac = A[:, idx]
+    assert np.array_equal(load("rest_idx", "<f8", (m, idx.size)), Ac)
+    Rg = {"kind": "global", "ny": N, "nx": N, "sy": f, "sx": f}
+    ref = ores.apply(A, Rg)
+    assert np.abs(load("rest_glob", "<f8", ref.shape) - ref).max() <= 1e-14 * np.abs(ref).max()
+    tau = N * N / idx.size
+    raw = load("pw_raw", "<f8", (m, 6))
+    ref = osk.power_iter(Ac, Q0, 2, tau, reorth=False)
+    assert np.abs(raw - ref).max() <= 1e-12 * np.abs(ref).max()
+    Qg = load("pw_orth", "<f8", (m, 6))
+    Qr = osk.power_iter(Ac, Q0, 2, tau, reorth=True)
+    assert np.abs(Qg.T @ Qg - np.eye(6)).max() <= 1e-12
+    assert np.linalg.norm(Qg @ Qg.T - Qr @ Qr.T, 2) <= 1e-10
 
     # learned conv restriction (the GPU learned tests' tolerances)
     from oracle import learned as olearn
