@@ -58,21 +58,61 @@ def _collect(p):
     return _Run(p.returncode, so, se)
 
 
+def _files_inputs(d=None):
+    """The seeded inputs of the file mode (written to d when given)."""
+    import numpy as np
+
+    from oracle import restrict as ores
+    from paper_2105_01271_amd import synth
+
+    m, N, f, k, mc = 120, 16, 2, 10, 30
+    rng = np.random.default_rng(61)
+    A = synth.heat_modes(m, N, seed=60, nu=0.002) + 1e-2 * rng.standard_normal((m, N * N))
+    idx = ores.di_index_2d(N, N, f, f)
+    taus = np.array([0.0, 1.0, 4.0, 16.0])
+    # BF16 storage: round to nearest even on the FP32 bit pattern
+    bits = A.astype(np.float32).view(np.uint32).astype(np.uint64)
+    bf = ((bits + 0x7FFF + ((bits >> 16) & 1)) >> 16).astype("<u2")
+    A_bf = (bf.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    Q = rng.standard_normal((m, 2 * k + 3)).astype("<f4")
+    Om = synth.gaussian_matrix(idx.size, k + 6, seed=62)
+    C, sl = 4, (N // 4) ** 2
+    w1 = (0.2 * rng.standard_normal((C, 5, 5))).astype("<f4")
+    w2 = (0.2 * rng.standard_normal((C, 5, 5))).astype("<f4")
+    w1[0, 2, 2] += 1.0
+    w2[0, 2, 2] += 1.0
+    gAc = rng.standard_normal((m, sl)).astype("<f4")
+    Q0 = rng.standard_normal((m, 6))
+    if d is not None:
+        (d / "dims.txt").write_text(f"{m} {N} {f} {k} {mc} {taus.size}\n")
+        for name, arr, dt in [("A", A, "<f8"), ("taus", taus, "<f8"), ("Abf", bf, "<u2"), ("Q", Q, "<f4"),
+                              ("Om", Om, "<f8"), ("w1", w1, "<f4"), ("w2", w2, "<f4"), ("gAc", gAc, "<f4"),
+                              ("Q0", Q0, "<f8")]:
+            arr.astype(dt).tofile(d / f"{name}.bin")
+    return {"m": m, "N": N, "f": f, "k": k, "mc": mc, "A": A, "idx": idx, "taus": taus, "A_bf": A_bf, "Q": Q,
+            "Om": Om, "w1": w1, "w2": w2, "gAc": gAc, "Q0": Q0}
+
+
 @pytest.fixture(scope="module")
-def emu():
+def emu(tmp_path_factory):
     procs = {}
     results = {}
+    files_dir = tmp_path_factory.mktemp("emu_files")
 
     def get(mode, order=None):
         if not procs:
             exe = _build()
             for key in _DEFAULT_RUNS:
                 procs[key] = _spawn(exe, *key)
+            _files_inputs(files_dir)
+            procs[("files", None)] = subprocess.Popen([exe, "files", str(files_dir)], stdout=subprocess.PIPE,
+                                                      stderr=subprocess.PIPE, text=True)
         key = (mode, order)
         if key not in results:
             results[key] = _collect(procs[key])
         return results[key]
 
+    get.files_dir = files_dir
     yield get
     for p in procs.values():   # runs no test collected (a -k selection) end with the module
         if p.poll() is None:
@@ -222,7 +262,7 @@ def test_multi_stream_entry_points_all_paths_interleaving_independent():
         assert _hashes(so) == ref, order
 
 
-def test_emulated_kernels_match_the_oracle(tmp_path):
+def test_emulated_kernels_match_the_oracle(emu):
     """The HIP path run in host emulation against the FP64 oracle on the same
     seeded input (120 x 16^2, direct injection 2 x 2, s = 64, k = 10, ell =
     20), at the GPU parity tests' tolerances: sketch SVD (FP64 q = 0, 1; FP32
@@ -230,46 +270,22 @@ def test_emulated_kernels_match_the_oracle(tmp_path):
     nearest-neighbour stencil restriction; a Gaussian second level, with the ID
     of the projected block), the learned conv restriction (forward, weight
     gradients, training loss and its gradients), the restriction and C-PWR
-    entry points, the projection, the single-pass
-    SVD (with its kappa(Y) term), row ID (pivots and P) and SPC-ID-ERR with its rho(tau) estimate."""
+    entry points, the projection, the single-pass SVD (with its kappa(Y)
+    term), the row ID (pivots and P) and SPC-ID-ERR with its rho(tau)
+    estimate.  The emulation runs beside the other default ones."""
     import numpy as np
 
     from oracle import restrict as ores
     from oracle import rowid as orid
     from oracle import sketch as osk
-    from paper_2105_01271_amd import synth
 
-    exe = _build()
-    m, N, f, k, mc = 120, 16, 2, 10, 30
-    rng = np.random.default_rng(61)
-    A = synth.heat_modes(m, N, seed=60, nu=0.002) + 1e-2 * rng.standard_normal((m, N * N))
-    idx = ores.di_index_2d(N, N, f, f)
-    taus = np.array([0.0, 1.0, 4.0, 16.0])
-    (tmp_path / "dims.txt").write_text(f"{m} {N} {f} {k} {mc} {taus.size}\n")
-    A.astype("<f8").tofile(tmp_path / "A.bin")
-    taus.astype("<f8").tofile(tmp_path / "taus.bin")
-    # BF16 storage: round to nearest even on the FP32 bit pattern
-    bits = A.astype(np.float32).view(np.uint32).astype(np.uint64)
-    bf = ((bits + 0x7FFF + ((bits >> 16) & 1)) >> 16).astype("<u2")
-    bf.tofile(tmp_path / "Abf.bin")
-    A_bf = (bf.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
-    ellp = 2 * k + 3
-    Q = rng.standard_normal((m, ellp)).astype("<f4")
-    Q.tofile(tmp_path / "Q.bin")
-    Om = synth.gaussian_matrix(idx.size, k + 6, seed=62)
-    Om.astype("<f8").tofile(tmp_path / "Om.bin")
-    C, sl = 4, (N // 4) ** 2
-    w1 = (0.2 * rng.standard_normal((C, 5, 5))).astype("<f4")
-    w2 = (0.2 * rng.standard_normal((C, 5, 5))).astype("<f4")
-    w1[0, 2, 2] += 1.0
-    w2[0, 2, 2] += 1.0
-    gAc = rng.standard_normal((m, sl)).astype("<f4")
-    Q0 = rng.standard_normal((m, 6))
-    Q0.astype("<f8").tofile(tmp_path / "Q0.bin")
-    w1.tofile(tmp_path / "w1.bin")
-    w2.tofile(tmp_path / "w2.bin")
-    gAc.tofile(tmp_path / "gAc.bin")
-    r = subprocess.run([exe, "files", str(tmp_path)], capture_output=True, text=True, timeout=900)
+    tmp_path = emu.files_dir
+    inp = _files_inputs()
+    m, N, f, k, mc = inp["m"], inp["N"], inp["f"], inp["k"], inp["mc"]
+    A, idx, taus, A_bf, Q, Om = inp["A"], inp["idx"], inp["taus"], inp["A_bf"], inp["Q"], inp["Om"]
+    w1, w2, gAc, Q0 = inp["w1"], inp["w2"], inp["gAc"], inp["Q0"]
+    ellp, C, sl = 2 * k + 3, 4, (N // 4) ** 2
+    r = emu("files")
     out = r.stdout + r.stderr
     assert r.returncode == 0, out[-4000:]
     assert "ERROR: AddressSanitizer" not in out and "SIMT FATAL" not in out and "runtime error" not in out, out[-4000:]
