@@ -9,7 +9,10 @@ that Thm 3.2 bounds, ||(I - Q Q^T) A_f||, measured in the Frobenius norm:
     L = ||A - Q Q^T A||_F^2 / ||A||_F^2 = 1 - ||Q^T A||_F^2 / ||A||_F^2,
 
 with Q the l-wide orthonormal block of the SVD path (start block Y = A_c S_l,
-q coarse power steps with re-orthonormalisation, Alg. 7).
+q coarse power steps with re-orthonormalisation, Alg. 7).  The power steps
+use the Gram sub-sample A_g = A_f(:, I) of Alg. 7 (the direct-injection points
+of the conv's output grid), which does not depend on the weights: the weights
+reach Q only through the start block.
 
 Gradient.  L depends on Q only through span(Q).  Each QR step X = Q R only
 changes the basis inside span(X), and every later step (a product with A_c or
@@ -31,19 +34,21 @@ def _qr(X):
     return Q, R
 
 
-def projection_loss(A: np.ndarray, Ac: np.ndarray, ell: int, q: int, S=None):
+def projection_loss(A: np.ndarray, Ac: np.ndarray, ell: int, q: int, S=None, Ag=None):
+    """L of the sketch A_c; Ag (the Gram sub-sample of the power steps) is
+    needed when q >= 1."""
     A = np.asarray(A, dtype=np.float64)
     Y = _sketch.start_block(Ac, ell, S)
     Q, _ = _qr(Y)
     for _ in range(q):
-        Z, _ = _qr(Ac.T @ Q)
-        Q, _ = _qr(Ac @ Z)
+        Z, _ = _qr(Ag.T @ Q)
+        Q, _ = _qr(Ag @ Z)
     B = Q.T @ A
     return 1.0 - float(np.sum(B * B)) / float(np.sum(A * A))
 
 
-def projection_loss_grad(A: np.ndarray, Ac: np.ndarray, ell: int, q: int, S=None):
-    """Returns (L, dL/dA_c)."""
+def projection_loss_grad(A: np.ndarray, Ac: np.ndarray, ell: int, q: int, S=None, Ag=None):
+    """Returns (L, dL/dA_c); Ag as in projection_loss (held fixed)."""
     A = np.asarray(A, dtype=np.float64)
     Ac = np.asarray(Ac, dtype=np.float64)
     s = Ac.shape[1]
@@ -51,29 +56,25 @@ def projection_loss_grad(A: np.ndarray, Ac: np.ndarray, ell: int, q: int, S=None
     # forward, keeping every factor
     Y = _sketch.start_block(Ac, ell, S)
     Q0, R0 = _qr(Y)
-    Qs = [Q0]
     Zs, Rzs, Rqs = [], [], []
     Q = Q0
     for _ in range(q):
-        Z, Rz = _qr(Ac.T @ Q)
-        Q, Rq = _qr(Ac @ Z)
+        Z, Rz = _qr(Ag.T @ Q)
+        Q, Rq = _qr(Ag @ Z)
         Zs.append(Z)
         Rzs.append(Rz)
         Rqs.append(Rq)
-        Qs.append(Q)
     B = Q.T @ A
     L = 1.0 - float(np.sum(B * B)) / nrmA2
-    # backward
+    # backward (A_g does not depend on A_c: only the start block carries dA_c)
     dQ = -(2.0 / nrmA2) * (A @ B.T - Q @ (B @ B.T))
     dAc = np.zeros_like(Ac)
     for i in range(q - 1, -1, -1):
-        Rq, Z, Rz, Qprev = Rqs[i], Zs[i], Rzs[i], Qs[i]
-        dW = np.linalg.solve(Rq, dQ.T).T            # dQ R^{-T}
-        dAc += dW @ Z.T                             # W = A_c Z
-        dZ = Ac.T @ dW
-        dZp = np.linalg.solve(Rz, dZ.T).T           # Z = Z' Rz^{-1}
-        dAc += Qprev @ dZp.T                        # Z' = A_c^T Q_prev
-        dQ = Ac @ dZp
+        Rq, Rz = Rqs[i], Rzs[i]
+        dW = np.linalg.solve(Rq, dQ.T).T            # dQ R^{-T}, W = A_g Z
+        dZ = Ag.T @ dW
+        dZp = np.linalg.solve(Rz, dZ.T).T           # Z = Z' Rz^{-1}, Z' = A_g^T Q_prev
+        dQ = Ag @ dZp
     dY = np.linalg.solve(R0, dQ.T).T
     if S is None:
         cols = _sketch.nested_di_columns(s, ell)
@@ -86,6 +87,7 @@ def projection_loss_grad(A: np.ndarray, Ac: np.ndarray, ell: int, q: int, S=None
 def learned_loss_and_grad(A: np.ndarray, ny: int, nx: int, w1, w2, ell: int, q: int, S=None):
     """Loss of the conv-restricted sketch and its weight gradients (gw1, gw2)."""
     Ac = _restrict.conv_restrict(A, ny, nx, w1, w2)
-    L, dAc = projection_loss_grad(A, Ac, ell, q, S)
+    Ag = _restrict.gather(A, _restrict.gram_index({"kind": "learned", "ny": ny, "nx": nx})) if q > 0 else None
+    L, dAc = projection_loss_grad(A, Ac, ell, q, S, Ag)
     gw1, gw2 = _restrict.conv_restrict_bwd(A, ny, nx, w1, w2, dAc)
     return L, gw1, gw2

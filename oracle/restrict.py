@@ -61,6 +61,23 @@ def di_index_2d(ny: int, nx: int, sy: int, sx: int) -> np.ndarray:
     return (ys[:, None] * nx + xs[None, :]).ravel().astype(np.int64)
 
 
+def gram_index(R: dict) -> np.ndarray:
+    """The sub-sampling index set I of C-PWR's coarse Gram A_c = A_f(:, I)
+    (Alg. 7), which the algorithm keeps apart from the sketch D of its start
+    block.  An index restriction is its own I.  A stencil or learned
+    restriction takes R["gram_index"] when given, else the direct-injection
+    points of the same grid and factor (the points the stencils are centred or
+    anchored on; factor 4 x 4 for the learned conv, whose output is that
+    sub-grid)."""
+    if R["kind"] == "index":
+        return np.asarray(R["index"], dtype=np.int64)
+    if R.get("gram_index") is not None:
+        return np.asarray(R["gram_index"], dtype=np.int64)
+    if R["kind"] == "learned":
+        return di_index_2d(R["ny"], R["nx"], 4, 4)
+    return di_index_2d(R["ny"], R["nx"], R["sy"], R["sx"])
+
+
 def gather(A: np.ndarray, index: np.ndarray) -> np.ndarray:
     """Direct injection / Gram sub-sample: A_c = A_f(:, I) (Sec. 2; Alg. 7)."""
     return np.asarray(A, dtype=np.float64)[:, np.asarray(index)]

@@ -12,11 +12,18 @@ Readings of the paper used here:
     downdating); exact ties go to the lowest original column index.
   * "Solve R_2 ~ R_1 C by least squares": R_1 is k x k upper triangular and
     nonsingular when the rank is >= k, so C = R_1^{-1} R_2 by a triangular
-    solve.
+    solve.  When R_1 has negligible pivots (|r_jj| <= 1e-14 |r_11|; the
+    pivoted factor's diagonal does not increase, so they are its last k - r
+    pivots) the least-squares problem has many solutions; the basic one is
+    taken: the negligible pivots get zero coefficients and the leading r x r
+    triangle is solved, i.e. the interpolation uses the r independent
+    skeleton rows.
   * TPC-ID with q >= 1 (C-PWR without re-orthonormalisation, Sec. 7): the ID
-    is taken of W_q = (tau A_c A_c^T)^q A_c, evaluated in Alg. 7's order
-    (G <- A_c^T G, then G <- A_c G).  With a second-level sketch (Alg. 4
-    optional projection) the ID is taken of W_q S_l instead.
+    is taken of W_q = (tau A_g A_g^T)^q A_c, with A_c = A_f D the sketch and
+    A_g = A_f(:, I) the Gram sub-sample of Alg. 7 (A_g = A_c for an index
+    restriction), evaluated in Alg. 7's order (G <- A_g^T G, then
+    G <- A_g G).  With a second-level sketch (Alg. 4 optional projection)
+    the ID is taken of (tau A_g A_g^T)^q A_c S_l instead.
 """
 from __future__ import annotations
 
@@ -83,22 +90,26 @@ def row_id(W: np.ndarray, k: int):
     R1 = R[:, :k]
     R2 = R[:, k:]
     d = np.abs(np.diag(R1))
-    deficient = bool(d.min() <= 1e-14 * d.max()) if k > 0 else False
-    if deficient:
-        C = np.linalg.lstsq(R1, R2, rcond=None)[0]
-    else:
-        C = sla.solve_triangular(R1, R2, lower=False)
+    keep = d > 1e-14 * d[0] if k > 0 else np.zeros(0, dtype=bool)
+    r = int(np.count_nonzero(keep))
+    deficient = r < k
+    C = np.zeros((k, R2.shape[1]))
+    if r > 0:
+        # basic least-squares solution: the leading r x r triangle (negligible
+        # pivots are a suffix of the diagonal), zero rows for the rest
+        C[:r] = sla.solve_triangular(R1[:r, :r], R2[:r], lower=False)
     P = np.zeros((m, k))
     P[perm[:k], :] = np.eye(k)
     P[perm[k:], :] = C.T
     return perm[:k].copy(), P, {"R": R, "perm": perm, "gaps": gaps, "C": C,
-                                "rank_deficient": deficient}
+                                "rank_deficient": deficient, "rank": r}
 
 
-def coarse_power(Ac: np.ndarray, q: int, tau: float, G: np.ndarray | None = None) -> np.ndarray:
-    """(tau A_c A_c^T)^q G without re-orthonormalisation, G = A_c by default."""
-    G = Ac if G is None else G
-    return _sketch.power_iter(Ac, G, q, tau, reorth=False)
+def coarse_power(Ag: np.ndarray, q: int, tau: float, G: np.ndarray | None = None) -> np.ndarray:
+    """(tau A_g A_g^T)^q G without re-orthonormalisation (Alg. 7 with its
+    optional QR steps left out), A_g the Gram sub-sample; G = A_g by default."""
+    G = Ag if G is None else G
+    return _sketch.power_iter(Ag, G, q, tau, reorth=False)
 
 
 def tpc_id(A: np.ndarray, k: int, R: dict, q: int = 0, tau: float | None = None,
@@ -106,21 +117,24 @@ def tpc_id(A: np.ndarray, k: int, R: dict, q: int = 0, tau: float | None = None,
            return_all: bool = False):
     """TPC-ID (Alg. 4): A_c = A_f D, (P_c, I_c) = ID(A_c^T), A ~ P_c A_f(I_c, :).
 
-    projected=True uses the l-wide second-level block W_q S_l instead of the
-    full coarse sketch (Alg. 4 optional projection)."""
+    q >= 1 applies C-PWR (Alg. 7, no re-orthonormalisation) with the Gram
+    sub-sample A_g = A_f(:, I).  projected=True uses the l-wide second-level
+    block A_c S_l instead of the full coarse sketch (Alg. 4 optional
+    projection)."""
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     if Ac is None:
         Ac = _restrict.apply(A, R)
     s = Ac.shape[1]
+    Ag = _sketch.gram_sample(A, R, Ac) if q > 0 else Ac
     if tau is None:
-        tau = n / s
+        tau = n / Ag.shape[1]
     if projected:
         ell = _sketch.ell_of(k, s, m, p) if S is None else np.asarray(S).shape[1]
         G = _sketch.start_block(Ac, ell, S)
     else:
         G = Ac
-    W = coarse_power(Ac, q, tau, G)
+    W = coarse_power(Ag, q, tau, G)
     I, P, info = row_id(W, k)
     if return_all:
         info.update({"Ac": Ac, "W": W, "skeleton_rows": A[I]})
@@ -202,7 +216,7 @@ def spc_id_err_curve(A: np.ndarray, R: dict, mc: int, taus, Ac=None) -> np.ndarr
 
 def spc_rho_curve(A: np.ndarray, R: dict, mc: int, taus, Ac=None) -> np.ndarray:
     """The subsampled estimate of rho(tau) = ||A_f A_f^T - tau A_c A_c^T||_2
-    (the Gram-mismatch measure of the C-PWR analysis, Sec. 3), formed from the
+    (the Gram-mismatch measure of the C-PWR analysis, Sec. 5), formed from the
     same kept rows as Alg. 6: rho_hat(tau) = c ||B_f B_f^T - tau B_c B_c^T||_2,
     c = m // mc.  The matrix is symmetric, so its 2-norm is its largest
     eigenvalue magnitude.  With mc = m it is rho(tau) itself."""
@@ -218,7 +232,7 @@ def spc_rho_curve(A: np.ndarray, R: dict, mc: int, taus, Ac=None) -> np.ndarray:
 
 
 def rho_tau(A: np.ndarray, Ac: np.ndarray, tau: float) -> float:
-    """rho(tau) = ||A_f A_f^T - tau A_c A_c^T||_2 (Sec. 3, C-PWR analysis)."""
+    """rho(tau) = ||A_f A_f^T - tau A_c A_c^T||_2 (Sec. 5, C-PWR analysis)."""
     return float(np.linalg.norm(A @ A.T - tau * (Ac @ Ac.T), 2))
 
 

@@ -52,9 +52,11 @@ def orth(Y: np.ndarray) -> np.ndarray:
 def power_iter(Ac: np.ndarray, G: np.ndarray, q: int, tau: float, reorth: bool = True) -> np.ndarray:
     """C-PWR loop (Alg. 7): repeat q times  G <- A_c^T G, [QR], G <- A_c G, [QR].
 
-    The coarse Gram is scaled by tau (Sec. 5: approximate power of
-    (tau A_c A_c^T)); the scale is applied on the A_c^T product.  With
-    reorth=False the raw block (tau A_c A_c^T)^q G is returned.
+    Ac is the Gram sub-sample A_f(:, I) of Alg. 7 (for an index restriction
+    the restriction itself; see restrict.gram_index).  The coarse Gram is
+    scaled by tau (Sec. 5: approximate power of (tau A_c A_c^T)); the scale is
+    applied on the A_c^T product.  With reorth=False the raw block
+    (tau A_c A_c^T)^q G is returned.
     """
     G = np.asarray(G, dtype=np.float64)
     for _ in range(q):
@@ -78,13 +80,22 @@ def sign_normalise(U: np.ndarray, V: np.ndarray):
     return U, V
 
 
+def gram_sample(A: np.ndarray, R: dict, Ac: np.ndarray) -> np.ndarray:
+    """A_f(:, I), the coarse matrix of C-PWR's Gram (Alg. 7): the restriction's
+    own A_c when it is an index restriction, else the gather of gram_index."""
+    if R is not None and R.get("kind") != "index":
+        return _restrict.gather(A, _restrict.gram_index(R))
+    return Ac
+
+
 def tpc_svd(A: np.ndarray, k: int, R: dict, q: int = 0, p: int = 10, S=None,
             tau: float | None = None, Ac: np.ndarray | None = None, return_all: bool = False):
     """Rank-k SVD via the deterministic sketch (Alg. 2) and C-PWR (Alg. 7).
 
     1. A_c = A_f D                                  (Sec. 2)
     2. Y = A_c S_l, Q = QR(Y)                       (Alg. 2 QR step; Alg. 7 start)
-    3. q coarse power steps with re-orthonormalisation (Alg. 7)
+    3. q coarse power steps with re-orthonormalisation (Alg. 7), on the
+       Gram sub-sample A_f(:, I) (= A_c for an index restriction)
     4. B = Q^T A_f                                  (Alg. 2; Sec. 3.1)
     5. SVD(B) = U_B Sigma V_B^T, U = Q U_B          (Alg. 2)
     6. truncate to k
@@ -96,24 +107,25 @@ def tpc_svd(A: np.ndarray, k: int, R: dict, q: int = 0, p: int = 10, S=None,
         Ac = _restrict.apply(A, R)
     s = Ac.shape[1]
     ell = ell_of(k, s, m, p) if S is None else np.asarray(S).shape[1]
+    Ag = gram_sample(A, R, Ac) if q > 0 else Ac
     if tau is None:
-        tau = n / s
+        tau = n / Ag.shape[1]
     Y = start_block(Ac, ell, S)
     Q = orth(Y)
-    Q = power_iter(Ac, Q, q, tau, reorth=True)
+    Q = power_iter(Ag, Q, q, tau, reorth=True)
     B = Q.T @ A
     UB, sig, VBt = np.linalg.svd(B, full_matrices=False)
     U = Q @ UB[:, :k]
     V = VBt[:k].T
     U, V = sign_normalise(U, V)
     if return_all:
-        return U, sig[:k], V, {"Ac": Ac, "Y": Y, "Q": Q, "B": B, "sigma_B": sig, "ell": ell,
+        return U, sig[:k], V, {"Ac": Ac, "Ag": Ag, "Y": Y, "Q": Q, "B": B, "sigma_B": sig, "ell": ell,
                                "tau": tau}
     return U, sig[:k], V
 
 
 def spc_svd(A: np.ndarray, k: int, R: dict, p: int = 10, S=None, Ac: np.ndarray | None = None,
-            rows_per_read: int = 1):
+            rows_per_read: int = 1, return_all: bool = False):
     """Single-pass SPC-SVD (Alg. 3).
 
     One pass over the rows of A_f accumulates the coarse rows a_c = a_f D S_l
@@ -142,6 +154,8 @@ def spc_svd(A: np.ndarray, k: int, R: dict, p: int = 10, S=None, Ac: np.ndarray 
     U = Qc @ Ut[:, :k]
     V = Vt[:k].T
     U, V = sign_normalise(U, V)
+    if return_all:
+        return U, sig[:k], V, {"sigma_B": sig, "ell": ell}
     return U, sig[:k], V
 
 

@@ -131,6 +131,86 @@ def test_large_q_converges_to_top_left_singular_subspace_of_Ac():
     assert sv.min() > 1 - 1e-10
 
 
+def _proj_dist(X, Y):
+    """Largest principal-angle sine between span(X) and span(Y)."""
+    Qx = np.linalg.qr(X)[0]
+    Qy = np.linalg.qr(Y)[0]
+    return float(np.linalg.norm(Qx @ Qx.T - Qy @ Qy.T, 2))
+
+
+@pytest.mark.parametrize("kind", ["nn", "global"])
+def test_cpwr_gram_uses_index_subsample_not_the_stencil(kind):
+    # Alg. 7: the start block is the sketch A_f D, the power steps use the
+    # index sub-sample A_c = A_f(:, I).  For a stencil sketch the default I is
+    # the set of direct-injection points, i.e. the columns where the explicit
+    # DI matrix of the same grid has its ones.
+    ny = nx = 12
+    sy = sx = 3
+    Ddi = restrict.d_matrix_2d("di", ny, nx, sy, sx)
+    I_expl = np.nonzero(Ddi.sum(axis=1))[0]
+    R = {"kind": kind, "ny": ny, "nx": nx, "sy": sy, "sx": sx}
+    np.testing.assert_array_equal(restrict.gram_index(R), I_expl)
+    rng = np.random.default_rng(21)
+    A = synth.heat_modes(40, 12, seed=3, nu=0.002) + 0.1 * rng.standard_normal((40, ny * nx))
+    D = restrict.d_matrix_2d(kind, ny, nx, sy, sx)
+    Ag = A @ Ddi                                    # A_f(:, I) through the explicit DI matrix
+    Y = (A @ D)[:, sketch.nested_di_columns(D.shape[1], 6)]
+    for q in (1, 2):
+        tau = A.shape[1] / Ag.shape[1]
+        raw = Y.copy()
+        for _ in range(q):                          # Alg. 7 without its optional QR steps
+            raw = Ag @ (tau * (Ag.T @ raw))
+        _, _, _, info = sketch.tpc_svd(A, 4, R, q=q, p=2, return_all=True)
+        assert info["ell"] == 6
+        assert _proj_dist(info["Q"], raw) < 1e-8, q
+        # the stencil's own Gram gives a different span: the sub-sample matters
+        Ac = A @ D
+        wrong = Y.copy()
+        for _ in range(q):
+            wrong = Ac @ (Ac.T @ wrong)
+        assert _proj_dist(info["Q"], wrong) > 1e-3, q
+    # the ID's power block: (tau A_g A_g^T)^q (A_f D), its row space in the W the ID factors
+    I, P, info = rowid.tpc_id(A, 4, R, q=1, return_all=True)
+    tau = A.shape[1] / Ag.shape[1]
+    np.testing.assert_allclose(info["W"], tau * Ag @ (Ag.T @ (A @ D)), rtol=1e-11, atol=1e-12 * np.abs(info["W"]).max())
+
+
+def test_cpwr_index_restriction_is_its_own_gram_subsample():
+    R = _di(8, 8, 2, 2)
+    A = np.random.default_rng(22).standard_normal((20, 64))
+    np.testing.assert_array_equal(restrict.gram_index(R), R["index"])
+    _, _, _, info = sketch.tpc_svd(A, 3, R, q=1, return_all=True)
+    assert info["Ag"] is info["Ac"]
+
+
+def test_proto_tpc_basis_is_the_large_q_limit_of_cpwr():
+    # PROTO-TPC (Alg. 1) takes U~ = the top-k left singular vectors of A_c; the
+    # re-orthonormalised coarse power iteration with all of A_c as its Gram
+    # converges to the same span (a different route: products and QR only)
+    rng = np.random.default_rng(23)
+    A = rng.standard_normal((50, 64)) @ np.diag(0.85 ** np.arange(64)) @ rng.standard_normal((64, 64))
+    R = _di(8, 8, 2, 2)
+    Ac = restrict.apply(A, R)
+    k = 5
+    Uk, Sk, Vk = sketch.proto_tpc(A, k, Ac)
+    Q = sketch.power_iter(Ac, sketch.orth(Ac[:, :k]), 80, 1.0)
+    assert _proj_dist(Uk, Q) < 1e-10
+    # S~ are the top singular values of A_c: the norms of A_c^T Q's columns at convergence
+    np.testing.assert_allclose(np.sort(np.linalg.svd(Ac.T @ Q, compute_uv=False))[::-1], Sk, rtol=1e-10)
+    # U~ S~ V~^T is the projection of A onto span(U~) (pseudo-inverse step of Alg. 1)
+    Ahat = (Uk * Sk) @ Vk.T
+    np.testing.assert_allclose(Ahat, Q @ (Q.T @ A), atol=1e-9 * np.abs(A).max())
+
+
+def test_proto_tpc_recovers_rank_k_inputs_exactly():
+    # rank-k A whose coarse columns keep the rank: range(A_c) = range(A), so
+    # U~ U~^T A = A (Alg. 1 with an exact sketch)
+    A = synth.lowrank(30, 64, 4, seed=24)
+    Ac = restrict.apply(A, _di(8, 8, 2, 2))
+    Uk, Sk, Vk = sketch.proto_tpc(A, 4, Ac)
+    assert np.linalg.norm(A - (Uk * Sk) @ Vk.T) < 1e-12 * np.linalg.norm(A)
+
+
 # ------------------------------------------------------------------ TPC-SVD (Alg. 2 + Alg. 7)
 
 def _di(ny, nx, sy, sx):
@@ -258,6 +338,35 @@ def test_row_id_interpolates_and_recovers_rank_k():
     I, P, info = rowid.row_id(A, 5)
     np.testing.assert_array_equal(P[I], np.eye(5))      # P(I,:) = I_k exactly
     assert metrics.id_error(A, I, P) < 1e-12
+
+
+@pytest.mark.parametrize("r,k", [(3, 6), (1, 4), (5, 8)])
+def test_row_id_rank_deficient_basic_solution(r, k):
+    # W of rank r < k: the pivoted factor's diagonal collapses after r steps,
+    # the ID flags the deficiency and takes the basic least-squares solution
+    # (zero coefficients on the negligible pivots).  Facts checked: P(I,:) = I_k,
+    # the reconstruction is exact, and it equals the orthogonal projection of
+    # every row onto the span of the first r skeleton rows, computed here by a
+    # separate least-squares fit on W itself.
+    W = synth.lowrank(14, 23, r, seed=30 + r)
+    I, P, info = rowid.row_id(W, k)
+    assert info["rank_deficient"] and info["rank"] == r
+    np.testing.assert_array_equal(P[I], np.eye(k))
+    assert np.all(info["C"][r:] == 0.0)
+    assert np.linalg.norm(W - P @ W[I]) < 1e-12 * np.linalg.norm(W)
+    Bk = W[I[:r]]
+    coef = np.linalg.lstsq(Bk.T, W.T, rcond=None)[0]
+    rest = np.setdiff1d(np.arange(W.shape[0]), I)     # rows of P that interpolate
+    np.testing.assert_allclose(P[rest, :r], coef.T[rest], atol=1e-9)
+    assert np.all(P[rest, r:] == 0.0)
+    # the first r pivots are the greedy-projection pivots (brute force)
+    assert list(I[:r]) == list(_greedy_pivots(W.T, r))
+
+
+def test_row_id_full_rank_is_not_flagged():
+    W = synth.lowrank(14, 23, 8, seed=40)
+    I, P, info = rowid.row_id(W, 6)
+    assert not info["rank_deficient"] and info["rank"] == 6
 
 
 def test_row_id_soft_bound():
@@ -443,13 +552,14 @@ def test_projection_loss_gradient_finite_difference():
     rng = np.random.default_rng(14)
     A = synth.heat_modes(20, 8, seed=9, nu=0.002) + 0.05 * rng.standard_normal((20, 64))
     Ac = restrict.apply(A, _di(8, 8, 2, 2)) + 0.01 * rng.standard_normal((20, 16))
-    for q in (0, 1):
-        L, g = learned.projection_loss_grad(A, Ac, 4, q)
-        assert abs(L - learned.projection_loss(A, Ac, 4, q)) < 1e-14
+    Ag = restrict.gather(A, restrict.di_index_2d(8, 8, 2, 2))     # the power steps' fixed Gram sub-sample
+    for q in (0, 1, 2):
+        L, g = learned.projection_loss_grad(A, Ac, 4, q, Ag=Ag)
+        assert abs(L - learned.projection_loss(A, Ac, 4, q, Ag=Ag)) < 1e-14
         h = 1e-6
-        for idx in [(0, 0), (3, 4), (7, 12), (19, 15)]:
+        for idx in [(0, 0), (3, 4), (7, 12), (19, 15), (5, 5)]:
             E = np.zeros_like(Ac); E[idx] = h
-            fd = (learned.projection_loss(A, Ac + E, 4, q) - learned.projection_loss(A, Ac - E, 4, q)) / (2 * h)
+            fd = (learned.projection_loss(A, Ac + E, 4, q, Ag=Ag) - learned.projection_loss(A, Ac - E, 4, q, Ag=Ag)) / (2 * h)
             assert abs(fd - g[idx]) < 1e-6 * max(1e-3, abs(fd)), (q, idx, fd, g[idx])
 
 
@@ -461,8 +571,10 @@ def test_learned_weight_gradient_finite_difference():
     w2 = rng.standard_normal((1, 4, 5, 5)) * 0.3
     L, gw1, gw2 = learned.learned_loss_and_grad(A, ny, nx, w1, w2, ell=3, q=1)
 
+    Ag = A[:, restrict.di_index_2d(ny, nx, 4, 4)]
+
     def loss(a, b):
-        return learned.projection_loss(A, restrict.conv_restrict(A, ny, nx, a, b), 3, 1)
+        return learned.projection_loss(A, restrict.conv_restrict(A, ny, nx, a, b), 3, 1, Ag=Ag)
 
     h = 1e-6
     for idx in [(0, 0, 2, 2), (2, 0, 1, 3)]:
