@@ -6,25 +6,32 @@ One step = one rank-k sketch SVD (TPC-SVD with q = 1 coarse power step,
 Alg. 2 + Alg. 7) plus one rank-k row ID (TPC-ID, Alg. 4, q = 0, with the
 skeleton rows) of the same snapshot matrix, inputs resident in HBM, issued as
 one dsk_sketch_svd_id call (the ID overlaps the SVD on a second stream).
-Workload: 1000 time steps x 256x256 grid (n = 65536), FP32, advection-diffusion
-Fourier modes with sigma_j = j^-0.5 plus 1e-3 relative Gaussian noise, direct
-injection every 4th grid point per axis (s = 4096), k = 50, l = 60.
 
-value = algorithmic HBM bytes of one step / step time (GB/s); the
-algorithmic bytes are those the method must move (A once for the projection,
-the coarse sketch for the gather and each power product, the factors written):
-  svd: 4 [m n + (1 + 2q) m s] + 4 (m + n) k + 8 k
-  id : 4 (m s + k n) + 8 m k
+Workload (the mixed-precision form): heat-mode snapshots 2000 time steps x
+512x512 grid (n = 262144), sigma_j = exp(-0.05 j), stored in BF16 (1.05 GB),
+direct injection with strides (8, 4) (s = 8192), k = 100, ell = 110.
+
+value = algorithmic HBM bytes of one step / step time (GB/s); the algorithmic
+bytes are what the method must move (A once for the projection, the coarse
+sketch for the gather and each power product, the factors written):
+  svd: e_A [m n + (1 + 2q) m s] + 4 (m + n) k + 8 k
+  id : e_A (m s + k n) + 8 m k
 roofline: the projection kernel B^T = A^T Q (the only full pass over A), timed
-with HIP events around that kernel on the stream it runs on, algorithmic bytes
-per launch 4 m n + 4 n l + 4 m l, against 8 TB/s.
-cpu_baseline: the FP64 NumPy oracle of the same step on the host cores.
+with HIP events around that kernel on the stream it runs on; bytes per launch
+e_A m n + 4 n ell + 4 m ell (A and Q read, B^T written), against 8 TB/s.
+time_to_eps: least sketch-SVD time over q in {0, 1, 2} whose rank-k error
+against the FP64 matrix is within (1 + 0.05) of the exact tail
+(sum_{j>k} sigma_j^2)^(1/2), for the same matrix stored FP32, BF16 and FP16.
+c2: the FP32 workload (advection-diffusion 1000 x 256^2, s = 4096, k = 50)
+timed the same way.
+cpu_baseline: the FP64 NumPy oracle of one step on the host cores.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -36,6 +43,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "HBM GB/s per rank-k sketch SVD/ID of A; time-to-ε (vs σ_{k+1}), mixed vs FP32"
 HBM_PEAK_GBS = 8000.0
+ESIZE = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
 
 
 def parse():
@@ -43,32 +51,26 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--m", type=int, default=1000)
-    ap.add_argument("--grid", type=int, default=256)
-    ap.add_argument("--factor", type=int, default=4)
-    ap.add_argument("--k", type=int, default=50)
     ap.add_argument("--q", type=int, default=1)
-    ap.add_argument("--mode", default="default")
-    ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-reps", type=int, default=4)
-    ap.add_argument("--no-breakdown", action="store_true", help="skip the per-component timings and time-to-eps")
-    ap.add_argument("--mreo-trials", type=int, default=100, help="trials of the hybrid-sketch MREO harness")
+    ap.add_argument("--no-breakdown", action="store_true", help="skip component timings and time-to-eps")
+    ap.add_argument("--no-c2", action="store_true", help="skip the FP32 advection-diffusion workload")
+    ap.add_argument("--mreo-trials", type=int, default=20, help="trials of the hybrid-sketch MREO harness (C2)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 256 MiB device copy (known bytes) to scale HBM counters")
     return ap.parse_args()
 
 
-def algorithmic_bytes(m, n, s, k, q, e=4):
-    svd = e * (m * n + (1 + 2 * q) * m * s) + e * (m + n) * k + 8 * k
+def algorithmic_bytes(m, n, s, k, q, e):
+    svd = e * (m * n + (1 + 2 * q) * m * s) + 4 * (m + n) * k + 8 * k
     rid = e * (m * s + k * n) + 8 * m * k
     return svd, rid
 
 
-def traffic_from_profile(kernel_src_hash):
+def traffic_from_profile(kernel_src_hash, name):
     """HBM bytes per launch of the projection kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "stream_tn_c2_counters.json")
+    path = os.path.join(ROOT, "profiles", name)
     try:
         with open(path) as f:
             d = json.load(f)
@@ -79,59 +81,114 @@ def traffic_from_profile(kernel_src_hash):
     return d.get("hbm_bytes_per_launch")
 
 
-def time_to_eps(torch, dsketch, A, A_np, k, R, svd_ms, timed, eps=0.05):
-    """Least sketch-SVD wall time over q in {0, 1, 2} whose rank-k error meets
-    ||A - U S V^T||_F <= (1 + eps) (sum_{j>k} sigma_j^2)^(1/2), for the FP32
-    input and for the same matrix stored in BF16 (mixed path).  The exact tail
-    comes from an FP64 eigendecomposition of A A^T on the host; errors are
-    measured against the FP32 matrix in FP64 on the host."""
-    Ad = A_np.astype(np.float64)
-    lam = np.linalg.eigvalsh(Ad @ Ad.T)[::-1]
-    tail = float(np.sqrt(max(lam[k:].sum(), 0.0)))
-    nA2 = float((Ad * Ad).sum())
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
-    def err(U, S, V):
-        Un, Sn, Vn = U.double().cpu().numpy(), S.cpu().numpy(), V.double().cpu().numpy()
-        AV = Ad @ Vn
-        cross = float(np.einsum("ij,ij,j->", Un, AV, Sn))
-        gram = (Un.T @ Un) * (Vn.T @ Vn)
-        return float(np.sqrt(max(nA2 - 2 * cross + Sn @ gram @ Sn, 0.0)))
 
-    out = {"eps": eps, "tail_fro": round(tail, 6)}
-    Ab = A.to(torch.bfloat16)
-    for name, X, ms in (("fp32", A, svd_ms), ("bf16", Ab, None)):
-        if ms is None:
-            ms = {qq: timed(lambda qq=qq: dsketch.sketch_svd(X, k, R, q=qq)) for qq in (0, 1, 2)}
-        ratios = {}
-        best = None
+def timed(torch, fn, reps=10, warm=2):
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t) / reps
+
+
+def time_step(torch, dsketch, step, warmup, steps):
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    dsketch.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    nlaunch, kms = dsketch.timing_read()
+    dsketch.timing_enable(False)
+    return 1e3 * dt / steps, nlaunch, kms
+
+
+def rank_k_error(torch, A64_dev, U, S, V):
+    """||A - U S V^T||_F against the FP64 matrix, expanded so that only
+    A V (one product) is formed: ||A||^2 - 2 tr(S U^T A V) + tr(S (U^T U) S (V^T V))."""
+    Ud, Vd, Sd = U.double(), V.double(), S.double()
+    AV = A64_dev @ Vd
+    cross = float((Ud * AV * Sd[None, :]).sum())
+    gram = (Ud.T @ Ud) * (Vd.T @ Vd)
+    nA2 = float((A64_dev * A64_dev).sum())
+    return math.sqrt(max(nA2 - 2 * cross + float(Sd @ gram @ Sd), 0.0))
+
+
+def time_to_eps(torch, dsketch, variants, A64_dev, k, R, tail, eps=0.05):
+    """Least sketch-SVD wall time over q in {0, 1, 2} with ||A - U S V^T||_F <=
+    (1 + eps) tail, for each stored variant of the same matrix (each call
+    warmed up before it is timed); errors against the FP64 matrix on the GPU
+    in FP64."""
+    out = {"eps": eps, "tail_fro": tail}
+    for name, X in variants:
+        ms, ratios = {}, {}
         for qq in (0, 1, 2):
+            ms[qq] = timed(torch, lambda qq=qq: dsketch.sketch_svd(X, k, R, q=qq), reps=5, warm=2)
             U, S, V = dsketch.sketch_svd(X, k, R, q=qq)
-            ratios[qq] = err(U, S, V) / tail
-            if ratios[qq] <= 1 + eps and (best is None or ms[qq] < ms[best]):
-                best = qq
+            ratios[qq] = rank_k_error(torch, A64_dev, U, S, V) / tail
+        ok = [qq for qq in (0, 1, 2) if ratios[qq] <= 1 + eps]
+        best = min(ok, key=lambda qq: ms[qq]) if ok else None
         out[name] = {"q": best, "ms": round(ms[best], 4) if best is not None else None,
                      "err_over_tail": {f"q{qq}": round(r, 5) for qq, r in ratios.items()},
                      "svd_ms": {f"q{qq}": round(t, 4) for qq, t in ms.items()}}
+        log(f"time-to-eps {name}: {out[name]}")
     return out
 
 
-def hybrid_mreo(torch, dsketch, A, k, R, tail, trials):
-    """MREO (max over trials of ||A - U S V^T||_F / ||A - A_k||_F, Sec. 6) of the
-    hybrid sketch (Gaussian s x ell second level, `trials` seeds) for TPC-SVD
-    at q = 0, 1 and SPC-SVD, next to the deterministic nested-DI start block."""
-    from paper_2105_01271_amd import hybrid
-    out = {"trials": trials}
-    for name, q, sp in (("tpc_q0", 0, False), ("tpc_q1", 1, False), ("spc", 0, True)):
-        t0 = time.perf_counter()
-        errs = hybrid.trial_errors(A, k, R, trials=trials, q=q, seed0=0, single_pass=sp)
-        dt = (time.perf_counter() - t0) / trials
-        if sp:
-            _, S, _, info = dsketch.sketch_svd_sp(A, k, R, want_info=True)
-        else:
-            _, S, _, info = dsketch.sketch_svd(A, k, R, q=q, want_info=True)
-        di = float(np.sqrt(max(info["normA_fro2"] - float((S * S).sum().item()), 0.0))) / tail
-        out[name] = {"mreo_gaussian": round(hybrid.mreo(errs, tail), 5), "ratio_nested_di": round(di, 5),
-                     "ms_per_trial": round(1e3 * dt, 3)}
+def roofline_of(kms, nlaunch, kern_bytes, traffic):
+    kern_ms = kms / max(nlaunch, 1)
+    achieved = kern_bytes / (kern_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "k_stream_mfma (B^T = A^T Q)", "avg_ms": round(kern_ms, 5), "launches": nlaunch,
+            "bytes_per_launch": kern_bytes}
+
+
+def c2_leg(torch, dsketch, synth, a, dev, src_hash):
+    m, N, f, k, q = 1000, 256, 4, 50, 1
+    n = N * N
+    A_np = synth.advdiff_exact(m, N, seed=0, r=m).astype(np.float32)
+    A = torch.from_numpy(A_np).to(dev)
+    R = dsketch.Restriction.di_grid(N, N, f, f, device=dev)
+    s = R.coarse_size()
+    ell = min(k + 10, s, m)
+    step = lambda: dsketch.sketch_svd_id(A, k, R, q_svd=q, q_id=0, skeleton_rows=True)
+    ms, nl, kms = time_step(torch, dsketch, step, a.warmup, a.steps)
+    b_svd, b_id = algorithmic_bytes(m, n, s, k, q, 4)
+    rl = roofline_of(kms, nl, 4 * m * n + 4 * n * ell + 4 * m * ell,
+                     traffic_from_profile(src_hash, "stream_tn_c2_counters.json"))
+    out = {"workload": f"advection-diffusion snapshots {m}x{N}x{N} f32 (sigma_j = j^-0.5, 1e-3 noise), direct "
+                       f"injection {f}x{f} (s={s}), k={k}, l={ell}: sketch SVD q={q} + row ID q=0",
+           "ms_per_step": round(ms, 4), "value": round((b_svd + b_id) / (ms * 1e-3) / 1e9, 2), "unit": "GB/s",
+           "roofline": rl}
+    if not a.no_breakdown:
+        out["breakdown_ms"] = {
+            "svd_q0": round(timed(torch, lambda: dsketch.sketch_svd(A, k, R, q=0)), 4),
+            "svd_q1": round(timed(torch, lambda: dsketch.sketch_svd(A, k, R, q=1)), 4),
+            "svd_q2": round(timed(torch, lambda: dsketch.sketch_svd(A, k, R, q=2)), 4),
+            "id_q0": round(timed(torch, lambda: dsketch.sketch_id(A, k, R, q=0, skeleton_rows=True)), 4),
+            "svd_single_pass": round(timed(torch, lambda: dsketch.sketch_svd_sp(A, k, R)), 4)}
+        if a.mreo_trials > 0:
+            from paper_2105_01271_amd import hybrid
+            Ad = A_np.astype(np.float64)
+            lam = np.linalg.eigvalsh(Ad @ Ad.T)[::-1]
+            tail = float(np.sqrt(max(lam[k:].sum(), 0.0)))
+            mre = {"trials": a.mreo_trials}
+            for name, qq, sp in (("tpc_q0", 0, False), ("tpc_q1", 1, False), ("spc", 0, True)):
+                errs = hybrid.trial_errors(A, k, R, trials=a.mreo_trials, q=qq, seed0=0, single_pass=sp)
+                mre[name] = round(hybrid.mreo(errs, tail), 5)
+            out["hybrid_mreo"] = mre
+    del A
+    torch.cuda.empty_cache()
     return out
 
 
@@ -145,34 +202,25 @@ def main():
 
     from paper_2105_01271_amd import dsketch, synth
 
-    m, N, f, k, q = a.m, a.grid, a.factor, a.k, a.q
-    n = N * N
+    m, NY, NX, sy, sx, k, q = 2000, 512, 512, 8, 4, 100, a.q
+    n = NY * NX
     t0 = time.time()
-    A_np = synth.advdiff_exact(m, N, seed=a.seed, r=m).astype(np.float32)
-    print(f"[bench] input generated in {time.time() - t0:.1f}s: {m}x{n} f32", file=sys.stderr, flush=True)
+    A64, sig = synth.heat_exact(m, NY, NX, seed=7, return_parts=True)
+    log(f"input generated in {time.time() - t0:.1f}s: {m}x{n}")
     dev = torch.device("cuda:0")
-    A = torch.from_numpy(A_np).to(dev)
-    R = dsketch.Restriction.di_grid(N, N, f, f, device=dev)
+    A = torch.from_numpy(A64).to(torch.bfloat16).to(dev)
+    R = dsketch.Restriction.di_grid(NY, NX, sy, sx, device=dev)
     s = R.coarse_size()
     ell = min(k + 10, s, m)
+    src = open(os.path.join(ROOT, "paper_2105_01271_amd", "csrc", "stream.hip"), "rb").read()
+    src_hash = hashlib.sha256(src).hexdigest()
 
     def step():
         # one call: the row ID runs on a worker stream concurrently with the SVD
-        return dsketch.sketch_svd_id(A, k, R, q_svd=q, q_id=0, skeleton_rows=True, mode=a.mode)
+        return dsketch.sketch_svd_id(A, k, R, q_svd=q, q_id=0, skeleton_rows=True)
 
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    dsketch.timing_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        out = step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    nlaunch, kms = dsketch.timing_read()
-    dsketch.timing_enable(False)
-    ms_per_step = 1e3 * dt / a.steps
+    ms_per_step, nlaunch, kms = time_step(torch, dsketch, step, a.warmup, a.steps)
+    log(f"step {ms_per_step:.4f} ms, projection {kms / max(nlaunch, 1):.4f} ms")
 
     if a.copy_calib:
         src_c = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
@@ -182,43 +230,32 @@ def main():
         torch.cuda.synchronize()
         del src_c, dst_c
 
-    # component timings (outside the timed region)
-    def timed(fn, reps=10):
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(reps):
-            fn()
-        torch.cuda.synchronize()
-        return 1e3 * (time.perf_counter() - t) / reps
-
-    breakdown = None
-    tte = None
-    mreo = None
-    if not a.no_breakdown:
-        svd_ms = {qq: timed(lambda qq=qq: dsketch.sketch_svd(A, k, R, q=qq, mode=a.mode)) for qq in (0, 1, 2)}
-        id_ms = timed(lambda: dsketch.sketch_id(A, k, R, q=0, skeleton_rows=True))
-        sp_ms = timed(lambda: dsketch.sketch_svd_sp(A, k, R, mode=a.mode))
-        sweeps = {qq: dsketch.sketch_svd(A, k, R, q=qq, mode=a.mode, want_info=True)[3]["core_sweeps"]
-                  for qq in (0, 1, 2)}
-        breakdown = {"svd_q0": round(svd_ms[0], 4), "svd_q1": round(svd_ms[1], 4), "svd_q2": round(svd_ms[2], 4),
-                     "id_q0": round(id_ms, 4), "svd_single_pass": round(sp_ms, 4),
-                     "core_sweeps": {f"q{qq}": sweeps[qq] for qq in (0, 1, 2)}}
-        tte = time_to_eps(torch, dsketch, A, A_np, k, R, svd_ms, timed)
-        mreo = hybrid_mreo(torch, dsketch, A, k, R, tte["tail_fro"], a.mreo_trials)
-
-    b_svd, b_id = algorithmic_bytes(m, n, s, k, q)
+    e = ESIZE["bf16"]
+    b_svd, b_id = algorithmic_bytes(m, n, s, k, q, e)
     step_bytes = b_svd + b_id
     value = step_bytes / (ms_per_step * 1e-3) / 1e9
+    roofline = roofline_of(kms, nlaunch, e * m * n + 4 * n * ell + 4 * m * ell,
+                           traffic_from_profile(src_hash, "stream_tn_c3_counters.json"))
 
-    kern_bytes = 4 * m * n + 4 * n * ell + 4 * m * ell
-    kern_ms = kms / max(nlaunch, 1)
-    achieved = kern_bytes / (kern_ms * 1e-3) / 1e9
-    src = open(os.path.join(ROOT, "paper_2105_01271_amd", "csrc", "stream.hip"), "rb").read()
-    traffic = traffic_from_profile(hashlib.sha256(src).hexdigest())
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_stream_mfma (B^T = A^T Q)", "avg_ms": round(kern_ms, 5), "launches": nlaunch,
-                "bytes_per_launch": kern_bytes}
+    breakdown = tte = c2 = None
+    if not a.no_breakdown:
+        breakdown = {
+            "svd_q0": round(timed(torch, lambda: dsketch.sketch_svd(A, k, R, q=0)), 4),
+            "svd_q1": round(timed(torch, lambda: dsketch.sketch_svd(A, k, R, q=1)), 4),
+            "svd_q1_refined": round(timed(torch, lambda: dsketch.sketch_svd(A, k, R, q=1, refine=True)), 4),
+            "id_q0": round(timed(torch, lambda: dsketch.sketch_id(A, k, R, q=0, skeleton_rows=True)), 4),
+            "svd_single_pass": round(timed(torch, lambda: dsketch.sketch_svd_sp(A, k, R)), 4),
+            "step_hbm_frac": round(value / HBM_PEAK_GBS, 4)}
+        log(f"breakdown {breakdown}")
+        A64_dev = torch.from_numpy(A64).to(dev)
+        tail = float(np.sqrt((sig[k:] ** 2).sum()))      # exact: sigma_j of the FP64 construction
+        variants = [("fp32", A64_dev.float()), ("bf16", A), ("fp16", A64_dev.half())]
+        tte = time_to_eps(torch, dsketch, variants, A64_dev, k, R, tail)
+        del variants, A64_dev
+        torch.cuda.empty_cache()
+    if not a.no_c2:
+        c2 = c2_leg(torch, dsketch, synth, a, dev, src_hash)
+        log(f"c2 {c2}")
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -232,31 +269,28 @@ def main():
             blas_name = blas[0].get("internal_api") if blas else "unknown"
         except Exception:
             threads, blas_name = os.cpu_count(), "unknown"
-        Ae = A_np.astype(np.float64)
-        Ro = {"kind": "index", "index": ores.di_index_2d(N, N, f, f)}
-        times = []
-        for _ in range(a.cpu_reps):
-            t = time.perf_counter()
-            osk.tpc_svd(Ae, k, Ro, q=q)
-            orid.tpc_id(Ae, k, Ro, q=0, return_all=True)
-            times.append(time.perf_counter() - t)
-        tc = float(np.median(times))
+        Ae = A.float().cpu().numpy().astype(np.float64)
+        Ro = {"kind": "index", "index": ores.di_index_2d(NY, NX, sy, sx)}
+        t = time.perf_counter()
+        osk.tpc_svd(Ae, k, Ro, q=q)
+        orid.tpc_id(Ae, k, Ro, q=0, return_all=True)
+        tc = time.perf_counter() - t
         cpu = {"value": round(step_bytes / tc / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
-               "sample": f"{a.cpu_reps} full steps of the same workload (median {tc:.2f} s/step), FP64 NumPy, "
+               "sample": f"one full step of the same workload ({tc:.1f} s), FP64 NumPy on the upcast BF16 values, "
                          f"BLAS {blas_name} with {threads} threads, os.cpu_count()={os.cpu_count()}"}
 
     rec = {
         "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"advection-diffusion snapshots {m}x{N}x{N} f32 (sigma_j = j^-0.5, 1e-3 noise), "
-                               f"direct injection {f}x{f} (s={s}), k={k}, l={ell}: sketch SVD q={q} + row ID q=0",
-                   "m": m, "n": n, "s": s, "k": k, "ell": ell, "q": q, "mode": a.mode},
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"heat-mode snapshots {m}x{NY}x{NX} stored bf16 (sigma_j = exp(-0.05 j)), direct "
+                               f"injection ({sy},{sx}) (s={s}), k={k}, l={ell}: sketch SVD q={q} + row ID q=0",
+                   "m": m, "n": n, "s": s, "k": k, "ell": ell, "q": q, "storage": "bf16"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "breakdown_ms": breakdown,
         "time_to_eps": tte,
-        "hybrid_mreo": mreo,
+        "c2": c2,
     }
     print(json.dumps(rec), flush=True)
 

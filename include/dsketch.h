@@ -68,8 +68,9 @@ enum {
   DSK_FLAG_RANK_DEFICIENT = 2,  /* a triangular factor had a negligible pivot */
   DSK_FLAG_NONFINITE = 4,       /* NaN/Inf met in a Gram or residual norm */
   DSK_FLAG_BAD_INDEX = 8,       /* an index of the restriction was outside [0, n); column 0 was used */
-  DSK_FLAG_SYNC_TIMEOUT = 16    /* a workgroup of the persistent pivoted-QR kernel waited past its spin
-                                   limit; the ID outputs of that call are not valid */
+  DSK_FLAG_SYNC_TIMEOUT = 16    /* a workgroup of the one-launch pivoted QR waited past its spin limit (its
+                                   workgroups were not all resident); a one-workgroup kernel then redid the
+                                   factorization, so the ID outputs are valid (but slow to come) */
 };
 
 typedef struct {
@@ -92,10 +93,18 @@ typedef struct {
   int32_t id_projected; /* sketch_id: 0 = ID of W_q = (tau A_c A_c^T)^q A_c (full coarse sketch),
                            1 = ID of the ell-wide block (tau A_c A_c^T)^q A_c S */
   int32_t mode;       /* DSK_MODE_* (F32 input only) */
-  int32_t refine;     /* 1 = one refinement sweep (second orthonormalisation + re-projection) */
-  int32_t id_per_step; /* sketch_id pivoted QR: 0 = one persistent launch when m <= 4 x (compute units)
-                          and the ID matrix is at most 4096 wide (else one launch per pivot step);
-                          1 = always one launch per pivot step.  Both give bitwise the same result. */
+  int32_t refine;     /* sketch_svd with FP32 / 16-bit input: 1 = one FP64 refinement sweep of the
+                         assembled factors: with FP64 Grams U^T U = R_U^T R_U and V^T V = R_V^T R_V,
+                         the k x k matrix R_U diag(S) R_V^T = U_m S' V_m^T is decomposed and
+                         U <- U R_U^-1 U_m, V <- V R_V^-1 V_m, S <- S', so that U S V^T is unchanged
+                         and U, V are orthonormal to the rounding of their storage (requires k <= 100;
+                         ignored for FP64 input) */
+  int32_t id_per_step; /* sketch_id pivoted QR: 0 = all k pivot steps in one launch when the ID matrix's
+                          rows fit the registers of one workgroup per compute unit (m <= 4 or 8 x compute
+                          units, m <= 2048, at most 8192 wide), else one launch per step; 1 = always one
+                          launch per pivot step.  The one launch takes the left-looking form of the pivoted
+                          QR with downdated residual norms, the per-step launches the right-looking form
+                          with recomputed norms: the same pivots wherever they are separated, P to rounding. */
 } dsk_opts;
 
 typedef struct {       /* host struct, filled when passed */
@@ -147,9 +156,13 @@ int dsk_project(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t 
 /*
  * dsk_sketch_svd -- rank-k SVD A ~ U diag(S) V^T by TPC-SVD (Alg. 2) with q
  * steps of the single-pass coarse power iteration C-PWR (Alg. 7):
- *   A_c = A D; Y = A_c S_ell; Q = orth(Y); q times { Z = orth(tau A_c^T Q); Q = orth(A_c Z) };
+ *   A_c = A D; Y = A_c S_ell; Q = orth(Y); q times { Z = orth(tau A_g^T Q); Q = orth(A_g Z) };
  *   B = Q^T A (the one full pass over A); SVD(B) = U_B Sigma V_B^T;
  *   U = Q U_B(:, :k), S = Sigma(:k), V = V_B(:, :k).
+ * A_g = A(:, I) is C-PWR's Gram sub-sample, which Alg. 7 keeps apart from the
+ * sketch D: for DSK_R_INDEX the restriction's own index set (A_g = A_c), for
+ * NN / GLOBAL the direct-injection points of the same grid and factor, for
+ * LEARNED those of its stride-4 output grid (s columns in every case).
  * Each (u_j, v_j) is sign-normalised so the largest-magnitude entry of u_j
  * (lowest index on ties) is positive.
  * Arguments: h=1, A=2, dtype=3, m=4, n=5, lda=6, k=7 (1 <= k <= ell), R=8, q=9 (>= 0),
@@ -197,7 +210,7 @@ int dsk_sketch_svd_sp(dsk_handle *h, const void *A, int32_t dtype, int64_t m, in
  * the positive semidefinite shift M + ||M||_F I (absolute error about
  * 1e-12 c (|tr M| + r ||M||_F)).
  * With rho, the same kept rows also give the estimate of the Gram mismatch
- * rho(tau) = ||A_f A_f^T - tau A_c A_c^T||_2 of the C-PWR analysis (Sec. 3):
+ * rho(tau) = ||A_f A_f^T - tau A_c A_c^T||_2 of the C-PWR analysis (Sec. 5):
  *   rho[i] = c ||B_f B_f^T - taus[i] B_c B_c^T||_2 = c max(lambda_max, -lambda_min),
  * from the same eigenvalues (rho(tau) itself when mc = m).
  * Arguments: h=1, A=2, dtype=3, m=4, n=5, lda=6, R=7, mc=8 (1 <= mc <= m, with
@@ -214,9 +227,14 @@ int dsk_spc_id_err(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64
 /*
  * dsk_sketch_id -- rank-k row interpolative decomposition A ~ P A(I, :) by
  * TPC-ID (Alg. 4): column-pivoted QR of W^T (Sec. 4, row ID) with W = A_c, or
- * W = (tau A_c A_c^T)^q A_c for q >= 1 (C-PWR without re-orthonormalisation),
- * pivots = largest residual norm, recomputed every step (lowest index on
- * exact ties); C = R_1^{-1} R_2; P(I, :) = I_k, P(rest, :) = C^T.
+ * W = (tau A_g A_g^T)^q A_c for q >= 1 (C-PWR without re-orthonormalisation,
+ * A_g the Gram sub-sample described under dsk_sketch_svd), pivots = largest
+ * residual norm, recomputed every step (lowest index on exact ties);
+ * C = R_1^{-1} R_2; P(I, :) = I_k, P(rest, :) = C^T.  When R_1 has negligible
+ * pivots (|r_jj| <= 1e-14 |r_11|, a suffix of its diagonal) the least-squares
+ * problem R_1 C = R_2 has many solutions and the basic one is returned: zero
+ * coefficients for those pivots, the leading triangle solved for the rest;
+ * DSK_FLAG_RANK_DEFICIENT is raised.
  * Arguments: h=1, A=2, dtype=3, m=4, n=5, lda=6, k=7 (1 <= k <= min(m, s) or ell),
  *   R=8, q=9, o=10 (host, may be NULL), skel=11 (k int64, 0-based row indices in pivot order),
  *   P=12 (m x k row-major F64), skel_rows=13 (k x n row-major in A's dtype, or NULL),
@@ -229,7 +247,7 @@ int dsk_sketch_id(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_
 /*
  * dsk_power_iter -- the C-PWR loop alone (Alg. 7):
  *   q times { G = tau A_c^T G; [G = orth(G)]; G = A_c G; [G = orth(G)] }
- * starting from G = Q0.  reorth = 1 orthonormalises after every product
+ * starting from G = Q0, where Ac is the caller's Gram sub-sample A(:, I).  reorth = 1 orthonormalises after every product
  * (result = orthonormal m x ell basis), reorth = 0 returns the raw block.
  * Arguments: h=1, Ac=2 (m x s row-major, ldc), dtype=3 (DSK_F64 or DSK_F32), m=4, s=5,
  *   ldc=6, Q0=7 (m x ell row-major), ell=8, q=9, tau=10, reorth=11, Qout=12 (m x ell).

@@ -310,6 +310,7 @@ int svd_check(const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, i
   if (k < 1 || k > ell) return -7;
   if (q < 0 || q > 64) return -9;
   if (od.mode < 0 || od.mode > DSK_MODE_SPLIT6) return -10;
+  if (od.refine && dtype != DSK_F64 && k > 100) return -10;
   if (!U) return -11;
   if (!S) return -12;
   if (!V) return -13;
@@ -361,6 +362,15 @@ int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, i
     char *Hb = single_pass ? c.take<char>((size_t)n * L * we) : nullptr;
     double *Mr = single_pass ? c.take<double>((size_t)L * L) : nullptr;
     double *GY = single_pass ? c.take<double>((size_t)L * L) : nullptr;
+    // C-PWR's Gram sub-sample A(:, I) (Alg. 7) when the restriction is not an index set
+    const bool own_gram = q > 0 && R->kind != DSK_R_INDEX;
+    char *Ag = own_gram ? c.take<char>((size_t)m * s * we) : nullptr;
+    // refinement sweep (FP32 / 16-bit input): unrefined factors, then FP64 re-orthonormalisation
+    const bool refine = od.refine && !f64;
+    float *U0 = refine ? c.take<float>((size_t)m * k) : nullptr;
+    float *V0 = refine ? c.take<float>((size_t)n * k) : nullptr;
+    double *rws = refine ? c.take<double>(refine_ws_bytes(k) / sizeof(double)) : nullptr;
+    double *ews = f64 ? nullptr : c.take<double>(core_eig_tri_ws_bytes(L) / sizeof(double));
     if (pass == 0) {
       if (need) {
         *need = c.off;
@@ -411,34 +421,38 @@ int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, i
     // intermediate bases of the power iteration only carry a span (one
     // CholeskyQR pass); the block that B is projected on is orthonormalised fully
     DSK_RET(orth(h, Y, f64, m, L, Q, tmp, cws, Rsm, q > 0));
+    const char *Gs = Ac;
+    if (own_gram) {
+      DSK_RET(launch_gram_sample(st, A, dtype, m, n, lda, R, s, f64, Ag, h->dflags));
+      Gs = Ag;
+    }
     for (int it = 0; it < q; ++it) {
-      // Z = A_c^T Q (s x ell), orthonormalised; Q = orth(A_c Z).  tau cancels under re-orthonormalisation.
-      DSK_RET(launch_stream(st, Ac, wdt, m, s, s, Q, f64, L, Z, L, od.mode, sws, h->cu_count));
+      // Z = A_g^T Q (s x ell), orthonormalised; Q = orth(A_g Z), A_g = A(:, I) the Gram
+      // sub-sample of Alg. 7.  tau cancels under re-orthonormalisation.
+      DSK_RET(launch_stream(st, Gs, wdt, m, s, s, Q, f64, L, Z, L, od.mode, sws, h->cu_count));
       DSK_RET(orth(h, Z, f64, s, L, Z, tmp, cws, Rsm, true));
-      DSK_RET(launch_stream_nn(st, Ac, wdt, m, s, s, Z, L, Y, L, od.mode, sws, h->cu_count));
+      DSK_RET(launch_stream_nn(st, Gs, wdt, m, s, s, Z, L, Y, L, od.mode, sws, h->cu_count));
       DSK_RET(orth(h, Y, f64, m, L, Q, tmp, cws, Rsm, it + 1 < q));
     }
     // B^T = A^T Q: the single full pass over A
     hipEvent_t e0, e1;
     timing_slot(h, &e0, &e1);
     DSK_RET(launch_stream(st, A, dtype, m, n, lda, Q, f64, L, Bt, L, od.mode, sws, h->cu_count, e0, e1));
-    if (od.refine && !f64) {
-      // one refinement sweep: re-orthonormalise Q against the projected block and re-project
-      DSK_RET(orth(h, Q, f64, m, L, Y, tmp, cws, Rsm));
-      DSK_RET(launch_convert(st, Y, 0, Q, 0, m * L));
-      DSK_RET(launch_stream(st, A, dtype, m, n, lda, Q, f64, L, Bt, L, od.mode, sws, h->cu_count));
-    }
     if (after_projection) DSK_RET((*after_projection)());
     }
     if (!f64) {
+      void *Ua = refine ? (void *)U0 : U;
+      void *Va = refine ? (void *)V0 : V;
       DSK_RET(launch_gram(st, Bt, 0, n, L, GB, part, nparts));
-      DSK_RET(launch_core_eig(st, GB, L, lam, UB, h->dflags));
-      DSK_RET(launch_tsmm(st, Q, 0, m, L, L, UB, L, k, nullptr, U, k));
-      DSK_RET(launch_sign_fix(st, U, 0, m, k, sign));
+      DSK_RET(launch_core_eig_tri(st, GB, L, lam, UB, ews, h->dflags));
+      DSK_RET(launch_tsmm(st, Q, 0, m, L, L, UB, L, k, nullptr, Ua, k));
+      DSK_RET(launch_sign_fix(st, Ua, 0, m, k, sign));
       hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, st, lam, 1, L, k, sign, 1, S, colscale, dinfo,
                          (const double *)UB, Mv);
       // V = B^T U_B(:, :k) diag(sign / sigma) on the MFMA stream kernel (n rows, K = ell)
-      DSK_RET(launch_stream_nn(st, Bt, DSK_F32, n, L, L, Mv, k, V, k, od.mode, sws, h->cu_count));
+      DSK_RET(launch_stream_nn(st, Bt, DSK_F32, n, L, L, Mv, k, Va, k, od.mode, sws, h->cu_count));
+      if (refine)
+        DSK_RET(launch_refine(st, U0, m, V0, n, k, S, (float *)U, (float *)V, part, nparts, rws, h->dflags));
     } else {
       DSK_RET(launch_convert(st, Bt, 1, tmp, 1, n * L));
       DSK_RET(launch_hhqr(st, tmp, n, L, QB, RB, h->dflags));
@@ -584,6 +598,8 @@ int id_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, in
   for (int pass = 0; pass < 2; ++pass) {
     c.off = 0;
     double *Ac = c.take<double>((size_t)m * s);
+    // C-PWR's Gram sub-sample A(:, I) (Alg. 7) when the restriction is not an index set
+    double *Ag = (q > 0 && R->kind != DSK_R_INDEX) ? c.take<double>((size_t)m * s) : nullptr;
     double *W = c.take<double>((size_t)m * cols);
     double *W2 = c.take<double>((size_t)m * cols);
     double *M = (q > 0 && !od.id_projected) ? c.take<double>((size_t)m * m) : nullptr;
@@ -593,8 +609,13 @@ int id_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, in
     double *nu0 = c.take<double>(m);
     double *nu1 = c.take<double>(m);
     double *Rk = c.take<double>((size_t)k * m);
-    const size_t pwsb = od.id_per_step ? 0 : cpqr_persist_ws_bytes(m, cols, h->cu_count);
-    char *pws = pwsb ? c.take<char>(pwsb) : nullptr;
+    // one launch for all pivot steps when the rows fit the registers of one
+    // workgroup per compute unit; W = A_c held as FP32 where its values are FP32
+    // numbers (an index restriction of FP32 / 16-bit data, no power step)
+    const bool w32 = dtype != DSK_F64 && q == 0 && !od.id_projected && R->kind == DSK_R_INDEX;
+    const size_t rwsb = od.id_per_step ? 0 : rowid_reg_ws_bytes(m, cols, k, w32 ? 0 : 1, h->cu_count);
+    char *rws = rwsb ? c.take<char>(rwsb) : nullptr;
+    float *Ac32 = (rwsb && w32) ? c.take<float>((size_t)m * s) : nullptr;   // (carved in the dry pass too)
     // a given S arrives in the work dtype; the ID works in FP64
     const bool s_conv = od.id_projected && od.S && dtype != DSK_F64;
     double *S64 = s_conv ? c.take<double>((size_t)s * ell) : nullptr;
@@ -610,8 +631,21 @@ int id_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, in
       continue;
     }
     hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, st, h->dflags);
+    if (rwsb && w32) {
+      DSK_RET(launch_restrict(st, A, dtype, m, n, lda, R, s, 0, Ac32, nullptr, h->dflags));
+      DSK_RET(launch_rowid_reg(st, Ac32, 0, m, s, k, nu0, Rk, skel, rws, h->cu_count, h->dflags));
+      DSK_RET(launch_id_solve(st, Rk, skel, nu0, m, k, P, h->dflags));
+      if (skel_rows) DSK_RET(launch_gather_rows(st, A, dtype, m, n, lda, skel, k, skel_rows));
+      DSK_TRY(hipGetLastError());
+      return read_info(h, nullptr, info, 0);
+    }
     // A_c in FP64 (exact for every storage dtype)
     DSK_RET(launch_restrict(st, A, dtype, m, n, lda, R, s, 1, Ac, nullptr, h->dflags));
+    const double *Gs = Ac;
+    if (Ag) {
+      DSK_RET(launch_gram_sample(st, A, dtype, m, n, lda, R, s, 1, Ag, h->dflags));
+      Gs = Ag;
+    }
     double *Wcur = nullptr;
     if (od.id_projected) {
       if (od.S) {
@@ -625,14 +659,14 @@ int id_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, in
         DSK_RET(launch_select_cols(st, Ac, 1, m, s, s, (int)ell, W));
       }
       for (int it = 0; it < q; ++it) {
-        DSK_RET(launch_stream(st, Ac, DSK_F64, m, s, s, W, 1, (int)ell, Zs, ell, 0, sws, h->cu_count));
+        DSK_RET(launch_stream(st, Gs, DSK_F64, m, s, s, W, 1, (int)ell, Zs, ell, 0, sws, h->cu_count));
         launch_scale(st, Zs, 1, s * ell, tau);
-        DSK_RET(launch_stream_nn(st, Ac, DSK_F64, m, s, s, Zs, (int)ell, W, ell, 0, sws, h->cu_count));
+        DSK_RET(launch_stream_nn(st, Gs, DSK_F64, m, s, s, Zs, (int)ell, W, ell, 0, sws, h->cu_count));
       }
       Wcur = W;
     } else if (q > 0) {
-      // (tau A_c A_c^T)^q A_c evaluated as M = tau A_c A_c^T, W <- M W (same product, reassociated)
-      DSK_RET(launch_gemm64(st, 0, 1, m, m, s, tau, Ac, s, Ac, s, M, m));
+      // (tau A_g A_g^T)^q A_c evaluated as M = tau A_g A_g^T, W <- M W (same product, reassociated)
+      DSK_RET(launch_gemm64(st, 0, 1, m, m, s, tau, Gs, s, Gs, s, M, m));
       const double *src = Ac;
       double *bufs[2] = {W, W2};
       for (int it = 0; it < q; ++it) {
@@ -643,8 +677,14 @@ int id_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, in
     } else {
       Wcur = Ac;
     }
-    DSK_RET(launch_cpqr(st, Wcur, m, cols, k, nu0, nu1, Rk, skel, h->dflags, pws, h->cu_count));
-    const double *nu_final = ((k - 1) & 1) ? nu0 : nu1;
+    const double *nu_final;
+    if (rwsb) {
+      DSK_RET(launch_rowid_reg(st, Wcur, 1, m, cols, k, nu0, Rk, skel, rws, h->cu_count, h->dflags));
+      nu_final = nu0;
+    } else {
+      DSK_RET(launch_cpqr(st, Wcur, m, cols, k, nu0, nu1, Rk, skel, h->dflags));
+      nu_final = ((k - 1) & 1) ? nu0 : nu1;
+    }
     DSK_RET(launch_id_solve(st, Rk, skel, nu_final, m, k, P, h->dflags));
     if (skel_rows) DSK_RET(launch_gather_rows(st, A, dtype, m, n, lda, skel, k, skel_rows));
     DSK_TRY(hipGetLastError());

@@ -20,7 +20,6 @@
 // it.  Selected candidates carry nu = -1.
 #include <algorithm>
 
-#include "devsync.h"
 #include "dsk_internal.h"
 
 namespace {
@@ -37,7 +36,7 @@ __device__ __forceinline__ double wsum(double v) {
 // Pivot order of a candidate with residual norm^2 v (larger wins): v truncated
 // to 34 mantissa bits, so candidates closer than 2^-34 relative rank equal and
 // the lower index wins; selected (negative) or NaN candidates rank 0 and never
-// win.  Both the per-step and the persistent factorization use it.
+// win.  The one-launch factorization (rowid_reg.hip) uses the same rule.
 __device__ __forceinline__ unsigned long long nu_rank(double v) {
   const unsigned long long bits = (unsigned long long)__double_as_longlong(v) & 0x7FFFFFFFFFFFFFFFull;
   return (v >= 0.0) ? (bits >> 18) + 1ull : 0ull;
@@ -307,231 +306,6 @@ __global__ void __launch_bounds__(NT) k_cpqr_step_reg(double *__restrict__ W, in
   }
 }
 
-// ---------------------------------------------------------------- persistent variant
-// One launch for all k steps.  Workgroup g owns candidates g*CB .. g*CB+CB-1 and
-// keeps their residual rows in registers for the whole factorization.  After
-// the norms of a step, every workgroup publishes, in the buffers of the step's
-// parity, its best live candidate's residual row with the exact norm^2, then
-// one 64-bit word: pivot rank (46 bits), inverted index (11 bits), step marker
-// (7 bits).  Every workgroup polls all words of the step, takes the same
-// maximum (the pivot p), reads p's row from its owner's buffer and updates its
-// own rows exactly as the per-step kernels do (same reductions and FMA order),
-// so pivots, R and the final norms are bitwise those of the per-step path.
-// Each step has one exchange: the word carries the argmax data, and the pivot
-// row is already published when its word is seen.
-//
-// Ordering without cache maintenance (devsync.h): rows, norms and words are
-// device-coherent relaxed atomic stores and loads; a workgroup's row stores
-// complete (s_waitcnt 0) before its word is stored, and a reader loads a row
-// only after it has seen the word of that step.
-//
-// Every workgroup must be resident at once: the launcher uses at most one
-// workgroup per compute unit.  A workgroup is at most one step ahead of any
-// other, so the two parities never collide (a buffer of parity t & 1 is
-// rewritten at step t + 2 only after every workgroup has published step
-// t + 1, i.e. has finished reading step t).  Each wait is bounded; past the
-// bound the workgroup raises DSK_FLAG_SYNC_TIMEOUT, sets the shared abort word,
-// and every workgroup leaves.
-constexpr long long SPIN_LIMIT = 1LL << 22;
-constexpr int TAGW = 32;              // one word per 256-byte line
-constexpr int RMAX = 256 * 16;        // widest row kept in registers (loads need no bounds branch)
-constexpr int RSTRIDE = RMAX + 32;    // a published row, its exact norm^2 at [RMAX], padding
-
-__device__ __forceinline__ unsigned long long pack_word(unsigned long long rank, long long idx, int marker) {
-  return (rank << 18) | ((unsigned long long)(~idx & 0x7FF) << 7) | (unsigned long long)(marker & 0x7F);
-}
-
-// bounded wait for the word of the current step (marker); 0 on timeout or abort
-__device__ __forceinline__ bool wait_word(const unsigned long long *wp, int marker, int *abort_flag,
-                                          unsigned long long &word) {
-  long long spins = 0;
-  for (;;) {
-    word = (unsigned long long)ds::ld_dev(reinterpret_cast<const long long *>(wp));
-    if ((int)(word & 0x7F) == (marker & 0x7F)) break;
-    if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || ++spins > SPIN_LIMIT) {
-      atomicOr(abort_flag, 1);
-      return false;
-    }
-    __builtin_amdgcn_s_sleep(2);
-  }
-  ds::after_flag();
-  return true;
-}
-
-template <int SPT, int CB>
-__global__ void __launch_bounds__(NT) k_cpqr_persist(const double *__restrict__ W, int64_t m, int64_t s, int k,
-                                                     unsigned long long *words, double *rows, int *abort_flag,
-                                                     double *__restrict__ nu_final, double *__restrict__ Rk,
-                                                     int64_t *__restrict__ piv, int *__restrict__ dflags) {
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int G = gridDim.x, gid = blockIdx.x;
-  __shared__ double redv[NT / 64][CB];
-  __shared__ double coef[CB];
-  __shared__ unsigned long long bk[NT / 64];
-  __shared__ unsigned long long key_sh;
-  __shared__ int stop_sh;
-
-  int64_t cand[CB];
-  bool live[CB];
-  double w[CB][SPT];
-  double nu[CB];
-#pragma unroll
-  for (int c = 0; c < CB; ++c) {
-    cand[c] = (int64_t)gid * CB + c;
-    live[c] = cand[c] < m;
-    nu[c] = -1.0;
-#pragma unroll
-    for (int u = 0; u < SPT; ++u) {
-      const int64_t e = t + (int64_t)NT * u;
-      w[c][u] = (live[c] && e < s) ? W[cand[c] * s + e] : 0.0;
-    }
-  }
-  if (t == 0) stop_sh = 0;
-
-  // residual norms of the live rows (wave sums, then waves in order) -> nu, and
-  // this workgroup's best live candidate in pivot order
-  auto norms = [&](unsigned long long &brank, int &bc) {
-#pragma unroll
-    for (int c = 0; c < CB; ++c) {
-      double a = 0.0;
-#pragma unroll
-      for (int u = 0; u < SPT; ++u) a = fma(w[c][u], w[c][u], a);
-      a = wsum(a);
-      if (lane == 0) redv[wave][c] = a;
-    }
-    __syncthreads();
-    if (t < CB) {
-      double v = 0.0;
-      for (int ww = 0; ww < NT / 64; ++ww) v += redv[ww][t];
-      coef[t] = v;
-      if (live[t] && !isfinite(v)) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_NONFINITE);
-    }
-    __syncthreads();
-    brank = 0;
-    bc = -1;
-#pragma unroll
-    for (int c = 0; c < CB; ++c) {
-      if (!live[c]) continue;
-      nu[c] = coef[c];
-      const unsigned long long r = nu_rank(nu[c]);
-      if (r > brank) { brank = r; bc = c; }   // ascending candidates: ties keep the lower index
-    }
-  };
-
-  unsigned long long myrank;
-  int mybc;
-  norms(myrank, mybc);
-  for (int step = 0; step < k; ++step) {
-    const int par = step & 1;
-    // ---- publish: best row and its exact norm^2, then the word
-    double *mine = rows + ((int64_t)par * G + gid) * RSTRIDE;
-    if (mybc >= 0) {
-#pragma unroll
-      for (int c = 0; c < CB; ++c) {
-        if (c != mybc) continue;
-#pragma unroll
-        for (int u = 0; u < SPT; ++u) ds::st_dev(&mine[t + NT * u], w[c][u]);
-        if (t == 0) ds::st_dev(&mine[RMAX], nu[c]);
-      }
-    }
-    ds::stores_done();
-    __syncthreads();
-    if (t == 0) {
-      const long long myidx = mybc >= 0 ? cand[mybc] : (long long)m;
-      ds::st_dev(reinterpret_cast<long long *>(&words[((int64_t)par * G + gid) * TAGW]),
-                 (long long)pack_word(myrank, myidx, step + 1));
-    }
-    // ---- every word of this step; maximum of (rank, inverted index)
-    unsigned long long best = 0;
-    for (int g = t; g < G; g += NT) {
-      unsigned long long wd;
-      if (!wait_word(&words[((int64_t)par * G + g) * TAGW], step + 1, abort_flag, wd)) {
-        stop_sh = 1;
-        break;
-      }
-      best = max(best, wd >> 7);
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) best = max(best, (unsigned long long)__shfl_xor((long long)best, o, 64));
-    if (lane == 0) bk[wave] = best;
-    __syncthreads();
-    if (t == 0) {
-      unsigned long long b = bk[0];
-      for (int ww = 1; ww < NT / 64; ++ww) b = max(b, bk[ww]);
-      key_sh = b;
-    }
-    __syncthreads();
-    if (stop_sh) break;
-    const unsigned long long key = key_sh;
-    const long long p = (key >> 11) ? (long long)(~key & 0x7FF) : (long long)m;
-    const int owner = (p < m) ? (int)(p / CB) : -1;
-    // ---- the pivot's residual row and exact norm^2 from its owner's buffer
-    double qv[SPT];
-    double nup = 0.0;
-    if (owner >= 0) {
-      const double *src = rows + ((int64_t)par * G + owner) * RSTRIDE;
-#pragma unroll
-      for (int u = 0; u < SPT; ++u) qv[u] = ds::ld_dev(&src[t + NT * u]);
-      nup = ds::ld_dev(&src[RMAX]);
-    } else {
-#pragma unroll
-      for (int u = 0; u < SPT; ++u) qv[u] = 0.0;
-    }
-    const double rpp = nup > 0.0 ? sqrt(nup) : 0.0;
-    const double qscale = rpp > 0.0 ? 1.0 / rpp : 0.0;
-#pragma unroll
-    for (int u = 0; u < SPT; ++u) {
-      const int64_t e = t + (int64_t)NT * u;
-      qv[u] = (e < s) ? qv[u] * qscale : 0.0;
-    }
-    if (gid == 0 && t == 0) {
-      piv[step] = p;
-      if (p < m) Rk[(int64_t)step * m + p] = rpp;
-      if (!(rpp > 0.0)) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_RANK_DEFICIENT);
-    }
-#pragma unroll
-    for (int c = 0; c < CB; ++c)
-      if (cand[c] == p) live[c] = false;
-    // ---- R(step, i) = q . residual_i, residual_i -= R(step, i) q, new norms
-#pragma unroll
-    for (int c = 0; c < CB; ++c) {
-      double a = 0.0;
-#pragma unroll
-      for (int u = 0; u < SPT; ++u) a = fma(qv[u], w[c][u], a);
-      a = wsum(a);
-      if (lane == 0) redv[wave][c] = a;
-    }
-    __syncthreads();
-    if (t < CB) {
-      double v = 0.0;
-      for (int ww = 0; ww < NT / 64; ++ww) v += redv[ww][t];
-      coef[t] = v;
-      if (live[t]) Rk[(int64_t)step * m + cand[t]] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < CB; ++c) {
-      const double r = coef[c];
-#pragma unroll
-      for (int u = 0; u < SPT; ++u) w[c][u] = fma(-r, qv[u], w[c][u]);
-    }
-    norms(myrank, mybc);
-  }
-  if (stop_sh) {
-    if (t == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_SYNC_TIMEOUT);
-    return;
-  }
-  // final residual norms of unselected candidates (selected: -1), as the per-step path writes
-#pragma unroll
-  for (int c = 0; c < CB; ++c)
-    if (t == c && cand[c] < m) nu_final[cand[c]] = live[c] ? nu[c] : -1.0;
-}
-
-__global__ void k_words_reset(unsigned long long *words, int n, int *abort_flag) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) words[i] = 0;
-  if (threadIdx.x == 0) *abort_flag = 0;
-}
-
 // C = R_1^{-1} R_2 by back substitution; P(piv[b], :) = e_b, P(i, :) = C(:, i)^T.
 // One wave per candidate: lane l holds entries a = l and a = l + 64 of the
 // right-hand side; the k substitution steps broadcast x_b by a lane shuffle and
@@ -583,40 +357,11 @@ __global__ void __launch_bounds__(64 * SOLVE_WAVES) k_id_solve(const double *__r
 
 }  // namespace
 
-// Workspace of the persistent variant: 2 G words of one 256-byte line each,
-// 2 G published rows (RSTRIDE doubles each), the abort word.
-size_t cpqr_persist_ws_bytes(int64_t m, int64_t s, int cu_count) {
-  const int64_t G = (m + 3) / 4;
-  if (s > RMAX || G > cu_count || m > 2048) return 0;
-  return (size_t)2 * G * TAGW * 8 + (size_t)2 * G * RSTRIDE * 8 + 256;
-}
-
 int launch_cpqr(hipStream_t st, double *W, int64_t m, int64_t s, int k, double *nu0, double *nu1, double *Rk,
-                int64_t *piv, int *dflags, void *pws, int cu_count) {
+                int64_t *piv, int *dflags) {
   hipLaunchKernelGGL(k_fill0, dim3((unsigned)std::min<int64_t>(((int64_t)k * m + 255) / 256, 4096)), dim3(256), 0, st,
                      Rk, (int64_t)k * m);
   DSK_TRY(hipGetLastError());
-  if (pws && cpqr_persist_ws_bytes(m, s, cu_count) > 0) {
-    // one launch, at most one workgroup per compute unit; the final norms go
-    // where the per-step path leaves them
-    const int G = (int)((m + 3) / 4);
-    char *w = reinterpret_cast<char *>(pws);
-    unsigned long long *words = reinterpret_cast<unsigned long long *>(w);
-    double *rows = reinterpret_cast<double *>(w + (size_t)2 * G * TAGW * 8);
-    int *abort_flag = reinterpret_cast<int *>(rows + (size_t)2 * G * RSTRIDE);
-    double *nu_final = ((k - 1) & 1) ? nu0 : nu1;
-    hipLaunchKernelGGL(k_words_reset, dim3(1), dim3(256), 0, st, words, 2 * G * TAGW, abort_flag);
-    DSK_TRY(hipGetLastError());
-#define DSK_PERSIST(SPT_)                                                                                      \
-  hipLaunchKernelGGL((k_cpqr_persist<SPT_, 4>), dim3(G), dim3(NT), 0, st, (const double *)W, m, s, k, words, rows, \
-                     abort_flag, nu_final, Rk, piv, dflags)
-    if (s <= 256 * 4) DSK_PERSIST(4);
-    else if (s <= 256 * 8) DSK_PERSIST(8);
-    else DSK_PERSIST(16);
-#undef DSK_PERSIST
-    DSK_TRY(hipGetLastError());
-    return 0;
-  }
   hipLaunchKernelGGL(k_cpqr_norms, dim3((unsigned)m), dim3(NT), 0, st, (const double *)W, m, s, nu0);
   DSK_TRY(hipGetLastError());
   const unsigned blocks = (unsigned)((m + CPB - 1) / CPB);

@@ -114,6 +114,11 @@ int read_info_words(dsk_handle *h, dsk_info *info, int ell);
 // restrict.hip
 int launch_restrict(hipStream_t st, const void *A, int dtype, int64_t m, int64_t n, int64_t lda,
                     const dsk_restriction *R, int64_t s, int work_f64, void *Ac, void *AcT, int *dflags);
+// A_g = A(:, I), C-PWR's Gram sub-sample (Alg. 7): the index set of an index
+// restriction, else the direct-injection points of the restriction's grid
+// (factor 4 x 4 for the learned conv); m x s compact in the work dtype.
+int launch_gram_sample(hipStream_t st, const void *A, int dtype, int64_t m, int64_t n, int64_t lda,
+                       const dsk_restriction *R, int64_t s, int work_f64, void *Ag, int *dflags);
 int launch_select_cols(hipStream_t st, const void *Ac, int work_f64, int64_t m, int64_t s,
                        int64_t ldc, int ell, void *Y);
 int launch_gather_rows(hipStream_t st, const void *A, int dtype, int64_t m, int64_t n, int64_t lda,
@@ -155,8 +160,21 @@ int launch_cholqr2(hipStream_t st, const void *Y, int f64, int64_t rows, int ell
 int launch_hhqr(hipStream_t st, double *X, int64_t rows, int ell, double *Q, double *R, int *dflags);
 int launch_gram(hipStream_t st, const void *X, int f64, int64_t rows, int ell, double *G,
                 double *part, int nparts);
+// refine.hip: FP64 re-orthonormalisation of the assembled FP32 factors (U0 m x k,
+// V0 n x k, S k) into U, V, S with U S V^T unchanged (k <= 100); ws: refine_ws_bytes(k)
+size_t refine_ws_bytes(int k);
+int launch_refine(hipStream_t st, const float *U0, int64_t m, const float *V0, int64_t n, int k, double *S,
+                  float *U, float *V, double *part, int nparts, double *ws, int *dflags);
 // jacobi.hip
 int launch_core_eig(hipStream_t st, const double *G, int ell, double *lam, double *U, int *dflags);
+// the same, run only where *gate != 0 (gate may be null: always); count matrices, one workgroup each
+int launch_core_eig_gated(hipStream_t st, const double *G, int ell, double *lam, double *U, int *dflags,
+                          const int *gate, int count);
+// eigtri.hip: the same eigenpairs by Householder tridiagonalisation, multisection and
+// twisted-factorisation eigenvectors (3 <= ell <= 112), with the Jacobi core as a gated
+// fallback; ws: core_eig_tri_ws_bytes(ell)
+size_t core_eig_tri_ws_bytes(int ell);
+int launch_core_eig_tri(hipStream_t st, const double *G, int ell, double *lam, double *U, double *ws, int *dflags);
 // count independent ell x ell matrices (consecutive), one workgroup each
 int launch_core_eig_batched(hipStream_t st, const double *G, int ell, double *lam, double *U, int *dflags,
                             int count);
@@ -191,11 +209,15 @@ int stream_autotune(hipStream_t st, const void *X, int dtype, int64_t K, int64_t
                     void *ws, void *Y, void *out, int cu_count, int *best_ns, float *best_ms);
 
 // cpqr.hip (row ID)
-// pws: workspace of the persistent one-launch variant (cpqr_persist_ws_bytes;
-// 0 bytes = not applicable for this shape), or nullptr for one launch per step.
-size_t cpqr_persist_ws_bytes(int64_t m, int64_t s, int cu_count);
 int launch_cpqr(hipStream_t st, double *W, int64_t m, int64_t s, int k, double *nu0, double *nu1,
-                double *Rk, int64_t *piv, int *dflags, void *pws = nullptr, int cu_count = 0);
+                double *Rk, int64_t *piv, int *dflags);
+// rowid_reg.hip: all k pivot steps in one launch with W's rows in registers
+// (left-looking form, downdated norms); 0 bytes = shape not supported.  W is
+// FP64 (w_f64) or FP32 holding exact FP32 values.  Outputs as launch_cpqr's,
+// final norms in nu_final.
+size_t rowid_reg_ws_bytes(int64_t m, int64_t s, int k, int w_f64, int cu_count);
+int launch_rowid_reg(hipStream_t st, const void *W, int w_f64, int64_t m, int64_t s, int k, double *nu_final,
+                     double *Rk, int64_t *piv, void *ws, int cu_count, int *dflags);
 int launch_id_solve(hipStream_t st, const double *Rk, const int64_t *piv, const double *nu_final,
                     int64_t m, int k, double *P, int *dflags);
 

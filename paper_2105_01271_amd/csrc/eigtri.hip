@@ -1,0 +1,403 @@
+// Symmetric eigensolver of the core SVD (Alg. 2, "SVD(B)" step) for the
+// FP32 / 16-bit paths: all eigenpairs of the ell x ell FP64 Gram G_B = B B^T
+// (ell <= 112), whose eigenvalues are sigma_j^2 and whose eigenvectors are the
+// left singular vectors U_B of B.
+//
+//   1. Householder tridiagonalisation Q^T G Q = T (G in LDS, one workgroup):
+//      step j reflects column j below the diagonal, p = tau A v (symmetric
+//      product), w = p - (tau/2)(p.v) v, A -= v w^T + w v^T.
+//   2. Eigenvalues of T by multisection: every eigenvalue index owns a group
+//      of threads, each round evaluates Sturm counts (the signs of the LDL^T
+//      pivots of T - x I) at the group's interior points and keeps the
+//      sub-interval that holds the index.
+//   3. Eigenvectors of T by the twisted factorisation at each eigenvalue:
+//      T - lambda I = N_r Delta_r N_r^T with the twist index r where |gamma_r|
+//      is smallest; z_r = 1 and the two bidiagonal solves give z.  Vectors of
+//      eigenvalues closer than 1e-9 ||T|| are re-orthogonalised in order.
+//      Every vector's residual ||T z - lambda z|| is checked against 2e-9 ||T||;
+//      a failure (or a non-finite value) sets the workspace's fail word, the
+//      back-transformation then writes nothing and the Jacobi core eigensolver,
+//      launched after it and gated on that word, computes the result instead.
+//   4. Back-transformation U = Q Z (second kernel): four threads per
+//      eigenvector, the reflectors applied from the last to the first.
+//
+// Absolute accuracy: eigenvalues within a few u ||G||, eigenvectors within
+// about u ||G|| / gap (backward stable reduction, bisection to the rounding
+// level), far inside the FP32 parity tolerances of the paths that use it.
+// Output as the Jacobi core: lam descending, U row-major with column j the
+// eigenvector of lam[j].
+#include <algorithm>
+
+#include "dsk_internal.h"
+#include "wavechol.h"
+
+namespace {
+
+constexpr int TNT = 1024;          // threads of the reduction / eigenvalue kernel
+constexpr int TMAX = 112;          // largest ell
+constexpr double TU = 1.1102230246251565e-16;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Number of eigenvalues of T (diagonal d, squared off-diagonal e2) below x:
+// the negative pivots of the LDL^T factorisation of T - x I, a pivot of
+// magnitude below pivmin replaced by -pivmin.
+__device__ __forceinline__ int sturm_count(const double *d, const double *e2, int n, double x, double pivmin) {
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int c = q < 0.0 ? 1 : 0;
+  for (int i = 1; i < n; ++i) {
+    q = (d[i] - x) - e2[i - 1] * wc::rcp_nr(q);
+    if (fabs(q) < pivmin) q = -pivmin;
+    c += q < 0.0 ? 1 : 0;
+  }
+  return c;
+}
+
+// LDS (dynamic): A [ell][ell + 1] (the matrix, later Z), then small arrays.
+__global__ void __launch_bounds__(TNT) k_tri_eig(const double *__restrict__ G, int ell, double *__restrict__ lam,
+                                                 double *__restrict__ Vt, double *__restrict__ taus,
+                                                 double *__restrict__ Zg, int *__restrict__ fail,
+                                                 int *__restrict__ dflags) {
+  extern __shared__ double dyn[];
+  const int n = ell, ld = ell + 1;
+  double *A = dyn;                          // n x ld
+  __shared__ double d[TMAX], e[TMAX], e2[TMAX], tau[TMAX], pv[TMAX], lo_sh[TMAX], hi_sh[TMAX], lamu[TMAX];
+  __shared__ int cnt_sh[TNT];
+  __shared__ double red[TNT / 64];
+  __shared__ double bcast[4];
+  __shared__ int clus_sh;
+  __shared__ int bad_sh;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+
+  for (int x = t; x < n * n; x += TNT) {
+    const int r = x / n, c = x - (x / n) * n;
+    A[r * ld + c] = G[x];
+  }
+  if (t < TMAX) tau[t] = 0.0;
+  if (t == 0) bad_sh = 0;
+  __syncthreads();
+
+  // ---- 1. tridiagonalisation
+  for (int j = 0; j + 2 < n; ++j) {
+    const int L = n - j - 1;                       // length of x = A[j+1:, j]
+    if (wave == 0) {
+      double s2 = 0.0;
+      for (int i = 1 + lane; i < L; i += 64) {
+        const double v = A[(j + 1 + i) * ld + j];
+        s2 = fma(v, v, s2);
+      }
+      s2 = wave_sum(s2);
+      if (lane == 0) {
+        const double alpha = A[(j + 1) * ld + j];
+        double beta, tj, scale;
+        if (s2 == 0.0) {
+          beta = alpha;
+          tj = 0.0;
+          scale = 0.0;
+        } else {
+          beta = -copysign(sqrt(fma(alpha, alpha, s2)), alpha);
+          tj = (beta - alpha) / beta;
+          scale = 1.0 / (alpha - beta);
+        }
+        tau[j] = tj;
+        e[j] = beta;
+        bcast[0] = scale;
+      }
+    }
+    __syncthreads();
+    {
+      const double scale = bcast[0];
+      for (int i = 1 + t; i < L; i += TNT) A[(j + 1 + i) * ld + j] *= scale;
+      if (t == 0) A[(j + 1) * ld + j] = 1.0;       // v_0 (e[j] keeps the subdiagonal)
+    }
+    __syncthreads();
+    const double tj = tau[j];
+    // p = tau A' v, A' = A[j+1:, j+1:]: 8 threads per row
+    {
+      const int r = t >> 3, g = t & 7;
+      double a = 0.0;
+      if (r < L) {
+        const double *row = &A[(j + 1 + r) * ld + j + 1];
+        for (int c = g; c < L; c += 8) a = fma(row[c], A[(j + 1 + c) * ld + j], a);
+      }
+      a += wc::dpp_f64<0xB1>(a);
+      a += wc::dpp_f64<0x4E>(a);
+      a += wc::dpp_f64<0x141>(a);
+      if (r < L && g == 0) pv[r] = tj * a;
+    }
+    __syncthreads();
+    // K = (tau / 2) (p . v)
+    if (wave == 0) {
+      double s = 0.0;
+      for (int i = lane; i < L; i += 64) s = fma(pv[i], A[(j + 1 + i) * ld + j], s);
+      s = wave_sum(s);
+      if (lane == 0) bcast[1] = 0.5 * tj * s;
+    }
+    __syncthreads();
+    // A' -= v w^T + w v^T, w = p - K v
+    {
+      const double K = bcast[1];
+      for (int x = t; x < L * L; x += TNT) {
+        const int r = x / L, c = x - (x / L) * L;
+        const double vr = A[(j + 1 + r) * ld + j], vc = A[(j + 1 + c) * ld + j];
+        const double wr = fma(-K, vr, pv[r]), wc2 = fma(-K, vc, pv[c]);
+        A[(j + 1 + r) * ld + j + 1 + c] -= fma(vr, wc2, wr * vc);
+      }
+    }
+    __syncthreads();
+  }
+  // diagonal, last subdiagonal; reflectors (row j of Vt: v_j at columns j+1 .. n-1)
+  if (t < n) d[t] = A[t * ld + t];
+  if (t == 0 && n >= 2) {
+    e[n - 2] = A[(n - 1) * ld + n - 2];
+    tau[n - 2] = 0.0;
+  }
+  for (int x = t; x < n * n; x += TNT) {
+    const int j = x / n, c = x - (x / n) * n;
+    Vt[x] = (j + 2 < n && c > j) ? A[c * ld + j] : 0.0;
+  }
+  if (t < n) taus[t] = (t + 2 < n) ? tau[t] : 0.0;
+  __syncthreads();
+
+  // ---- 2. eigenvalues: multisection on Sturm counts
+  if (t < n) e2[t] = (t + 1 < n) ? e[t] * e[t] : 0.0;
+  if (t == 0) {
+    double lo = d[0], hi = d[0], tmax = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
+      lo = fmin(lo, d[i] - r);
+      hi = fmax(hi, d[i] + r);
+      tmax = fmax(tmax, fabs(d[i]) + r);
+    }
+    double emax = 0.0;
+    for (int i = 0; i + 1 < n; ++i) emax = fmax(emax, e[i] * e[i]);
+    const double pad = 2.0 * TU * tmax * n + 1e-300;
+    bcast[0] = lo - pad;
+    bcast[1] = hi + pad;
+    bcast[2] = 1e-290 * fmax(1.0, emax);          // pivmin
+    bcast[3] = tmax;
+    if (!isfinite(tmax)) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_NONFINITE);
+  }
+  __syncthreads();
+  const double pivmin = bcast[2], tnorm = bcast[3];
+  if (t < n) {
+    lo_sh[t] = bcast[0];
+    hi_sh[t] = bcast[1];
+  }
+  const int ns = TNT / n;                         // threads per eigenvalue (>= 9)
+  const int ei = t / ns, si = t - (t / ns) * ns;
+  int rounds = 0;
+  for (; rounds < 64; ++rounds) {
+    __syncthreads();
+    if (t == 0) clus_sh = 0;
+    __syncthreads();
+    double a = 0.0, b = 0.0;
+    if (ei < n) {
+      a = lo_sh[ei];
+      b = hi_sh[ei];
+      if (b - a > 4.0 * TU * fmax(fabs(a), fabs(b)) + 1e-300 && b - a > 2.0 * TU * tnorm) clus_sh = 1;
+    }
+    __syncthreads();
+    if (!clus_sh) break;
+    if (ei < n) {
+      const double x = a + (b - a) * (double)(si + 1) / (double)(ns + 1);
+      cnt_sh[t] = sturm_count(d, e2, n, x, pivmin);
+    }
+    __syncthreads();
+    if (ei < n && si == 0) {
+      // points x_s increase with s; keep [last x with count <= ei, first x with count > ei]
+      double na = a, nb = b;
+      for (int s = 0; s < ns; ++s) {
+        const double x = a + (b - a) * (double)(s + 1) / (double)(ns + 1);
+        if (cnt_sh[ei * ns + s] <= ei) na = x;
+        else { nb = x; break; }
+      }
+      lo_sh[ei] = na;
+      hi_sh[ei] = nb;
+    }
+  }
+  __syncthreads();
+  if (t < n) lamu[t] = 0.5 * (lo_sh[t] + hi_sh[t]);   // ascending
+  if (t == 0) dflags[FLAGW_SWEEPS] = rounds;
+  __syncthreads();
+
+  // ---- 3. eigenvectors of T: twisted factorisation, column t of Z (A reused, ld)
+  double *Z = A;
+  if (t < n) {
+    const double lm = lamu[t];
+    // top-down: D+_i into Z[i][t]
+    double dp = d[0] - lm;
+    if (fabs(dp) < pivmin) dp = -pivmin;
+    Z[t] = dp;
+    for (int i = 0; i + 1 < n; ++i) {
+      dp = (d[i + 1] - lm) - e2[i] * wc::rcp_nr(dp);
+      if (fabs(dp) < pivmin) dp = -pivmin;
+      Z[(i + 1) * ld + t] = dp;
+    }
+    // bottom-up: D-_i and gamma_i = D+_i + D-_i - (d_i - lambda); r = argmin |gamma|
+    double dm = d[n - 1] - lm;
+    if (fabs(dm) < pivmin) dm = -pivmin;
+    int r = n - 1;
+    double gbest = fabs(Z[(n - 1) * ld + t]);          // gamma_{n-1} = D+_{n-1}
+    for (int i = n - 2; i >= 0; --i) {
+      dm = (d[i] - lm) - e2[i] * wc::rcp_nr(dm);
+      if (fabs(dm) < pivmin) dm = -pivmin;
+      const double g = fabs(Z[i * ld + t] + dm - (d[i] - lm));
+      if (g < gbest) { gbest = g; r = i; }
+    }
+    // D-_i for i > r into Z[i][t]
+    dm = d[n - 1] - lm;
+    if (fabs(dm) < pivmin) dm = -pivmin;
+    for (int i = n - 1; i > r; --i) {
+      Z[i * ld + t] = dm;
+      if (i - 1 > r) {
+        dm = (d[i - 1] - lm) - e2[i - 1] * wc::rcp_nr(dm);
+        if (fabs(dm) < pivmin) dm = -pivmin;
+      }
+    }
+    // z_r = 1; up: z_i = -(e_i / D+_i) z_{i+1}; down: z_{i+1} = -(e_i / D-_{i+1}) z_i
+    double zr = 1.0, nrm = 1.0;
+    double z = zr;
+    for (int i = r - 1; i >= 0; --i) {
+      z = -(e[i] * wc::rcp_nr(Z[i * ld + t])) * z;
+      Z[i * ld + t] = z;
+      nrm = fma(z, z, nrm);
+    }
+    Z[r * ld + t] = zr;
+    z = zr;
+    for (int i = r; i + 1 < n; ++i) {
+      z = -(e[i] * wc::rcp_nr(Z[(i + 1) * ld + t])) * z;
+      Z[(i + 1) * ld + t] = z;
+      nrm = fma(z, z, nrm);
+    }
+    const double sc = wc::rsq_nr(nrm);
+    for (int i = 0; i < n; ++i) Z[i * ld + t] *= sc;
+  }
+  __syncthreads();
+  // re-orthogonalise vectors of close eigenvalues (one wave, in ascending order)
+  if (wave == 0) {
+    const double gtol = 1e-9 * fmax(tnorm, 1e-300);
+    for (int c = 1; c < n; ++c) {
+      if (lamu[c] - lamu[c - 1] > gtol) continue;
+      int s0 = c - 1;
+      while (s0 > 0 && lamu[s0] - lamu[s0 - 1] <= gtol) --s0;
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int sv = s0; sv < c; ++sv) {
+          double dot = 0.0;
+          for (int i = lane; i < n; i += 64) dot = fma(Z[i * ld + sv], Z[i * ld + c], dot);
+          dot = wave_sum(dot);
+          for (int i = lane; i < n; i += 64) Z[i * ld + c] = fma(-dot, Z[i * ld + sv], Z[i * ld + c]);
+          wc::wave_lds_sync();
+        }
+      }
+      double nn = 0.0;
+      for (int i = lane; i < n; i += 64) nn = fma(Z[i * ld + c], Z[i * ld + c], nn);
+      nn = wave_sum(nn);
+      const double sc = nn > 0.0 ? wc::rsq_nr(nn) : 0.0;
+      for (int i = lane; i < n; i += 64) Z[i * ld + c] *= sc;
+      wc::wave_lds_sync();
+    }
+  }
+  __syncthreads();
+  // residual check of every vector
+  if (t < n) {
+    const double lm = lamu[t];
+    double rmax = 0.0;
+    bool fin = isfinite(lm);
+    for (int i = 0; i < n; ++i) {
+      const double zi = Z[i * ld + t];
+      double r = (d[i] - lm) * zi;
+      if (i > 0) r = fma(e[i - 1], Z[(i - 1) * ld + t], r);
+      if (i + 1 < n) r = fma(e[i], Z[(i + 1) * ld + t], r);
+      rmax = fmax(rmax, fabs(r));
+      fin = fin && isfinite(zi);
+    }
+    if (!fin || !(rmax <= 2e-9 * tnorm)) bad_sh = 1;
+  }
+  __syncthreads();
+  if (t == 0) *fail = bad_sh;
+  // descending order out: column j of Zg = eigenvector of lamu[n - 1 - j]
+  for (int x = t; x < n * n; x += TNT) {
+    const int i = x / n, j = x - (x / n) * n;
+    Zg[x] = Z[i * ld + (n - 1 - j)];
+  }
+  if (t < n) lam[t] = lamu[n - 1 - t];
+}
+
+// U = Q Z: Q = H_0 H_1 ... H_{n-3}, H_j = I - tau_j v_j v_j^T (v_j in row j of Vt,
+// columns j+1 ..).  Four threads per column, rows interleaved by 4; the
+// reflectors go from the last to the first.  RPT = rows per thread.
+template <int RPT>
+__global__ void __launch_bounds__(512) k_tri_back(const double *__restrict__ Vt, const double *__restrict__ taus,
+                                                  const double *__restrict__ Zg, int ell, const int *__restrict__ fail,
+                                                  double *__restrict__ U) {
+  extern __shared__ double vlds[];         // Vt, ell x ell
+  if (*fail) return;                       // the gated Jacobi core writes U
+  const int n = ell, t = threadIdx.x;
+  for (int x = t; x < n * n; x += 512) vlds[x] = Vt[x];
+  __syncthreads();
+  const int c = t >> 2, g = t & 3;
+  const bool act = c < n;
+  double z[RPT];
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int r = g + 4 * u;
+    z[u] = (act && r < n) ? Zg[r * n + c] : 0.0;
+  }
+  for (int j = n - 3; j >= 0; --j) {
+    const double tj = taus[j];
+    const double *v = &vlds[j * n];
+    double w = 0.0;
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int r = g + 4 * u;
+      if (r > j && r < n) w = fma(v[r], z[u], w);
+    }
+    w += wc::dpp_f64<0xB1>(w);
+    w += wc::dpp_f64<0x4E>(w);
+    const double tw = tj * w;
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int r = g + 4 * u;
+      if (r > j && r < n) z[u] = fma(-tw, v[r], z[u]);
+    }
+  }
+  if (act)
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int r = g + 4 * u;
+      if (r < n) U[r * n + c] = z[u];
+    }
+}
+
+}  // namespace
+
+size_t core_eig_tri_ws_bytes(int ell) { return ((size_t)2 * ell * ell + ell + 64) * sizeof(double); }
+
+int launch_core_eig_tri(hipStream_t st, const double *G, int ell, double *lam, double *U, double *ws, int *dflags) {
+  if (ell < 3 || ell > TMAX) return launch_core_eig(st, G, ell, lam, U, dflags);
+  double *Vt = ws;
+  double *Zg = ws + (size_t)ell * ell;
+  double *taus = Zg + (size_t)ell * ell;
+  int *fail = reinterpret_cast<int *>(taus + ell);
+  const size_t lds1 = (size_t)ell * (ell + 1) * sizeof(double);
+  allow_lds(k_tri_eig, lds1);
+  hipLaunchKernelGGL(k_tri_eig, dim3(1), dim3(TNT), lds1, st, G, ell, lam, Vt, taus, Zg, fail, dflags);
+  DSK_TRY(hipGetLastError());
+  const size_t lds2 = (size_t)ell * ell * sizeof(double);
+  if (ell <= 64) {
+    allow_lds(k_tri_back<16>, lds2);
+    hipLaunchKernelGGL(k_tri_back<16>, dim3(1), dim3(512), lds2, st, Vt, taus, Zg, ell, fail, U);
+  } else {
+    allow_lds(k_tri_back<28>, lds2);
+    hipLaunchKernelGGL(k_tri_back<28>, dim3(1), dim3(512), lds2, st, Vt, taus, Zg, ell, fail, U);
+  }
+  DSK_TRY(hipGetLastError());
+  // fallback: the Jacobi core, which leaves at once unless the fail word is set
+  return launch_core_eig_gated(st, G, ell, lam, U, dflags, fail, 1);
+}

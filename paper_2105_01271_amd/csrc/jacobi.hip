@@ -165,7 +165,8 @@ constexpr int eig_ldg() { return NT == 256 ? 65 : 113; }   // LDS column stride 
 template <int NT>
 __global__ void __launch_bounds__(NT) k_core_eig(const double *__restrict__ G_in, int ell,
                                                   double *__restrict__ lam, double *__restrict__ Uout,
-                                                  int *__restrict__ dflags) {
+                                                  int *__restrict__ dflags, const int *__restrict__ gate) {
+  if (gate && *gate == 0) return;   // gated: runs only where the tridiagonal eigensolver failed
   // a batch: workgroup b factors matrix b (G_in, lam, Uout advance by ell^2, ell, ell^2)
   G_in += (size_t)blockIdx.x * ell * ell;
   lam += (size_t)blockIdx.x * ell;
@@ -456,25 +457,30 @@ __global__ void __launch_bounds__(1024) k_jacobi_svd(const double *__restrict__ 
 
 }  // namespace
 
-int launch_core_eig_batched(hipStream_t st, const double *G, int ell, double *lam, double *U, int *dflags,
-                            int count) {
+int launch_core_eig_gated(hipStream_t st, const double *G, int ell, double *lam, double *U, int *dflags,
+                          const int *gate, int count) {
   if (ell < 1 || ell > JELL_MAX || count < 1) return -1;
   const int n = (ell + 1) & ~1;
   if (ell <= 64) {
     const size_t lds = ((size_t)64 * eig_ldg<256>() + 64 * wc::LDL + 128) * sizeof(double);
     allow_lds(k_core_eig<256>, lds);
-    hipLaunchKernelGGL(k_core_eig<256>, dim3(count), dim3(256), lds, st, G, ell, lam, U, dflags);
+    hipLaunchKernelGGL(k_core_eig<256>, dim3(count), dim3(256), lds, st, G, ell, lam, U, dflags, gate);
   } else {
     const size_t lds = (size_t)std::max(n, ell) * eig_ldg<JNT>() * sizeof(double);
     allow_lds(k_core_eig<JNT>, lds);
-    hipLaunchKernelGGL(k_core_eig<JNT>, dim3(count), dim3(JNT), lds, st, G, ell, lam, U, dflags);
+    hipLaunchKernelGGL(k_core_eig<JNT>, dim3(count), dim3(JNT), lds, st, G, ell, lam, U, dflags, gate);
   }
   DSK_TRY(hipGetLastError());
   return 0;
 }
 
+int launch_core_eig_batched(hipStream_t st, const double *G, int ell, double *lam, double *U, int *dflags,
+                            int count) {
+  return launch_core_eig_gated(st, G, ell, lam, U, dflags, nullptr, count);
+}
+
 int launch_core_eig(hipStream_t st, const double *G, int ell, double *lam, double *U, int *dflags) {
-  return launch_core_eig_batched(st, G, ell, lam, U, dflags, 1);
+  return launch_core_eig_gated(st, G, ell, lam, U, dflags, nullptr, 1);
 }
 
 int launch_jacobi_svd(hipStream_t st, const double *Rm, int ell, double *sig, double *Vr, double *Ur, int *dflags) {

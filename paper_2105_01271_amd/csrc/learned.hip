@@ -6,11 +6,13 @@
 //
 // with Q the ell-wide orthonormal block of the SVD path built from A_c = A D
 // (start block by nested direct injection, q coarse power steps with
-// re-orthonormalisation, Alg. 7).  L depends on Q only through span(Q), so
-// every QR step X = Q R is differentiated with R held constant (dX = dQ R^{-T});
-// at the output dL/dQ = -(2 / ||A||^2) (A B^T - Q B B^T) with B = Q^T A.  The
-// chain runs backwards through the power steps to dL/dA_c, and the conv
-// backward turns it into weight gradients.  All coarse-sketch algebra is FP64
+// re-orthonormalisation on the Gram sub-sample A_g = A(:, I) of Alg. 7, the
+// direct-injection points of the conv's output grid).  L depends on Q only
+// through span(Q), so every QR step X = Q R is differentiated with R held
+// constant (dX = dQ R^{-T}); at the output dL/dQ = -(2 / ||A||^2) (A B^T - Q B B^T)
+// with B = Q^T A.  The chain runs backwards through the power steps (A_g is
+// fixed) to the start block, i.e. to dL/dA_c, and the conv backward turns it
+// into weight gradients.  All coarse-sketch algebra is FP64
 // (Householder QR, FP64 GEMM); the two passes over A use the projection
 // kernels.  A plain Adam step updates the weights on the device.
 #include <algorithm>
@@ -148,6 +150,7 @@ int dsk_learned_loss_grad(dsk_handle *h, const void *A, int32_t dtype, int64_t m
   for (int pass = 0; pass < 2; ++pass) {
     c.off = 0;
     double *Ac = c.take<double>((size_t)m * s);
+    double *Ag = q > 0 ? c.take<double>((size_t)m * s) : nullptr;   // C-PWR's Gram sub-sample (fixed)
     double *dAc = c.take<double>((size_t)m * s);
     double *Y = c.take<double>((size_t)m * L);
     std::vector<double *> Qs(q + 1), Zs(q), Rq(q + 1), Rz(q);
@@ -189,10 +192,11 @@ int dsk_learned_loss_grad(dsk_handle *h, const void *A, int32_t dtype, int64_t m
     DSK_RET(launch_select_cols(st, Ac, 1, m, s, s, L, Y));
     DSK_RET(launch_convert(st, Y, 1, tmp, 1, m * L));
     DSK_RET(launch_hhqr(st, tmp, m, L, Qs[0], Rq[0], h->dflags));
+    if (q > 0) DSK_RET(launch_gram_sample(st, A, dtype, m, n, lda, R, s, 1, Ag, h->dflags));
     for (int i = 0; i < q; ++i) {
-      DSK_RET(launch_gemm64(st, 1, 0, s, L, m, 1.0, Ac, s, Qs[i], L, tmp, L));          // A_c^T Q
+      DSK_RET(launch_gemm64(st, 1, 0, s, L, m, 1.0, Ag, s, Qs[i], L, tmp, L));          // A_g^T Q
       DSK_RET(launch_hhqr(st, tmp, s, L, Zs[i], Rz[i], h->dflags));
-      DSK_RET(launch_gemm64(st, 0, 0, m, L, s, 1.0, Ac, s, Zs[i], L, tmp, L));          // A_c Z
+      DSK_RET(launch_gemm64(st, 0, 0, m, L, s, 1.0, Ag, s, Zs[i], L, tmp, L));          // A_g Z
       DSK_RET(launch_hhqr(st, tmp, m, L, Qs[i + 1], Rq[i + 1], h->dflags));
     }
     // B^T = A^T Q, ||A||^2, ||B||^2, A B^T, B B^T
@@ -210,16 +214,15 @@ int dsk_learned_loss_grad(dsk_handle *h, const void *A, int32_t dtype, int64_t m
       hipLaunchKernelGGL(k_dq<float>, dim3(grid_of(m * L)), dim3(256), 0, st, (const float *)ABt, QG, scal, m * L,
                          dQ);
     hipLaunchKernelGGL(k_fill64, dim3(grid_of(m * s)), dim3(256), 0, st, dAc, m * s, 0.0);
-    // backward through the power steps (R factors held constant)
+    // backward through the power steps (R factors held constant; A_g does not
+    // depend on the weights, so only the start block carries dA_c)
     for (int i = q - 1; i >= 0; --i) {
       DSK_RET(trinv_t(st, Rq[i + 1], L, Minv, h->dflags));
       DSK_RET(launch_tsmm(st, dQ, 1, m, L, L, Minv, L, L, nullptr, dW, L));             // dW = dQ Rq^{-T}
-      DSK_RET(launch_gemm64(st, 0, 1, m, s, L, 1.0, dW, L, Zs[i], L, dAc, s, 1.0));     // += dW Z^T
-      DSK_RET(launch_gemm64(st, 1, 0, s, L, m, 1.0, Ac, s, dW, L, dZ, L));              // dZ = A_c^T dW
+      DSK_RET(launch_gemm64(st, 1, 0, s, L, m, 1.0, Ag, s, dW, L, dZ, L));              // dZ = A_g^T dW
       DSK_RET(trinv_t(st, Rz[i], L, Minv, h->dflags));
       DSK_RET(launch_tsmm(st, dZ, 1, s, L, L, Minv, L, L, nullptr, Wb, L));             // dZ' = dZ Rz^{-T}
-      DSK_RET(launch_gemm64(st, 0, 1, m, s, L, 1.0, Qs[i], L, Wb, L, dAc, s, 1.0));     // += Q_i dZ'^T
-      DSK_RET(launch_gemm64(st, 0, 0, m, L, s, 1.0, Ac, s, Wb, L, dQ, L));              // dQ = A_c dZ'
+      DSK_RET(launch_gemm64(st, 0, 0, m, L, s, 1.0, Ag, s, Wb, L, dQ, L));              // dQ = A_g dZ'
     }
     DSK_RET(trinv_t(st, Rq[0], L, Minv, h->dflags));
     DSK_RET(launch_tsmm(st, dQ, 1, m, L, L, Minv, L, L, nullptr, dW, L));               // dY = dQ R0^{-T}

@@ -38,8 +38,11 @@ struct Grid2 {
   int ny, nx, sy, sx, cy, cx;
 };
 
+constexpr int KIND_DI_GRID = 100;   // internal: direct injection on the grid of a stencil / learned restriction
+
 // Value of coarse column j of row i for each restriction kind.
-// KIND 0: index gather; 1: nearest neighbour; 2: global (block mean).
+// KIND 0: index gather; 1: nearest neighbour; 2: global (block mean);
+// 3: direct injection on the grid (the point (sy b, sx a) itself).
 template <int DT, int KIND, typename W>
 __device__ __forceinline__ W coarse_value(const void *A, int64_t row_off, int64_t j,
                                           const int64_t *__restrict__ idx, Grid2 g, int64_t n, int *dflags) {
@@ -55,7 +58,10 @@ __device__ __forceinline__ W coarse_value(const void *A, int64_t row_off, int64_
     const int b = (int)(j / g.cx), a = (int)(j % g.cx);
     const int y0 = b * g.sy, x0 = a * g.sx;
     W acc = 0;
-    if constexpr (KIND == 1) {
+    if constexpr (KIND == 3) {
+      if constexpr (sizeof(W) == 8) return load_as_f64<DT>(A, row_off + (int64_t)y0 * g.nx + x0);
+      else return load_as_f32<DT>(A, row_off + (int64_t)y0 * g.nx + x0);
+    } else if constexpr (KIND == 1) {
       const W w[3] = {W(0.25), W(0.5), W(0.25)};
 #pragma unroll
       for (int dy = -1; dy <= 1; ++dy) {
@@ -138,6 +144,7 @@ int restrict_dt(hipStream_t st, int kind, const void *A, int64_t m, int64_t n, i
                 const int64_t *idx, Grid2 g, int work_f64, void *Ac, void *AcT, int *dflags) {
   if (kind == DSK_R_INDEX) return restrict_typed<DT, 0>(st, A, m, n, lda, s, idx, g, work_f64, Ac, AcT, dflags);
   if (kind == DSK_R_NN) return restrict_typed<DT, 1>(st, A, m, n, lda, s, idx, g, work_f64, Ac, AcT, dflags);
+  if (kind == KIND_DI_GRID) return restrict_typed<DT, 3>(st, A, m, n, lda, s, idx, g, work_f64, Ac, AcT, dflags);
   return restrict_typed<DT, 2>(st, A, m, n, lda, s, idx, g, work_f64, Ac, AcT, dflags);
 }
 
@@ -235,6 +242,28 @@ int launch_restrict(hipStream_t st, const void *A, int dtype, int64_t m, int64_t
     case DSK_F32: return restrict_dt<DSK_F32>(st, R->kind, A, m, n, lda, s, idx, g, work_f64, Ac, AcT, dflags);
     case DSK_BF16: return restrict_dt<DSK_BF16>(st, R->kind, A, m, n, lda, s, idx, g, work_f64, Ac, AcT, dflags);
     default: return restrict_dt<DSK_F16>(st, R->kind, A, m, n, lda, s, idx, g, work_f64, Ac, AcT, dflags);
+  }
+}
+
+// The Gram sub-sample A_g = A(:, I) of C-PWR (Alg. 7).  An index restriction
+// is its own I; a stencil restriction uses the direct-injection points of its
+// grid and factor, the learned conv those of its stride-4 output grid.  The
+// sub-sample has as many columns as the restriction (s).
+int launch_gram_sample(hipStream_t st, const void *A, int dtype, int64_t m, int64_t n, int64_t lda,
+                       const dsk_restriction *R, int64_t s, int work_f64, void *Ag, int *dflags) {
+  if (R->kind == DSK_R_INDEX) return launch_restrict(st, A, dtype, m, n, lda, R, s, work_f64, Ag, nullptr, dflags);
+  Grid2 g{};
+  g.ny = R->ny; g.nx = R->nx;
+  g.sy = R->kind == DSK_R_LEARNED ? 4 : R->sy;
+  g.sx = R->kind == DSK_R_LEARNED ? 4 : R->sx;
+  g.cy = (g.ny + g.sy - 1) / g.sy;
+  g.cx = (g.nx + g.sx - 1) / g.sx;
+  if ((int64_t)g.cy * g.cx != s) return -1;
+  switch (dtype) {
+    case DSK_F64: return restrict_dt<DSK_F64>(st, KIND_DI_GRID, A, m, n, lda, s, nullptr, g, work_f64, Ag, nullptr, dflags);
+    case DSK_F32: return restrict_dt<DSK_F32>(st, KIND_DI_GRID, A, m, n, lda, s, nullptr, g, work_f64, Ag, nullptr, dflags);
+    case DSK_BF16: return restrict_dt<DSK_BF16>(st, KIND_DI_GRID, A, m, n, lda, s, nullptr, g, work_f64, Ag, nullptr, dflags);
+    default: return restrict_dt<DSK_F16>(st, KIND_DI_GRID, A, m, n, lda, s, nullptr, g, work_f64, Ag, nullptr, dflags);
   }
 }
 

@@ -1,0 +1,399 @@
+// Row ID pivot steps in one launch with the rows of W held in registers
+// (paper Sec. 4, row ID; TPC-ID, Alg. 4): rank-k column-pivoted QR of W^T,
+// W m x s row-major, taken in its left-looking (pivoted Cholesky) form so that
+// no residual is ever stored or exchanged.
+//
+// With c_{i,l} = q_l . w_i (the entries R[l, i] of the pivoted QR) and
+// nu_i = ||residual_i||^2, step j with pivot p computes, for every unselected i,
+//
+//   R_jj = sqrt(nu_p),   c_{i,j} = (w_i . w_p - sum_{l<j} c_{p,l} c_{i,l}) / R_jj,
+//   nu_i <- nu_i - c_{i,j}^2,
+//
+// which is the Gram-Schmidt recurrence with q_j = (w_p - sum_l c_{p,l} q_l) / R_jj
+// written without q: only the original rows (read-only) and the coefficients
+// are needed.  The pivot rule is that of the other ID kernels (largest nu, nu
+// truncated to 34 mantissa bits, ties to the lowest index), on downdated norms:
+// nu_i carries a relative error of about u (nu_0 / nu_i)^(3/2) (the
+// subtraction and the coefficients' own rounding), which stays below 1e-8 of
+// a pivot gap while the pivot's norm^2 is above 1e-5 of the first pivot's.
+// Past that point the launch stops (every workgroup takes the same decision)
+// and the one-workgroup kernel after it redoes the factorization with
+// recomputed norms.  Products are FP64; W is read as FP32 only when its
+// values are FP32 numbers exactly.
+//
+// Launch: G = ceil(m / RPW) workgroups of NT threads, at most one per compute
+// unit (the rows of a workgroup fill its registers), all resident at once.
+// Thread t holds entries t + NT u (u < EPT) of each of its workgroup's rows.
+// Each step has one exchange: a workgroup stores the norms of its rows and
+// its coefficient column (into R), then one packed word (pivot rank, index,
+// step); once every word of the step is seen, the pivot's norm and
+// coefficients are read back from where its owner stored them.  Exchanges use
+// device-coherent relaxed atomic stores and loads, a writer's data stores
+// complete before its word (devsync.h), and the buffers alternate by step
+// parity (a workgroup is at most one step ahead of any other).  Every wait is
+// bounded: past the bound the workgroup raises DSK_FLAG_SYNC_TIMEOUT and sets
+// the abort word, every workgroup leaves, and the one-workgroup kernel after
+// it (k_rowid_rescue: right-looking Gram-Schmidt with norms recomputed from the
+// residuals, as the per-step kernels) redoes the factorization from W, so the
+// outputs stay valid without the host having to look.
+#include <algorithm>
+
+#include "devsync.h"
+#include "dsk_internal.h"
+
+namespace {
+
+constexpr int NT = 512;
+constexpr int NW = NT / 64;
+constexpr int KMAX = 112;
+constexpr int TAGW = 32;                   // one word per 256-byte line
+constexpr long long SPIN_LIMIT = 1LL << 22;
+constexpr double DOWNDATE_MIN = 1e-5;      // smallest pivot norm^2 / first pivot norm^2 taken here
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// pivot order: nu truncated to 34 mantissa bits (+1); selected / NaN -> 0
+__device__ __forceinline__ unsigned long long nu_rank(double v) {
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(v) & 0x7FFFFFFFFFFFFFFFull;
+  return (v >= 0.0) ? (bits >> 18) + 1ull : 0ull;
+}
+
+// rank in bits 18.., inverted index (11 bits) in 7..17, step marker in 0..6:
+// the maximum over words is the pivot (largest rank, then lowest index)
+__device__ __forceinline__ unsigned long long pack_word(unsigned long long rank, long long idx, int marker) {
+  return (rank << 18) | ((unsigned long long)(~idx & 0x7FF) << 7) | (unsigned long long)(marker & 0x7F);
+}
+
+__device__ __forceinline__ bool wait_word(const unsigned long long *wp, int marker, int *abort_flag,
+                                          unsigned long long &word) {
+  long long spins = 0;
+  for (;;) {
+    word = (unsigned long long)ds::ld_dev(reinterpret_cast<const long long *>(wp));
+    if ((int)(word & 0x7F) == (marker & 0x7F)) break;
+    if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || ++spins > SPIN_LIMIT) {
+      atomicOr(abort_flag, 1);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  ds::after_flag();
+  return true;
+}
+
+template <typename T>
+__device__ __forceinline__ double to_f64(T v) { return (double)v; }
+
+// Sum over the workgroup of v[r] for each r < R (wave sums, then waves in a
+// fixed order); the totals land in out[r].  Called by all threads.
+template <int R>
+__device__ __forceinline__ void block_sums(double (&v)[R], double (*red)[R], double *out) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const double a = wsum(v[r]);
+    if (lane == 0) red[wave][r] = a;
+  }
+  __syncthreads();
+  if (t < R) {
+    double a = 0.0;
+    for (int w = 0; w < NW; ++w) a += red[w][t];
+    out[t] = a;
+  }
+  __syncthreads();
+}
+
+template <typename T, int RPW, int EPT>
+__global__ void __launch_bounds__(NT) k_rowid_reg(const T *__restrict__ W, int64_t m, int64_t s, int k,
+                                                  unsigned long long *words, double *nuG, int *abort_flag,
+                                                  double *__restrict__ nu_final, double *Rk,
+                                                  int64_t *__restrict__ piv, int *__restrict__ dflags) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int G = gridDim.x, gid = blockIdx.x;
+  __shared__ double red[NW][RPW];
+  __shared__ double num[RPW];
+  __shared__ double nu_sh[RPW];
+  __shared__ int live_sh[RPW];
+  __shared__ double cl[RPW][KMAX];     // c_{i,l} of this workgroup's rows
+  __shared__ double cp[KMAX];          // c_{p,l} of the pivot
+  __shared__ unsigned long long bk[NW];
+  __shared__ unsigned long long key_sh;
+  __shared__ double rjj_sh;
+  __shared__ double nu_first;
+  __shared__ int stop_sh;
+
+  const int64_t row0 = (int64_t)gid * RPW;
+  T w[RPW][EPT];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    const int64_t i = row0 + r;
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int64_t e = t + (int64_t)NT * u;
+      w[r][u] = (i < m && e < s) ? W[i * s + e] : T(0);
+    }
+  }
+  {
+    double v[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      double a = 0.0;
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) a = fma(to_f64(w[r][u]), to_f64(w[r][u]), a);
+      v[r] = a;
+    }
+    block_sums<RPW>(v, red, nu_sh);
+  }
+  if (t < RPW) {
+    live_sh[t] = (row0 + t < m) ? 1 : 0;
+    if (live_sh[t] && !isfinite(nu_sh[t])) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_NONFINITE);
+  }
+  if (t == 0) stop_sh = 0;
+  __syncthreads();
+
+  for (int j = 0; j < k; ++j) {
+    const int par = j & 1;
+    // ---- publish: norms of this workgroup's rows (selected: -1), then the word
+    if (t < RPW && row0 + t < m) ds::st_dev(&nuG[(int64_t)par * m + row0 + t], live_sh[t] ? nu_sh[t] : -1.0);
+    ds::stores_done();
+    __syncthreads();
+    if (t == 0) {
+      unsigned long long brank = 0;
+      long long bidx = m;
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        if (!live_sh[r]) continue;
+        const unsigned long long rk = nu_rank(nu_sh[r]);
+        if (rk > brank) { brank = rk; bidx = row0 + r; }   // ascending rows: ties keep the lower index
+      }
+      ds::st_dev(reinterpret_cast<long long *>(&words[((int64_t)par * G + gid) * TAGW]),
+                 (long long)pack_word(brank, bidx, j + 1));
+    }
+    // ---- every word of the step; maximum of (rank, inverted index)
+    unsigned long long best = 0;
+    for (int g = t; g < G; g += NT) {
+      unsigned long long wd;
+      if (!wait_word(&words[((int64_t)par * G + g) * TAGW], j + 1, abort_flag, wd)) {
+        stop_sh = 1;
+        break;
+      }
+      best = max(best, wd >> 7);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) best = max(best, (unsigned long long)__shfl_xor((long long)best, o, 64));
+    if (lane == 0) bk[wave] = best;
+    __syncthreads();
+    if (t == 0) {
+      unsigned long long b = bk[0];
+      for (int w2 = 1; w2 < NW; ++w2) b = max(b, bk[w2]);
+      key_sh = b;
+    }
+    __syncthreads();
+    if (stop_sh) break;
+    const unsigned long long key = key_sh;
+    const int64_t p = (key >> 11) ? (int64_t)(~key & 0x7FF) : m;
+    // ---- the pivot: its norm and coefficients from where its owner stored them, its row from W
+    if (t == 0) {
+      const double nup = (p < m) ? ds::ld_dev(&nuG[(int64_t)par * m + p]) : 0.0;
+      rjj_sh = nup > 0.0 ? sqrt(nup) : 0.0;
+      if (j == 0) nu_first = nup;
+      // downdated norms no longer resolve 1e-8 pivot gaps: leave to the exact rescue
+      if (nup < DOWNDATE_MIN * nu_first && nup > 0.0) stop_sh = 2;
+    }
+    if (t < j) cp[t] = (p < m) ? ds::ld_dev(&Rk[(int64_t)t * m + p]) : 0.0;
+    __syncthreads();
+    if (stop_sh) break;
+    double wp[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int64_t e = t + (int64_t)NT * u;
+      wp[u] = (p < m && e < s) ? to_f64(W[p * s + e]) : 0.0;
+    }
+    __syncthreads();
+    const double rjj = rjj_sh;
+    if (gid == 0 && t == 0) {
+      piv[j] = p;
+      if (p < m) ds::st_dev(&Rk[(int64_t)j * m + p], rjj);
+      if (!(rjj > 0.0)) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_RANK_DEFICIENT);
+    }
+    // ---- w_i . w_p - sum_{l<j} c_{p,l} c_{i,l} for this workgroup's rows
+    double v[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      double a = 0.0;
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) a = fma(to_f64(w[r][u]), wp[u], a);
+      if (t < j) a = fma(-cp[t], cl[r][t], a);
+      v[r] = a;
+    }
+    block_sums<RPW>(v, red, num);
+    if (t < RPW) {
+      const int64_t i = row0 + t;
+      if (i == p) live_sh[t] = 0;
+      if (live_sh[t]) {
+        const double c = rjj > 0.0 ? num[t] / rjj : 0.0;
+        cl[t][j] = c;
+        ds::st_dev(&Rk[(int64_t)j * m + i], c);
+        const double nn = nu_sh[t] - c * c;
+        nu_sh[t] = nn > 0.0 ? nn : 0.0;
+      }
+    }
+    __syncthreads();
+  }
+  if (stop_sh) {
+    if (t == 0) {
+      atomicOr(&dflags[FLAGW_BITS], stop_sh == 1 ? DSK_FLAG_SYNC_TIMEOUT : DSK_FLAG_FALLBACK);
+      if (stop_sh == 2) atomicOr(abort_flag, 1);
+    }
+    return;
+  }
+  if (t < RPW && row0 + t < m) nu_final[row0 + t] = live_sh[t] ? nu_sh[t] : -1.0;
+}
+
+// Leaves at once unless the one-launch kernel gave up (a wait timed out, or the
+// downdated norms ran out of accuracy); then one workgroup redoes the whole
+// factorization as the per-step kernels do: right-looking modified
+// Gram-Schmidt on an FP64 copy Wr of W, norms recomputed from the residuals
+// every step, the same pivot rule.  Slow for wide W, but only taken then.
+template <typename T>
+__global__ void __launch_bounds__(1024) k_rowid_rescue(const T *__restrict__ W, int64_t m, int64_t s, int k,
+                                                       const int *abort_flag, double *__restrict__ Wr,
+                                                       double *__restrict__ nuR, double *__restrict__ nu_final,
+                                                       double *__restrict__ Rk, int64_t *__restrict__ piv,
+                                                       int *__restrict__ dflags) {
+  if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  constexpr int WV = 16;
+  __shared__ unsigned long long bk[WV];
+  __shared__ int64_t p_sh;
+  __shared__ double rjj_sh;
+  for (int64_t x = t; x < m * s; x += 1024) Wr[x] = to_f64(W[x]);
+  __syncthreads();
+  for (int64_t i = wave; i < m; i += WV) {
+    double a = 0.0;
+    for (int64_t e = lane; e < s; e += 64) a = fma(Wr[i * s + e], Wr[i * s + e], a);
+    a = wsum(a);
+    if (lane == 0) nuR[i] = a;
+  }
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    unsigned long long best = 0;
+    for (int64_t i = t; i < m; i += 1024) {
+      const unsigned long long key = (nu_rank(nuR[i]) << 11) | (unsigned long long)(~i & 0x7FF);
+      best = max(best, key);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) best = max(best, (unsigned long long)__shfl_xor((long long)best, o, 64));
+    if (lane == 0) bk[wave] = best;
+    __syncthreads();
+    if (t == 0) {
+      unsigned long long b = bk[0];
+      for (int w2 = 1; w2 < WV; ++w2) b = max(b, bk[w2]);
+      const int64_t p = (b >> 11) ? (int64_t)(~b & 0x7FF) : m;
+      const double nup = p < m ? nuR[p] : 0.0;
+      p_sh = p;
+      rjj_sh = nup > 0.0 ? sqrt(nup) : 0.0;
+      piv[j] = p;
+      if (p < m) {
+        Rk[(int64_t)j * m + p] = rjj_sh;
+        nuR[p] = -1.0;
+      }
+      if (!(rjj_sh > 0.0)) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_RANK_DEFICIENT);
+    }
+    __syncthreads();
+    const int64_t p = p_sh;
+    const double qs = rjj_sh > 0.0 ? 1.0 / rjj_sh : 0.0;
+    for (int64_t i = wave; i < m; i += WV) {
+      if (!(nuR[i] >= 0.0) || p >= m) continue;
+      double a = 0.0;
+      for (int64_t e = lane; e < s; e += 64) a = fma(Wr[p * s + e] * qs, Wr[i * s + e], a);
+      a = wsum(a);
+      double nn = 0.0;
+      for (int64_t e = lane; e < s; e += 64) {
+        const double v = fma(-a, Wr[p * s + e] * qs, Wr[i * s + e]);
+        Wr[i * s + e] = v;
+        nn = fma(v, v, nn);
+      }
+      nn = wsum(nn);
+      if (lane == 0) {
+        Rk[(int64_t)j * m + i] = a;
+        nuR[i] = nn;
+      }
+    }
+    __syncthreads();
+  }
+  for (int64_t i = t; i < m; i += 1024) nu_final[i] = nuR[i] >= 0.0 ? nuR[i] : -1.0;
+}
+
+__global__ void k_rowid_reset(unsigned long long *words, int nwords, int *abort_flag, int64_t *piv, int k) {
+  for (int i = threadIdx.x; i < nwords; i += blockDim.x) words[i] = 0;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) piv[i] = -1;
+  if (threadIdx.x == 0) *abort_flag = 0;
+}
+
+struct Plan {
+  int rpw, ept, g;
+};
+
+// Rows per workgroup and entries per thread, or rpw = 0 when the shape does
+// not fit (more than one workgroup per compute unit, rows wider than 16 NT,
+// more than 2048 candidates, or more than 128 registers of row data).
+Plan plan_of(int64_t m, int64_t s, int k, int esize, int cu_count) {
+  Plan pl{0, 0, 0};
+  if (m < 1 || s < 1 || k < 1 || k > KMAX || m > 2048 || s > 16 * NT) return pl;
+  const int ept = s <= 4 * NT ? 4 : (s <= 8 * NT ? 8 : 16);
+  for (int rpw : {4, 8}) {
+    const int64_t g = (m + rpw - 1) / rpw;
+    if (g > cu_count) continue;
+    if (rpw * ept * esize / 4 > 128) continue;
+    pl.rpw = rpw;
+    pl.ept = ept;
+    pl.g = (int)g;
+    return pl;
+  }
+  return pl;
+}
+
+template <typename T>
+int launch_typed(hipStream_t st, const T *W, int64_t m, int64_t s, int k, double *nu_final, double *Rk, int64_t *piv,
+                 char *ws, const Plan &pl, int *dflags) {
+  unsigned long long *words = reinterpret_cast<unsigned long long *>(ws);
+  const size_t wbytes = (size_t)2 * pl.g * TAGW * 8;
+  double *nuG = reinterpret_cast<double *>(ws + wbytes);
+  double *nuR = nuG + 2 * m;
+  double *Wr = nuR + m;                          // the rescue's FP64 residuals, m x s
+  int *abort_flag = reinterpret_cast<int *>(Wr + (size_t)m * s);
+  hipLaunchKernelGGL(k_rowid_reset, dim3(1), dim3(256), 0, st, words, 2 * pl.g * TAGW, abort_flag, piv, k);
+  DSK_TRY(hipGetLastError());
+#define DSK_RREG(R_, E_)                                                                                       \
+  if (pl.rpw == R_ && pl.ept == E_)                                                                            \
+    hipLaunchKernelGGL((k_rowid_reg<T, R_, E_>), dim3(pl.g), dim3(NT), 0, st, W, m, s, k, words, nuG, abort_flag, \
+                       nu_final, Rk, piv, dflags);
+  DSK_RREG(4, 4) DSK_RREG(4, 8) DSK_RREG(4, 16) DSK_RREG(8, 4) DSK_RREG(8, 8) DSK_RREG(8, 16)
+#undef DSK_RREG
+  DSK_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_rowid_rescue<T>, dim3(1), dim3(1024), 0, st, W, m, s, k, abort_flag, Wr, nuR, nu_final, Rk,
+                     piv, dflags);
+  DSK_TRY(hipGetLastError());
+  return 0;
+}
+
+}  // namespace
+
+size_t rowid_reg_ws_bytes(int64_t m, int64_t s, int k, int w_f64, int cu_count) {
+  const Plan pl = plan_of(m, s, k, w_f64 ? 8 : 4, cu_count);
+  if (!pl.rpw) return 0;
+  return (size_t)2 * pl.g * TAGW * 8 + (size_t)3 * m * 8 + (size_t)m * s * 8 + 256;
+}
+
+int launch_rowid_reg(hipStream_t st, const void *W, int w_f64, int64_t m, int64_t s, int k, double *nu_final,
+                     double *Rk, int64_t *piv, void *ws, int cu_count, int *dflags) {
+  const Plan pl = plan_of(m, s, k, w_f64 ? 8 : 4, cu_count);
+  if (!pl.rpw) return -1;
+  char *w = reinterpret_cast<char *>(ws);
+  if (w_f64) return launch_typed<double>(st, (const double *)W, m, s, k, nu_final, Rk, piv, w, pl, dflags);
+  return launch_typed<float>(st, (const float *)W, m, s, k, nu_final, Rk, piv, w, pl, dflags);
+}

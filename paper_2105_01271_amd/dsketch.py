@@ -252,7 +252,7 @@ def spc_id_err(A: torch.Tensor, R: Restriction, mc: int, taus, with_rho: bool = 
 def sketch_id(A: torch.Tensor, k: int, R: Restriction, q: int = 0, p: int = 10, S=None, tau=None,
               projected=False, skeleton_rows=False, want_info: bool = False, per_step: bool = False):
     """Rank-k row ID by TPC-ID (dsk_sketch_id).  Returns I (k, int64), P (m x k, f64)[, A(I,:)][, info].
-    per_step: run the pivoted QR as one launch per pivot step even where one persistent launch fits."""
+    per_step: run the pivoted QR as one launch per pivot step even where the one-launch form fits."""
     _check_matrix(A)
     lib = _lib.load()
     m, n = A.shape

@@ -163,11 +163,17 @@ def heat_exact(m: int, ny: int, nx: int, seed: int, rate: float = 0.05, r: int |
     Ut = _orthonormal_columns(G)
     sigma = np.exp(-rate * np.arange(1, r + 1, dtype=np.float64))
     C = Ut * sigma[None, :]
-    A = np.zeros((m, ny, nx))
-    for qy in np.unique(iy):
-        sel = np.nonzero(iy == qy)[0]
-        part = C[:, sel] @ Sx[:, ix[sel]].T                 # m x nx
-        A += part[:, None, :] * Sy[:, qy][None, :, None]
+    # A[t, y, x] = sum_j C[t, j] Sy[y, iy_j] Sx[x, ix_j], as two products over the
+    # (q, p) mode grid: M[t, q, p] = sum_j C[t, j] [iy_j = q][ix_j = p]
+    nq, npx = Sy.shape[1], Sx.shape[1]
+    M = np.zeros((m, nq, npx))
+    np.add.at(M, (slice(None), iy, ix), C)
+    T1 = M.reshape(m * nq, npx) @ Sx.T                       # (m q) x nx
+    A = np.empty((m, ny, nx))
+    step = max(1, (1 << 27) // max(1, ny * nx))             # rows per block (bounded temporaries)
+    T1 = T1.reshape(m, nq, nx)
+    for t0 in range(0, m, step):
+        A[t0:t0 + step] = np.einsum("yq,tqx->tyx", Sy, T1[t0:t0 + step], optimize=True)
     A = A.reshape(m, ny * nx)
     if return_parts:
         return A, sigma

@@ -59,7 +59,7 @@ def build(verbose: bool = False) -> str:
         s = open(p).read()
         # dynamic LDS: a heap buffer of exactly the launch's size
         s = re.sub(r"extern __shared__ (\w+) (\w+)\[\];", r"\1 *\2 = (\1 *)simt::dyn_lds();", s)
-        if os.path.basename(p) == "cpqr.hip":
+        if os.path.basename(p) in ("cpqr.hip", "rowid_reg.hip"):
             # workgroups of the one-launch factorization run together: one copy of
             # each static LDS variable per resident block
             s = re.sub(r"__shared__ ((?:unsigned )?(?:long long|\w+)) (\w+)((?:\[[^\]]+\])*);",

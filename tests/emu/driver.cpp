@@ -633,9 +633,16 @@ int main(int argc, char **argv) {
                                 P[ps].data(), nullptr, &inf[ps]));
         res[ps] = simt::g_resident_launches - before;
       }
-      const bool same = I[0] == I[1] && memcmp(P[0].data(), P[1].data(), P[0].size() * 8) == 0;
-      printf("   I0 %lld I%d %lld flags %d %d resident launches %lld %lld same %d\n", (long long)I[0][0], c.k - 1,
-             (long long)I[0][c.k - 1], inf[0].flags, inf[1].flags, res[0], res[1], same ? 1 : 0);
+      // the one-launch kernel takes the left-looking recurrence: same pivots, P to rounding
+      const bool same = I[0] == I[1];
+      double maxdp = 0.0, maxp = 1.0;
+      for (size_t e = 0; e < P[0].size(); ++e) {
+        maxdp = std::max(maxdp, std::fabs(P[0][e] - P[1][e]));
+        maxp = std::max(maxp, std::fabs(P[1][e]));
+      }
+      printf("   I0 %lld I%d %lld flags %d %d resident launches %lld %lld same %d maxdp %.3e\n", (long long)I[0][0],
+             c.k - 1, (long long)I[0][c.k - 1], inf[0].flags, inf[1].flags, res[0], res[1], same ? 1 : 0,
+             maxdp / maxp);
     }
   }
   dsk_destroy(h);

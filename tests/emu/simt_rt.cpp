@@ -59,8 +59,8 @@ struct Fiber {
   int where = 0;   // 1 block barrier, 10 + lg group barrier
   Ctx c;
 };
-static Fiber g_fib[MAXB * 256];   // a sequential launch uses up to 1024 of them
-static int g_fib_blk[MAXB * 256];
+static Fiber g_fib[MAXB * 512];   // a sequential launch uses up to 1024 of them
+static int g_fib_blk[MAXB * 512];
 static void *g_sched_sp = nullptr;
 static const void *g_main_bottom = nullptr;
 static size_t g_main_size = 0;
@@ -147,7 +147,7 @@ static void dump_states() {
 static void run_blocks(const std::vector<dim3> &blocks, dim3 g, dim3 bd, size_t lds) {
   const int per = (int)(bd.x * bd.y * bd.z);
   const int nb = (int)blocks.size();
-  if (nb > MAXB || (nb > 1 && per > 256)) die("too many resident blocks");
+  if (nb > MAXB || (nb > 1 && per > 512)) die("too many resident blocks");
   for (int bi = 0; bi < nb; ++bi) {
     if (!g_bs[bi]) g_bs[bi] = new BlockState();
     BlockState &B = *g_bs[bi];
@@ -227,7 +227,7 @@ void launch_exec(const char *name, dim3 grid, dim3 block, size_t lds, const std:
   g_kernel = name;
   g_body = &body;
   // workgroups that wait on each other run as one set of fibers
-  const bool together = strstr(name, "k_cpqr_persist") != nullptr;
+  const bool together = strstr(name, "k_cpqr_persist") != nullptr || strstr(name, "k_rowid_reg") != nullptr;
   if (together) {
     std::vector<dim3> all;
     for (unsigned by = 0; by < grid.y; ++by)

@@ -17,6 +17,8 @@ from oracle import rowid as orid
 from oracle import sketch as osk
 from paper_2105_01271_amd import synth
 
+import svdcheck   # tests/svdcheck.py
+
 pytestmark = pytest.mark.gpu
 
 TOL32 = 1e-5
@@ -45,7 +47,7 @@ def test_fullsize_sketch_svd_q1(c2):
     R = dsk().Restriction.di_grid(256, 256, 4, 4)
     U, S, V, info = dsk().sketch_svd(A, 50, R, q=1, want_info=True)
     Rd = {"kind": "index", "index": ores.di_index_2d(256, 256, 4, 4)}
-    Uo, So, Vo = osk.tpc_svd(Aup, 50, Rd, q=1)
+    Uo, So, Vo, oi = osk.tpc_svd(Aup, 50, Rd, q=1, return_all=True)
     S = S.cpu().numpy()
     err = np.abs(S - So).max() / So[0]
     say("  sigma error / sigma_1", err, "sweeps", info["core_sweeps"])
@@ -55,12 +57,9 @@ def test_fullsize_sketch_svd_q1(c2):
     e_or = omet.svd_error(Aup, Uo, So, Vo)
     say("  rank-k error gpu / oracle", e_gpu, e_or)
     assert abs(e_gpu - e_or) <= TOL32 * e_or
-    # leading singular vectors, where the gaps are wide, agree column by column
-    gaps = np.abs(np.diff(So[:11])) / So[0]
-    for j in range(10):
-        if gaps[j] > 1e-3 and (j == 0 or gaps[j - 1] > 1e-3):
-            assert np.abs(Un[:, j] - Uo[:, j]).max() <= 1e-3, j
-            assert np.abs(Vn[:, j] - Vo[:, j]).max() <= 1e-3, j
+    # singular vectors: one by one where the gaps resolve them, cluster projectors elsewhere
+    nchk = svdcheck.compare_vectors(Un, Uo, Vn, Vo, oi["sigma_B"], 50, TOL32)
+    say("  singular pairs compared one by one:", nchk)
     assert abs(info["normA_fro2"] - omet.fro2(Aup)) <= 1e-6 * omet.fro2(Aup)
 
 
@@ -83,13 +82,17 @@ def test_fullsize_sketch_id_q0(c2):
     assert list(I[:npre]) == list(Io[:npre])
     np.testing.assert_array_equal(P[I], np.eye(50))
     if npre == 50:
-        assert np.abs(P - Po).max() <= 1e-7 * max(1.0, np.abs(Po).max())
+        kap = np.linalg.cond(info["R"][:, :50])
+        ptol = max(1e-7, 10 * 2.0 ** -53 * kap)
+        assert np.abs(P - Po).max() <= ptol * max(1.0, np.abs(Po).max())
     e_gpu = omet.id_error(Aup, I, P)
     e_or = omet.id_error(Aup, Io, Po)
     say("  ID error gpu / oracle", e_gpu, e_or)
     assert e_gpu <= e_or * (1 + 1e-6) + 1e-12
     np.testing.assert_array_equal(rows.cpu().numpy(), A.cpu().numpy()[I])
-    # the timed launch configuration (one persistent launch) equals the per-step factorization
+    # the timed launch configuration (one launch, left-looking recurrence) takes the
+    # pivots of the per-step factorization and its P to rounding
     I1, P1 = dsk().sketch_id(A, 50, R, q=0, per_step=True)
     np.testing.assert_array_equal(I1.cpu().numpy(), I)
-    np.testing.assert_array_equal(P1.cpu().numpy(), P)
+    kap = np.linalg.cond(info["R"][:, :50])
+    np.testing.assert_allclose(P1.cpu().numpy(), P, rtol=0, atol=max(1e-9, 10 * 2.0 ** -53 * kap))
