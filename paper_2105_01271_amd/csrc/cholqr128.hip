@@ -1,0 +1,388 @@
+// CholeskyQR for blocks 65 .. 128 wide: the QR steps of Alg. 2 and Alg. 7
+// (range finder, power-iteration bases) when ell = k + p exceeds 64.  Same
+// contract and numerics as the 64-wide path: Q = Y L^{-T} with L L^T = Y^T Y,
+// FP64 Gram, FP64 factorization, FP64 products; on a non-positive or
+// negligible pivot the factorization is retried with the shift
+// 11 (rows ell + ell (ell + 1)) u tr(Y^T Y), DSK_FLAG_FALLBACK is raised and a
+// third pass restores orthonormality (shifted CholeskyQR3).
+//
+// A pass is three launches:
+//  * Gram partials of the block (gram64.hip, tile-major lower 16 x 16 tiles,
+//    one partial per 128 rows);
+//  * fold + factor: every workgroup sums 64 entries of the partials in a
+//    fixed order (four threads per entry, partials strided by four, then the
+//    four in order) and publishes them; the last workgroup to arrive factors
+//    G = L L^T in LDS.  Each 16-column panel is factored by one wave in
+//    registers (no barrier inside a panel, only 1 / d on the chain from pivot
+//    to pivot), the trailing tiles A_IJ -= L_IK L_JK^T go to all four waves on
+//    MFMA: two barriers per panel.  Then W_K = L_KK^{-1} for the diagonal
+//    blocks;
+//  * apply: each wave owns 16 rows of a 64-row chunk and forms
+//    Q_J = (Y_J - sum_{K<J} Q_K L_JK^T) W_J^T block column by block column
+//    on MFMA, with no barrier; when the next pass needs the Gram of the
+//    rounded Q, the workgroup accumulates its tiles (two barriers per chunk).
+// All sums run in fixed orders, so repeated runs give identical bytes.
+#include <algorithm>
+
+#include "devsync.h"
+#include "dsk_internal.h"
+#include "gramtile.h"
+
+namespace {
+
+using wc::d4;
+using wc::mfma;
+
+constexpr int NBM = 8;                    // 16-column blocks at most
+constexpr int EMAX = 16 * NBM;            // widest block
+constexpr int NTM = NBM * (NBM + 1) / 2;  // lower tiles at most
+constexpr int TILE = 256;
+constexpr int PART = NTM * TILE;          // doubles of a (largest) partial
+constexpr int PMAX = 256;                 // partials at most
+constexpr int GRPB = 128;                 // rows per Gram partial (at least)
+constexpr int LDA = EMAX + 2;             // LDS row stride of the factor (conflict-free MFMA operand reads)
+constexpr int RCH = 64;                   // rows per apply chunk (16 per wave)
+constexpr int LDQ = EMAX + 2;             // LDS row stride of the apply chunk
+constexpr int MST = 16 * 17;              // LDS footprint of a factor tile (row stride 17)
+constexpr int FE = 64;                    // entries per fold workgroup
+constexpr double U64 = 1.1102230246251565e-16;
+
+constexpr int FACT_LDS = EMAX * LDA + 64 + EMAX + 8;       // A, colb, dinv, words
+constexpr int APPLY_LDS = NTM * MST + RCH * LDQ + 4 * MST;  // factor tiles, chunk, per-wave S
+
+__device__ __forceinline__ int ltile(int J, int K) { return J * (J + 1) / 2 + K; }
+
+__device__ __forceinline__ void tile_ij(int id, int &I, int &J) {
+  I = 0;
+  while ((I + 1) * (I + 2) / 2 <= id) ++I;
+  J = id - I * (I + 1) / 2;
+}
+
+// A (LDS, lower triangle) from the folded Gram (tile-major, published by other
+// workgroups of this launch); identity past ell; shift added to the diagonal.
+__device__ void load_gram(const double *G, int ell, int nb, double shift, double *A) {
+  const int ne = nb * (nb + 1) / 2 * TILE;
+  for (int e = threadIdx.x; e < ne; e += 256) {
+    int I, J;
+    tile_ij(e >> 8, I, J);
+    const int r = 16 * I + ((e >> 4) & 15), c = 16 * J + (e & 15);
+    double v = ds::ld_dev(&G[e]);
+    if (r >= ell || c >= ell) v = (r == c) ? 1.0 : 0.0;
+    else if (r == c) v += shift;
+    A[r * LDA + c] = v;
+  }
+}
+
+// Panel K of the factorization by the calling wave (rows 16 K .. ellp - 1,
+// lane l keeps rows 16 K + l and 16 K + 64 + l): the column of pivot p reaches
+// every lane through one LDS write (colb) and uniform-address reads, the pivot
+// itself by v_readlane; A(i, c) -= A(i, p) A(c, p) / d needs no square root
+// on the chain.  Padded columns (p >= ell) are identity columns.  Writes L's
+// panel (zero above the diagonal) back to A and 1 / L(p, p) to dinv.
+__device__ __forceinline__ bool panel(double *A, int K, int ell, int ellp, double thr, double *colb, double *dinv) {
+  const int l = threadIdx.x & 63, c0 = 16 * K;
+  const int r0 = c0 + l, r1 = c0 + 64 + l;
+  const bool h0 = r0 < ellp, h1 = r1 < ellp;
+  double g0[16], g1[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    g0[j] = h0 ? A[r0 * LDA + c0 + j] : 0.0;
+    g1[j] = h1 ? A[r1 * LDA + c0 + j] : 0.0;
+  }
+  bool ok = true;
+  double mydinv = 1.0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int p = c0 + j;
+    const bool live = p < ell;
+    const double dp = wc::readlane_f64(g0[j], j);
+    colb[l] = g0[j];
+    wc::wave_lds_sync();
+    double lc[16];
+#pragma unroll
+    for (int c = j + 1; c < 16; ++c) lc[c] = colb[c];
+    const double d = live ? dp : 1.0;
+    ok = ok && (!live || (d > thr && isfinite(d)));
+    const double inv = wc::rcp_nr(d), rs = wc::rsq_nr(d);
+    const double t0 = g0[j] * inv, t1 = g1[j] * inv;
+#pragma unroll
+    for (int c = j + 1; c < 16; ++c) {
+      g0[c] = fma(-t0, lc[c], g0[c]);
+      g1[c] = fma(-t1, lc[c], g1[c]);
+    }
+    g0[j] = live ? (r0 > p ? g0[j] * rs : (r0 == p ? d * rs : 0.0)) : (r0 == p ? 1.0 : 0.0);
+    g1[j] = live ? g1[j] * rs : 0.0;
+    mydinv = (r0 == p) ? (live ? rs : 1.0) : mydinv;
+    wc::wave_lds_sync();   // colb is rewritten by the next step
+  }
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    if (h0) A[r0 * LDA + c0 + j] = (r0 >= c0 + j) ? g0[j] : 0.0;
+    if (h1) A[r1 * LDA + c0 + j] = g1[j];
+  }
+  if (l < 16) dinv[c0 + l] = mydinv;
+  return ok;
+}
+
+// A_IJ -= L_IK L_JK^T for K < J <= I < nb, tiles dealt to the four waves.
+// MFMA operands: A(i, k) = L(16 I + i, 16 K + k) in lane i + 16 k,
+// B(k, j) = L(16 J + j, 16 K + k) in lane j + 16 k.
+__device__ __forceinline__ void trailing(double *A, int K, int nb) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6, c0 = 16 * K;
+  const int mrest = nb - 1 - K, cnt = mrest * (mrest + 1) / 2;
+  for (int id = w; id < cnt; id += 4) {
+    int I, J;
+    tile_ij(id, I, J);
+    I += K + 1;
+    J += K + 1;
+    d4 c;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) c[v] = A[(16 * I + (l >> 4) + 4 * v) * LDA + 16 * J + (l & 15)];
+#pragma unroll
+    for (int k4 = 0; k4 < 4; ++k4)
+      c = mfma(-A[(16 * I + (l & 15)) * LDA + c0 + 4 * k4 + (l >> 4)],
+               A[(16 * J + (l & 15)) * LDA + c0 + 4 * k4 + (l >> 4)], c);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) A[(16 * I + (l >> 4) + 4 * v) * LDA + 16 * J + (l & 15)] = c[v];
+  }
+}
+
+// The last workgroup of the fold: factor (with the shifted retry), invert the
+// diagonal blocks, write the factor tiles Mf: tile (J, K), K < J, is L_JK and
+// tile (J, J) is W_J = L_JJ^{-1}, each 16 x 16 row-major.
+__device__ void factor(const double *G, int ell, int64_t rows, double *Mf, int *dflags, double *pool) {
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  const int nb = (ell + 15) / 16, ellp = 16 * nb, ntile = nb * (nb + 1) / 2;
+  double *A = pool, *colb = A + EMAX * LDA, *dinv = colb + 64, *word = dinv + EMAX;
+  load_gram(G, ell, nb, 0.0, A);
+  __syncthreads();
+  if (w == 0) {
+    double v = 0.0;
+    for (int i = l; i < ell; i += 64) v += A[i * LDA + i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (l == 0) word[0] = v;
+  }
+  __syncthreads();
+  const double tr = word[0];
+  const bool trok = tr > 0.0 && isfinite(tr);
+  bool ok = false;
+#pragma nounroll
+  for (int attempt = 0; attempt < 2 && trok && !ok; ++attempt) {
+    if (attempt) {
+      load_gram(G, ell, nb, 11.0 * ((double)rows * ell + (double)ell * (ell + 1)) * U64 * tr, A);
+      __syncthreads();
+    }
+    bool okw = true;
+    for (int K = 0; K < nb; ++K) {
+      if (w == 0) okw = panel(A, K, ell, ellp, 1e-15 * tr, colb, dinv) && okw;
+      __syncthreads();
+      trailing(A, K, nb);
+      __syncthreads();
+    }
+    if (t == 0) word[1] = okw ? 1.0 : 0.0;
+    __syncthreads();
+    ok = word[1] != 0.0;
+    if (!ok && attempt == 0 && t == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_FALLBACK);
+    __syncthreads();
+  }
+  if (!ok) {
+    // non-finite or zero input: identity factor keeps the pipeline finite
+    if (t == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_FALLBACK | DSK_FLAG_RANK_DEFICIENT | DSK_FLAG_NONFINITE);
+    for (int e = t; e < ntile * TILE; e += 256) {
+      int I, J;
+      tile_ij(e >> 8, I, J);
+      Mf[e] = (I == J && ((e >> 4) & 15) == (e & 15)) ? 1.0 : 0.0;
+    }
+    return;
+  }
+  // W_K = L_KK^{-1} (lower): wave K mod 4, lane j < 16 forms column j
+  for (int K = w; K < nb; K += 4) {
+    if (l < 16) {
+      const int j = l;
+      const double *Lk = A + 16 * K * LDA + 16 * K;
+      double x[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        double s = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+        for (int c = 0; c < i; ++c) s = fma(-Lk[i * LDA + c], x[c], s);
+        x[i] = (i >= j) ? s * dinv[16 * K + i] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) Mf[ltile(K, K) * TILE + i * 16 + j] = x[i];
+    }
+  }
+  for (int e = t; e < ntile * TILE; e += 256) {
+    int J, K;
+    tile_ij(e >> 8, J, K);
+    if (K < J) Mf[e] = A[(16 * J + ((e >> 4) & 15)) * LDA + 16 * K + (e & 15)];
+  }
+}
+
+// ---------------------------------------------------------------- launches
+// G = sum of the P partials (fixed order); the last workgroup factors G.
+// cond = 1: only after a shifted first pass.
+__global__ void __launch_bounds__(256) k_q8_fold_factor(const double *__restrict__ part, int P, int ell,
+                                                        int64_t rows, double *G, double *__restrict__ Mf,
+                                                        unsigned *ticket, int *dflags, int cond) {
+  if (cond && !(dflags[FLAGW_BITS] & DSK_FLAG_FALLBACK)) return;
+  extern __shared__ double pool[];
+  __shared__ double red[4][FE];
+  const int nb = (ell + 15) / 16, ne = nb * (nb + 1) / 2 * TILE;
+  const int t = threadIdx.x, q = t >> 6, el = t & 63;
+  const int e = blockIdx.x * FE + el;
+  double s = 0.0;
+  if (e < ne) {
+    for (int p0 = q; p0 < P; p0 += 64) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int p = p0 + 4 * u;
+        v[u] = p < P ? part[(int64_t)p * ne + e] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s += v[u];
+    }
+  }
+  red[q][el] = s;
+  __syncthreads();
+  if (q == 0 && e < ne) ds::st_dev(&G[e], (red[0][el] + red[1][el]) + (red[2][el] + red[3][el]));
+  if (ds::last_arrival(ticket)) factor(G, ell, rows, Mf, dflags, pool);
+}
+
+// Q = Y L^{-T} for the rows of this workgroup (Q may alias Y: each wave reads
+// its rows before it writes them).  With part, also the Gram partial of the
+// rounded Q.  cond = 1: only after a shifted pass; gram_cond = 1: the Gram
+// only after a shifted pass.
+template <typename T>
+__global__ void __launch_bounds__(256) k_q8_apply(const T *Y, int64_t rows, int ell, const double *__restrict__ Mf,
+                                                  T *Q, int64_t rpw, double *__restrict__ part, int *dflags,
+                                                  int cond, int gram_cond) {
+  const bool fallback = (dflags[FLAGW_BITS] & DSK_FLAG_FALLBACK) != 0;
+  if (cond && !fallback) return;
+  if (gram_cond && !fallback) part = nullptr;
+  extern __shared__ double pool[];
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  const int nb = (ell + 15) / 16, ellp = 16 * nb, ntile = nb * (nb + 1) / 2;
+  double *Ms = pool, *YQ = Ms + NTM * MST, *Sw = YQ + RCH * LDQ + w * MST;
+  for (int e = t; e < ntile * TILE; e += 256) Ms[(e >> 8) * MST + ((e >> 4) & 15) * 17 + (e & 15)] = Mf[e];
+  __syncthreads();
+  const gt::Tiles tl = gt::tiles_of(w, nb);
+  d4 acc[gt::MAXT];
+  gt::zero(acc);
+  const int i16 = l & 15, kk = l >> 4, rb = 16 * w;
+  const int64_t r0 = (int64_t)blockIdx.x * rpw, r1 = std::min<int64_t>(rows, r0 + rpw);
+  for (int64_t c0 = r0; c0 < r1; c0 += RCH) {
+    // this wave's 16 rows, FP64, zero padded
+    for (int e = l; e < 16 * ellp; e += 64) {
+      const int rr = e / ellp, c = e - rr * ellp;
+      const int64_t r = c0 + rb + rr;
+      YQ[(rb + rr) * LDQ + c] = (r < r1 && c < ell) ? (double)Y[r * ell + c] : 0.0;
+    }
+    wc::wave_lds_sync();
+    for (int J = 0; J < nb; ++J) {
+      // S = Y_J - sum_{K<J} Q_K L_JK^T: one accumulator per K (independent MFMA chains), summed in K order
+      d4 c, ck[NBM - 1];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) c[v] = YQ[(rb + kk + 4 * v) * LDQ + 16 * J + i16];
+#pragma unroll
+      for (int K = 0; K < NBM - 1; ++K) ck[K] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k4 = 0; k4 < 4; ++k4)
+#pragma unroll
+        for (int K = 0; K < NBM - 1; ++K)
+          if (K < J)
+            ck[K] = mfma(-YQ[(rb + i16) * LDQ + 16 * K + 4 * k4 + kk], Ms[ltile(J, K) * MST + i16 * 17 + 4 * k4 + kk],
+                         ck[K]);
+#pragma unroll
+      for (int K = 0; K < NBM - 1; ++K)
+        if (K < J) c += ck[K];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Sw[(kk + 4 * v) * 17 + i16] = c[v];
+      wc::wave_lds_sync();
+      const double *Wt = Ms + ltile(J, J) * MST;
+      d4 qv = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k4 = 0; k4 < 4; ++k4) qv = mfma(Sw[i16 * 17 + 4 * k4 + kk], Wt[i16 * 17 + 4 * k4 + kk], qv);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) YQ[(rb + kk + 4 * v) * LDQ + 16 * J + i16] = qv[v];
+      wc::wave_lds_sync();
+    }
+    // round this wave's rows to the output type (the Gram describes the stored Q)
+    for (int e = l; e < 16 * ellp; e += 64) {
+      const int rr = e / ellp, c = e - rr * ellp;
+      const int64_t r = c0 + rb + rr;
+      double *p = &YQ[(rb + rr) * LDQ + c];
+      const T v = (T)(*p);
+      *p = (double)v;
+      if (r < r1 && c < ell) Q[r * ell + c] = v;
+    }
+    if (part) {
+      __syncthreads();
+      gt::accum<RCH / 4>(YQ, LDQ, tl, acc);
+      __syncthreads();
+    } else {
+      wc::wave_lds_sync();
+    }
+  }
+  if (part) gt::store_tiles(acc, tl, w, part + (int64_t)blockIdx.x * ntile * TILE);
+}
+
+int pick_parts(int64_t rows, int64_t unit, int64_t &rpw) {
+  rpw = unit;
+  if ((rows + rpw - 1) / rpw > PMAX) rpw = ((rows + PMAX - 1) / PMAX + unit - 1) / unit * unit;
+  return (int)((rows + rpw - 1) / rpw);
+}
+
+template <typename T>
+int cholqr128_typed(hipStream_t st, const T *Y, int64_t rows, int ell, T *Q, void *ws, int *dflags, int passes) {
+  double *part = reinterpret_cast<double *>(ws);
+  double *G = part + (size_t)PMAX * PART;
+  double *Mf = G + PART;
+  T *Q1 = reinterpret_cast<T *>(Mf + PART);
+  unsigned *ticket = reinterpret_cast<unsigned *>(dflags + FLAGW_TICKET);
+  const int nb = (ell + 15) / 16;
+  const int nfold = (nb * (nb + 1) / 2 * TILE + FE - 1) / FE;
+  const size_t flds = (size_t)FACT_LDS * sizeof(double), alds = (size_t)APPLY_LDS * sizeof(double);
+  allow_lds(k_q8_fold_factor, flds);
+  allow_lds(k_q8_apply<T>, alds);
+  int64_t grpb, arpw;
+  const int gparts = pick_parts(rows, GRPB, grpb);
+  const int aparts = pick_parts(rows, RCH, arpw);
+  DSK_RET(launch_gram_tiles(st, Y, sizeof(T) == 8, rows, ell, grpb, part));
+  auto fold = [&](int P, int cond) {
+    hipLaunchKernelGGL(k_q8_fold_factor, dim3(nfold), dim3(256), flds, st, (const double *)part, P, ell, rows, G, Mf,
+                       ticket, dflags, cond);
+  };
+  auto apply = [&](const T *src, T *dst, double *prt, int cond, int gcond) {
+    hipLaunchKernelGGL(k_q8_apply<T>, dim3(aparts), dim3(256), alds, st, src, rows, ell, (const double *)Mf, dst,
+                       arpw, prt, dflags, cond, gcond);
+  };
+  fold(gparts, 0);
+  if (passes == 1) {
+    apply(Y, Q, nullptr, 0, 0);   // span only
+  } else {
+    apply(Y, Q1, part, 0, 0);     // second factorization
+    fold(aparts, 0);
+    apply(Q1, Q, part, 0, 1);     // third factorization only after a shifted first pass
+    fold(aparts, 1);
+    apply(Q, Q, nullptr, 1, 0);   // third application only after a shifted first pass
+  }
+  DSK_TRY(hipGetLastError());
+  return 0;
+}
+
+}  // namespace
+
+size_t cholqr128_ws_bytes(int64_t rows, int ell) {
+  (void)ell;
+  return ((size_t)PMAX * PART + 2 * (size_t)PART) * sizeof(double) + (size_t)rows * EMAX * sizeof(double) + 256;
+}
+
+int launch_cholqr128(hipStream_t st, const void *Y, int f64, int64_t rows, int ell, void *Q, void *ws, int *dflags,
+                     int passes) {
+  if (ell < 1 || ell > EMAX || rows < 1 || passes < 1 || passes > 2) return -1;
+  if (f64) return cholqr128_typed<double>(st, (const double *)Y, rows, ell, (double *)Q, ws, dflags, passes);
+  return cholqr128_typed<float>(st, (const float *)Y, rows, ell, (float *)Q, ws, dflags, passes);
+}

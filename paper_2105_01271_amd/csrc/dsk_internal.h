@@ -152,6 +152,11 @@ int launch_cholqr64(hipStream_t st, const void *Y, int f64, int64_t rows, int el
 // the last launch_cholqr64 on ws computed (with passes = 1: Y^T Y = L L^T)
 int launch_cholqr64_apply(hipStream_t st, const void *X, int f64, int64_t rows, int ell, const void *ws, void *out,
                           int *dflags);
+// 64 < ell <= 128 (cholqr128.hip): the same contract, Gram partials + fold/factor
+// + blocked-substitution apply per pass.
+size_t cholqr128_ws_bytes(int64_t rows, int ell);
+int launch_cholqr128(hipStream_t st, const void *Y, int f64, int64_t rows, int ell, void *Q, void *ws, int *dflags,
+                     int passes);
 // passes = 2: CholeskyQR2 (orthonormal to working precision); passes = 1: one
 // CholeskyQR pass, an orthonormal-up-to-kappa^2 u basis of span(Y) (enough
 // where only the span is used, as in the intermediate power steps).
@@ -160,6 +165,16 @@ int launch_cholqr2(hipStream_t st, const void *Y, int f64, int64_t rows, int ell
 int launch_hhqr(hipStream_t st, double *X, int64_t rows, int ell, double *Q, double *R, int *dflags);
 int launch_gram(hipStream_t st, const void *X, int f64, int64_t rows, int ell, double *G,
                 double *part, int nparts);
+// gram64.hip: the same on the FP64 matrix cores (ell <= 128), at most
+// gram_mfma_blocks(rows) <= nparts partials
+int gram_mfma_blocks(int64_t rows);
+int launch_gram_mfma(hipStream_t st, const void *X, int f64, int64_t rows, int ell, double *G, double *part,
+                     int nparts);
+// tile-major lower-tile partials (16 x 16 tiles numbered I (I + 1) / 2 + J), one per
+// rows_per_blk rows (a multiple of 32): ceil(rows / rows_per_blk) partials of
+// nb (nb + 1) / 2 * 256 doubles each, nb = ceil(ell / 16)
+int launch_gram_tiles(hipStream_t st, const void *X, int f64, int64_t rows, int ell, int64_t rows_per_blk,
+                      double *part);
 // refine.hip: FP64 re-orthonormalisation of the assembled FP32 factors (U0 m x k,
 // V0 n x k, S k) into U, V, S with U S V^T unchanged (k <= 100); ws: refine_ws_bytes(k)
 size_t refine_ws_bytes(int k);

@@ -3,13 +3,13 @@
 // (ell <= 112), whose eigenvalues are sigma_j^2 and whose eigenvectors are the
 // left singular vectors U_B of B.
 //
-//   1. Householder tridiagonalisation Q^T G Q = T (G in LDS, one workgroup):
-//      step j reflects column j below the diagonal, p = tau A v (symmetric
-//      product), w = p - (tau/2)(p.v) v, A -= v w^T + w v^T.
+//   1. Householder tridiagonalisation Q^T G Q = T (G in LDS, one workgroup of
+//      four waves): step j reflects column j below the diagonal, p = tau A v
+//      (symmetric product), w = p - (tau/2)(p.v) v, A -= v w^T + w v^T.
 //   2. Eigenvalues of T by multisection: every eigenvalue index owns a group
 //      of threads, each round evaluates Sturm counts (the signs of the LDL^T
-//      pivots of T - x I) at the group's interior points and keeps the
-//      sub-interval that holds the index.
+//      pivots of T - x I) at the group's interior points (four per thread,
+//      interleaved) and keeps the sub-interval that holds the index.
 //   3. Eigenvectors of T by the twisted factorisation at each eigenvalue:
 //      T - lambda I = N_r Delta_r N_r^T with the twist index r where |gamma_r|
 //      is smallest; z_r = 1 and the two bidiagonal solves give z.  Vectors of
@@ -33,8 +33,9 @@
 
 namespace {
 
-constexpr int TNT = 1024;          // threads of the reduction / eigenvalue kernel
+constexpr int TNT = 256;           // threads of the reduction / eigenvalue kernel (one wave per SIMD)
 constexpr int TMAX = 112;          // largest ell
+constexpr int NPT = 4;             // Sturm counts per thread and multisection round
 constexpr double TU = 1.1102230246251565e-16;
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -43,19 +44,34 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Number of eigenvalues of T (diagonal d, squared off-diagonal e2) below x:
-// the negative pivots of the LDL^T factorisation of T - x I, a pivot of
-// magnitude below pivmin replaced by -pivmin.
-__device__ __forceinline__ int sturm_count(const double *d, const double *e2, int n, double x, double pivmin) {
-  double q = d[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  int c = q < 0.0 ? 1 : 0;
-  for (int i = 1; i < n; ++i) {
-    q = (d[i] - x) - e2[i - 1] * wc::rcp_nr(q);
-    if (fabs(q) < pivmin) q = -pivmin;
-    c += q < 0.0 ? 1 : 0;
+// Numbers of eigenvalues of T (diagonal d, squared off-diagonal e2) below
+// each of P shifts x[u]: the negative pivots of the LDL^T factorisation of
+// T - x I, a pivot of magnitude below pivmin replaced by -pivmin.  The P
+// recurrences are interleaved so that their latencies overlap.
+template <int P>
+__device__ __forceinline__ void sturm_counts(const double *d, const double *e2, int n, const double *x,
+                                             double pivmin, int *c) {
+  double q[P];
+#pragma unroll
+  for (int u = 0; u < P; ++u) {
+    q[u] = d[0] - x[u];
+    if (fabs(q[u]) < pivmin) q[u] = -pivmin;
+    c[u] = q[u] < 0.0 ? 1 : 0;
   }
-  return c;
+  for (int i = 1; i < n; ++i) {
+    const double di = d[i], ei = e2[i - 1];
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      q[u] = (di - x[u]) - ei * wc::rcp_nr(q[u]);
+      if (fabs(q[u]) < pivmin) q[u] = -pivmin;
+      c[u] += q[u] < 0.0 ? 1 : 0;
+    }
+  }
+}
+
+// Point s (0 .. np - 1) of the np interior points of [a, b]; increasing in s.
+__device__ __forceinline__ double msec_point(double a, double b, int s, int np) {
+  return a + (b - a) * (double)(s + 1) / (double)(np + 1);
 }
 
 // LDS (dynamic): A [ell][ell + 1] (the matrix, later Z), then small arrays.
@@ -66,8 +82,9 @@ __global__ void __launch_bounds__(TNT) k_tri_eig(const double *__restrict__ G, i
   extern __shared__ double dyn[];
   const int n = ell, ld = ell + 1;
   double *A = dyn;                          // n x ld
-  __shared__ double d[TMAX], e[TMAX], e2[TMAX], tau[TMAX], pv[TMAX], lo_sh[TMAX], hi_sh[TMAX], lamu[TMAX];
-  __shared__ int cnt_sh[TNT];
+  __shared__ double d[TMAX], e[TMAX], e2[TMAX], tau[TMAX], vv[TMAX], lo_sh[TMAX], hi_sh[TMAX], lamu[TMAX];
+  __shared__ double pp[2][128];
+  __shared__ int cnt_sh[TNT * NPT];
   __shared__ double red[TNT / 64];
   __shared__ double bcast[4];
   __shared__ int clus_sh;
@@ -82,71 +99,63 @@ __global__ void __launch_bounds__(TNT) k_tri_eig(const double *__restrict__ G, i
   if (t == 0) bad_sh = 0;
   __syncthreads();
 
-  // ---- 1. tridiagonalisation
+  // ---- 1. tridiagonalisation, three barriers per column: wave 0 forms the
+  // reflector; p = tau A' v by columns (A' = A[j+1:, j+1:] is symmetric), two
+  // row halves per column; every wave forms K = (tau/2) p.v itself, then
+  // A' -= v w^T + w v^T with w = p - K v.  A thread owns one column of A' and
+  // every other row, so its LDS accesses run along rows (v_r, w_r broadcast).
+  const int cc = t & 127, hh = t >> 7;
   for (int j = 0; j + 2 < n; ++j) {
-    const int L = n - j - 1;                       // length of x = A[j+1:, j]
+    const int L = n - j - 1, o = j + 1;          // x = A[o:, j], length L
     if (wave == 0) {
       double s2 = 0.0;
       for (int i = 1 + lane; i < L; i += 64) {
-        const double v = A[(j + 1 + i) * ld + j];
+        const double v = A[(o + i) * ld + j];
         s2 = fma(v, v, s2);
       }
       s2 = wave_sum(s2);
+      const double alpha = A[o * ld + j];
+      double beta, tj, scale;
+      if (s2 == 0.0) {
+        beta = alpha;
+        tj = 0.0;
+        scale = 0.0;
+      } else {
+        beta = -copysign(sqrt(fma(alpha, alpha, s2)), alpha);
+        tj = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      for (int i = 1 + lane; i < L; i += 64) {
+        const double v = A[(o + i) * ld + j] * scale;
+        A[(o + i) * ld + j] = v;
+        vv[i] = v;
+      }
+      wc::wave_lds_sync();                         // every lane has read alpha
       if (lane == 0) {
-        const double alpha = A[(j + 1) * ld + j];
-        double beta, tj, scale;
-        if (s2 == 0.0) {
-          beta = alpha;
-          tj = 0.0;
-          scale = 0.0;
-        } else {
-          beta = -copysign(sqrt(fma(alpha, alpha, s2)), alpha);
-          tj = (beta - alpha) / beta;
-          scale = 1.0 / (alpha - beta);
-        }
+        A[o * ld + j] = 1.0;                       // v_0 (e[j] keeps the subdiagonal)
+        vv[0] = 1.0;
         tau[j] = tj;
         e[j] = beta;
-        bcast[0] = scale;
       }
-    }
-    __syncthreads();
-    {
-      const double scale = bcast[0];
-      for (int i = 1 + t; i < L; i += TNT) A[(j + 1 + i) * ld + j] *= scale;
-      if (t == 0) A[(j + 1) * ld + j] = 1.0;       // v_0 (e[j] keeps the subdiagonal)
     }
     __syncthreads();
     const double tj = tau[j];
-    // p = tau A' v, A' = A[j+1:, j+1:]: 8 threads per row
-    {
-      const int r = t >> 3, g = t & 7;
+    if (cc < L) {
       double a = 0.0;
-      if (r < L) {
-        const double *row = &A[(j + 1 + r) * ld + j + 1];
-        for (int c = g; c < L; c += 8) a = fma(row[c], A[(j + 1 + c) * ld + j], a);
-      }
-      a += wc::dpp_f64<0xB1>(a);
-      a += wc::dpp_f64<0x4E>(a);
-      a += wc::dpp_f64<0x141>(a);
-      if (r < L && g == 0) pv[r] = tj * a;
+      for (int r = hh; r < L; r += 2) a = fma(A[(o + r) * ld + o + cc], vv[r], a);
+      pp[hh][cc] = a;
     }
     __syncthreads();
-    // K = (tau / 2) (p . v)
-    if (wave == 0) {
-      double s = 0.0;
-      for (int i = lane; i < L; i += 64) s = fma(pv[i], A[(j + 1 + i) * ld + j], s);
-      s = wave_sum(s);
-      if (lane == 0) bcast[1] = 0.5 * tj * s;
-    }
-    __syncthreads();
-    // A' -= v w^T + w v^T, w = p - K v
-    {
-      const double K = bcast[1];
-      for (int x = t; x < L * L; x += TNT) {
-        const int r = x / L, c = x - (x / L) * L;
-        const double vr = A[(j + 1 + r) * ld + j], vc = A[(j + 1 + c) * ld + j];
-        const double wr = fma(-K, vr, pv[r]), wc2 = fma(-K, vc, pv[c]);
-        A[(j + 1 + r) * ld + j + 1 + c] -= fma(vr, wc2, wr * vc);
+    double sk = 0.0;
+    for (int i = lane; i < L; i += 64) sk = fma(tj * (pp[0][i] + pp[1][i]), vv[i], sk);
+    const double K = 0.5 * tj * wave_sum(sk);
+    if (cc < L) {
+      const double vc = vv[cc];
+      const double wcc = fma(-K, vc, tj * (pp[0][cc] + pp[1][cc]));
+      for (int r = hh; r < L; r += 2) {
+        const double vr = vv[r];
+        const double wr = fma(-K, vr, tj * (pp[0][r] + pp[1][r]));
+        A[(o + r) * ld + o + cc] -= fma(vr, wcc, wr * vc);
       }
     }
     __syncthreads();
@@ -189,10 +198,11 @@ __global__ void __launch_bounds__(TNT) k_tri_eig(const double *__restrict__ G, i
     lo_sh[t] = bcast[0];
     hi_sh[t] = bcast[1];
   }
-  const int ns = TNT / n;                         // threads per eigenvalue (>= 9)
+  const int ns = TNT / n;                         // threads per eigenvalue (>= 2)
+  const int np = ns * NPT;                        // points per eigenvalue and round
   const int ei = t / ns, si = t - (t / ns) * ns;
   int rounds = 0;
-  for (; rounds < 64; ++rounds) {
+  for (; rounds < 128; ++rounds) {
     __syncthreads();
     if (t == 0) clus_sh = 0;
     __syncthreads();
@@ -205,16 +215,21 @@ __global__ void __launch_bounds__(TNT) k_tri_eig(const double *__restrict__ G, i
     __syncthreads();
     if (!clus_sh) break;
     if (ei < n) {
-      const double x = a + (b - a) * (double)(si + 1) / (double)(ns + 1);
-      cnt_sh[t] = sturm_count(d, e2, n, x, pivmin);
+      double xs[NPT];
+      int cs[NPT];
+#pragma unroll
+      for (int u = 0; u < NPT; ++u) xs[u] = msec_point(a, b, si * NPT + u, np);
+      sturm_counts<NPT>(d, e2, n, xs, pivmin, cs);
+#pragma unroll
+      for (int u = 0; u < NPT; ++u) cnt_sh[t * NPT + u] = cs[u];
     }
     __syncthreads();
     if (ei < n && si == 0) {
       // points x_s increase with s; keep [last x with count <= ei, first x with count > ei]
       double na = a, nb = b;
-      for (int s = 0; s < ns; ++s) {
-        const double x = a + (b - a) * (double)(s + 1) / (double)(ns + 1);
-        if (cnt_sh[ei * ns + s] <= ei) na = x;
+      for (int s = 0; s < np; ++s) {
+        const double x = msec_point(a, b, s, np);
+        if (cnt_sh[ei * np + s] <= ei) na = x;
         else { nb = x; break; }
       }
       lo_sh[ei] = na;
@@ -337,9 +352,11 @@ __global__ void __launch_bounds__(512) k_tri_back(const double *__restrict__ Vt,
                                                   const double *__restrict__ Zg, int ell, const int *__restrict__ fail,
                                                   double *__restrict__ U) {
   extern __shared__ double vlds[];         // Vt, ell x ell
+  __shared__ double tls[TMAX];
   if (*fail) return;                       // the gated Jacobi core writes U
   const int n = ell, t = threadIdx.x;
   for (int x = t; x < n * n; x += 512) vlds[x] = Vt[x];
+  if (t < n) tls[t] = taus[t];
   __syncthreads();
   const int c = t >> 2, g = t & 3;
   const bool act = c < n;
@@ -350,7 +367,7 @@ __global__ void __launch_bounds__(512) k_tri_back(const double *__restrict__ Vt,
     z[u] = (act && r < n) ? Zg[r * n + c] : 0.0;
   }
   for (int j = n - 3; j >= 0; --j) {
-    const double tj = taus[j];
+    const double tj = tls[j];
     const double *v = &vlds[j * n];
     double w = 0.0;
 #pragma unroll

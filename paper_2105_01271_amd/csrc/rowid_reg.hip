@@ -25,12 +25,14 @@
 // unit (the rows of a workgroup fill its registers), all resident at once.
 // Thread t holds entries t + NT u (u < EPT) of each of its workgroup's rows.
 // Each step has one exchange: a workgroup stores the norms of its rows and
-// its coefficient column (into R), then one packed word (pivot rank, index,
-// step); once every word of the step is seen, the pivot's norm and
-// coefficients are read back from where its owner stored them.  Exchanges use
-// device-coherent relaxed atomic stores and loads, a writer's data stores
-// complete before its word (devsync.h), and the buffers alternate by step
-// parity (a workgroup is at most one step ahead of any other).  Every wait is
+// its coefficient column (into R), then its word (step in the top bits, then
+// pivot rank, then the inverted index) in its own slot; thread g of every
+// workgroup waits for slot g to carry the step and the maximum over the slots
+// names the pivot, whose norm and coefficients are read back from where its
+// owner stored them.  Exchanges use device-coherent relaxed atomic stores and
+// loads, a writer's data stores complete before its word (devsync.h), and the
+// slots alternate by step parity (a workgroup is at most one step ahead of any
+// other).  Every wait is
 // bounded: past the bound the workgroup raises DSK_FLAG_SYNC_TIMEOUT and sets
 // the abort word, every workgroup leaves, and the one-workgroup kernel after
 // it (k_rowid_rescue: right-looking Gram-Schmidt with norms recomputed from the
@@ -43,8 +45,6 @@
 
 namespace {
 
-constexpr int NT = 512;
-constexpr int NW = NT / 64;
 constexpr int KMAX = 112;
 constexpr int TAGW = 32;                   // one word per 256-byte line
 constexpr long long SPIN_LIMIT = 1LL << 22;
@@ -62,23 +62,25 @@ __device__ __forceinline__ unsigned long long nu_rank(double v) {
   return (v >= 0.0) ? (bits >> 18) + 1ull : 0ull;
 }
 
-// rank in bits 18.., inverted index (11 bits) in 7..17, step marker in 0..6:
-// the maximum over words is the pivot (largest rank, then lowest index)
-__device__ __forceinline__ unsigned long long pack_word(unsigned long long rank, long long idx, int marker) {
-  return (rank << 18) | ((unsigned long long)(~idx & 0x7FF) << 7) | (unsigned long long)(marker & 0x7F);
+// step (7 bits) at 57.., pivot rank (46 bits) at 11.., inverted index (11 bits)
+// at 0..10: the maximum over a step's words is its pivot (largest rank, then
+// lowest index), and any word of a later step exceeds every word of this one
+__device__ __forceinline__ unsigned long long pack_word(int step, unsigned long long rank, long long idx) {
+  return ((unsigned long long)step << 57) | (rank << 11) | (unsigned long long)(~idx & 0x7FF);
 }
 
-__device__ __forceinline__ bool wait_word(const unsigned long long *wp, int marker, int *abort_flag,
+// bounded wait for slot wp to carry step `step`; false on timeout or abort
+__device__ __forceinline__ bool wait_word(const unsigned long long *wp, int step, int *abort_flag,
                                           unsigned long long &word) {
   long long spins = 0;
   for (;;) {
     word = (unsigned long long)ds::ld_dev(reinterpret_cast<const long long *>(wp));
-    if ((int)(word & 0x7F) == (marker & 0x7F)) break;
+    if ((int)(word >> 57) == step) break;
     if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || ++spins > SPIN_LIMIT) {
       atomicOr(abort_flag, 1);
       return false;
     }
-    __builtin_amdgcn_s_sleep(2);
+    __builtin_amdgcn_s_sleep(1);
   }
   ds::after_flag();
   return true;
@@ -89,7 +91,7 @@ __device__ __forceinline__ double to_f64(T v) { return (double)v; }
 
 // Sum over the workgroup of v[r] for each r < R (wave sums, then waves in a
 // fixed order); the totals land in out[r].  Called by all threads.
-template <int R>
+template <int NW, int R>
 __device__ __forceinline__ void block_sums(double (&v)[R], double (*red)[R], double *out) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
 #pragma unroll
@@ -106,24 +108,25 @@ __device__ __forceinline__ void block_sums(double (&v)[R], double (*red)[R], dou
   __syncthreads();
 }
 
-template <typename T, int RPW, int EPT>
+template <typename T, int NT, int RPW, int EPT>
 __global__ void __launch_bounds__(NT) k_rowid_reg(const T *__restrict__ W, int64_t m, int64_t s, int k,
-                                                  unsigned long long *words, double *nuG, int *abort_flag,
-                                                  double *__restrict__ nu_final, double *Rk,
+                                                  unsigned long long *words, double *nuG, int *abort_flag, double *__restrict__ nu_final, double *Rk,
                                                   int64_t *__restrict__ piv, int *__restrict__ dflags) {
+  constexpr int NW = NT / 64;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int G = gridDim.x, gid = blockIdx.x;
   __shared__ double red[NW][RPW];
+  __shared__ unsigned long long bk[NW];
   __shared__ double num[RPW];
   __shared__ double nu_sh[RPW];
   __shared__ int live_sh[RPW];
   __shared__ double cl[RPW][KMAX];     // c_{i,l} of this workgroup's rows
   __shared__ double cp[KMAX];          // c_{p,l} of the pivot
-  __shared__ unsigned long long bk[NW];
   __shared__ unsigned long long key_sh;
   __shared__ double rjj_sh;
   __shared__ double nu_first;
-  __shared__ int stop_sh;
+  __shared__ int stop_sh;   // written by thread 0 before the barrier that precedes every read
+  __shared__ int down_sh;   // likewise, in the pivot phase
 
   const int64_t row0 = (int64_t)gid * RPW;
   T w[RPW][EPT];
@@ -145,13 +148,16 @@ __global__ void __launch_bounds__(NT) k_rowid_reg(const T *__restrict__ W, int64
       for (int u = 0; u < EPT; ++u) a = fma(to_f64(w[r][u]), to_f64(w[r][u]), a);
       v[r] = a;
     }
-    block_sums<RPW>(v, red, nu_sh);
+    block_sums<NW, RPW>(v, red, nu_sh);
   }
   if (t < RPW) {
     live_sh[t] = (row0 + t < m) ? 1 : 0;
     if (live_sh[t] && !isfinite(nu_sh[t])) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_NONFINITE);
   }
-  if (t == 0) stop_sh = 0;
+  if (t == 0) {
+    stop_sh = 0;
+    down_sh = 0;
+  }
   __syncthreads();
 
   for (int j = 0; j < k; ++j) {
@@ -170,9 +176,9 @@ __global__ void __launch_bounds__(NT) k_rowid_reg(const T *__restrict__ W, int64
         if (rk > brank) { brank = rk; bidx = row0 + r; }   // ascending rows: ties keep the lower index
       }
       ds::st_dev(reinterpret_cast<long long *>(&words[((int64_t)par * G + gid) * TAGW]),
-                 (long long)pack_word(brank, bidx, j + 1));
+                 (long long)pack_word(j + 1, brank, bidx));
     }
-    // ---- every word of the step; maximum of (rank, inverted index)
+    // ---- every slot of the step; maximum of (rank, inverted index)
     unsigned long long best = 0;
     for (int g = t; g < G; g += NT) {
       unsigned long long wd;
@@ -180,7 +186,7 @@ __global__ void __launch_bounds__(NT) k_rowid_reg(const T *__restrict__ W, int64
         stop_sh = 1;
         break;
       }
-      best = max(best, wd >> 7);
+      best = max(best, wd);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) best = max(best, (unsigned long long)__shfl_xor((long long)best, o, 64));
@@ -194,23 +200,23 @@ __global__ void __launch_bounds__(NT) k_rowid_reg(const T *__restrict__ W, int64
     __syncthreads();
     if (stop_sh) break;
     const unsigned long long key = key_sh;
-    const int64_t p = (key >> 11) ? (int64_t)(~key & 0x7FF) : m;
+    const int64_t p = ((key >> 11) & ((1ull << 46) - 1)) ? (int64_t)(~key & 0x7FF) : m;
     // ---- the pivot: its norm and coefficients from where its owner stored them, its row from W
     if (t == 0) {
       const double nup = (p < m) ? ds::ld_dev(&nuG[(int64_t)par * m + p]) : 0.0;
       rjj_sh = nup > 0.0 ? sqrt(nup) : 0.0;
       if (j == 0) nu_first = nup;
       // downdated norms no longer resolve 1e-8 pivot gaps: leave to the exact rescue
-      if (nup < DOWNDATE_MIN * nu_first && nup > 0.0) stop_sh = 2;
+      if (nup < DOWNDATE_MIN * nu_first && nup > 0.0) down_sh = 1;
     }
     if (t < j) cp[t] = (p < m) ? ds::ld_dev(&Rk[(int64_t)t * m + p]) : 0.0;
     __syncthreads();
-    if (stop_sh) break;
-    double wp[EPT];
+    if (down_sh) break;
+    T wp[EPT];
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
       const int64_t e = t + (int64_t)NT * u;
-      wp[u] = (p < m && e < s) ? to_f64(W[p * s + e]) : 0.0;
+      wp[u] = (p < m && e < s) ? W[p * s + e] : T(0);
     }
     __syncthreads();
     const double rjj = rjj_sh;
@@ -219,17 +225,23 @@ __global__ void __launch_bounds__(NT) k_rowid_reg(const T *__restrict__ W, int64
       if (p < m) ds::st_dev(&Rk[(int64_t)j * m + p], rjj);
       if (!(rjj > 0.0)) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_RANK_DEFICIENT);
     }
-    // ---- w_i . w_p - sum_{l<j} c_{p,l} c_{i,l} for this workgroup's rows
+    // ---- w_i . w_p - sum_{l<j} c_{p,l} c_{i,l} for this workgroup's rows.  The rows
+    // are marked as rewritten each step so that their FP64 conversions are not
+    // hoisted out of the loop (that would double the registers they take).
+#pragma unroll
+    for (int r = 0; r < RPW; ++r)
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) asm volatile("" : "+v"(w[r][u]));
     double v[RPW];
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
       double a = 0.0;
 #pragma unroll
-      for (int u = 0; u < EPT; ++u) a = fma(to_f64(w[r][u]), wp[u], a);
+      for (int u = 0; u < EPT; ++u) a = fma(to_f64(w[r][u]), to_f64(wp[u]), a);
       if (t < j) a = fma(-cp[t], cl[r][t], a);
       v[r] = a;
     }
-    block_sums<RPW>(v, red, num);
+    block_sums<NW, RPW>(v, red, num);
     if (t < RPW) {
       const int64_t i = row0 + t;
       if (i == p) live_sh[t] = 0;
@@ -243,10 +255,10 @@ __global__ void __launch_bounds__(NT) k_rowid_reg(const T *__restrict__ W, int64
     }
     __syncthreads();
   }
-  if (stop_sh) {
+  if (stop_sh || down_sh) {
     if (t == 0) {
-      atomicOr(&dflags[FLAGW_BITS], stop_sh == 1 ? DSK_FLAG_SYNC_TIMEOUT : DSK_FLAG_FALLBACK);
-      if (stop_sh == 2) atomicOr(abort_flag, 1);
+      atomicOr(&dflags[FLAGW_BITS], stop_sh ? DSK_FLAG_SYNC_TIMEOUT : DSK_FLAG_FALLBACK);
+      if (!stop_sh) atomicOr(abort_flag, 1);
     }
     return;
   }
@@ -328,27 +340,30 @@ __global__ void __launch_bounds__(1024) k_rowid_rescue(const T *__restrict__ W, 
   for (int64_t i = t; i < m; i += 1024) nu_final[i] = nuR[i] >= 0.0 ? nuR[i] : -1.0;
 }
 
-__global__ void k_rowid_reset(unsigned long long *words, int nwords, int *abort_flag, int64_t *piv, int k) {
-  for (int i = threadIdx.x; i < nwords; i += blockDim.x) words[i] = 0;
-  for (int i = threadIdx.x; i < k; i += blockDim.x) piv[i] = -1;
+__global__ void k_rowid_reset(unsigned long long *words, int nslots, int *abort_flag, int64_t *piv, int k) {
+  for (int i = threadIdx.x; i < nslots; i += blockDim.x) words[(int64_t)i * TAGW] = 0;
   if (threadIdx.x == 0) *abort_flag = 0;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) piv[i] = -1;
 }
 
 struct Plan {
-  int rpw, ept, g;
+  int nt, rpw, ept, g;
 };
 
-// Rows per workgroup and entries per thread, or rpw = 0 when the shape does
-// not fit (more than one workgroup per compute unit, rows wider than 16 NT,
-// more than 2048 candidates, or more than 128 registers of row data).
+// Workgroup size, rows per workgroup and entries per thread, or rpw = 0 when
+// the shape does not fit (more than one workgroup per compute unit, rows wider
+// than 8192, more than 2048 candidates, or more than 128 registers of row
+// data per thread).
 Plan plan_of(int64_t m, int64_t s, int k, int esize, int cu_count) {
-  Plan pl{0, 0, 0};
-  if (m < 1 || s < 1 || k < 1 || k > KMAX || m > 2048 || s > 16 * NT) return pl;
-  const int ept = s <= 4 * NT ? 4 : (s <= 8 * NT ? 8 : 16);
+  Plan pl{0, 0, 0, 0};
+  if (m < 1 || s < 1 || k < 1 || k > KMAX || m > 2048 || s > 8192) return pl;
+  const int nt = 512;
+  const int ept = s <= 2048 ? 4 : (s <= 4096 ? 8 : 16);
   for (int rpw : {4, 8}) {
     const int64_t g = (m + rpw - 1) / rpw;
     if (g > cu_count) continue;
     if (rpw * ept * esize / 4 > 128) continue;
+    pl.nt = nt;
     pl.rpw = rpw;
     pl.ept = ept;
     pl.g = (int)g;
@@ -360,19 +375,19 @@ Plan plan_of(int64_t m, int64_t s, int k, int esize, int cu_count) {
 template <typename T>
 int launch_typed(hipStream_t st, const T *W, int64_t m, int64_t s, int k, double *nu_final, double *Rk, int64_t *piv,
                  char *ws, const Plan &pl, int *dflags) {
-  unsigned long long *words = reinterpret_cast<unsigned long long *>(ws);
-  const size_t wbytes = (size_t)2 * pl.g * TAGW * 8;
-  double *nuG = reinterpret_cast<double *>(ws + wbytes);
+  unsigned long long *words = reinterpret_cast<unsigned long long *>(ws);           // 2 G slots, one line each
+  double *nuG = reinterpret_cast<double *>(ws + (size_t)2 * pl.g * TAGW * 8);
   double *nuR = nuG + 2 * m;
   double *Wr = nuR + m;                          // the rescue's FP64 residuals, m x s
   int *abort_flag = reinterpret_cast<int *>(Wr + (size_t)m * s);
-  hipLaunchKernelGGL(k_rowid_reset, dim3(1), dim3(256), 0, st, words, 2 * pl.g * TAGW, abort_flag, piv, k);
+  hipLaunchKernelGGL(k_rowid_reset, dim3(1), dim3(256), 0, st, words, 2 * pl.g, abort_flag, piv, k);
   DSK_TRY(hipGetLastError());
-#define DSK_RREG(R_, E_)                                                                                       \
-  if (pl.rpw == R_ && pl.ept == E_)                                                                            \
-    hipLaunchKernelGGL((k_rowid_reg<T, R_, E_>), dim3(pl.g), dim3(NT), 0, st, W, m, s, k, words, nuG, abort_flag, \
-                       nu_final, Rk, piv, dflags);
-  DSK_RREG(4, 4) DSK_RREG(4, 8) DSK_RREG(4, 16) DSK_RREG(8, 4) DSK_RREG(8, 8) DSK_RREG(8, 16)
+#define DSK_RREG(NT_, R_, E_)                                                                                   \
+  if (pl.nt == NT_ && pl.rpw == R_ && pl.ept == E_)                                                             \
+    hipLaunchKernelGGL((k_rowid_reg<T, NT_, R_, E_>), dim3(pl.g), dim3(NT_), 0, st, W, m, s, k, words, nuG,        \
+                       abort_flag, nu_final, Rk, piv, dflags);
+  DSK_RREG(512, 4, 4) DSK_RREG(512, 8, 4) DSK_RREG(512, 4, 8) DSK_RREG(512, 8, 8) DSK_RREG(512, 4, 16)
+  DSK_RREG(512, 8, 16)
 #undef DSK_RREG
   DSK_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_rowid_rescue<T>, dim3(1), dim3(1024), 0, st, W, m, s, k, abort_flag, Wr, nuR, nu_final, Rk,

@@ -1,11 +1,12 @@
 // Small dense factorizations of the sketch pipeline.
 //
 //  * Orthonormalisation of tall-skinny blocks (the QR steps of Alg. 2 and
-//    Alg. 7): CholeskyQR2 with an FP64 Gram, FP64 Cholesky and FP64 R^{-1}.
-//    If the first Cholesky meets a non-positive or negligible pivot, the same
-//    kernel retries with the shift 11 (rows*ell + ell(ell+1)) u ||Y||_F^2 and
-//    raises DSK_FLAG_FALLBACK; a third (conditional) pass then restores
-//    orthonormality (shifted CholeskyQR3, Fukaya et al. 2020).
+//    Alg. 7): CholeskyQR2 with an FP64 Gram and FP64 Cholesky, dispatched to
+//    cholqr64.hip (ell <= 64) and cholqr128.hip (wider).  If the first
+//    Cholesky meets a non-positive or negligible pivot, it is retried with the
+//    shift 11 (rows*ell + ell(ell+1)) u ||Y||_F^2 and DSK_FLAG_FALLBACK is
+//    raised; a third (conditional) pass then restores orthonormality (shifted
+//    CholeskyQR3, Fukaya et al. 2020).
 //  * Single-workgroup Householder QR with explicit Q (FP64 path, where blocks
 //    may be numerically rank deficient).
 //  * Skinny products out = X M diag(scale) and the sign normalisation of U.
@@ -42,63 +43,11 @@ __device__ double block_sum(double v, double *scratch /* >= NT/64 + 1 */) {
   return scratch[NT / 64];
 }
 
-// ---------------------------------------------------------------- Gram partials
-// Each thread owns up to three 4x4 blocks (bi <= bj) of the ellp x ellp Gram,
-// block ids threadIdx.x, threadIdx.x + 256, threadIdx.x + 512; three separate
-// statically indexed accumulators keep everything in registers.
-struct GramAcc {
-  double a0[16], a1[16], a2[16];
-};
-
-__device__ __forceinline__ void gram_zero(GramAcc &g) {
-#pragma unroll
-  for (int e = 0; e < 16; ++e) { g.a0[e] = 0.0; g.a1[e] = 0.0; g.a2[e] = 0.0; }
-}
-
 __device__ __forceinline__ void pair_of(int pid, int nb, int &bi, int &bj) {
   int r = 0, rem = pid;
   while (rem >= nb - r) { rem -= nb - r; ++r; }
   bi = r;
   bj = r + rem;
-}
-
-__device__ __forceinline__ void gram_chunk_u(const double *sh, int CH, int ellp, int bi, int bj, bool on,
-                                             double (&acc)[16]) {
-  if (!on) return;
-  for (int r = 0; r < CH; ++r) {
-    const double *row = sh + r * ellp;
-    double xs[4], ys[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) { xs[a] = row[4 * bi + a]; ys[a] = row[4 * bj + a]; }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a * 4 + b] = fma(xs[a], ys[b], acc[a * 4 + b]);
-  }
-}
-
-struct GramSlots {
-  int bi[3], bj[3];
-  bool on[3];
-};
-
-__device__ __forceinline__ GramSlots gram_slots(int ellp) {
-  GramSlots s;
-  const int nb = ellp / 4, npairs = nb * (nb + 1) / 2;
-#pragma unroll
-  for (int u = 0; u < 3; ++u) {
-    const int pid = threadIdx.x + 256 * u;
-    s.on[u] = pid < npairs;
-    s.bi[u] = s.bj[u] = 0;
-    if (s.on[u]) pair_of(pid, nb, s.bi[u], s.bj[u]);
-  }
-  return s;
-}
-
-__device__ __forceinline__ void gram_chunk(const double *sh, int CH, int ellp, const GramSlots &s, GramAcc &g) {
-  gram_chunk_u(sh, CH, ellp, s.bi[0], s.bj[0], s.on[0], g.a0);
-  gram_chunk_u(sh, CH, ellp, s.bi[1], s.bj[1], s.on[1], g.a1);
-  gram_chunk_u(sh, CH, ellp, s.bi[2], s.bj[2], s.on[2], g.a2);
 }
 
 __device__ __forceinline__ void gram_store_u(const double (&acc)[16], int bi, int bj, bool on, int ell,
@@ -116,38 +65,7 @@ __device__ __forceinline__ void gram_store_u(const double (&acc)[16], int bi, in
     }
 }
 
-__device__ __forceinline__ void gram_store(const GramAcc &g, const GramSlots &s, int ell, double *part) {
-  gram_store_u(g.a0, s.bi[0], s.bj[0], s.on[0], ell, part);
-  gram_store_u(g.a1, s.bi[1], s.bj[1], s.on[1], ell, part);
-  gram_store_u(g.a2, s.bi[2], s.bj[2], s.on[2], ell, part);
-}
-
 constexpr int GCH = 32;
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_gram_part(const T *__restrict__ X, int64_t rows, int ell, int64_t ldx,
-                                                   int64_t rows_per_blk, double *__restrict__ part,
-                                                   const int *__restrict__ dflags, int cond) {
-  if (cond && !(dflags[FLAGW_BITS] & DSK_FLAG_FALLBACK)) return;
-  __shared__ double sh[GCH * ELL_MAX];
-  const int ellp = (ell + 3) & ~3;
-  const GramSlots slots = gram_slots(ellp);
-  GramAcc g;
-  gram_zero(g);
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
-  const int64_t r1 = std::min<int64_t>(rows, r0 + rows_per_blk);
-  for (int64_t c0 = r0; c0 < r1; c0 += GCH) {
-    for (int e = threadIdx.x; e < GCH * ellp; e += 256) {
-      const int rr = e / ellp, c = e - rr * ellp;
-      const int64_t r = c0 + rr;
-      sh[e] = (r < r1 && c < ell) ? (double)X[r * ldx + c] : 0.0;
-    }
-    __syncthreads();
-    gram_chunk(sh, GCH, ellp, slots, g);
-    __syncthreads();
-  }
-  gram_store(g, slots, ell, part + (int64_t)blockIdx.x * ell * ell);
-}
 
 // Gram partials of a long block (ell <= 64): every thread owns one 4x4 block of
 // the Gram for one of RG = 256 / npairs row groups (rows r = rg mod RG of each
@@ -243,256 +161,6 @@ __global__ void __launch_bounds__(256) k_gram_reduce(const double *__restrict__ 
     double tot = 0.0;
     for (int i = 0; i < 16; ++i) tot += red[i][t];
     G[blockIdx.x * 16 + t] = tot;
-  }
-}
-
-// G (LDS) = sum of the nparts (<= 32) Gram partials, n2 entries each, added in
-// part order.  The partials were just written by other workgroups (other
-// XCDs' L2), so every load is a long round trip: each thread keeps two entries
-// x 16 parts of loads in flight per batch (256-thread workgroup).
-__device__ void sum_parts_lds(const double *__restrict__ part, int nparts, int n2, double *G) {
-  const int t = threadIdx.x;
-  for (int e0 = t; e0 < n2; e0 += 2 * 256) {
-    const int e1 = e0 + 256;
-    double a = 0.0, b = 0.0;
-    for (int p0 = 0; p0 < nparts; p0 += 16) {
-      double va[16], vb[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int p = p0 + u;
-        va[u] = (p < nparts) ? part[(int64_t)p * n2 + e0] : 0.0;
-        vb[u] = (p < nparts && e1 < n2) ? part[(int64_t)p * n2 + e1] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        a += va[u];
-        b += vb[u];
-      }
-    }
-    G[e0] = a;
-    if (e1 < n2) G[e1] = b;
-  }
-}
-
-// ---------------------------------------------------------------- Cholesky + inverse (one block)
-// Sums the Gram partials in a fixed order, factors G = L L^T (retrying once with
-// a shift on breakdown), inverts L in place and writes R = L^T, Rinv = L^{-T}.
-// Thread t works on rows j + 1 + t/4 (+64) and on every 4th column (t % 4).
-// Runs on one 256-thread workgroup; dyn must hold ell*ell + ell doubles.
-__device__ void chol_body(const double *__restrict__ part, int nparts, int ell, int64_t rows,
-                          double *__restrict__ R, double *__restrict__ Rinv, int *__restrict__ dflags,
-                          double *dyn) {
-  double *G = dyn;                 // ell x ell
-  double *tmp = dyn + ell * ell;   // ell
-  __shared__ double red[8];
-  __shared__ int bad;
-  __shared__ double pivinv;
-  const int t = threadIdx.x;
-  const int tr4 = t >> 2, tc4 = t & 3;
-  const int n2 = ell * ell;
-  for (int attempt = 0; attempt < 2; ++attempt) {
-    sum_parts_lds(part, nparts, n2, G);
-    __syncthreads();
-    double trc = 0.0;
-    for (int i = t; i < ell; i += 256) trc += G[i * ell + i];
-    trc = block_sum<256>(trc, red);
-    if (attempt == 1) {
-      const double shift = 11.0 * ((double)rows * ell + (double)ell * (ell + 1)) * U64 * trc;
-      for (int i = t; i < ell; i += 256) G[i * ell + i] += shift;
-    }
-    if (t == 0) bad = !(trc > 0.0) || !isfinite(trc);
-    __syncthreads();
-    const double thr = 1e-15 * trc;
-    for (int j = 0; j < ell; ++j) {
-      if (t == 0 && !bad) {
-        const double d = G[j * ell + j];
-        if (!(d > thr) || !isfinite(d)) {
-          bad = 1;
-        } else {
-          G[j * ell + j] = sqrt(d);
-          pivinv = 1.0 / d;
-        }
-      }
-      __syncthreads();
-      if (bad) break;
-      // scale the column of the previous step (no thread reads it in this step)
-      if (j > 0) {
-        const double inv_prev = 1.0 / G[(j - 1) * ell + (j - 1)];
-        for (int i = j + t; i < ell; i += 256) G[i * ell + (j - 1)] *= inv_prev;
-      }
-      // trailing update with the unscaled column j: G_ic -= G_ij G_cj / d
-      const double pinv = pivinv;
-      for (int i = j + 1 + tr4; i < ell; i += 64) {
-        const double gij = G[i * ell + j] * pinv;
-        for (int c = j + 1 + tc4; c <= i; c += 4) G[i * ell + c] -= gij * G[c * ell + j];
-      }
-      __syncthreads();
-    }
-    if (!bad) break;   // (the last column has nothing below its diagonal to scale)
-    if (t == 0) atomicOr(&dflags[FLAGW_BITS], attempt == 0 ? DSK_FLAG_FALLBACK : DSK_FLAG_RANK_DEFICIENT);
-    __syncthreads();
-    if (attempt == 1) {
-      // still failing (non-finite input): identity factors keep the pipeline finite
-      for (int i = t >> 6; i < ell; i += 4)
-        for (int c = t & 63; c < ell; c += 64) {
-          R[i * ell + c] = (i == c) ? 1.0 : 0.0;
-          Rinv[i * ell + c] = (i == c) ? 1.0 : 0.0;
-        }
-      if (t == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_NONFINITE);
-      return;
-    }
-    if (t == 0) bad = 0;
-    __syncthreads();
-  }
-  // R = L^T
-  for (int i = t >> 6; i < ell; i += 4)
-    for (int c = t & 63; c < ell; c += 64) R[i * ell + c] = (c >= i) ? G[c * ell + i] : 0.0;
-  __syncthreads();
-  // in-place inverse of the lower-triangular L, column j from the inverted trailing block
-  for (int j = ell - 1; j >= 0; --j) {
-    if (t == 0) G[j * ell + j] = 1.0 / G[j * ell + j];
-    for (int i = j + 1 + t; i < ell; i += 256) tmp[i] = G[i * ell + j];
-    __syncthreads();
-    const double ajj = -G[j * ell + j];
-    for (int ib = j + 1; ib < ell; ib += 64) {
-      const int i = ib + tr4;
-      double s = 0.0;
-      if (i < ell)
-        for (int c = j + 1 + tc4; c <= i; c += 4) s += G[i * ell + c] * tmp[c];
-      s += __shfl_xor(s, 1, 4);
-      s += __shfl_xor(s, 2, 4);
-      if (i < ell && tc4 == 0) G[i * ell + j] = ajj * s;
-    }
-    __syncthreads();
-  }
-  for (int i = t >> 6; i < ell; i += 4)
-    for (int c = t & 63; c < ell; c += 64) Rinv[i * ell + c] = (c >= i) ? G[c * ell + i] : 0.0;
-}
-
-__global__ void __launch_bounds__(256) k_chol(const double *__restrict__ part, int nparts, int ell, int64_t rows,
-                                              double *__restrict__ R, double *__restrict__ Rinv,
-                                              int *__restrict__ dflags, int cond) {
-  if (cond && !(dflags[FLAGW_BITS] & DSK_FLAG_FALLBACK)) return;
-  extern __shared__ double dyn[];
-  chol_body(part, nparts, ell, rows, R, Rinv, dflags, dyn);
-}
-
-// True in exactly one workgroup of the grid: the last one to publish its
-// partial.  Release fence before the ticket, acquire fence after it (device
-// scope), so the elected workgroup sees every partial.  The ticket counter is
-// reset for the next launch by the elected workgroup.
-__device__ bool last_block_done(unsigned *counter) {
-  __shared__ int last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == gridDim.x - 1) ? 1 : 0;
-    if (last) atomicExch(counter, 0u);
-  }
-  __syncthreads();
-  if (last) __threadfence();
-  return last != 0;
-}
-
-// Gram partials of X; with a counter, the last workgroup also reduces them and
-// factors (Cholesky + inverse), writing R and Rinv.
-template <typename T>
-__global__ void __launch_bounds__(256) k_gram_chol(const T *__restrict__ X, int64_t rows, int ell, int64_t ldx,
-                                                   int64_t rows_per_blk, double *__restrict__ part,
-                                                   unsigned *__restrict__ counter, double *__restrict__ R,
-                                                   double *__restrict__ Rinv, int *__restrict__ dflags) {
-  extern __shared__ double dyn[];
-  double *sh = dyn;   // GCH x ellp (reused by the factorization afterwards)
-  const int ellp = (ell + 3) & ~3;
-  const GramSlots slots = gram_slots(ellp);
-  GramAcc g;
-  gram_zero(g);
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
-  const int64_t r1 = std::min<int64_t>(rows, r0 + rows_per_blk);
-  for (int64_t c0 = r0; c0 < r1; c0 += GCH) {
-    for (int e = threadIdx.x; e < GCH * ellp; e += 256) {
-      const int rr = e / ellp, c = e - rr * ellp;
-      const int64_t r = c0 + rr;
-      sh[e] = (r < r1 && c < ell) ? (double)X[r * ldx + c] : 0.0;
-    }
-    __syncthreads();
-    gram_chunk(sh, GCH, ellp, slots, g);
-    __syncthreads();
-  }
-  gram_store(g, slots, ell, part + (int64_t)blockIdx.x * ell * ell);
-  if (last_block_done(counter)) chol_body(part, gridDim.x, ell, rows, R, Rinv, dflags, dyn);
-}
-
-// ---------------------------------------------------------------- Q = Y Rinv (+ Gram partials of Q)
-// Thread t owns output column c = t % CW and rows t/CW + (256/CW) u of each
-// 32-row chunk; every Rinv entry is read once per chunk and reused across rows.
-// cond = 1: run only after a shifted first pass.  With part != nullptr the
-// workgroup also accumulates the Gram of the rounded output, and with a counter
-// the last workgroup factors it into R, Rinv (all other workgroups have finished
-// reading Rinv by then).  gram_cond = 1: the Gram/factorization only after a
-// shifted first pass.
-template <typename T, int CW>
-__global__ void __launch_bounds__(256) k_apply(const T *__restrict__ Y, int64_t rows, int ell, int64_t ldy,
-                                               double *__restrict__ Rinv, T *__restrict__ Q, int64_t ldq,
-                                               int64_t rows_per_blk, double *__restrict__ part,
-                                               int *__restrict__ dflags, int cond, unsigned *__restrict__ counter,
-                                               double *__restrict__ R, int gram_cond) {
-  const bool fallback = (dflags[FLAGW_BITS] & DSK_FLAG_FALLBACK) != 0;
-  if (cond && !fallback) return;
-  if (gram_cond && !fallback) {
-    part = nullptr;
-    counter = nullptr;
-  }
-  constexpr int RG = 256 / CW;            // row groups
-  constexpr int RPT = GCH / RG;           // rows per thread per chunk
-  extern __shared__ double dyn[];
-  const int ellp = (ell + 3) & ~3;
-  double *Rs = dyn;                       // ell x ell
-  double *sh = dyn + ell * ell;           // GCH x ellp
-  for (int e = threadIdx.x; e < ell * ell; e += 256) Rs[e] = Rinv[e];
-  const GramSlots slots = gram_slots(ellp);
-  GramAcc g;
-  gram_zero(g);
-  const int c = threadIdx.x % CW, rg = threadIdx.x / CW;
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
-  const int64_t r1 = std::min<int64_t>(rows, r0 + rows_per_blk);
-  for (int64_t c0 = r0; c0 < r1; c0 += GCH) {
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-      const int rr = rg + RG * u;
-      const int64_t r = c0 + rr;
-      for (int cc = c; cc < ellp; cc += CW) sh[rr * ellp + cc] = (r < r1 && cc < ell) ? (double)Y[r * ldy + cc] : 0.0;
-    }
-    __syncthreads();
-    double acc[RPT];
-#pragma unroll
-    for (int u = 0; u < RPT; ++u) acc[u] = 0.0;
-    if (c < ell) {
-      for (int q = 0; q <= c; ++q) {
-        const double rv = Rs[q * ell + c];
-#pragma unroll
-        for (int u = 0; u < RPT; ++u) acc[u] = fma(sh[(rg + RG * u) * ellp + q], rv, acc[u]);
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-      const int rr = rg + RG * u;
-      const int64_t r = c0 + rr;
-      const T v = (T)acc[u];
-      const bool ok = r < r1 && c < ell;
-      if (c < ellp) sh[rr * ellp + c] = ok ? (double)v : 0.0;
-      if (ok) Q[r * ldq + c] = v;
-    }
-    __syncthreads();
-    if (part) gram_chunk(sh, GCH, ellp, slots, g);
-  }
-  if (part) gram_store(g, slots, ell, part + (int64_t)blockIdx.x * ell * ell);
-  if (part && counter) {
-    __syncthreads();   // LDS (Rs, sh) is reused by the factorization
-    if (last_block_done(counter)) chol_body(part, gridDim.x, ell, rows, R, Rinv, dflags, dyn);
   }
 }
 
@@ -661,61 +329,17 @@ __global__ void __launch_bounds__(256) k_sign_fix(T *__restrict__ U, int64_t m, 
     for (int64_t i = threadIdx.x; i < m; i += 256) U[i * k + j] = -U[i * k + j];
 }
 
-int gram_parts(int64_t rows) { return (int)std::min<int64_t>(std::max<int64_t>(1, (rows + 127) / 128), 16); }
-
-template <typename T, int CW>
-void launch_apply(hipStream_t st, int nparts, size_t lds, const T *Y, int64_t rows, int ell, double *Rinv, T *Q,
-                  int64_t rpb, double *part, int *dflags, int cond, unsigned *counter, double *R, int gram_cond) {
-  allow_lds(k_apply<T, CW>, lds);
-  hipLaunchKernelGGL((k_apply<T, CW>), dim3(nparts), dim3(256), lds, st, Y, rows, ell, (int64_t)ell, Rinv, Q,
-                     (int64_t)ell, rpb, part, dflags, cond, counter, R, gram_cond);
-}
-
-// CholeskyQR2 in 3 launches (+1 after a shifted first pass):
-//   [Gram(Y) -> chol]  [Q1 = Y R1^-1, Gram(Q1) -> chol]  [Q = Q1 R2^-1 (, Gram(Q) -> chol)]  [(Q = Q R3^-1)]
-// The factorizations run in the workgroup that finishes its Gram partial last.
-// Blocks at most 64 wide take the MFMA path of cholqr64.hip; wider blocks
-// multiply by an explicit inverse.
 template <typename T>
 int cholqr2_typed(hipStream_t st, const T *Y, int64_t rows, int ell, T *Q, void *ws, int *dflags, int passes) {
   if (ell <= 64) return launch_cholqr64(st, Y, sizeof(T) == 8, rows, ell, Q, ws, dflags, passes);
-  // ws layout: part (nparts*ell*ell f64) | R (ell^2) | Rinv (ell^2) | Q1 (rows*ell T)
-  const int nparts = gram_parts(rows);
-  const int64_t rpb = ((rows + nparts - 1) / nparts + GCH - 1) / GCH * GCH;
-  double *part = reinterpret_cast<double *>(ws);
-  double *R = part + (size_t)nparts * ell * ell;
-  double *Rinv = R + ell * ell;
-  T *Q1 = reinterpret_cast<T *>(Rinv + ell * ell);
-  unsigned *counter = reinterpret_cast<unsigned *>(dflags + FLAGW_TICKET);
-  const int ellp = (ell + 3) & ~3;
-  const size_t chol_lds = (size_t)(ell * ell + ell) * sizeof(double);
-  const size_t gram_lds = std::max<size_t>(chol_lds, (size_t)GCH * ellp * sizeof(double));
-  const size_t apply_lds = std::max<size_t>(chol_lds, (size_t)(ell * ell + GCH * ellp) * sizeof(double));
-  auto apply = [&](const T *src, T *dst, double *prt, int cond, unsigned *ctr, int gcond) {
-    launch_apply<T, 128>(st, nparts, apply_lds, src, rows, ell, Rinv, dst, rpb, prt, dflags, cond, ctr, R, gcond);
-  };
-  allow_lds(k_gram_chol<T>, gram_lds);
-  hipLaunchKernelGGL(k_gram_chol<T>, dim3(nparts), dim3(256), gram_lds, st, Y, rows, ell, (int64_t)ell, rpb, part,
-                     counter, R, Rinv, dflags);
-  if (passes == 1) {
-    launch_apply<T, 128>(st, nparts, apply_lds, Y, rows, ell, Rinv, Q, rpb, nullptr, dflags, 0, nullptr, R, 0);
-    DSK_TRY(hipGetLastError());
-    return 0;
-  }
-  apply(Y, Q1, part, 0, counter, 0);
-  apply(Q1, Q, part, 0, counter, 1);     // third factorization only after a shifted first pass
-  apply(Q, Q, nullptr, 1, nullptr, 0);   // third application only after a shifted first pass
-  DSK_TRY(hipGetLastError());
-  return 0;
+  return launch_cholqr128(st, Y, sizeof(T) == 8, rows, ell, Q, ws, dflags, passes);
 }
 
 }  // namespace
 
 size_t cholqr2_ws_bytes(int64_t rows, int ell) {
   if (ell <= 64) return cholqr64_ws_bytes(rows, ell);
-  const int nparts = gram_parts(rows);
-  return ((size_t)nparts * ell * ell + 2 * (size_t)ell * ell) * sizeof(double) + (size_t)rows * ell * sizeof(double) +
-         1024;
+  return cholqr128_ws_bytes(rows, ell);
 }
 
 int launch_cholqr2(hipStream_t st, const void *Y, int f64, int64_t rows, int ell, void *Q, void *ws, int *dflags,
@@ -737,15 +361,12 @@ int launch_hhqr(hipStream_t st, double *X, int64_t rows, int ell, double *Q, dou
 // nparts row ranges, then a fixed-order reduction.  part: nparts * ell^2 doubles.
 template <typename T>
 void gram_parts_launch(hipStream_t st, const T *X, int64_t rows, int ell, int64_t rpb, int nblk, double *part) {
-  if (ell <= 64)
-    hipLaunchKernelGGL(k_gram_rows<T>, dim3(nblk), dim3(256), 0, st, X, rows, ell, (int64_t)ell, rpb, part);
-  else
-    hipLaunchKernelGGL(k_gram_part<T>, dim3(nblk), dim3(256), 0, st, X, rows, ell, (int64_t)ell, rpb, part,
-                       (const int *)nullptr, 0);
+  hipLaunchKernelGGL(k_gram_rows<T>, dim3(nblk), dim3(256), 0, st, X, rows, ell, (int64_t)ell, rpb, part);
 }
 
 int launch_gram(hipStream_t st, const void *X, int f64, int64_t rows, int ell, double *G, double *part, int nparts) {
   if (ell < 1 || ell > ELL_MAX || nparts < 1 || rows < 1) return -1;
+  if (ell > 16) return launch_gram_mfma(st, X, f64, rows, ell, G, part, nparts);
   const int64_t rpb = ((rows + nparts - 1) / nparts + GCH - 1) / GCH * GCH;
   const int nblk = (int)((rows + rpb - 1) / rpb);
   if (f64) gram_parts_launch<double>(st, (const double *)X, rows, ell, rpb, nblk, part);

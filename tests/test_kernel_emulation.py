@@ -185,7 +185,9 @@ def _check_persist(r):
         # raised no flag (a timed-out wait would), takes the per-step pivots and
         # gives P to rounding (left-looking against right-looking Gram-Schmidt)
         assert (int(n0), int(n1)) == (1, 0), res
-        assert int(f0) == 0 and int(f1) == 0, res
+        # flag 1 (fallback): the downdated norms ran out of accuracy and the exact
+        # one-workgroup factorization finished the job; no other flag may appear
+        assert int(f0) in (0, 1) and int(f1) == 0, res
         assert same == "1", res
         assert float(maxdp) <= 1e-9, res
     return len(res)
