@@ -60,16 +60,30 @@ __device__ __forceinline__ void tile_ij(int id, int &I, int &J) {
 
 // A (LDS, lower triangle) from the folded Gram (tile-major, published by other
 // workgroups of this launch); identity past ell; shift added to the diagonal.
-__device__ void load_gram(const double *G, int ell, int nb, double shift, double *A) {
+// A thread's loads go out in two batches of 18, each issued before its first use.
+__device__ __forceinline__ void load_gram(const double *G, int ell, int nb, double shift, double *A) {
+  constexpr int LG = NTM * TILE / 256 / 2;
   const int ne = nb * (nb + 1) / 2 * TILE;
-  for (int e = threadIdx.x; e < ne; e += 256) {
-    int I, J;
-    tile_ij(e >> 8, I, J);
-    const int r = 16 * I + ((e >> 4) & 15), c = 16 * J + (e & 15);
-    double v = ds::ld_dev(&G[e]);
-    if (r >= ell || c >= ell) v = (r == c) ? 1.0 : 0.0;
-    else if (r == c) v += shift;
-    A[r * LDA + c] = v;
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    double v[LG];
+#pragma unroll
+    for (int u = 0; u < LG; ++u) {
+      const int e = threadIdx.x + 256 * (u + LG * h);
+      v[u] = e < ne ? ds::ld_dev(&G[e]) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < LG; ++u) {
+      const int e = threadIdx.x + 256 * (u + LG * h);
+      if (e >= ne) continue;
+      int I, J;
+      tile_ij(e >> 8, I, J);
+      const int r = 16 * I + ((e >> 4) & 15), c = 16 * J + (e & 15);
+      double x = v[u];
+      if (r >= ell || c >= ell) x = (r == c) ? 1.0 : 0.0;
+      else if (r == c) x += shift;
+      A[r * LDA + c] = x;
+    }
   }
 }
 
@@ -150,7 +164,7 @@ __device__ __forceinline__ void trailing(double *A, int K, int nb) {
 // The last workgroup of the fold: factor (with the shifted retry), invert the
 // diagonal blocks, write the factor tiles Mf: tile (J, K), K < J, is L_JK and
 // tile (J, J) is W_J = L_JJ^{-1}, each 16 x 16 row-major.
-__device__ void factor(const double *G, int ell, int64_t rows, double *Mf, int *dflags, double *pool) {
+__device__ __forceinline__ void factor(const double *G, int ell, int64_t rows, double *Mf, int *dflags, double *pool) {
   const int t = threadIdx.x, l = t & 63, w = t >> 6;
   const int nb = (ell + 15) / 16, ellp = 16 * nb, ntile = nb * (nb + 1) / 2;
   double *A = pool, *colb = A + EMAX * LDA, *dinv = colb + 64, *word = dinv + EMAX;
@@ -266,7 +280,21 @@ __global__ void __launch_bounds__(256) k_q8_apply(const T *Y, int64_t rows, int 
   const int t = threadIdx.x, l = t & 63, w = t >> 6;
   const int nb = (ell + 15) / 16, ellp = 16 * nb, ntile = nb * (nb + 1) / 2;
   double *Ms = pool, *YQ = Ms + NTM * MST, *Sw = YQ + RCH * LDQ + w * MST;
-  for (int e = t; e < ntile * TILE; e += 256) Ms[(e >> 8) * MST + ((e >> 4) & 15) * 17 + (e & 15)] = Mf[e];
+  {
+    // all of a thread's factor loads in flight at once
+    constexpr int LM = NTM * TILE / 256;
+    double mv[LM];
+#pragma unroll
+    for (int u = 0; u < LM; ++u) {
+      const int e = t + 256 * u;
+      mv[u] = e < ntile * TILE ? Mf[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < LM; ++u) {
+      const int e = t + 256 * u;
+      if (e < ntile * TILE) Ms[(e >> 8) * MST + ((e >> 4) & 15) * 17 + (e & 15)] = mv[u];
+    }
+  }
   __syncthreads();
   const gt::Tiles tl = gt::tiles_of(w, nb);
   d4 acc[gt::MAXT];
@@ -274,11 +302,21 @@ __global__ void __launch_bounds__(256) k_q8_apply(const T *Y, int64_t rows, int 
   const int i16 = l & 15, kk = l >> 4, rb = 16 * w;
   const int64_t r0 = (int64_t)blockIdx.x * rpw, r1 = std::min<int64_t>(rows, r0 + rpw);
   for (int64_t c0 = r0; c0 < r1; c0 += RCH) {
-    // this wave's 16 rows, FP64, zero padded
-    for (int e = l; e < 16 * ellp; e += 64) {
-      const int rr = e / ellp, c = e - rr * ellp;
-      const int64_t r = c0 + rb + rr;
-      YQ[(rb + rr) * LDQ + c] = (r < r1 && c < ell) ? (double)Y[r * ell + c] : 0.0;
+    // this wave's 16 rows, FP64, zero padded (all loads in flight at once)
+    {
+      constexpr int SV = 16 * EMAX / 64;
+      T yv[SV];
+#pragma unroll
+      for (int u = 0; u < SV; ++u) {
+        const int e = l + 64 * u, rr = e / ellp, c = e - rr * ellp;
+        const int64_t r = c0 + rb + rr;
+        yv[u] = (e < 16 * ellp && r < r1 && c < ell) ? Y[r * ell + c] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < SV; ++u) {
+        const int e = l + 64 * u, rr = e / ellp, c = e - rr * ellp;
+        if (e < 16 * ellp) YQ[(rb + rr) * LDQ + c] = (double)yv[u];
+      }
     }
     wc::wave_lds_sync();
     for (int J = 0; J < nb; ++J) {

@@ -33,15 +33,16 @@
 
 namespace {
 
-constexpr int TNT = 256;           // threads of the reduction / eigenvalue kernel (one wave per SIMD)
+constexpr int TNT = 512;           // threads of the reduction / eigenvalue kernel (two waves per SIMD)
 constexpr int TMAX = 112;          // largest ell
 constexpr int NPT = 4;             // Sturm counts per thread and multisection round
 constexpr double TU = 1.1102230246251565e-16;
 
+// Sum over the wave, the same value in every lane: DPP sums within each row of
+// 16 lanes, then the four row sums in row order.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v = wc::row16_sum(v);
+  return (wc::readlane_f64(v, 0) + wc::readlane_f64(v, 16)) + (wc::readlane_f64(v, 32) + wc::readlane_f64(v, 48));
 }
 
 // Numbers of eigenvalues of T (diagonal d, squared off-diagonal e2) below
@@ -82,8 +83,8 @@ __global__ void __launch_bounds__(TNT) k_tri_eig(const double *__restrict__ G, i
   extern __shared__ double dyn[];
   const int n = ell, ld = ell + 1;
   double *A = dyn;                          // n x ld
-  __shared__ double d[TMAX], e[TMAX], e2[TMAX], tau[TMAX], vv[TMAX], lo_sh[TMAX], hi_sh[TMAX], lamu[TMAX];
-  __shared__ double pp[2][128];
+  __shared__ double d[TMAX], e[TMAX], e2[TMAX], tau[TMAX], vv[TMAX], pv[TMAX], lo_sh[TMAX], hi_sh[TMAX],
+      lamu[TMAX];
   __shared__ int cnt_sh[TNT * NPT];
   __shared__ double red[TNT / 64];
   __shared__ double bcast[4];
@@ -100,11 +101,13 @@ __global__ void __launch_bounds__(TNT) k_tri_eig(const double *__restrict__ G, i
   __syncthreads();
 
   // ---- 1. tridiagonalisation, three barriers per column: wave 0 forms the
-  // reflector; p = tau A' v by columns (A' = A[j+1:, j+1:] is symmetric), two
-  // row halves per column; every wave forms K = (tau/2) p.v itself, then
-  // A' -= v w^T + w v^T with w = p - K v.  A thread owns one column of A' and
-  // every other row, so its LDS accesses run along rows (v_r, w_r broadcast).
-  const int cc = t & 127, hh = t >> 7;
+  // reflector; p = tau A' v by columns (A' = A[j+1:, j+1:] is symmetric), four
+  // threads of a quad per column, each every fourth row, summed by DPP; every
+  // wave forms K = (tau/2) p.v itself, then A' -= v w^T + w v^T with
+  // w = p - K v, a thread owning one column and every fourth row (row-wise LDS
+  // access; v_r, p_r are broadcast reads).  Loads go out four at a time.
+  const int qc = t >> 2, qh = t & 3;          // matvec: column, row phase
+  const int uc = t & 127, uh = t >> 7;        // update: column, row phase
   for (int j = 0; j + 2 < n; ++j) {
     const int L = n - j - 1, o = j + 1;          // x = A[o:, j], length L
     if (wave == 0) {
@@ -140,22 +143,53 @@ __global__ void __launch_bounds__(TNT) k_tri_eig(const double *__restrict__ G, i
     }
     __syncthreads();
     const double tj = tau[j];
-    if (cc < L) {
-      double a = 0.0;
-      for (int r = hh; r < L; r += 2) a = fma(A[(o + r) * ld + o + cc], vv[r], a);
-      pp[hh][cc] = a;
+    {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      if (qc < L) {
+        const double *col = &A[o * ld + o + qc];
+        int r = qh;
+        for (; r + 12 < L; r += 16) {
+          const double x0 = col[r * ld], x1 = col[(r + 4) * ld], x2 = col[(r + 8) * ld], x3 = col[(r + 12) * ld];
+          const double y0 = vv[r], y1 = vv[r + 4], y2 = vv[r + 8], y3 = vv[r + 12];
+          a0 = fma(x0, y0, a0);
+          a1 = fma(x1, y1, a1);
+          a2 = fma(x2, y2, a2);
+          a3 = fma(x3, y3, a3);
+        }
+        for (; r < L; r += 4) a0 = fma(col[r * ld], vv[r], a0);
+      }
+      double a = (a0 + a1) + (a2 + a3);
+      a += wc::dpp_f64<0xB1>(a);                   // quad: lanes 2i, 2i+1
+      a += wc::dpp_f64<0x4E>(a);                   // quad: pairs
+      if (qc < L && qh == 0) pv[qc] = tj * a;
     }
     __syncthreads();
     double sk = 0.0;
-    for (int i = lane; i < L; i += 64) sk = fma(tj * (pp[0][i] + pp[1][i]), vv[i], sk);
+    for (int i = lane; i < L; i += 64) sk = fma(pv[i], vv[i], sk);
     const double K = 0.5 * tj * wave_sum(sk);
-    if (cc < L) {
-      const double vc = vv[cc];
-      const double wcc = fma(-K, vc, tj * (pp[0][cc] + pp[1][cc]));
-      for (int r = hh; r < L; r += 2) {
+    if (uc < L) {
+      const double vc = vv[uc];
+      const double wcc = fma(-K, vc, pv[uc]);
+      double *col = &A[o * ld + o + uc];
+      int r = uh;
+      for (; r + 12 < L; r += 16) {
+        double x[4], vr[4], pr[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          x[u] = col[(r + 4 * u) * ld];
+          vr[u] = vv[r + 4 * u];
+          pr[u] = pv[r + 4 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double wr = fma(-K, vr[u], pr[u]);
+          col[(r + 4 * u) * ld] = x[u] - fma(vr[u], wcc, wr * vc);
+        }
+      }
+      for (; r < L; r += 4) {
         const double vr = vv[r];
-        const double wr = fma(-K, vr, tj * (pp[0][r] + pp[1][r]));
-        A[(o + r) * ld + o + cc] -= fma(vr, wcc, wr * vc);
+        const double wr = fma(-K, vr, pv[r]);
+        col[r * ld] -= fma(vr, wcc, wr * vc);
       }
     }
     __syncthreads();
@@ -198,7 +232,7 @@ __global__ void __launch_bounds__(TNT) k_tri_eig(const double *__restrict__ G, i
     lo_sh[t] = bcast[0];
     hi_sh[t] = bcast[1];
   }
-  const int ns = TNT / n;                         // threads per eigenvalue (>= 2)
+  const int ns = TNT / n;                         // threads per eigenvalue (>= 4)
   const int np = ns * NPT;                        // points per eigenvalue and round
   const int ei = t / ns, si = t - (t / ns) * ns;
   int rounds = 0;
@@ -346,16 +380,22 @@ __global__ void __launch_bounds__(TNT) k_tri_eig(const double *__restrict__ G, i
 
 // U = Q Z: Q = H_0 H_1 ... H_{n-3}, H_j = I - tau_j v_j v_j^T (v_j in row j of Vt,
 // columns j+1 ..).  Four threads per column, rows interleaved by 4; the
-// reflectors go from the last to the first.  RPT = rows per thread.
+// reflectors go from the last to the first.  RPT = rows per thread; the rows
+// of Vt sit in LDS with stride 4 RPT, zero outside v_j's support, so the
+// products need no bounds tests (a load behind a branch waits on its own).
 template <int RPT>
 __global__ void __launch_bounds__(512) k_tri_back(const double *__restrict__ Vt, const double *__restrict__ taus,
                                                   const double *__restrict__ Zg, int ell, const int *__restrict__ fail,
                                                   double *__restrict__ U) {
-  extern __shared__ double vlds[];         // Vt, ell x ell
+  extern __shared__ double vlds[];         // ell rows of 4 RPT
   __shared__ double tls[TMAX];
   if (*fail) return;                       // the gated Jacobi core writes U
+  constexpr int NP = 4 * RPT;
   const int n = ell, t = threadIdx.x;
-  for (int x = t; x < n * n; x += 512) vlds[x] = Vt[x];
+  for (int x = t; x < n * NP; x += 512) {
+    const int j = x / NP, c = x - (x / NP) * NP;
+    vlds[x] = c < n ? Vt[j * n + c] : 0.0;
+  }
   if (t < n) tls[t] = taus[t];
   __syncthreads();
   const int c = t >> 2, g = t & 3;
@@ -368,21 +408,22 @@ __global__ void __launch_bounds__(512) k_tri_back(const double *__restrict__ Vt,
   }
   for (int j = n - 3; j >= 0; --j) {
     const double tj = tls[j];
-    const double *v = &vlds[j * n];
-    double w = 0.0;
+    const double *v = &vlds[j * NP + g];
+    double vr[RPT];
 #pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-      const int r = g + 4 * u;
-      if (r > j && r < n) w = fma(v[r], z[u], w);
+    for (int u = 0; u < RPT; ++u) vr[u] = v[4 * u];
+    double w0 = 0.0, w1 = 0.0;
+#pragma unroll
+    for (int u = 0; u < RPT; u += 2) {
+      w0 = fma(vr[u], z[u], w0);
+      w1 = fma(vr[u + 1], z[u + 1], w1);
     }
+    double w = w0 + w1;
     w += wc::dpp_f64<0xB1>(w);
     w += wc::dpp_f64<0x4E>(w);
     const double tw = tj * w;
 #pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-      const int r = g + 4 * u;
-      if (r > j && r < n) z[u] = fma(-tw, v[r], z[u]);
-    }
+    for (int u = 0; u < RPT; ++u) z[u] = fma(-tw, vr[u], z[u]);
   }
   if (act)
 #pragma unroll
@@ -406,11 +447,12 @@ int launch_core_eig_tri(hipStream_t st, const double *G, int ell, double *lam, d
   allow_lds(k_tri_eig, lds1);
   hipLaunchKernelGGL(k_tri_eig, dim3(1), dim3(TNT), lds1, st, G, ell, lam, Vt, taus, Zg, fail, dflags);
   DSK_TRY(hipGetLastError());
-  const size_t lds2 = (size_t)ell * ell * sizeof(double);
   if (ell <= 64) {
+    const size_t lds2 = (size_t)ell * 64 * sizeof(double);
     allow_lds(k_tri_back<16>, lds2);
     hipLaunchKernelGGL(k_tri_back<16>, dim3(1), dim3(512), lds2, st, Vt, taus, Zg, ell, fail, U);
   } else {
+    const size_t lds2 = (size_t)ell * 112 * sizeof(double);
     allow_lds(k_tri_back<28>, lds2);
     hipLaunchKernelGGL(k_tri_back<28>, dim3(1), dim3(512), lds2, st, Vt, taus, Zg, ell, fail, U);
   }
