@@ -22,7 +22,8 @@
  *    makes the call synchronise the stream before it returns.
  *  * Return value: 0 on success; -i when argument i (1-based) is invalid,
  *    detected on the host before anything is enqueued (no side effects);
- *    DSK_ERR_* (> 100) for HIP runtime errors (100 + hipError_t).
+ *    DSK_ERR_* (> 100) for HIP runtime errors (100 + hipError_t);
+ *    DSK_ERR_SCRATCH (90) from dsk_project_noalloc (size beyond its fixed scratch).
  *    Numerical events (fallback taken, rank deficiency, non-finite input)
  *    are reported through dsk_info.flags, not through the return value.
  *  * Scratch memory comes from a per-handle arena that grows on demand
@@ -152,6 +153,28 @@ int dsk_restrict(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t
  */
 int dsk_project(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                 const void *Q, int32_t ell, void *Bt, int32_t mode);
+
+/*
+ * dsk_project_noalloc -- dsk_project without any device allocation, for callers
+ * that cannot allocate: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, kernels and launch plan as
+ * dsk_project, so the same bytes in Bt.  The workspace (the packed Q and, when
+ * the pass is split over the rows of A, the per-split partial outputs) is a
+ * fixed device array of DSK_NOALLOC_SCRATCH_BYTES (32 MiB) that the library
+ * holds on every device it runs on, from the first dsk_create on that device
+ * until the process ends.  The caller passes A, Q and Bt and creates the handle
+ * beforehand; the call itself allocates nothing (no hipMalloc, no arena growth).
+ * Calls on one device share the array: calls that overlap on a device (other
+ * streams, handles or threads) race.  Errors: as dsk_project; DSK_ERR_SCRATCH
+ * when this size's plan needs more than DSK_NOALLOC_SCRATCH_BYTES (nothing is
+ * enqueued).  The plan needs 3 ceil(m / 32) ceil(ell / 16) KiB (rounded up to
+ * 256 bytes) for F32 / 16-bit input, plus split partials (4 or 8 bytes per
+ * n * ell per split) when n alone is too small to fill the device.
+ */
+#define DSK_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+#define DSK_ERR_SCRATCH 90
+int dsk_project_noalloc(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                        const void *Q, int32_t ell, void *Bt, int32_t mode);
 
 /*
  * dsk_sketch_svd -- rank-k SVD A ~ U diag(S) V^T by TPC-SVD (Alg. 2) with q

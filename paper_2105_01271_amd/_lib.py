@@ -104,6 +104,7 @@ def load():
         lib.dsk_set_stream.argtypes = [vp, vp]
         lib.dsk_restrict.argtypes = [vp, vp, i32, i64, i64, i64, P(Restriction), vp]
         lib.dsk_project.argtypes = [vp, vp, i32, i64, i64, i64, vp, i32, vp, i32]
+        lib.dsk_project_noalloc.argtypes = [vp, vp, i32, i64, i64, i64, vp, i32, vp, i32]
         lib.dsk_sketch_svd.argtypes = [vp, vp, i32, i64, i64, i64, i32, P(Restriction), i32, P(Opts),
                                        vp, vp, vp, P(Info)]
         lib.dsk_sketch_id.argtypes = [vp, vp, i32, i64, i64, i64, i32, P(Restriction), i32, P(Opts),

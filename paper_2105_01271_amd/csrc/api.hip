@@ -146,6 +146,21 @@ int arena_reserve(dsk_handle *h, size_t bytes) {
   return 0;
 }
 
+int project_args(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, const void *Q,
+                 int32_t ell, void *Bt, int32_t mode) {
+  if (!h) return -1;
+  if (!A) return -2;
+  if (!valid_dtype(dtype)) return -3;
+  if (m < 1) return -4;
+  if (n < 1) return -5;
+  if (lda < n) return -6;
+  if (!Q) return -7;
+  if (ell < 1 || ell > ELL_CAP) return -8;
+  if (!Bt) return -9;
+  if (mode < 0 || mode > DSK_MODE_SPLIT6) return -10;
+  return 0;
+}
+
 extern "C" {
 
 void dsk_opts_default(dsk_opts *o) {
@@ -160,6 +175,7 @@ int dsk_create(dsk_handle **h, int device, void *stream) {
   if (!h) return -1;
   *h = nullptr;
   DSK_TRY(hipSetDevice(device));
+  DSK_RET(noalloc_setup(device));   // the fixed scratch of dsk_project_noalloc on this device
   dsk_handle *x = new dsk_handle();
   x->device = device;
   x->stream = reinterpret_cast<hipStream_t>(stream);
@@ -215,6 +231,7 @@ const char *dsk_status_string(int status) {
     const int i = -status;
     return i < 15 ? names[i] : "invalid argument";
   }
+  if (status == DSK_ERR_SCRATCH) return "size exceeds the fixed scratch of the allocation-free entry point";
   if (status >= DSK_ERR_BASE) return hipGetErrorString((hipError_t)(status - DSK_ERR_BASE));
   return "unknown status";
 }
@@ -237,16 +254,7 @@ int dsk_restrict(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t
 
 int dsk_project(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, const void *Q,
                 int32_t ell, void *Bt, int32_t mode) {
-  if (!h) return -1;
-  if (!A) return -2;
-  if (!valid_dtype(dtype)) return -3;
-  if (m < 1) return -4;
-  if (n < 1) return -5;
-  if (lda < n) return -6;
-  if (!Q) return -7;
-  if (ell < 1 || ell > ELL_CAP) return -8;
-  if (!Bt) return -9;
-  if (mode < 0 || mode > DSK_MODE_SPLIT6) return -10;
+  if (const int bad = project_args(h, A, dtype, m, n, lda, Q, ell, Bt, mode)) return bad;
   DSK_TRY(hipSetDevice(h->device));
   DSK_RET(arena_reserve(h, stream_ws_bytes(dtype, m, n, ell, mode)));
   hipEvent_t e0, e1;

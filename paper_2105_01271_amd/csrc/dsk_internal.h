@@ -211,7 +211,16 @@ int launch_fro2(hipStream_t st, const void *A, int dtype, int64_t m, int64_t n, 
                 double *part, int nparts, double *out);
 
 // stream.hip (B^T = X^T Y and X Y for tall-skinny Y)
+// argument checks of dsk_project (0 or -i for argument i)
+int project_args(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, const void *Q,
+                 int32_t ell, void *Bt, int32_t mode);
+// noalloc.hip: takes the device address of dsk_project_noalloc's fixed scratch
+// on `device` (current); called by dsk_create
+int noalloc_setup(int device);
 size_t stream_ws_bytes(int dtype, int64_t K, int64_t N, int ell, int mode);
+// the workspace launch_stream (X^T Y) uses at these sizes on a device with cu_count CUs
+// (at most stream_ws_bytes)
+size_t stream_scratch_bytes(int dtype, int64_t K, int64_t N, int ell, int mode, int cu_count);
 int launch_stream(hipStream_t st, const void *X, int dtype, int64_t K, int64_t N, int64_t ldx,
                   const void *Y, int f64y, int ell, void *out, int64_t ldo, int mode, void *ws,
                   int cu_count, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);

@@ -521,14 +521,45 @@ int mode_of(int dtype, int mode) {
   return MODE_SPLIT6;
 }
 
+// The split of a launch over K and the workspace it uses: the packed Y (16-bit
+// and F32 inputs) and, when K is split, the per-split partial outputs.
+struct StreamPlan {
+  Plan p;
+  size_t yp_bytes, part_bytes;
+};
+
+StreamPlan stream_plan(bool nn, int dtype, int64_t K, int64_t N, int ell, int mode, int cu_count) {
+  StreamPlan sp{};
+  if (dtype == DSK_F64) {
+    sp.p = plan_split(K, N, 64, 16, cu_count, 2);
+    sp.part_bytes = sp.p.nsplit > 1 ? (size_t)sp.p.nsplit * N * ell * sizeof(double) : 0;
+    return sp;
+  }
+  const int md = mode_of(dtype, mode);
+  const int nct = (ell + 15) / 16;
+  const int jt = nct <= 4 ? 4 : 2;
+  const int64_t nkb = (K + 31) / 32;
+  sp.yp_bytes = ((size_t)nkb * nct * 3 * 64 * sizeof(uint4) + 255) & ~size_t(255);
+  sp.p = plan_split(K, N, 16 * jt, 32, cu_count, 4);
+  if (const int tn = tuned_ns(md, nn, K, N, ell); tn > 0) {
+    // an autotuned split, within the partial buffers stream_ws_bytes provides (nkb / 4)
+    const int64_t ns = std::max<int64_t>(1, std::min<int64_t>(tn, std::max<int64_t>(1, nkb / 4)));
+    sp.p.kb_per_split = (int)((nkb + ns - 1) / ns);
+    sp.p.nsplit = (int)((nkb + sp.p.kb_per_split - 1) / sp.p.kb_per_split);
+  }
+  sp.part_bytes = sp.p.nsplit > 1 ? (size_t)sp.p.nsplit * N * ell * sizeof(float) : 0;
+  return sp;
+}
+
 int stream_any(hipStream_t st, bool nn, const void *X, int dtype, int64_t K, int64_t N, int64_t ldx,
                const void *Y, int ell, void *out, int64_t ldo, int mode, void *ws, int cu_count,
                hipEvent_t ev0, hipEvent_t ev1) {
   if (ell < 1 || ell > 128) return -1;
   char *w = reinterpret_cast<char *>(ws);
+  const StreamPlan sp = stream_plan(nn, dtype, K, N, ell, mode, cu_count);
   if (dtype == DSK_F64) {
     const int ellp = ell <= 16 ? 16 : ell <= 32 ? 32 : ell <= 64 ? 64 : 128;
-    Plan p = plan_split(K, N, 64, 16, cu_count, 2);
+    const Plan p = sp.p;
     double *dst = reinterpret_cast<double *>(out);
     int64_t ldd = ldo;
     if (p.nsplit > 1) { dst = reinterpret_cast<double *>(w); ldd = ell; }
@@ -550,11 +581,10 @@ int stream_any(hipStream_t st, bool nn, const void *X, int dtype, int64_t K, int
   }
   const int md = mode_of(dtype, mode);
   const int nct = (ell + 15) / 16;
-  const int jt = nct <= 4 ? 4 : 2;
   const int64_t nkb = (K + 31) / 32;
   // packed Y
   uint4 *Yp = reinterpret_cast<uint4 *>(w);
-  const size_t yp_bytes = ((size_t)nkb * nct * 3 * 64 * sizeof(uint4) + 255) & ~size_t(255);
+  const size_t yp_bytes = sp.yp_bytes;
   dim3 pgrid((unsigned)nkb, (unsigned)nct);
   switch (md) {
     case MODE_SPLIT6:
@@ -575,13 +605,7 @@ int stream_any(hipStream_t st, bool nn, const void *X, int dtype, int64_t K, int
                          (int64_t)ell, nct, Yp);
   }
   DSK_TRY(hipGetLastError());
-  Plan p = plan_split(K, N, 16 * jt, 32, cu_count, 4);
-  if (const int tn = tuned_ns(md, nn, K, N, ell); tn > 0) {
-    // an autotuned split, within the partial buffers stream_ws_bytes provides (nkb / 4)
-    const int64_t ns = std::max<int64_t>(1, std::min<int64_t>(tn, std::max<int64_t>(1, nkb / 4)));
-    p.kb_per_split = (int)((nkb + ns - 1) / ns);
-    p.nsplit = (int)((nkb + p.kb_per_split - 1) / p.kb_per_split);
-  }
+  const Plan p = sp.p;
   float *dst = reinterpret_cast<float *>(out);
   int64_t ldd = ldo;
   if (p.nsplit > 1) { dst = reinterpret_cast<float *>(w + yp_bytes); ldd = ell; }
@@ -635,6 +659,11 @@ size_t stream_ws_bytes(int dtype, int64_t K, int64_t N, int ell, int mode) {
   size_t yp = ((size_t)nkb * nct * 3 * 64 * sizeof(uint4) + 255) & ~size_t(255);   // same as stream_any
   const int64_t ns = std::min<int64_t>(std::max<int64_t>(1, nkb / 4), 1024);
   return yp + (size_t)ns * N * ell * sizeof(float) + 256;
+}
+
+size_t stream_scratch_bytes(int dtype, int64_t K, int64_t N, int ell, int mode, int cu_count) {
+  const StreamPlan sp = stream_plan(false, dtype, K, N, ell, mode, cu_count);
+  return sp.yp_bytes + sp.part_bytes;
 }
 
 int launch_stream(hipStream_t st, const void *X, int dtype, int64_t K, int64_t N, int64_t ldx, const void *Y,

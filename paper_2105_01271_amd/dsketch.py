@@ -22,6 +22,7 @@ _MODES = {"default": _lib.DSK_MODE_DEFAULT, "split3": _lib.DSK_MODE_SPLIT3, "f32
           "split6": _lib.DSK_MODE_SPLIT6}
 
 _handles: dict = {}
+DSK_ERR_SCRATCH = 90   # dsk_project_noalloc: size beyond its fixed scratch
 
 
 def _handle(device: torch.device):
@@ -183,6 +184,26 @@ def project(A: torch.Tensor, Q: torch.Tensor, mode="default") -> torch.Tensor:
     _lib.check("dsk_project", lib.dsk_project(_handle(A.device), _ptr(A), _DT[A.dtype], m, n, A.stride(0), _ptr(Q),
                                               ell, _ptr(Bt), _MODES[mode] if isinstance(mode, str) else int(mode)))
     return Bt
+
+
+def project_noalloc(A: torch.Tensor, Q: torch.Tensor, Bt: torch.Tensor, mode="default") -> int:
+    """B^T = A^T Q into the caller's Bt (n x ell, work dtype) by dsk_project_noalloc:
+    no device allocation in the call (the handle must exist: create it beforehand with
+    handle(device)).  Returns the status (0, or DSK_ERR_SCRATCH when the size's plan
+    exceeds the fixed scratch); argument errors raise."""
+    lib = _lib.load()
+    m, n = A.shape
+    st = lib.dsk_project_noalloc(_handle(A.device), _ptr(A), _DT[A.dtype], m, n, A.stride(0), _ptr(Q),
+                                 Q.shape[1], _ptr(Bt), _MODES[mode] if isinstance(mode, str) else int(mode))
+    if st not in (0, DSK_ERR_SCRATCH):
+        _lib.check("dsk_project_noalloc", st)
+    return st
+
+
+def handle(device: torch.device):
+    """The library handle of `device` (created on first use; creating it is the
+    set-up the allocation-free entry point relies on)."""
+    return _handle(device)
 
 
 def sketch_svd(A: torch.Tensor, k: int, R: Restriction, q: int = 0, p: int = 10, S=None, tau=None,

@@ -273,7 +273,8 @@ template <typename T, unsigned N> using HIP_vector_type = T;
 
 // ---------------------------------------------------------------- runtime API
 typedef int hipError_t;
-enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorOutOfMemory = 2, hipErrorLaunchFailure = 719 };
+enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorOutOfMemory = 2, hipErrorInvalidDevice = 101,
+       hipErrorLaunchFailure = 719 };
 struct ihipStream_t;
 struct ihipEvent_t;
 struct ihipGraph;
@@ -309,6 +310,12 @@ hipError_t hipSetDevice(int d);
 hipError_t hipDeviceGetAttribute(int *v, hipDeviceAttribute_t a, int d);
 hipError_t hipFuncSetAttribute(const void *f, hipFuncAttribute a, int v);
 hipError_t hipGetLastError();
+// device globals are host globals here: the symbol's address is the array's
+#define HIP_SYMBOL(x) (&(x))
+inline hipError_t hipGetSymbolAddress(void **p, const void *sym) {
+  *p = const_cast<void *>(sym);
+  return hipSuccess;
+}
 hipError_t hipStreamBeginCapture(hipStream_t s, hipStreamCaptureMode m);
 hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t *g);
 hipError_t hipGraphInstantiate(hipGraphExec_t *x, hipGraph_t g, void *, char *, size_t);
