@@ -1,26 +1,27 @@
 // Symmetric eigensolver of the core SVD (Alg. 2, "SVD(B)" step) for the
 // FP32 / 16-bit paths: all eigenpairs of the ell x ell FP64 Gram G_B = B B^T
 // (ell <= 112), whose eigenvalues are sigma_j^2 and whose eigenvectors are the
-// left singular vectors U_B of B.
+// left singular vectors U_B of B.  Three launches:
 //
-//   1. Householder tridiagonalisation Q^T G Q = T (G in LDS, one workgroup of
-//      four waves): step j reflects column j below the diagonal, p = tau A v
-//      (symmetric product), w = p - (tau/2)(p.v) v, A -= v w^T + w v^T.
-//   2. Eigenvalues of T by multisection: every eigenvalue index owns a group
-//      of threads, each round evaluates Sturm counts (the signs of the LDL^T
-//      pivots of T - x I) at the group's interior points (four per thread,
-//      interleaved) and keeps the sub-interval that holds the index.
-//   3. Eigenvectors of T by the twisted factorisation at each eigenvalue:
-//      T - lambda I = N_r Delta_r N_r^T with the twist index r where |gamma_r|
-//      is smallest; z_r = 1 and the two bidiagonal solves give z.  Vectors of
-//      eigenvalues closer than 1e-9 ||T|| are re-orthogonalised in order.
-//      Every vector's residual ||T z - lambda z|| is checked against 2e-9 ||T||;
-//      a failure (or a non-finite value) sets the workspace's fail word, the
-//      back-transformation then writes nothing and the Jacobi core eigensolver,
-//      launched after it and gated on that word, computes the result instead.
-//   4. Back-transformation U = Q Z (second kernel): four threads per
-//      eigenvector, the reflectors applied from the last to the first.
+//   1. k_tri_reduce (one workgroup): Householder tridiagonalisation
+//      Q^T G Q = T in LDS; step j reflects column j below the diagonal,
+//      p = tau A v (symmetric product), w = p - (tau/2)(p.v) v,
+//      A -= v w^T + w v^T.  Writes T (d, e), the reflectors and the
+//      Gershgorin bounds.
+//   2. k_tri_vec (one workgroup per eigenvalue index): multisection on Sturm
+//      counts (the signs of the LDL^T pivots of T - x I), 512 points per
+//      round, to the rounding level; then the eigenvector of T by the twisted
+//      factorisation T - lambda I = N_r Delta_r N_r^T at the twist index r of
+//      smallest |gamma_r| (z_r = 1, the two bidiagonal solves on two waves at
+//      once), normalised, and its residual ||T z - lambda z|| checked against
+//      2e-9 ||T||.
+//   3. k_tri_back (one workgroup): vectors of eigenvalues closer than
+//      1e-9 ||T|| are re-orthogonalised in order; then U = Q Z, four threads
+//      per eigenvector, the reflectors applied from the last to the first.
 //
+// A failed residual (or a non-finite value) sets the workspace's fail word:
+// the back-transformation then writes nothing and the Jacobi core
+// eigensolver, launched after it and gated on that word, computes the result.
 // Absolute accuracy: eigenvalues within a few u ||G||, eigenvectors within
 // about u ||G|| / gap (backward stable reduction, bisection to the rounding
 // level), far inside the FP32 parity tolerances of the paths that use it.
@@ -33,9 +34,8 @@
 
 namespace {
 
-constexpr int TNT = 512;           // threads of the reduction / eigenvalue kernel (two waves per SIMD)
+constexpr int TNT = 512;           // threads of the reduction kernel (two waves per SIMD)
 constexpr int TMAX = 112;          // largest ell
-constexpr int NPT = 4;             // Sturm counts per thread and multisection round
 constexpr double TU = 1.1102230246251565e-16;
 
 // Sum over the wave, the same value in every lane: DPP sums within each row of
@@ -75,21 +75,17 @@ __device__ __forceinline__ double msec_point(double a, double b, int s, int np) 
   return a + (b - a) * (double)(s + 1) / (double)(np + 1);
 }
 
-// LDS (dynamic): A [ell][ell + 1] (the matrix, later Z), then small arrays.
-__global__ void __launch_bounds__(TNT) k_tri_eig(const double *__restrict__ G, int ell, double *__restrict__ lam,
-                                                 double *__restrict__ Vt, double *__restrict__ taus,
-                                                 double *__restrict__ Zg, int *__restrict__ fail,
-                                                 int *__restrict__ dflags) {
+// LDS (dynamic): A [ell][ell + 1].  Outputs: Td = (d, e) of T, the reflectors
+// (Vt, taus), bnd = (lo, hi, pivmin, ||T||) for the multisection; clears the
+// fail word.
+__global__ void __launch_bounds__(TNT) k_tri_reduce(const double *__restrict__ G, int ell,
+                                                    double *__restrict__ Vt, double *__restrict__ taus,
+                                                    double *__restrict__ Td, double *__restrict__ bnd,
+                                                    int *__restrict__ fail, int *__restrict__ dflags) {
   extern __shared__ double dyn[];
   const int n = ell, ld = ell + 1;
   double *A = dyn;                          // n x ld
-  __shared__ double d[TMAX], e[TMAX], e2[TMAX], tau[TMAX], vv[TMAX], pv[TMAX], lo_sh[TMAX], hi_sh[TMAX],
-      lamu[TMAX];
-  __shared__ int cnt_sh[TNT * NPT];
-  __shared__ double red[TNT / 64];
-  __shared__ double bcast[4];
-  __shared__ int clus_sh;
-  __shared__ int bad_sh;
+  __shared__ double d[TMAX], e[TMAX], tau[TMAX], vv[TMAX], pv[TMAX];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
 
   for (int x = t; x < n * n; x += TNT) {
@@ -97,7 +93,7 @@ __global__ void __launch_bounds__(TNT) k_tri_eig(const double *__restrict__ G, i
     A[r * ld + c] = G[x];
   }
   if (t < TMAX) tau[t] = 0.0;
-  if (t == 0) bad_sh = 0;
+  if (t == 0) *fail = 0;
   __syncthreads();
 
   // ---- 1. tridiagonalisation, three barriers per column: wave 0 forms the
@@ -198,6 +194,7 @@ __global__ void __launch_bounds__(TNT) k_tri_eig(const double *__restrict__ G, i
   if (t < n) d[t] = A[t * ld + t];
   if (t == 0 && n >= 2) {
     e[n - 2] = A[(n - 1) * ld + n - 2];
+    e[n - 1] = 0.0;
     tau[n - 2] = 0.0;
   }
   for (int x = t; x < n * n; x += TNT) {
@@ -207,8 +204,10 @@ __global__ void __launch_bounds__(TNT) k_tri_eig(const double *__restrict__ G, i
   if (t < n) taus[t] = (t + 2 < n) ? tau[t] : 0.0;
   __syncthreads();
 
-  // ---- 2. eigenvalues: multisection on Sturm counts
-  if (t < n) e2[t] = (t + 1 < n) ? e[t] * e[t] : 0.0;
+  if (t < n) {
+    Td[t] = d[t];
+    Td[TMAX + t] = e[t];
+  }
   if (t == 0) {
     double lo = d[0], hi = d[0], tmax = 0.0;
     for (int i = 0; i < n; ++i) {
@@ -220,178 +219,235 @@ __global__ void __launch_bounds__(TNT) k_tri_eig(const double *__restrict__ G, i
     double emax = 0.0;
     for (int i = 0; i + 1 < n; ++i) emax = fmax(emax, e[i] * e[i]);
     const double pad = 2.0 * TU * tmax * n + 1e-300;
-    bcast[0] = lo - pad;
-    bcast[1] = hi + pad;
-    bcast[2] = 1e-290 * fmax(1.0, emax);          // pivmin
-    bcast[3] = tmax;
-    if (!isfinite(tmax)) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_NONFINITE);
-  }
-  __syncthreads();
-  const double pivmin = bcast[2], tnorm = bcast[3];
-  if (t < n) {
-    lo_sh[t] = bcast[0];
-    hi_sh[t] = bcast[1];
-  }
-  const int ns = TNT / n;                         // threads per eigenvalue (>= 4)
-  const int np = ns * NPT;                        // points per eigenvalue and round
-  const int ei = t / ns, si = t - (t / ns) * ns;
-  int rounds = 0;
-  for (; rounds < 128; ++rounds) {
-    __syncthreads();
-    if (t == 0) clus_sh = 0;
-    __syncthreads();
-    double a = 0.0, b = 0.0;
-    if (ei < n) {
-      a = lo_sh[ei];
-      b = hi_sh[ei];
-      if (b - a > 4.0 * TU * fmax(fabs(a), fabs(b)) + 1e-300 && b - a > 2.0 * TU * tnorm) clus_sh = 1;
-    }
-    __syncthreads();
-    if (!clus_sh) break;
-    if (ei < n) {
-      double xs[NPT];
-      int cs[NPT];
-#pragma unroll
-      for (int u = 0; u < NPT; ++u) xs[u] = msec_point(a, b, si * NPT + u, np);
-      sturm_counts<NPT>(d, e2, n, xs, pivmin, cs);
-#pragma unroll
-      for (int u = 0; u < NPT; ++u) cnt_sh[t * NPT + u] = cs[u];
-    }
-    __syncthreads();
-    if (ei < n && si == 0) {
-      // points x_s increase with s; keep [last x with count <= ei, first x with count > ei]
-      double na = a, nb = b;
-      for (int s = 0; s < np; ++s) {
-        const double x = msec_point(a, b, s, np);
-        if (cnt_sh[ei * np + s] <= ei) na = x;
-        else { nb = x; break; }
-      }
-      lo_sh[ei] = na;
-      hi_sh[ei] = nb;
+    bnd[0] = lo - pad;
+    bnd[1] = hi + pad;
+    bnd[2] = 1e-290 * fmax(1.0, emax);          // pivmin
+    bnd[3] = tmax;
+    if (!isfinite(tmax)) {
+      atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_NONFINITE);
+      *fail = 1;
     }
   }
-  __syncthreads();
-  if (t < n) lamu[t] = 0.5 * (lo_sh[t] + hi_sh[t]);   // ascending
-  if (t == 0) dflags[FLAGW_SWEEPS] = rounds;
-  __syncthreads();
-
-  // ---- 3. eigenvectors of T: twisted factorisation, column t of Z (A reused, ld)
-  double *Z = A;
-  if (t < n) {
-    const double lm = lamu[t];
-    // top-down: D+_i into Z[i][t]
-    double dp = d[0] - lm;
-    if (fabs(dp) < pivmin) dp = -pivmin;
-    Z[t] = dp;
-    for (int i = 0; i + 1 < n; ++i) {
-      dp = (d[i + 1] - lm) - e2[i] * wc::rcp_nr(dp);
-      if (fabs(dp) < pivmin) dp = -pivmin;
-      Z[(i + 1) * ld + t] = dp;
-    }
-    // bottom-up: D-_i and gamma_i = D+_i + D-_i - (d_i - lambda); r = argmin |gamma|
-    double dm = d[n - 1] - lm;
-    if (fabs(dm) < pivmin) dm = -pivmin;
-    int r = n - 1;
-    double gbest = fabs(Z[(n - 1) * ld + t]);          // gamma_{n-1} = D+_{n-1}
-    for (int i = n - 2; i >= 0; --i) {
-      dm = (d[i] - lm) - e2[i] * wc::rcp_nr(dm);
-      if (fabs(dm) < pivmin) dm = -pivmin;
-      const double g = fabs(Z[i * ld + t] + dm - (d[i] - lm));
-      if (g < gbest) { gbest = g; r = i; }
-    }
-    // D-_i for i > r into Z[i][t]
-    dm = d[n - 1] - lm;
-    if (fabs(dm) < pivmin) dm = -pivmin;
-    for (int i = n - 1; i > r; --i) {
-      Z[i * ld + t] = dm;
-      if (i - 1 > r) {
-        dm = (d[i - 1] - lm) - e2[i - 1] * wc::rcp_nr(dm);
-        if (fabs(dm) < pivmin) dm = -pivmin;
-      }
-    }
-    // z_r = 1; up: z_i = -(e_i / D+_i) z_{i+1}; down: z_{i+1} = -(e_i / D-_{i+1}) z_i
-    double zr = 1.0, nrm = 1.0;
-    double z = zr;
-    for (int i = r - 1; i >= 0; --i) {
-      z = -(e[i] * wc::rcp_nr(Z[i * ld + t])) * z;
-      Z[i * ld + t] = z;
-      nrm = fma(z, z, nrm);
-    }
-    Z[r * ld + t] = zr;
-    z = zr;
-    for (int i = r; i + 1 < n; ++i) {
-      z = -(e[i] * wc::rcp_nr(Z[(i + 1) * ld + t])) * z;
-      Z[(i + 1) * ld + t] = z;
-      nrm = fma(z, z, nrm);
-    }
-    const double sc = wc::rsq_nr(nrm);
-    for (int i = 0; i < n; ++i) Z[i * ld + t] *= sc;
-  }
-  __syncthreads();
-  // re-orthogonalise vectors of close eigenvalues (one wave, in ascending order)
-  if (wave == 0) {
-    const double gtol = 1e-9 * fmax(tnorm, 1e-300);
-    for (int c = 1; c < n; ++c) {
-      if (lamu[c] - lamu[c - 1] > gtol) continue;
-      int s0 = c - 1;
-      while (s0 > 0 && lamu[s0] - lamu[s0 - 1] <= gtol) --s0;
-      for (int pass = 0; pass < 2; ++pass) {
-        for (int sv = s0; sv < c; ++sv) {
-          double dot = 0.0;
-          for (int i = lane; i < n; i += 64) dot = fma(Z[i * ld + sv], Z[i * ld + c], dot);
-          dot = wave_sum(dot);
-          for (int i = lane; i < n; i += 64) Z[i * ld + c] = fma(-dot, Z[i * ld + sv], Z[i * ld + c]);
-          wc::wave_lds_sync();
-        }
-      }
-      double nn = 0.0;
-      for (int i = lane; i < n; i += 64) nn = fma(Z[i * ld + c], Z[i * ld + c], nn);
-      nn = wave_sum(nn);
-      const double sc = nn > 0.0 ? wc::rsq_nr(nn) : 0.0;
-      for (int i = lane; i < n; i += 64) Z[i * ld + c] *= sc;
-      wc::wave_lds_sync();
-    }
-  }
-  __syncthreads();
-  // residual check of every vector
-  if (t < n) {
-    const double lm = lamu[t];
-    double rmax = 0.0;
-    bool fin = isfinite(lm);
-    for (int i = 0; i < n; ++i) {
-      const double zi = Z[i * ld + t];
-      double r = (d[i] - lm) * zi;
-      if (i > 0) r = fma(e[i - 1], Z[(i - 1) * ld + t], r);
-      if (i + 1 < n) r = fma(e[i], Z[(i + 1) * ld + t], r);
-      rmax = fmax(rmax, fabs(r));
-      fin = fin && isfinite(zi);
-    }
-    if (!fin || !(rmax <= 2e-9 * tnorm)) bad_sh = 1;
-  }
-  __syncthreads();
-  if (t == 0) *fail = bad_sh;
-  // descending order out: column j of Zg = eigenvector of lamu[n - 1 - j]
-  for (int x = t; x < n * n; x += TNT) {
-    const int i = x / n, j = x - (x / n) * n;
-    Zg[x] = Z[i * ld + (n - 1 - j)];
-  }
-  if (t < n) lam[t] = lamu[n - 1 - t];
 }
 
-// U = Q Z: Q = H_0 H_1 ... H_{n-3}, H_j = I - tau_j v_j v_j^T (v_j in row j of Vt,
+// Eigenpair ei = blockIdx.x (ascending order) of T.  Multisection: every
+// round evaluates the Sturm counts at NPV = 512 interior points of the
+// current interval [a, b] (two interleaved recurrences per thread) and keeps
+// [x_{s-1}, x_s] for the first point s whose count exceeds ei; the first such
+// s is a workgroup minimum in LDS, one barrier per round (three slots used in
+// rotation, so the slot reset for round r + 1 is one no thread still reads).
+// Stops when b - a <= max(4 u max(|a|, |b|), 2 u ||T||).
+__global__ void __launch_bounds__(256) k_tri_vec(const double *__restrict__ Td, const double *__restrict__ bnd,
+                                                 int ell, double *__restrict__ lam, double *__restrict__ Zg,
+                                                 int *__restrict__ fail, int *__restrict__ dflags) {
+  constexpr int NPV = 512;
+  __shared__ double d[TMAX], e[TMAX], e2[TMAX], dp[TMAX], dm[TMAX], z[TMAX], red[4];
+  __shared__ int smin[3];
+  __shared__ unsigned long long gkey;
+  __shared__ int rsh;
+  const int n = ell, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int ei = blockIdx.x;
+  if (t < n) {
+    d[t] = Td[t];
+    e[t] = Td[TMAX + t];
+    e2[t] = (t + 1 < n) ? e[t] * e[t] : 0.0;
+  }
+  if (t < 3) smin[t] = NPV;
+  if (t == 0) gkey = ~0ull;
+  __syncthreads();
+  const double pivmin = bnd[2], tnorm = bnd[3];
+  double a = bnd[0], b = bnd[1];
+  int round = 0;
+  for (; round < 64; ++round) {
+    if (!(b - a > 4.0 * TU * fmax(fabs(a), fabs(b)) + 1e-300 && b - a > 2.0 * TU * tnorm)) break;
+    double xs[2];
+    int cs[2];
+    xs[0] = msec_point(a, b, 2 * t, NPV);
+    xs[1] = msec_point(a, b, 2 * t + 1, NPV);
+    sturm_counts<2>(d, e2, n, xs, pivmin, cs);
+    const int mine = cs[0] > ei ? 2 * t : (cs[1] > ei ? 2 * t + 1 : NPV);
+    const int slot = round % 3;
+    if (mine < NPV) atomicMin(&smin[slot], mine);
+    if (t == 0) smin[(round + 1) % 3] = NPV;
+    __syncthreads();
+    const int sf = smin[slot];
+    const double na = sf > 0 ? msec_point(a, b, sf - 1, NPV) : a;
+    const double nb = sf < NPV ? msec_point(a, b, sf, NPV) : b;
+    a = na;
+    b = nb;
+  }
+  const double lm = 0.5 * (a + b);
+  // twisted factorisation: D+ top-down (wave 0), D- bottom-up (wave 1), at once
+  if (t == 0) {
+    double v = d[0] - lm;
+    if (fabs(v) < pivmin) v = -pivmin;
+    dp[0] = v;
+    for (int i = 0; i + 1 < n; ++i) {
+      v = (d[i + 1] - lm) - e2[i] * wc::rcp_nr(v);
+      if (fabs(v) < pivmin) v = -pivmin;
+      dp[i + 1] = v;
+    }
+  } else if (t == 64) {
+    double v = d[n - 1] - lm;
+    if (fabs(v) < pivmin) v = -pivmin;
+    dm[n - 1] = v;
+    for (int i = n - 2; i >= 0; --i) {
+      v = (d[i] - lm) - e2[i] * wc::rcp_nr(v);
+      if (fabs(v) < pivmin) v = -pivmin;
+      dm[i] = v;
+    }
+  }
+  __syncthreads();
+  // r = argmin |gamma_i|, gamma_i = D+_i + D-_i - (d_i - lambda); ties: lowest i
+  if (t < n) {
+    const double g = fabs(dp[t] + dm[t] - (d[t] - lm));
+    const unsigned long long key = ((unsigned long long)__double_as_longlong(g) & ~0x7Full) | (unsigned)t;
+    atomicMin(&gkey, key);
+  }
+  __syncthreads();
+  const int r = (int)(gkey & 0x7F);
+  // z_r = 1; up: z_i = -(e_i / D+_i) z_{i+1} (wave 0); down: z_{i+1} = -(e_i / D-_{i+1}) z_i (wave 1)
+  if (t == 0) {
+    double v = 1.0;
+    z[r] = 1.0;
+    for (int i = r - 1; i >= 0; --i) {
+      v = -(e[i] * wc::rcp_nr(dp[i])) * v;
+      z[i] = v;
+    }
+  } else if (t == 64) {
+    double v = 1.0;
+    for (int i = r; i + 1 < n; ++i) {
+      v = -(e[i] * wc::rcp_nr(dm[i + 1])) * v;
+      z[i + 1] = v;
+    }
+  }
+  __syncthreads();
+  // ||z||^2 in a fixed order: per wave, then the waves in order
+  double s2 = 0.0;
+  if (t < n) s2 = z[t] * z[t];
+  s2 = wave_sum(s2);
+  if (lane == 0) red[wave] = s2;
+  __syncthreads();
+  const double sc = wc::rsq_nr((red[0] + red[1]) + (red[2] + red[3]));
+  bool bad = false;
+  if (t < n) {
+    const double zi = z[t] * sc;
+    double res = (d[t] - lm) * zi;
+    if (t > 0) res = fma(e[t - 1], z[t - 1] * sc, res);
+    if (t + 1 < n) res = fma(e[t], z[t + 1] * sc, res);
+    bad = !isfinite(zi) || !(fabs(res) <= 2e-9 * tnorm);
+    Zg[t * n + (n - 1 - ei)] = zi;            // column n - 1 - ei: descending order
+  }
+  if (bad) atomicOr(fail, 1);
+  if (t == 0) {
+    lam[n - 1 - ei] = lm;
+    if (!isfinite(lm)) atomicOr(fail, 1);
+    atomicMax(&dflags[FLAGW_SWEEPS], round);
+  }
+}
+
+// Vectors of close eigenvalues (gap <= 1e-9 ||T||) re-orthogonalised in
+// ascending order of eigenvalue, two passes of Gram-Schmidt against the
+// earlier members of the cluster, by wave 0 on Zg in global memory (column
+// n - 1 - a holds the vector of ascending index a).  Equal eigenvalues give
+// equal twisted vectors; a member that keeps less than half its norm is
+// replaced by one step of inverse iteration, (T - lambda I) y = x with the
+// LDL^T factorisation of T - lambda I, from a fixed start x orthogonal to the
+// earlier members (the step amplifies the cluster's eigenspace by about
+// 1 / (u ||T||)), then orthogonalised again.  Then U = Q Z:
+// Q = H_0 H_1 ... H_{n-3}, H_j = I - tau_j v_j v_j^T (v_j in row j of Vt,
 // columns j+1 ..).  Four threads per column, rows interleaved by 4; the
 // reflectors go from the last to the first.  RPT = rows per thread; the rows
 // of Vt sit in LDS with stride 4 RPT, zero outside v_j's support, so the
 // products need no bounds tests (a load behind a branch waits on its own).
 template <int RPT>
 __global__ void __launch_bounds__(512) k_tri_back(const double *__restrict__ Vt, const double *__restrict__ taus,
-                                                  const double *__restrict__ Zg, int ell, const int *__restrict__ fail,
-                                                  double *__restrict__ U) {
+                                                  double *__restrict__ Zg, const double *__restrict__ lam,
+                                                  const double *__restrict__ Td, const double *__restrict__ bnd,
+                                                  int ell, const int *__restrict__ fail, double *__restrict__ U) {
   extern __shared__ double vlds[];         // ell rows of 4 RPT
-  __shared__ double tls[TMAX];
+  __shared__ double tls[TMAX], lsh[TMAX];
   if (*fail) return;                       // the gated Jacobi core writes U
   constexpr int NP = 4 * RPT;
   const int n = ell, t = threadIdx.x;
+  if (t < 64) {
+    const int lane = t;
+    const double gtol = 1e-9 * fmax(bnd[3], 1e-300), pivmin = bnd[2];
+    auto col = [&](int asc) { return n - 1 - asc; };
+    // x <- x - sum over the members s0 .. c-1 of (x . z_s) z_s, twice; returns ||x||^2
+    auto mgs = [&](int s0, int c) {
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int sv = s0; sv < c; ++sv) {
+          double dot = 0.0;
+          for (int i = lane; i < n; i += 64) dot = fma(Zg[i * n + col(sv)], Zg[i * n + col(c)], dot);
+          dot = wave_sum(dot);
+          for (int i = lane; i < n; i += 64) Zg[i * n + col(c)] = fma(-dot, Zg[i * n + col(sv)], Zg[i * n + col(c)]);
+        }
+      }
+      double nn = 0.0;
+      for (int i = lane; i < n; i += 64) nn = fma(Zg[i * n + col(c)], Zg[i * n + col(c)], nn);
+      return wave_sum(nn);
+    };
+    auto scale = [&](int c, double f) {
+      for (int i = lane; i < n; i += 64) Zg[i * n + col(c)] *= f;
+    };
+    for (int c = 1; c < n; ++c) {
+      if (lam[col(c)] - lam[col(c - 1)] > gtol) continue;   // ascending gap
+      int s0 = c - 1;
+      while (s0 > 0 && lam[col(s0)] - lam[col(s0 - 1)] <= gtol) --s0;
+      double nn = mgs(s0, c);
+      if (!(nn >= 0.25)) {
+        // fixed start: entries in (-1/2, 1/2) from a multiplicative hash of (i, c)
+        for (int i = lane; i < n; i += 64)
+          Zg[i * n + col(c)] = (double)((unsigned)(i * 2654435761u + c * 40503u) >> 8) * 0x1p-24 - 0.5;
+        nn = mgs(s0, c);
+        scale(c, nn > 0.0 ? wc::rsq_nr(nn) : 0.0);
+        // lane 0 reads every row: the wave's stores come first
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) {
+          // (T - lambda I) y = x: T - lambda I = L D L^T, L unit lower bidiagonal (l_i = e_i / D_i)
+          const double lm = lam[col(c)];
+          const double *dT = Td, *eT = Td + TMAX;
+          double Dp = dT[0] - lm;
+          if (fabs(Dp) < pivmin) Dp = -pivmin;
+          double w = Zg[col(c)];
+          Zg[col(c)] = w / Dp;                     // v_0 = w_0 / D_0; l_0 kept implicit
+          for (int i = 0; i + 1 < n; ++i) {
+            const double li = eT[i] / Dp;
+            double Dn = (dT[i + 1] - lm) - li * eT[i];
+            if (fabs(Dn) < pivmin) Dn = -pivmin;
+            w = Zg[(i + 1) * n + col(c)] - li * w;  // forward: w_{i+1} = x_{i+1} - l_i w_i
+            Zg[(i + 1) * n + col(c)] = w / Dn;
+            Dp = Dn;
+          }
+          // backward: y_i = v_i - l_i y_{i+1}, with l_i recomputed from the same pivots
+          double Dq = dT[0] - lm;
+          if (fabs(Dq) < pivmin) Dq = -pivmin;
+          double *ls = lsh;
+          for (int i = 0; i + 1 < n; ++i) {
+            ls[i] = eT[i] / Dq;
+            double Dn = (dT[i + 1] - lm) - ls[i] * eT[i];
+            if (fabs(Dn) < pivmin) Dn = -pivmin;
+            Dq = Dn;
+          }
+          double y = Zg[(n - 1) * n + col(c)], ymax = fabs(y);
+          for (int i = n - 2; i >= 0; --i) {
+            y = Zg[i * n + col(c)] - ls[i] * y;
+            Zg[i * n + col(c)] = y;
+            ymax = fmax(ymax, fabs(y));
+          }
+          const double f = (ymax > 0.0 && isfinite(ymax)) ? 1.0 / ymax : 0.0;
+          for (int i = 0; i < n; ++i) Zg[i * n + col(c)] *= f;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        nn = mgs(s0, c);
+      }
+      scale(c, nn > 0.0 ? wc::rsq_nr(nn) : 0.0);
+    }
+  }
+  __syncthreads();
   for (int x = t; x < n * NP; x += 512) {
     const int j = x / NP, c = x - (x / NP) * NP;
     vlds[x] = c < n ? Vt[j * n + c] : 0.0;
@@ -435,26 +491,35 @@ __global__ void __launch_bounds__(512) k_tri_back(const double *__restrict__ Vt,
 
 }  // namespace
 
-size_t core_eig_tri_ws_bytes(int ell) { return ((size_t)2 * ell * ell + ell + 64) * sizeof(double); }
+size_t core_eig_tri_ws_bytes(int ell) {
+  return ((size_t)2 * ell * ell + ell + 2 * TMAX + 4 + 8) * sizeof(double);
+}
 
 int launch_core_eig_tri(hipStream_t st, const double *G, int ell, double *lam, double *U, double *ws, int *dflags) {
   if (ell < 3 || ell > TMAX) return launch_core_eig(st, G, ell, lam, U, dflags);
   double *Vt = ws;
-  double *Zg = ws + (size_t)ell * ell;
+  double *Zg = Vt + (size_t)ell * ell;
   double *taus = Zg + (size_t)ell * ell;
-  int *fail = reinterpret_cast<int *>(taus + ell);
+  double *Td = taus + ell;
+  double *bnd = Td + 2 * TMAX;
+  int *fail = reinterpret_cast<int *>(bnd + 4);
   const size_t lds1 = (size_t)ell * (ell + 1) * sizeof(double);
-  allow_lds(k_tri_eig, lds1);
-  hipLaunchKernelGGL(k_tri_eig, dim3(1), dim3(TNT), lds1, st, G, ell, lam, Vt, taus, Zg, fail, dflags);
+  allow_lds(k_tri_reduce, lds1);
+  hipLaunchKernelGGL(k_tri_reduce, dim3(1), dim3(TNT), lds1, st, G, ell, Vt, taus, Td, bnd, fail, dflags);
+  DSK_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_tri_vec, dim3(ell), dim3(256), 0, st, (const double *)Td, (const double *)bnd, ell, lam, Zg,
+                     fail, dflags);
   DSK_TRY(hipGetLastError());
   if (ell <= 64) {
     const size_t lds2 = (size_t)ell * 64 * sizeof(double);
     allow_lds(k_tri_back<16>, lds2);
-    hipLaunchKernelGGL(k_tri_back<16>, dim3(1), dim3(512), lds2, st, Vt, taus, Zg, ell, fail, U);
+    hipLaunchKernelGGL(k_tri_back<16>, dim3(1), dim3(512), lds2, st, Vt, taus, Zg, (const double *)lam,
+                       (const double *)Td, (const double *)bnd, ell, fail, U);
   } else {
     const size_t lds2 = (size_t)ell * 112 * sizeof(double);
     allow_lds(k_tri_back<28>, lds2);
-    hipLaunchKernelGGL(k_tri_back<28>, dim3(1), dim3(512), lds2, st, Vt, taus, Zg, ell, fail, U);
+    hipLaunchKernelGGL(k_tri_back<28>, dim3(1), dim3(512), lds2, st, Vt, taus, Zg, (const double *)lam,
+                       (const double *)Td, (const double *)bnd, ell, fail, U);
   }
   DSK_TRY(hipGetLastError());
   // fallback: the Jacobi core, which leaves at once unless the fail word is set

@@ -217,6 +217,23 @@ inline int atomicAdd(int *p, int v) { return __atomic_fetch_add(p, v, __ATOMIC_S
 inline unsigned atomicAdd(unsigned *p, unsigned v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
 inline unsigned atomicExch(unsigned *p, unsigned v) { return __atomic_exchange_n(p, v, __ATOMIC_SEQ_CST); }
 inline int atomicExch(int *p, int v) { return __atomic_exchange_n(p, v, __ATOMIC_SEQ_CST); }
+template <typename T>
+inline T simt_atomic_min(T *p, T v) {
+  T cur = __atomic_load_n(p, __ATOMIC_SEQ_CST);
+  while (v < cur && !__atomic_compare_exchange_n(p, &cur, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {
+  }
+  return cur;
+}
+template <typename T>
+inline T simt_atomic_max(T *p, T v) {
+  T cur = __atomic_load_n(p, __ATOMIC_SEQ_CST);
+  while (v > cur && !__atomic_compare_exchange_n(p, &cur, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {
+  }
+  return cur;
+}
+inline int atomicMin(int *p, int v) { return simt_atomic_min(p, v); }
+inline unsigned long long atomicMin(unsigned long long *p, unsigned long long v) { return simt_atomic_min(p, v); }
+inline int atomicMax(int *p, int v) { return simt_atomic_max(p, v); }
 
 inline long long __double_as_longlong(double d) { long long r; memcpy(&r, &d, 8); return r; }
 inline double __longlong_as_double(long long l) { double r; memcpy(&r, &l, 8); return r; }
