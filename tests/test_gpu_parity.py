@@ -204,6 +204,30 @@ def test_sketch_svd_exact_low_rank_recovery():
     assert np.abs(_up(V).T @ _up(V) - np.eye(6)).max() < 1e-12
 
 
+def test_sketch_svd_exactly_repeated_singular_values():
+    # a scaled partial permutation: sigma = 4, 4, 4, 2, 2, 2, 1, 1, 0.5, 0.5 exactly, the
+    # nonzeros on columns the start block samples; rank 10 < ell = 16, so the core Gram
+    # has exactly repeated eigenvalues and a cluster at zero (the eigensolver's cluster path)
+    say("svd repeated singular values")
+    m, ny, nx = 120, 24, 24
+    di = ores.di_index_2d(ny, nx, 2, 2)
+    cols = osk.nested_di_columns(len(di), 16)
+    sig = [4.0, 4.0, 4.0, 2.0, 2.0, 2.0, 1.0, 1.0, 0.5, 0.5]
+    A_np = np.zeros((m, ny * nx))
+    for i, sv in enumerate(sig):
+        A_np[3 * i + 1, di[cols[(3 * i) % 16]]] = sv
+    A = _A(A_np, torch.float32)
+    R = dsk().Restriction.di_grid(ny, nx, 2, 2)
+    U, S, V = dsk().sketch_svd(A, 6, R, q=0)
+    Uo, So, Vo, sig_all = _tpc(A_np, 6, {"kind": "index", "index": di})
+    _compare_svd(A_np, U, S, V, Uo, So, Vo, TOL[torch.float32])
+    Ug, Vg = _up(U), _up(V)
+    # every pair sits in a cluster (4, 4, 4 and 2, 2, 2): projectors only
+    assert svdcheck.compare_vectors(Ug, Uo, Vg, Vo, sig_all, 6, TOL[torch.float32], min_checked=0) == 0
+    assert np.abs(Ug.T @ Ug - np.eye(6)).max() < 1e-6
+    assert np.abs(Vg.T @ Vg - np.eye(6)).max() < 1e-6
+
+
 def test_sketch_svd_is_deterministic():
     say("svd determinism")
     A = _A(synth.advdiff_exact(256, 32, seed=9, r=256), torch.float32)
