@@ -26,8 +26,17 @@
 //     4th 32-row block of the K range; their accumulators are reduced in LDS
 //     in a fixed order (deterministic).  Small N is split over K across
 //     workgroups (grid.y) and summed by a second kernel in a fixed order.
+//   * TN form with 16-bit X (the BF16 / F16 snapshots, B^T = A^T Q): a
+//     workgroup owns 128 output rows j and sweeps K in 32-row chunks.  A
+//     chunk (32 x 128 values, 8 KB) arrives by row-contiguous 16-byte loads
+//     (prefetched three chunks ahead), goes to a double-buffered LDS tile (one
+//     barrier per chunk) and is read back k-contiguous by the transposing
+//     LDS read ds_read_b64_tr_b16 (two per 32 x 16 operand); wave w owns the
+//     ell tiles (w + blockIdx) mod 4 + 4 i and all eight j tiles, so each
+//     packed Y operand is read once per workgroup and chunk.
 // FP64 path: VALU kernel with LDS tiles (f64 FMA), same TN/NN forms.
 #include <algorithm>
+#include <type_traits>
 
 #include <map>
 #include <tuple>
@@ -173,6 +182,161 @@ __device__ __forceinline__ f32x4 mfma_bf16(uint4 a, uint4 b, f32x4 c) {
 __device__ __forceinline__ f32x4 mfma_f16(uint4 a, uint4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
                                                 0, 0, 0);
+}
+
+// ---------------------------------------------------------------- TN kernel for 16-bit X
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// ds_read_b64_tr_b16: in each aligned group of 16 lanes, lane i points at 4
+// consecutive 16-bit values (row i / 4, columns 4 (i % 4) .. + 3 of a 4 x 16
+// block); lane j receives column j of the block, rows 0 .. 3.
+__device__ __forceinline__ uint2 lds_read_tr16(const unsigned short *p) {
+  const i16x4 r = __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) i16x4 *)p);
+  return __builtin_bit_cast(uint2, r);
+}
+
+constexpr int TN16_W = 128;   // output rows (columns of X) per workgroup
+
+// VEC: X 16-byte aligned, ldx and N multiples of 8 (every 8-column group of a
+// row is one 16-byte load, wholly inside or wholly outside [0, N)).  Loads are
+// issued unconditionally (rows past K read row K - 1, groups past N read
+// columns 0 .. 7, prefetches past the range re-read the last chunk, an L2
+// hit), so the number of loads in flight is the same on every path and the
+// waits on them stay partial.
+template <int MODE, int NCT, bool VEC>
+__global__ void __launch_bounds__(256) k_stream_tn16(const unsigned short *__restrict__ X, int64_t K, int64_t N,
+                                                     int64_t ldx, const uint4 *__restrict__ Yp, int ell,
+                                                     float *__restrict__ out, int64_t ldo, int kb_per_split) {
+  constexpr int W = TN16_W, LDW = W + 8;       // LDS row stride 272 bytes
+  constexpr int NCW = (NCT + 3) / 4;           // ell tiles per wave
+  __shared__ __attribute__((aligned(16))) unsigned short xs[2][32][LDW];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4, i = lane & 15;
+  const int nkb = (int)((K + 31) / 32);
+  const int kb_begin = blockIdx.y * kb_per_split;
+  const int kb_end = min(nkb, kb_begin + kb_per_split);
+  const int64_t j0 = (int64_t)blockIdx.x * W;
+  const int wsh = (wave + (int)blockIdx.x) & 3;   // rotates the lighter wave over the SIMDs
+  // loads: thread t fetches rows t / 16 and t / 16 + 16 of the chunk, columns 8 (t % 16) .. + 7
+  const int lr = t >> 4, lc = 8 * (t & 15);
+  const int64_t gj = j0 + lc;
+  const int64_t gjc = gj < N ? gj : 0;              // VEC: the whole 8-column group is inside or outside
+  // (16-byte values as a native vector type: a struct copy from global memory
+  // would become a memcpy that keeps the prefetch slots out of registers)
+  auto gload = [&](int kb, u32x4 (&v)[2]) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t r = (int64_t)kb * 32 + lr + 16 * u;
+      if constexpr (VEC) {
+        v[u] = *reinterpret_cast<const u32x4 *>(X + (r < K ? r : K - 1) * ldx + gjc);
+      } else {
+        unsigned e[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) e[q] = (r < K && gj + q < N) ? X[r * ldx + gj + q] : 0u;
+        v[u] = u32x4{e[0] | (e[1] << 16), e[2] | (e[3] << 16), e[4] | (e[5] << 16), e[6] | (e[7] << 16)};
+      }
+    }
+  };
+  // (a wave with one ell tile also loads a second, clamped one, unused: loads stay unconditional)
+  auto yload = [&](int kb, uint4 (&ya)[NCW], uint4 (&yb)[NCW]) {
+#pragma unroll
+    for (int cw = 0; cw < NCW; ++cw) {
+      const int ct = min(wsh + 4 * cw, NCT - 1);
+      const uint4 *src = Yp + ((int64_t)(kb * NCT + ct) * 2) * 64 + lane;
+      ya[cw] = src[0];
+      yb[cw] = src[64];
+    }
+  };
+  f32x4 acc[NCW][8];
+#pragma unroll
+  for (int cw = 0; cw < NCW; ++cw)
+#pragma unroll
+    for (int jt = 0; jt < 8; ++jt) acc[cw][jt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // X chunks are fetched XD chunks ahead and the packed Y one chunk ahead; Y's
+  // loads go out before X's, so that waiting for Y (loads complete in issue
+  // order) leaves the later X fetches in flight
+  constexpr int XD = 3;
+  u32x4 v[XD][2];
+  uint4 ya[2][NCW], yb[2][NCW];
+  if (kb_begin >= kb_end) return;
+  const int kb_last = kb_end - 1;
+  yload(kb_begin, ya[0], yb[0]);
+#pragma unroll
+  for (int s = 0; s < XD; ++s) gload(min(kb_begin + s, kb_last), v[s]);
+  int buf = 0;
+  // one chunk; S (a compile-time constant) picks the X slot S mod XD and the Y slot S mod 2
+  auto step = [&](int kb, auto SC) {
+    constexpr int S = decltype(SC)::value, sx = S % XD, sy = S & 1;
+    // LDS copy of the fetched chunk.  VEC stores what it read: a row past K (a
+    // copy of row K - 1) meets packed-Y rows that are zero, a group past N (a
+    // copy of columns 0 .. 7) feeds output rows that are never stored.
+    *reinterpret_cast<u32x4 *>(&xs[buf][lr][lc]) = v[sx][0];
+    *reinterpret_cast<u32x4 *>(&xs[buf][lr + 16][lc]) = v[sx][1];
+    __syncthreads();   // (also: every wave is done with this buffer's previous chunk)
+    yload(min(kb + 1, kb_last), ya[sy ^ 1], yb[sy ^ 1]);
+    gload(min(kb + XD, kb_last), v[sx]);
+#pragma unroll
+    for (int jt = 0; jt < 8; ++jt) {
+      // rows 8 g .. 8 g + 7 of column 16 jt + i: two 4 x 16 blocks, lane i of the group at row i / 4
+      const unsigned short *p0 = &xs[buf][8 * g + (i >> 2)][16 * jt + 4 * (i & 3)];
+      const uint2 lo = lds_read_tr16(p0), hi = lds_read_tr16(p0 + 4 * LDW);
+      const uint4 xop = make_uint4(lo.x, lo.y, hi.x, hi.y);
+#pragma unroll
+      for (int cw = 0; cw < NCW; ++cw) {
+        if (wsh + 4 * cw >= NCT) continue;
+        if constexpr (MODE == MODE_BF16X) {
+          acc[cw][jt] = mfma_bf16(ya[sy][cw], xop, acc[cw][jt]);
+          acc[cw][jt] = mfma_bf16(yb[sy][cw], xop, acc[cw][jt]);
+        } else {
+          acc[cw][jt] = mfma_f16(ya[sy][cw], xop, acc[cw][jt]);
+          acc[cw][jt] = mfma_f16(yb[sy][cw], xop, acc[cw][jt]);
+        }
+      }
+    }
+    buf ^= 1;
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  using I3 = std::integral_constant<int, 3>;
+  using I4 = std::integral_constant<int, 4>;
+  using I5 = std::integral_constant<int, 5>;
+  static_assert(6 % XD == 0, "six steps cover the X and Y slot cycles");
+  int kb = kb_begin;
+  for (; kb + 6 <= kb_end; kb += 6) {
+    step(kb, I0{});
+    step(kb + 1, I1{});
+    step(kb + 2, I2{});
+    step(kb + 3, I3{});
+    step(kb + 4, I4{});
+    step(kb + 5, I5{});
+  }
+  if (kb < kb_end) step(kb, I0{});
+  if (kb + 1 < kb_end) step(kb + 1, I1{});
+  if (kb + 2 < kb_end) step(kb + 2, I2{});
+  if (kb + 3 < kb_end) step(kb + 3, I3{});
+  if (kb + 4 < kb_end) step(kb + 4, I4{});
+  float *dst = out + (int64_t)blockIdx.y * N * ldo;
+#pragma unroll
+  for (int cw = 0; cw < NCW; ++cw) {
+    const int ct = wsh + 4 * cw;
+    if (ct >= NCT) continue;
+    const int c0 = ct * 16 + 4 * g;
+#pragma unroll
+    for (int jt = 0; jt < 8; ++jt) {
+      const int64_t j = j0 + 16 * jt + i;
+      if (j >= N) continue;
+      const f32x4 a = acc[cw][jt];
+      float *p = dst + j * ldo + c0;
+      if (c0 + 3 < ell && ((reinterpret_cast<uintptr_t>(p) & 15) == 0)) {
+        *reinterpret_cast<float4 *>(p) = make_float4(a[0], a[1], a[2], a[3]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (c0 + r < ell) p[r] = a[r];
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------- MFMA stream kernel
@@ -523,6 +687,35 @@ int mode_of(int dtype, int mode) {
 
 // The split of a launch over K and the workspace it uses: the packed Y (16-bit
 // and F32 inputs) and, when K is split, the per-split partial outputs.
+// The TN form with 16-bit X runs on k_stream_tn16.
+bool use_tn16(bool nn, int md) { return !nn && (md == MODE_BF16X || md == MODE_F16X); }
+
+template <int MODE, bool VEC>
+int launch_tn16_v(hipStream_t st, int nct, dim3 grid, const unsigned short *x, int64_t K, int64_t N, int64_t ldx,
+                  const uint4 *Yp, int ell, float *out, int64_t ldo, int kbps) {
+#define DSK_TN16(NC)                                                                                     \
+  case NC:                                                                                               \
+    hipLaunchKernelGGL((k_stream_tn16<MODE, NC, VEC>), grid, dim3(256), 0, st, x, K, N, ldx, Yp, ell, out, ldo, \
+                       kbps);                                                                            \
+    break;
+  switch (nct) {
+    DSK_TN16(1) DSK_TN16(2) DSK_TN16(3) DSK_TN16(4) DSK_TN16(5) DSK_TN16(6) DSK_TN16(7) DSK_TN16(8)
+    default: return -1;
+  }
+#undef DSK_TN16
+  DSK_TRY(hipGetLastError());
+  return 0;
+}
+
+template <int MODE>
+int launch_tn16(hipStream_t st, int nct, dim3 grid, const void *X, int64_t K, int64_t N, int64_t ldx,
+                const uint4 *Yp, int ell, float *out, int64_t ldo, int kbps) {
+  const unsigned short *x = reinterpret_cast<const unsigned short *>(X);
+  const bool vec = (N & 7) == 0 && (ldx & 7) == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0;
+  return vec ? launch_tn16_v<MODE, true>(st, nct, grid, x, K, N, ldx, Yp, ell, out, ldo, kbps)
+             : launch_tn16_v<MODE, false>(st, nct, grid, x, K, N, ldx, Yp, ell, out, ldo, kbps);
+}
+
 struct StreamPlan {
   Plan p;
   size_t yp_bytes, part_bytes;
@@ -540,7 +733,7 @@ StreamPlan stream_plan(bool nn, int dtype, int64_t K, int64_t N, int ell, int mo
   const int jt = nct <= 4 ? 4 : 2;
   const int64_t nkb = (K + 31) / 32;
   sp.yp_bytes = ((size_t)nkb * nct * 3 * 64 * sizeof(uint4) + 255) & ~size_t(255);
-  sp.p = plan_split(K, N, 16 * jt, 32, cu_count, 4);
+  sp.p = plan_split(K, N, use_tn16(nn, md) ? TN16_W : 16 * jt, 32, cu_count, 4);
   if (const int tn = tuned_ns(md, nn, K, N, ell); tn > 0) {
     // an autotuned split, within the partial buffers stream_ws_bytes provides (nkb / 4)
     const int64_t ns = std::max<int64_t>(1, std::min<int64_t>(tn, std::max<int64_t>(1, nkb / 4)));
@@ -612,6 +805,10 @@ int stream_any(hipStream_t st, bool nn, const void *X, int dtype, int64_t K, int
   dim3 grid(p.gx, (unsigned)p.nsplit);
   if (ev0) DSK_TRY(hipEventRecord(ev0, st));
   int r;
+  if (use_tn16(nn, md)) {
+    r = md == MODE_BF16X ? launch_tn16<MODE_BF16X>(st, nct, grid, X, K, N, ldx, Yp, ell, dst, ldd, p.kb_per_split)
+                         : launch_tn16<MODE_F16X>(st, nct, grid, X, K, N, ldx, Yp, ell, dst, ldd, p.kb_per_split);
+  } else {
   switch (md) {
     case MODE_SPLIT6:
       r = nn ? launch_mfma_nct<MODE_SPLIT6, true>(st, nct, grid, X, K, N, ldx, Yp, ell, dst, ldd, p.kb_per_split)
@@ -625,13 +822,12 @@ int stream_any(hipStream_t st, bool nn, const void *X, int dtype, int64_t K, int
       r = nn ? launch_mfma_nct<MODE_F32, true>(st, nct, grid, X, K, N, ldx, Yp, ell, dst, ldd, p.kb_per_split)
              : launch_mfma_nct<MODE_F32, false>(st, nct, grid, X, K, N, ldx, Yp, ell, dst, ldd, p.kb_per_split);
       break;
-    case MODE_BF16X:
-      r = nn ? launch_mfma_nct<MODE_BF16X, true>(st, nct, grid, X, K, N, ldx, Yp, ell, dst, ldd, p.kb_per_split)
-             : launch_mfma_nct<MODE_BF16X, false>(st, nct, grid, X, K, N, ldx, Yp, ell, dst, ldd, p.kb_per_split);
+    case MODE_BF16X:   // NN form (the TN form took k_stream_tn16 above)
+      r = launch_mfma_nct<MODE_BF16X, true>(st, nct, grid, X, K, N, ldx, Yp, ell, dst, ldd, p.kb_per_split);
       break;
     default:
-      r = nn ? launch_mfma_nct<MODE_F16X, true>(st, nct, grid, X, K, N, ldx, Yp, ell, dst, ldd, p.kb_per_split)
-             : launch_mfma_nct<MODE_F16X, false>(st, nct, grid, X, K, N, ldx, Yp, ell, dst, ldd, p.kb_per_split);
+      r = launch_mfma_nct<MODE_F16X, true>(st, nct, grid, X, K, N, ldx, Yp, ell, dst, ldd, p.kb_per_split);
+  }
   }
   if (ev1) DSK_TRY(hipEventRecord(ev1, st));
   if (r) return r;

@@ -61,6 +61,8 @@ def build(verbose: bool = False) -> str:
         s = re.sub(r"extern __shared__ (\w+) (\w+)\[\];", r"\1 *\2 = (\1 *)simt::dyn_lds();", s)
         # register-class optimisation barriers (empty GPU asm) have no host meaning
         s = re.sub(r'asm volatile\(""\s*:\s*"\+v"\([^;]*\)\);', ";", s)
+        # LDS address-space qualifiers: host memory has one address space
+        s = s.replace("__attribute__((address_space(3)))", "")
         if os.path.basename(p) in ("cpqr.hip", "rowid_reg.hip"):
             # workgroups of the one-launch factorization run together: one copy of
             # each static LDS variable per resident block

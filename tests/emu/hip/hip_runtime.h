@@ -181,6 +181,19 @@ inline simt_f4 simt_mfma_k32(V a, V b, simt_f4 c) {
   simt::group_sync(64);
   return d;
 }
+typedef short simt_i16x4 __attribute__((ext_vector_type(4)));
+// ds_read_b64_tr_b16: in each aligned group of 16 lanes, lane i points at 4
+// consecutive 16-bit values (row i / 4, columns 4 (i % 4) .. + 3 of a 4 x 16
+// block); lane j receives column j of the block, rows 0 .. 3.
+inline simt_i16x4 __builtin_amdgcn_ds_read_tr16_b64_v4i16(const void *p) {
+  const int t = simt::ctx.flat, lane = t & 63, base = t - (lane & 15), j = lane & 15;
+  simt::put(0, p);
+  simt::group_sync(16);
+  simt_i16x4 r;
+  for (int y = 0; y < 4; ++y) r[y] = static_cast<const short *>(simt::get<const void *>(base + 4 * y + (j >> 2), 0))[j & 3];
+  simt::group_sync(16);
+  return r;
+}
 inline simt_f4 __builtin_amdgcn_mfma_f32_16x16x32_bf16(simt_bf8 a, simt_bf8 b, simt_f4 c, int, int, int) {
   return simt_mfma_k32(a, b, c);
 }
