@@ -144,12 +144,12 @@ def time_to_eps(torch, dsketch, variants, A64_dev, k, R, tail, eps=0.05):
     return out
 
 
-def roofline_of(kms, nlaunch, kern_bytes, traffic):
+def roofline_of(kms, nlaunch, kern_bytes, traffic, kernel):
     kern_ms = kms / max(nlaunch, 1)
     achieved = kern_bytes / (kern_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_stream_mfma (B^T = A^T Q)", "avg_ms": round(kern_ms, 5), "launches": nlaunch,
+            "kernel": kernel + " (B^T = A^T Q)", "avg_ms": round(kern_ms, 5), "launches": nlaunch,
             "bytes_per_launch": kern_bytes}
 
 
@@ -165,7 +165,7 @@ def c2_leg(torch, dsketch, synth, a, dev, src_hash):
     ms, nl, kms = time_step(torch, dsketch, step, a.warmup, a.steps)
     b_svd, b_id = algorithmic_bytes(m, n, s, k, q, 4)
     rl = roofline_of(kms, nl, 4 * m * n + 4 * n * ell + 4 * m * ell,
-                     traffic_from_profile(src_hash, "stream_tn_c2_counters.json"))
+                     traffic_from_profile(src_hash, "stream_tn_c2_counters.json"), "k_stream_mfma")
     out = {"workload": f"advection-diffusion snapshots {m}x{N}x{N} f32 (sigma_j = j^-0.5, 1e-3 noise), direct "
                        f"injection {f}x{f} (s={s}), k={k}, l={ell}: sketch SVD q={q} + row ID q=0",
            "ms_per_step": round(ms, 4), "value": round((b_svd + b_id) / (ms * 1e-3) / 1e9, 2), "unit": "GB/s",
@@ -235,7 +235,7 @@ def main():
     step_bytes = b_svd + b_id
     value = step_bytes / (ms_per_step * 1e-3) / 1e9
     roofline = roofline_of(kms, nlaunch, e * m * n + 4 * n * ell + 4 * m * ell,
-                           traffic_from_profile(src_hash, "stream_tn_c3_counters.json"))
+                           traffic_from_profile(src_hash, "stream_tn_c3_counters.json"), "k_stream_tn16")
 
     breakdown = tte = c2 = None
     if not a.no_breakdown:

@@ -618,12 +618,15 @@ int id_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, in
     double *nu1 = c.take<double>(m);
     double *Rk = c.take<double>((size_t)k * m);
     // one launch for all pivot steps when the rows fit the registers of one
-    // workgroup per compute unit; W = A_c held as FP32 where its values are FP32
-    // numbers (an index restriction of FP32 / 16-bit data, no power step)
-    const bool w32 = dtype != DSK_F64 && q == 0 && !od.id_projected && R->kind == DSK_R_INDEX;
-    const size_t rwsb = od.id_per_step ? 0 : rowid_reg_ws_bytes(m, cols, k, w32 ? 0 : 1, h->cu_count);
+    // workgroup per compute unit; W = A_c held in the storage dtype where it is
+    // a plain gather of stored values (an index restriction of FP32 / 16-bit
+    // data, no power step): FP32, or the 16-bit values themselves
+    const bool wstore = dtype != DSK_F64 && q == 0 && !od.id_projected && R->kind == DSK_R_INDEX;
+    const int wdt = wstore ? dtype : DSK_F64;
+    const size_t rwsb = od.id_per_step ? 0 : rowid_reg_ws_bytes(m, cols, k, wdt, h->cu_count);
     char *rws = rwsb ? c.take<char>(rwsb) : nullptr;
-    float *Ac32 = (rwsb && w32) ? c.take<float>((size_t)m * s) : nullptr;   // (carved in the dry pass too)
+    // (carved in the dry pass too)
+    char *Acs = (rwsb && wstore) ? c.take<char>((size_t)m * s * (dtype == DSK_F32 ? 4 : 2)) : nullptr;
     // a given S arrives in the work dtype; the ID works in FP64
     const bool s_conv = od.id_projected && od.S && dtype != DSK_F64;
     double *S64 = s_conv ? c.take<double>((size_t)s * ell) : nullptr;
@@ -639,9 +642,10 @@ int id_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, in
       continue;
     }
     hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, st, h->dflags);
-    if (rwsb && w32) {
-      DSK_RET(launch_restrict(st, A, dtype, m, n, lda, R, s, 0, Ac32, nullptr, h->dflags));
-      DSK_RET(launch_rowid_reg(st, Ac32, 0, m, s, k, nu0, Rk, skel, rws, h->cu_count, h->dflags));
+    if (rwsb && wstore) {
+      if (dtype == DSK_F32) DSK_RET(launch_restrict(st, A, dtype, m, n, lda, R, s, 0, Acs, nullptr, h->dflags));
+      else DSK_RET(launch_gather_cols16(st, A, m, n, lda, R, s, Acs));
+      DSK_RET(launch_rowid_reg(st, Acs, wdt, m, s, k, nu0, Rk, skel, rws, h->cu_count, h->dflags));
       DSK_RET(launch_id_solve(st, Rk, skel, nu0, m, k, P, h->dflags));
       if (skel_rows) DSK_RET(launch_gather_rows(st, A, dtype, m, n, lda, skel, k, skel_rows));
       DSK_TRY(hipGetLastError());
@@ -687,7 +691,7 @@ int id_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, in
     }
     const double *nu_final;
     if (rwsb) {
-      DSK_RET(launch_rowid_reg(st, Wcur, 1, m, cols, k, nu0, Rk, skel, rws, h->cu_count, h->dflags));
+      DSK_RET(launch_rowid_reg(st, Wcur, DSK_F64, m, cols, k, nu0, Rk, skel, rws, h->cu_count, h->dflags));
       nu_final = nu0;
     } else {
       DSK_RET(launch_cpqr(st, Wcur, m, cols, k, nu0, nu1, Rk, skel, h->dflags));

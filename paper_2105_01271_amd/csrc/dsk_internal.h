@@ -123,6 +123,9 @@ int launch_select_cols(hipStream_t st, const void *Ac, int work_f64, int64_t m, 
                        int64_t ldc, int ell, void *Y);
 int launch_gather_rows(hipStream_t st, const void *A, int dtype, int64_t m, int64_t n, int64_t lda,
                        const int64_t *rows, int k, void *out);
+// out (m x s, 16-bit) = A(:, index) of a DSK_R_INDEX restriction, A 16-bit, bits unchanged
+int launch_gather_cols16(hipStream_t st, const void *A, int64_t m, int64_t n, int64_t lda, const dsk_restriction *R,
+                         int64_t s, void *out);
 int launch_convert(hipStream_t st, const void *src, int src_f64, void *dst, int dst_f64, int64_t count);
 int launch_transpose(hipStream_t st, const void *src, int f64, int64_t rows, int64_t cols, void *dst);
 
@@ -236,11 +239,12 @@ int stream_autotune(hipStream_t st, const void *X, int dtype, int64_t K, int64_t
 int launch_cpqr(hipStream_t st, double *W, int64_t m, int64_t s, int k, double *nu0, double *nu1,
                 double *Rk, int64_t *piv, int *dflags);
 // rowid_reg.hip: all k pivot steps in one launch with W's rows in registers
-// (left-looking form, downdated norms); 0 bytes = shape not supported.  W is
-// FP64 (w_f64) or FP32 holding exact FP32 values.  Outputs as launch_cpqr's,
+// (left-looking form, downdated norms); 0 bytes = shape not supported.  W's
+// dtype wdt: DSK_F64, or DSK_F32 / DSK_BF16 / DSK_F16 holding the stored values
+// exactly (products and sums in FP64 either way).  Outputs as launch_cpqr's,
 // final norms in nu_final.
-size_t rowid_reg_ws_bytes(int64_t m, int64_t s, int k, int w_f64, int cu_count);
-int launch_rowid_reg(hipStream_t st, const void *W, int w_f64, int64_t m, int64_t s, int k, double *nu_final,
+size_t rowid_reg_ws_bytes(int64_t m, int64_t s, int k, int wdt, int cu_count);
+int launch_rowid_reg(hipStream_t st, const void *W, int wdt, int64_t m, int64_t s, int k, double *nu_final,
                      double *Rk, int64_t *piv, void *ws, int cu_count, int *dflags);
 int launch_id_solve(hipStream_t st, const double *Rk, const int64_t *piv, const double *nu_final,
                     int64_t m, int k, double *P, int *dflags);

@@ -171,6 +171,15 @@ __global__ void k_gather_rows(const T *__restrict__ A, int64_t m, int64_t n, int
     out[(int64_t)r * n + c] = ok ? A[src + c] : T(0);
 }
 
+// out[i, c] = A[i, idx[c]] for 16-bit storage, the bits copied unchanged
+__global__ void __launch_bounds__(256) k_gather_cols16(const unsigned short *__restrict__ A, int64_t m, int64_t lda,
+                                                       const int64_t *__restrict__ idx, int64_t s,
+                                                       unsigned short *__restrict__ out) {
+  const int64_t i = blockIdx.y;
+  for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < s; c += (int64_t)gridDim.x * 256)
+    out[i * s + c] = A[i * lda + idx[c]];
+}
+
 template <typename S, typename D>
 __global__ void k_convert(const S *__restrict__ src, D *__restrict__ dst, int64_t count) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
@@ -345,6 +354,16 @@ int launch_fro2(hipStream_t st, const void *A, int dtype, int64_t m, int64_t n, 
   }
   DSK_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, part, nparts, out);
+  DSK_TRY(hipGetLastError());
+  return 0;
+}
+
+int launch_gather_cols16(hipStream_t st, const void *A, int64_t m, int64_t n, int64_t lda, const dsk_restriction *R,
+                         int64_t s, void *out) {
+  if (R->kind != DSK_R_INDEX || !R->index || m < 1 || s < 1 || n < 1 || m > 65535) return -1;
+  const unsigned gx = (unsigned)std::min<int64_t>((s + 255) / 256, 64);
+  hipLaunchKernelGGL(k_gather_cols16, dim3(gx, (unsigned)m), dim3(256), 0, st, (const unsigned short *)A, m, lda,
+                     R->index, s, (unsigned short *)out);
   DSK_TRY(hipGetLastError());
   return 0;
 }

@@ -42,6 +42,7 @@
 
 #include "devsync.h"
 #include "dsk_internal.h"
+#include "wavechol.h"
 
 namespace {
 
@@ -88,28 +89,67 @@ __device__ __forceinline__ bool wait_word(const unsigned long long *wp, int step
 
 template <typename T>
 __device__ __forceinline__ double to_f64(T v) { return (double)v; }
+__device__ __forceinline__ double to_f64(__bf16 v) { return (double)(float)v; }
+__device__ __forceinline__ double to_f64(_Float16 v) { return (double)(float)v; }
+
+// 16 bytes of T as a native vector (a struct copy from global memory would
+// become a memcpy that keeps the values out of registers)
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct Vec16<__bf16> { typedef __bf16 type __attribute__((ext_vector_type(8))); };
+template <> struct Vec16<_Float16> { typedef _Float16 type __attribute__((ext_vector_type(8))); };
+
+// The EPT elements of row i that thread t holds: runs of VE = 16 / sizeof(T)
+// consecutive columns, VE t + NT VE q + v (q < EPT / VE), fetched with 16-byte
+// loads when rows start 16-byte aligned (vec); else one element per load.
+template <typename T, int NT, int EPT>
+__device__ __forceinline__ void load_row(const T *__restrict__ W, int64_t m, int64_t s, int64_t i, bool vec,
+                                         T (&dst)[EPT]) {
+  constexpr int VE = 16 / (int)sizeof(T);
+  static_assert(EPT % VE == 0, "whole 16-byte runs per thread");
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < EPT / VE; ++q) {
+    const int64_t e0 = (int64_t)VE * t + (int64_t)NT * VE * q;
+    if (vec && i < m && e0 + VE <= s) {
+      const typename Vec16<T>::type x = *reinterpret_cast<const typename Vec16<T>::type *>(W + i * s + e0);
+#pragma unroll
+      for (int v = 0; v < VE; ++v) dst[q * VE + v] = x[v];
+    } else {
+#pragma unroll
+      for (int v = 0; v < VE; ++v) dst[q * VE + v] = (i < m && e0 + v < s) ? W[i * s + e0 + v] : T(0);
+    }
+  }
+}
+
+// Sum over the wave in lane 0: DPP sums within each row of 16 lanes, then the
+// four row sums in row order (no LDS round trips).
+__device__ __forceinline__ double wave_total(double v) {
+  v = wc::row16_sum(v);
+  return (wc::readlane_f64(v, 0) + wc::readlane_f64(v, 16)) + (wc::readlane_f64(v, 32) + wc::readlane_f64(v, 48));
+}
 
 // Sum over the workgroup of v[r] for each r < R (wave sums, then waves in a
-// fixed order); the totals land in out[r].  Called by all threads.
+// fixed order); thread r < R receives the total of v[r].  One barrier; the
+// caller keeps a barrier between this call and the next (red is reused).
 template <int NW, int R>
-__device__ __forceinline__ void block_sums(double (&v)[R], double (*red)[R], double *out) {
+__device__ __forceinline__ double block_sums(double (&v)[R], double (*red)[R]) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const double a = wsum(v[r]);
+    const double a = wave_total(v[r]);
     if (lane == 0) red[wave][r] = a;
   }
   __syncthreads();
-  if (t < R) {
-    double a = 0.0;
+  double a = 0.0;
+  if (t < R)
     for (int w = 0; w < NW; ++w) a += red[w][t];
-    out[t] = a;
-  }
-  __syncthreads();
+  return a;
 }
 
 template <typename T, int NT, int RPW, int EPT>
-__global__ void __launch_bounds__(NT) k_rowid_reg(const T *__restrict__ W, int64_t m, int64_t s, int k,
+__global__ void __launch_bounds__(NT) k_rowid_reg(const T *__restrict__ W, int64_t m, int64_t s, int k, int vec,
                                                   unsigned long long *words, double *nuG, int *abort_flag, double *__restrict__ nu_final, double *Rk,
                                                   int64_t *__restrict__ piv, int *__restrict__ dflags) {
   constexpr int NW = NT / 64;
@@ -117,7 +157,6 @@ __global__ void __launch_bounds__(NT) k_rowid_reg(const T *__restrict__ W, int64
   const int G = gridDim.x, gid = blockIdx.x;
   __shared__ double red[NW][RPW];
   __shared__ unsigned long long bk[NW];
-  __shared__ double num[RPW];
   __shared__ double nu_sh[RPW];
   __shared__ int live_sh[RPW];
   __shared__ double cl[RPW][KMAX];     // c_{i,l} of this workgroup's rows
@@ -131,14 +170,7 @@ __global__ void __launch_bounds__(NT) k_rowid_reg(const T *__restrict__ W, int64
   const int64_t row0 = (int64_t)gid * RPW;
   T w[RPW][EPT];
 #pragma unroll
-  for (int r = 0; r < RPW; ++r) {
-    const int64_t i = row0 + r;
-#pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-      const int64_t e = t + (int64_t)NT * u;
-      w[r][u] = (i < m && e < s) ? W[i * s + e] : T(0);
-    }
-  }
+  for (int r = 0; r < RPW; ++r) load_row<T, NT, EPT>(W, m, s, row0 + r, vec != 0, w[r]);
   {
     double v[RPW];
 #pragma unroll
@@ -148,7 +180,8 @@ __global__ void __launch_bounds__(NT) k_rowid_reg(const T *__restrict__ W, int64
       for (int u = 0; u < EPT; ++u) a = fma(to_f64(w[r][u]), to_f64(w[r][u]), a);
       v[r] = a;
     }
-    block_sums<NW, RPW>(v, red, nu_sh);
+    const double a = block_sums<NW, RPW>(v, red);
+    if (t < RPW) nu_sh[t] = a;
   }
   if (t < RPW) {
     live_sh[t] = (row0 + t < m) ? 1 : 0;
@@ -201,7 +234,10 @@ __global__ void __launch_bounds__(NT) k_rowid_reg(const T *__restrict__ W, int64
     if (stop_sh) break;
     const unsigned long long key = key_sh;
     const int64_t p = ((key >> 11) & ((1ull << 46) - 1)) ? (int64_t)(~key & 0x7FF) : m;
-    // ---- the pivot: its norm and coefficients from where its owner stored them, its row from W
+    // ---- the pivot: its row from W, its norm and coefficients from where its owner
+    // stored them, all requested at once (one round trip)
+    T wp[EPT];
+    load_row<T, NT, EPT>(W, m, s, p, vec != 0, wp);
     if (t == 0) {
       const double nup = (p < m) ? ds::ld_dev(&nuG[(int64_t)par * m + p]) : 0.0;
       rjj_sh = nup > 0.0 ? sqrt(nup) : 0.0;
@@ -212,13 +248,6 @@ __global__ void __launch_bounds__(NT) k_rowid_reg(const T *__restrict__ W, int64
     if (t < j) cp[t] = (p < m) ? ds::ld_dev(&Rk[(int64_t)t * m + p]) : 0.0;
     __syncthreads();
     if (down_sh) break;
-    T wp[EPT];
-#pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-      const int64_t e = t + (int64_t)NT * u;
-      wp[u] = (p < m && e < s) ? W[p * s + e] : T(0);
-    }
-    __syncthreads();
     const double rjj = rjj_sh;
     if (gid == 0 && t == 0) {
       piv[j] = p;
@@ -241,12 +270,12 @@ __global__ void __launch_bounds__(NT) k_rowid_reg(const T *__restrict__ W, int64
       if (t < j) a = fma(-cp[t], cl[r][t], a);
       v[r] = a;
     }
-    block_sums<NW, RPW>(v, red, num);
+    const double num = block_sums<NW, RPW>(v, red);
     if (t < RPW) {
       const int64_t i = row0 + t;
       if (i == p) live_sh[t] = 0;
       if (live_sh[t]) {
-        const double c = rjj > 0.0 ? num[t] / rjj : 0.0;
+        const double c = rjj > 0.0 ? num / rjj : 0.0;
         cl[t][j] = c;
         ds::st_dev(&Rk[(int64_t)j * m + i], c);
         const double nn = nu_sh[t] - c * c;
@@ -358,7 +387,8 @@ Plan plan_of(int64_t m, int64_t s, int k, int esize, int cu_count) {
   Plan pl{0, 0, 0, 0};
   if (m < 1 || s < 1 || k < 1 || k > KMAX || m > 2048 || s > 8192) return pl;
   const int nt = 512;
-  const int ept = s <= 2048 ? 4 : (s <= 4096 ? 8 : 16);
+  // (at least one 16-byte run per thread)
+  const int ept = std::max(s <= 2048 ? 4 : (s <= 4096 ? 8 : 16), 16 / esize);
   for (int rpw : {4, 8}) {
     const int64_t g = (m + rpw - 1) / rpw;
     if (g > cu_count) continue;
@@ -382,10 +412,13 @@ int launch_typed(hipStream_t st, const T *W, int64_t m, int64_t s, int k, double
   int *abort_flag = reinterpret_cast<int *>(Wr + (size_t)m * s);
   hipLaunchKernelGGL(k_rowid_reset, dim3(1), dim3(256), 0, st, words, 2 * pl.g, abort_flag, piv, k);
   DSK_TRY(hipGetLastError());
+  // 16-byte runs need aligned row starts
+  const int vec = ((s * (int64_t)sizeof(T)) % 16 == 0 && (reinterpret_cast<uintptr_t>(W) & 15) == 0) ? 1 : 0;
 #define DSK_RREG(NT_, R_, E_)                                                                                   \
-  if (pl.nt == NT_ && pl.rpw == R_ && pl.ept == E_)                                                             \
-    hipLaunchKernelGGL((k_rowid_reg<T, NT_, R_, E_>), dim3(pl.g), dim3(NT_), 0, st, W, m, s, k, words, nuG,        \
-                       abort_flag, nu_final, Rk, piv, dflags);
+  if constexpr (E_ % (16 / (int)sizeof(T)) == 0 && R_ * E_ * (int)sizeof(T) / 4 <= 128)                       \
+    if (pl.nt == NT_ && pl.rpw == R_ && pl.ept == E_)                                                           \
+      hipLaunchKernelGGL((k_rowid_reg<T, NT_, R_, E_>), dim3(pl.g), dim3(NT_), 0, st, W, m, s, k, vec, words, nuG, \
+                         abort_flag, nu_final, Rk, piv, dflags);
   DSK_RREG(512, 4, 4) DSK_RREG(512, 8, 4) DSK_RREG(512, 4, 8) DSK_RREG(512, 8, 8) DSK_RREG(512, 4, 16)
   DSK_RREG(512, 8, 16)
 #undef DSK_RREG
@@ -398,17 +431,23 @@ int launch_typed(hipStream_t st, const T *W, int64_t m, int64_t s, int k, double
 
 }  // namespace
 
-size_t rowid_reg_ws_bytes(int64_t m, int64_t s, int k, int w_f64, int cu_count) {
-  const Plan pl = plan_of(m, s, k, w_f64 ? 8 : 4, cu_count);
+static int wsize(int wdt) { return wdt == DSK_F64 ? 8 : (wdt == DSK_F32 ? 4 : 2); }
+
+size_t rowid_reg_ws_bytes(int64_t m, int64_t s, int k, int wdt, int cu_count) {
+  const Plan pl = plan_of(m, s, k, wsize(wdt), cu_count);
   if (!pl.rpw) return 0;
   return (size_t)2 * pl.g * TAGW * 8 + (size_t)3 * m * 8 + (size_t)m * s * 8 + 256;
 }
 
-int launch_rowid_reg(hipStream_t st, const void *W, int w_f64, int64_t m, int64_t s, int k, double *nu_final,
+int launch_rowid_reg(hipStream_t st, const void *W, int wdt, int64_t m, int64_t s, int k, double *nu_final,
                      double *Rk, int64_t *piv, void *ws, int cu_count, int *dflags) {
-  const Plan pl = plan_of(m, s, k, w_f64 ? 8 : 4, cu_count);
+  const Plan pl = plan_of(m, s, k, wsize(wdt), cu_count);
   if (!pl.rpw) return -1;
   char *w = reinterpret_cast<char *>(ws);
-  if (w_f64) return launch_typed<double>(st, (const double *)W, m, s, k, nu_final, Rk, piv, w, pl, dflags);
-  return launch_typed<float>(st, (const float *)W, m, s, k, nu_final, Rk, piv, w, pl, dflags);
+  switch (wdt) {
+    case DSK_F64: return launch_typed<double>(st, (const double *)W, m, s, k, nu_final, Rk, piv, w, pl, dflags);
+    case DSK_F32: return launch_typed<float>(st, (const float *)W, m, s, k, nu_final, Rk, piv, w, pl, dflags);
+    case DSK_BF16: return launch_typed<__bf16>(st, (const __bf16 *)W, m, s, k, nu_final, Rk, piv, w, pl, dflags);
+    default: return launch_typed<_Float16>(st, (const _Float16 *)W, m, s, k, nu_final, Rk, piv, w, pl, dflags);
+  }
 }

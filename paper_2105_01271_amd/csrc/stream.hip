@@ -27,13 +27,14 @@
 //     in a fixed order (deterministic).  Small N is split over K across
 //     workgroups (grid.y) and summed by a second kernel in a fixed order.
 //   * TN form with 16-bit X (the BF16 / F16 snapshots, B^T = A^T Q): a
-//     workgroup owns 128 output rows j and sweeps K in 32-row chunks.  A
-//     chunk (32 x 128 values, 8 KB) arrives by row-contiguous 16-byte loads
-//     (prefetched three chunks ahead), goes to a double-buffered LDS tile (one
-//     barrier per chunk) and is read back k-contiguous by the transposing
-//     LDS read ds_read_b64_tr_b16 (two per 32 x 16 operand); wave w owns the
-//     ell tiles (w + blockIdx) mod 4 + 4 i and all eight j tiles, so each
-//     packed Y operand is read once per workgroup and chunk.
+//     workgroup owns W = 128 output rows j and sweeps K in 32-row chunks.  A
+//     chunk (32 x W values) arrives by row-contiguous 16-byte loads
+//     (prefetched three chunks ahead), goes to a double-buffered,
+//     bank-swizzled LDS tile (one barrier per chunk) and is
+//     read back k-contiguous by the transposing LDS read ds_read_b64_tr_b16
+//     (two per 32 x 16 operand); wave w owns the ell tiles
+//     (w + blockIdx) mod 4 + 4 i and all W / 16 j tiles, so each packed Y
+//     operand is read once per workgroup and chunk.
 // FP64 path: VALU kernel with LDS tiles (f64 FMA), same TN/NN forms.
 #include <algorithm>
 #include <type_traits>
@@ -196,7 +197,18 @@ __device__ __forceinline__ uint2 lds_read_tr16(const unsigned short *p) {
   return __builtin_bit_cast(uint2, r);
 }
 
-constexpr int TN16_W = 128;   // output rows (columns of X) per workgroup
+// Output rows (columns of X) per workgroup.  (256 would halve the packed-Y
+// traffic per byte of X, but its 2 x 16 accumulator tiles per wave leave one
+// wave per SIMD, too few loads in flight.)
+constexpr int TN16_W = 128;
+
+// LDS tile of a chunk: 32 rows of W 16-bit values, no padding; the 16-byte
+// unit u of row r sits at unit u ^ swz(r).  A transposing read of a 16-lane
+// group touches rows r0 .. r0 + 3 (units 2 jt, 2 jt + 1), the other group of
+// its half-wave rows r0 + 8 .. r0 + 11: with swz(r) = 2 ((r & 3) | ((r >> 3 & 1) << 2))
+// those 16 units land on 16 different 4-bank slots, so every read is free of
+// bank conflicts; a 16-byte store stays contiguous.
+__device__ __forceinline__ int tn16_swz(int r) { return 2 * ((r & 3) | (((r >> 3) & 1) << 2)); }
 
 // VEC: X 16-byte aligned, ldx and N multiples of 8 (every 8-column group of a
 // row is one 16-byte load, wholly inside or wholly outside [0, N)).  Loads are
@@ -204,36 +216,40 @@ constexpr int TN16_W = 128;   // output rows (columns of X) per workgroup
 // columns 0 .. 7, prefetches past the range re-read the last chunk, an L2
 // hit), so the number of loads in flight is the same on every path and the
 // waits on them stay partial.
-template <int MODE, int NCT, bool VEC>
+template <int MODE, int NCT, bool VEC, int W>
 __global__ void __launch_bounds__(256) k_stream_tn16(const unsigned short *__restrict__ X, int64_t K, int64_t N,
                                                      int64_t ldx, const uint4 *__restrict__ Yp, int ell,
                                                      float *__restrict__ out, int64_t ldo, int kb_per_split) {
-  constexpr int W = TN16_W, LDW = W + 8;       // LDS row stride 272 bytes
+  constexpr int UPR = W / 8;                   // 16-byte units per row
+  constexpr int RPS = 256 / UPR;               // rows one pass of the 256 threads covers
+  constexpr int NL = 32 / RPS;                 // 16-byte loads per thread and chunk
+  constexpr int NJT = W / 16;                  // j tiles
   constexpr int NCW = (NCT + 3) / 4;           // ell tiles per wave
-  __shared__ __attribute__((aligned(16))) unsigned short xs[2][32][LDW];
+  constexpr int XD = W == 128 ? 3 : 2;         // chunks fetched ahead
+  __shared__ __attribute__((aligned(16))) unsigned short xs[2][32][W];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4, i = lane & 15;
   const int nkb = (int)((K + 31) / 32);
   const int kb_begin = blockIdx.y * kb_per_split;
   const int kb_end = min(nkb, kb_begin + kb_per_split);
   const int64_t j0 = (int64_t)blockIdx.x * W;
   const int wsh = (wave + (int)blockIdx.x) & 3;   // rotates the lighter wave over the SIMDs
-  // loads: thread t fetches rows t / 16 and t / 16 + 16 of the chunk, columns 8 (t % 16) .. + 7
-  const int lr = t >> 4, lc = 8 * (t & 15);
-  const int64_t gj = j0 + lc;
+  // loads: thread t fetches rows t / UPR + RPS q of the chunk, columns 8 (t % UPR) .. + 7
+  const int lr = t / UPR, lu = t % UPR;
+  const int64_t gj = j0 + 8 * lu;
   const int64_t gjc = gj < N ? gj : 0;              // VEC: the whole 8-column group is inside or outside
   // (16-byte values as a native vector type: a struct copy from global memory
   // would become a memcpy that keeps the prefetch slots out of registers)
-  auto gload = [&](int kb, u32x4 (&v)[2]) {
+  auto gload = [&](int kb, u32x4 (&v)[NL]) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int64_t r = (int64_t)kb * 32 + lr + 16 * u;
+    for (int q = 0; q < NL; ++q) {
+      const int64_t r = (int64_t)kb * 32 + lr + RPS * q;
       if constexpr (VEC) {
-        v[u] = *reinterpret_cast<const u32x4 *>(X + (r < K ? r : K - 1) * ldx + gjc);
+        v[q] = *reinterpret_cast<const u32x4 *>(X + (r < K ? r : K - 1) * ldx + gjc);
       } else {
         unsigned e[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) e[q] = (r < K && gj + q < N) ? X[r * ldx + gj + q] : 0u;
-        v[u] = u32x4{e[0] | (e[1] << 16), e[2] | (e[3] << 16), e[4] | (e[5] << 16), e[6] | (e[7] << 16)};
+        for (int c = 0; c < 8; ++c) e[c] = (r < K && gj + c < N) ? X[r * ldx + gj + c] : 0u;
+        v[q] = u32x4{e[0] | (e[1] << 16), e[2] | (e[3] << 16), e[4] | (e[5] << 16), e[6] | (e[7] << 16)};
       }
     }
   };
@@ -247,16 +263,15 @@ __global__ void __launch_bounds__(256) k_stream_tn16(const unsigned short *__res
       yb[cw] = src[64];
     }
   };
-  f32x4 acc[NCW][8];
+  f32x4 acc[NCW][NJT];
 #pragma unroll
   for (int cw = 0; cw < NCW; ++cw)
 #pragma unroll
-    for (int jt = 0; jt < 8; ++jt) acc[cw][jt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int jt = 0; jt < NJT; ++jt) acc[cw][jt] = f32x4{0.f, 0.f, 0.f, 0.f};
   // X chunks are fetched XD chunks ahead and the packed Y one chunk ahead; Y's
   // loads go out before X's, so that waiting for Y (loads complete in issue
   // order) leaves the later X fetches in flight
-  constexpr int XD = 3;
-  u32x4 v[XD][2];
+  u32x4 v[XD][NL];
   uint4 ya[2][NCW], yb[2][NCW];
   if (kb_begin >= kb_end) return;
   const int kb_last = kb_end - 1;
@@ -270,16 +285,21 @@ __global__ void __launch_bounds__(256) k_stream_tn16(const unsigned short *__res
     // LDS copy of the fetched chunk.  VEC stores what it read: a row past K (a
     // copy of row K - 1) meets packed-Y rows that are zero, a group past N (a
     // copy of columns 0 .. 7) feeds output rows that are never stored.
-    *reinterpret_cast<u32x4 *>(&xs[buf][lr][lc]) = v[sx][0];
-    *reinterpret_cast<u32x4 *>(&xs[buf][lr + 16][lc]) = v[sx][1];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int r = lr + RPS * q;
+      *reinterpret_cast<u32x4 *>(&xs[buf][r][8 * (lu ^ tn16_swz(r))]) = v[sx][q];
+    }
     __syncthreads();   // (also: every wave is done with this buffer's previous chunk)
     yload(min(kb + 1, kb_last), ya[sy ^ 1], yb[sy ^ 1]);
     gload(min(kb + XD, kb_last), v[sx]);
 #pragma unroll
-    for (int jt = 0; jt < 8; ++jt) {
-      // rows 8 g .. 8 g + 7 of column 16 jt + i: two 4 x 16 blocks, lane i of the group at row i / 4
-      const unsigned short *p0 = &xs[buf][8 * g + (i >> 2)][16 * jt + 4 * (i & 3)];
-      const uint2 lo = lds_read_tr16(p0), hi = lds_read_tr16(p0 + 4 * LDW);
+    for (int jt = 0; jt < NJT; ++jt) {
+      // rows 8 g .. 8 g + 7 of column 16 jt + i: two 4 x 16 blocks, lane i of the group
+      // at row r = 8 g + i / 4 (+ 4), columns 16 jt + 4 (i % 4): unit 2 jt + (i % 4) / 2
+      const int r0 = 8 * g + (i >> 2), r1 = r0 + 4, u = 2 * jt + ((i & 3) >> 1), h = 4 * (i & 1);
+      const uint2 lo = lds_read_tr16(&xs[buf][r0][8 * (u ^ tn16_swz(r0)) + h]);
+      const uint2 hi = lds_read_tr16(&xs[buf][r1][8 * (u ^ tn16_swz(r1)) + h]);
       const uint4 xop = make_uint4(lo.x, lo.y, hi.x, hi.y);
 #pragma unroll
       for (int cw = 0; cw < NCW; ++cw) {
@@ -323,7 +343,7 @@ __global__ void __launch_bounds__(256) k_stream_tn16(const unsigned short *__res
     if (ct >= NCT) continue;
     const int c0 = ct * 16 + 4 * g;
 #pragma unroll
-    for (int jt = 0; jt < 8; ++jt) {
+    for (int jt = 0; jt < NJT; ++jt) {
       const int64_t j = j0 + 16 * jt + i;
       if (j >= N) continue;
       const f32x4 a = acc[cw][jt];
@@ -690,13 +710,13 @@ int mode_of(int dtype, int mode) {
 // The TN form with 16-bit X runs on k_stream_tn16.
 bool use_tn16(bool nn, int md) { return !nn && (md == MODE_BF16X || md == MODE_F16X); }
 
-template <int MODE, bool VEC>
+template <int MODE, bool VEC, int W>
 int launch_tn16_v(hipStream_t st, int nct, dim3 grid, const unsigned short *x, int64_t K, int64_t N, int64_t ldx,
                   const uint4 *Yp, int ell, float *out, int64_t ldo, int kbps) {
-#define DSK_TN16(NC)                                                                                     \
-  case NC:                                                                                               \
-    hipLaunchKernelGGL((k_stream_tn16<MODE, NC, VEC>), grid, dim3(256), 0, st, x, K, N, ldx, Yp, ell, out, ldo, \
-                       kbps);                                                                            \
+#define DSK_TN16(NC)                                                                                         \
+  case NC:                                                                                                   \
+    hipLaunchKernelGGL((k_stream_tn16<MODE, NC, VEC, W>), grid, dim3(256), 0, st, x, K, N, ldx, Yp, ell, out, ldo, \
+                       kbps);                                                                                \
     break;
   switch (nct) {
     DSK_TN16(1) DSK_TN16(2) DSK_TN16(3) DSK_TN16(4) DSK_TN16(5) DSK_TN16(6) DSK_TN16(7) DSK_TN16(8)
@@ -712,8 +732,8 @@ int launch_tn16(hipStream_t st, int nct, dim3 grid, const void *X, int64_t K, in
                 const uint4 *Yp, int ell, float *out, int64_t ldo, int kbps) {
   const unsigned short *x = reinterpret_cast<const unsigned short *>(X);
   const bool vec = (N & 7) == 0 && (ldx & 7) == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0;
-  return vec ? launch_tn16_v<MODE, true>(st, nct, grid, x, K, N, ldx, Yp, ell, out, ldo, kbps)
-             : launch_tn16_v<MODE, false>(st, nct, grid, x, K, N, ldx, Yp, ell, out, ldo, kbps);
+  return vec ? launch_tn16_v<MODE, true, TN16_W>(st, nct, grid, x, K, N, ldx, Yp, ell, out, ldo, kbps)
+             : launch_tn16_v<MODE, false, TN16_W>(st, nct, grid, x, K, N, ldx, Yp, ell, out, ldo, kbps);
 }
 
 struct StreamPlan {

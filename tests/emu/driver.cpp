@@ -643,6 +643,41 @@ int main(int argc, char **argv) {
       printf("   I0 %lld I%d %lld flags %d %d resident launches %lld %lld same %d maxdp %.3e\n", (long long)I[0][0],
              c.k - 1, (long long)I[0][c.k - 1], inf[0].flags, inf[1].flags, res[0], res[1], same ? 1 : 0,
              maxdp / maxp);
+      // 16-bit storage: the restricted columns stay 16-bit in the factorization's
+      // input; the same values given as FP32 must give the same pivots, P to rounding
+      // (persist-quick: the first configuration only, to bound its run time)
+      for (int half = 0; half < (which == "persist-quick" && &c != &cfgs[0] ? 0 : 2); ++half) {
+        std::vector<uint16_t> A16(c.m * n);
+        std::vector<float> Ar(c.m * n);
+        for (int64_t e = 0; e < c.m * n; ++e) {
+          if (half) {
+            const _Float16 v = (_Float16)A32[e];
+            memcpy(&A16[e], &v, 2);
+            Ar[e] = (float)v;
+          } else {
+            const __bf16 v = (__bf16)A32[e];
+            memcpy(&A16[e], &v, 2);
+            Ar[e] = (float)v;
+          }
+        }
+        std::vector<int64_t> Ih(c.k, -1), Ir(c.k, -1);
+        std::vector<double> Ph(c.m * c.k, 0.0), Pr(c.m * c.k, 0.0);
+        dsk_info ih{}, ir{};
+        char nm[128];
+        snprintf(nm, sizeof nm, "id m=%lld s=%lld k=%d %s storage", (long long)c.m, (long long)R.s, c.k,
+                 half ? "f16" : "bf16");
+        check(nm, dsk_sketch_id(h, A16.data(), half ? DSK_F16 : DSK_BF16, c.m, n, n, c.k, &R, 0, &o, Ih.data(),
+                                Ph.data(), nullptr, &ih));
+        check("id same values as f32", dsk_sketch_id(h, Ar.data(), DSK_F32, c.m, n, n, c.k, &R, 0, &o, Ir.data(),
+                                                     Pr.data(), nullptr, &ir));
+        double dp = 0.0, mp = 1.0;
+        for (size_t e = 0; e < Pr.size(); ++e) {
+          dp = std::max(dp, std::fabs(Ph[e] - Pr[e]));
+          mp = std::max(mp, std::fabs(Pr[e]));
+        }
+        printf("   16-bit %s flags %d %d same16 %d maxdp16 %.3e\n", half ? "f16" : "bf16", ih.flags, ir.flags,
+               Ih == Ir ? 1 : 0, dp / mp);
+      }
     }
   }
   dsk_destroy(h);

@@ -190,6 +190,14 @@ def _check_persist(r):
         assert int(f0) in (0, 1) and int(f1) == 0, res
         assert same == "1", res
         assert float(maxdp) <= 1e-9, res
+    # 16-bit input (index restriction, no power iteration): the factorization reads
+    # the restricted columns in their 16-bit storage; the same values as FP32 give
+    # the same pivots and P to rounding (both accumulate in FP64)
+    r16 = re.findall(r"16-bit (\w+) flags (\d+) (\d+) same16 (\d) maxdp16 (\S+)", r.stdout)
+    assert len(r16) >= 2, r.stdout
+    for dt, f0, f1, same, maxdp in r16:
+        assert f0 == f1 and same == "1", r16
+        assert float(maxdp) <= 1e-9, r16
     return len(res)
 
 
