@@ -89,7 +89,7 @@ typedef struct {
   int32_t p;          /* oversampling; range-finder width ell = min(k+p, s, m); default 10 */
   const void *S;      /* optional device s x ell second-level sketch, row-major, work dtype;
                          NULL = nested direct injection (every floor(s/ell)-th coarse column) */
-  int32_t ell;        /* width of S when S != NULL: 1 <= ell <= min(s, 112) (and <= m for the SVD) */
+  int32_t ell;        /* width of S when S != NULL: 1 <= ell <= min(s, 112) (and <= m, and <= 100 for FP64 input, for the SVD) */
   double tau;         /* coarse Gram scale (Sec. 5); <= 0 means n/s */
   int32_t id_projected; /* sketch_id: 0 = ID of W_q = (tau A_c A_c^T)^q A_c (full coarse sketch),
                            1 = ID of the ell-wide block (tau A_c A_c^T)^q A_c S */
@@ -188,6 +188,8 @@ int dsk_project_noalloc(dsk_handle *h, const void *A, int32_t dtype, int64_t m, 
  * LEARNED those of its stride-4 output grid (s columns in every case).
  * Each (u_j, v_j) is sign-normalised so the largest-magnitude entry of u_j
  * (lowest index on ties) is positive.
+ * Range finder width ell = min(k + p, s, m, 112), or the given S's width; at most
+ * 100 for FP64 input (its core SVD holds two ell x ell FP64 blocks in LDS).
  * Arguments: h=1, A=2, dtype=3, m=4, n=5, lda=6, k=7 (1 <= k <= ell), R=8, q=9 (>= 0),
  *   o=10 (host, may be NULL = defaults), U=11 (m x k row-major, work dtype),
  *   S=12 (k, F64), V=13 (n x k row-major, work dtype), info=14 (host, may be NULL).
@@ -252,7 +254,9 @@ int dsk_spc_id_err(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64
  * TPC-ID (Alg. 4): column-pivoted QR of W^T (Sec. 4, row ID) with W = A_c, or
  * W = (tau A_g A_g^T)^q A_c for q >= 1 (C-PWR without re-orthonormalisation,
  * A_g the Gram sub-sample described under dsk_sketch_svd), pivots = largest
- * residual norm, recomputed every step (lowest index on exact ties);
+ * residual norm (squared norms ranked at 34 mantissa bits, lowest index on
+ * ties; downdated while the pivot's squared norm stays above 1e-5 of the
+ * first pivot's, recomputed from the residuals after that);
  * C = R_1^{-1} R_2; P(I, :) = I_k, P(rest, :) = C^T.  When R_1 has negligible
  * pivots (|r_jj| <= 1e-14 |r_11|, a suffix of its diagonal) the least-squares
  * problem R_1 C = R_2 has many solutions and the basic one is returned: zero
@@ -266,6 +270,42 @@ int dsk_spc_id_err(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64
 int dsk_sketch_id(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                   int32_t k, const dsk_restriction *R, int32_t q, const dsk_opts *o,
                   int64_t *skel, double *P, void *skel_rows, dsk_info *info);
+
+/*
+ * dsk_spc_id -- rank-k row ID by the single-pass SPC-ID (Alg. 5, Sec. 4):
+ *   A ~ P X,  X = A_c(I, :) T_r,  T_r = A_c^+ U_r U_r^T A = V_r S_r^{-2} V_r^T H^T,
+ * where the one pass over A forms A_c = A D and H = A^T A_c (n x s), U_r S_r V_r^T
+ * are the leading r singular triplets of A_c (the lifting operator's rank r acts
+ * as a regulariser, k <= r <= rank(A_c)), and (I, P) is the row ID of A_c, i.e.
+ * exactly dsk_sketch_id's at q = 0.  The singular triplets of A_c come from the
+ * sketch SVD of A_c with every coarse column kept and qc orthonormalised power
+ * steps (range finder width ell = min(m, s, 112), 100 for FP64 input): the r-th singular
+ * direction's error falls like (sigma_{ell+1} / sigma_r)^(2 qc + 1), so qc sets
+ * how close this is to the exact SVD of Alg. 5.  Singular values at or below
+ * max(m, s) eps sigma_1 (eps the machine epsilon of the work precision) are
+ * dropped from S_r^{-2} (the pseudo-inverse) and raise DSK_FLAG_RANK_DEFICIENT.  T_r is never formed:
+ * X = (A_c(I, :) V_r) W_r with W_r = S_r^{-2} V_r^T H^T, and T_r = V_r W_r.
+ * Work precision: FP64 for FP64 input, else FP32 (H on the projection kernel:
+ * FP32 to about 2^-24 relative, exact products for 16-bit storage); the
+ * rounding of H is amplified by about sigma_1 / sigma_r in X.
+ * The row ID and the SVD of A_c run on two worker streams of the handle beside
+ * the pass over A; the call is ordered on the handle's stream like any other.
+ * Arguments: h=1, A=2, dtype=3, m=4, n=5, lda=6, k=7 (1 <= k <= min(m, s)),
+ *   r=8 (k <= r <= ell), R=9, qc=10 (0..64), o=11 (host, may be NULL;
+ *   mode is used, S and id_projected must be unset), skel=12 (device, k
+ *   int64), P=13 (device, m x k row-major F64), X=14 (device, k x n row-major,
+ *   work dtype), Vr=15 (device, s x r row-major, work dtype, or NULL),
+ *   Wr=16 (device, r x n row-major, work dtype, or NULL), info=17 (host, may be
+ *   NULL: flags of all three streams, core_sweeps and ell of the SVD of A_c).
+ * Workspace: n s (H) + about (m + n + 3 s) r + (n + 2 s) k elements of the work
+ * dtype in the handle's arena, plus the two workers' arenas.
+ * Errors: -1..-7 and -9 as dsk_sketch_id's arguments 1..8, -8 r, -10 qc,
+ *   -11 o (a second-level sketch or projected ID asked for), -12 skel NULL,
+ *   -13 P NULL, -14 X NULL.
+ */
+int dsk_spc_id(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,
+               int32_t r, const dsk_restriction *R, int32_t qc, const dsk_opts *o, int64_t *skel, double *P,
+               void *X, void *Vr, void *Wr, dsk_info *info);
 
 /*
  * dsk_power_iter -- the C-PWR loop alone (Alg. 7):

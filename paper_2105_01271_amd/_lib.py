@@ -21,7 +21,7 @@ EXPORTED = (
     "dsk_project", "dsk_sketch_svd", "dsk_sketch_id", "dsk_power_iter", "dsk_status_string",
     "dsk_timing_enable", "dsk_timing_read", "dsk_conv_restrict_bwd", "dsk_learned_loss_grad",
     "dsk_adam_step", "dsk_sketch_svd_batched", "dsk_autotune", "dsk_sketch_svd_id", "dsk_sketch_svd_sp",
-    "dsk_spc_id_err",
+    "dsk_spc_id_err", "dsk_spc_id",
 )
 DSK_BATCH_GRAPH = 1
 
@@ -112,6 +112,8 @@ def load():
         lib.dsk_sketch_svd_sp.argtypes = [vp, vp, i32, i64, i64, i64, i32, P(Restriction), P(Opts),
                                           vp, vp, vp, P(Info)]
         lib.dsk_spc_id_err.argtypes = [vp, vp, i32, i64, i64, i64, P(Restriction), i32, vp, i32, vp, vp]
+        lib.dsk_spc_id.argtypes = [vp, vp, i32, i64, i64, i64, i32, i32, P(Restriction), i32, P(Opts),
+                                   vp, vp, vp, vp, vp, P(Info)]
         lib.dsk_power_iter.argtypes = [vp, vp, i32, i64, i64, i64, vp, i32, i32, dbl, i32, vp]
         lib.dsk_status_string.argtypes = [ctypes.c_int]
         lib.dsk_status_string.restype = ctypes.c_char_p
@@ -129,7 +131,8 @@ def load():
         for name in ("dsk_create", "dsk_destroy", "dsk_set_stream", "dsk_restrict", "dsk_project",
                      "dsk_sketch_svd", "dsk_sketch_id", "dsk_power_iter", "dsk_timing_enable",
                      "dsk_timing_read", "dsk_conv_restrict_bwd", "dsk_learned_loss_grad", "dsk_adam_step",
-                     "dsk_sketch_svd_batched", "dsk_autotune", "dsk_sketch_svd_id", "dsk_sketch_svd_sp", "dsk_spc_id_err"):
+                     "dsk_sketch_svd_batched", "dsk_autotune", "dsk_sketch_svd_id", "dsk_sketch_svd_sp", "dsk_spc_id_err",
+                     "dsk_spc_id"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
         return lib

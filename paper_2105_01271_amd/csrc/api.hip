@@ -10,8 +10,6 @@
 
 namespace {
 
-constexpr int ELL_CAP = 112;
-
 __global__ void k_zero_flags(int *f) {
   if (threadIdx.x < FLAGW_COUNT) f[threadIdx.x] = 0;
 }
@@ -313,8 +311,10 @@ int svd_check(const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, i
   if (od.p < 0) return -10;
   int64_t ell = od.S ? od.ell : std::min<int64_t>(std::min<int64_t>((int64_t)k + od.p, s), m);
   if (s < 1) return -8;
-  if (od.S && (od.ell < 1 || od.ell > std::min<int64_t>(s, m) || od.ell > ELL_CAP)) return -10;
-  ell = std::min<int64_t>(ell, ELL_CAP);
+  // the FP64 core SVD (one-sided Jacobi on R of B^T) holds two ell x ell blocks in LDS
+  const int cap = dtype == DSK_F64 ? ELL_CAP_F64 : ELL_CAP;
+  if (od.S && (od.ell < 1 || od.ell > std::min<int64_t>(s, m) || od.ell > cap)) return -10;
+  ell = std::min<int64_t>(ell, cap);
   if (k < 1 || k > ell) return -7;
   if (q < 0 || q > 64) return -9;
   if (od.mode < 0 || od.mode > DSK_MODE_SPLIT6) return -10;

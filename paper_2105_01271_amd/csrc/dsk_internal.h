@@ -51,6 +51,8 @@ struct dsk_handle {
 };
 
 constexpr int TIMING_CAP = 4096;
+constexpr int ELL_CAP = 112;       // widest range finder / projection tile set
+constexpr int ELL_CAP_F64 = 100;   // widest range finder of FP64 input (the FP64 core SVD's LDS)
 
 // next (start, stop) event pair for a timed projection launch, or nulls
 inline void timing_slot(dsk_handle *h, hipEvent_t *e0, hipEvent_t *e1) {

@@ -296,6 +296,36 @@ def sketch_id(A: torch.Tensor, k: int, R: Restriction, q: int = 0, p: int = 10, 
     return tuple(out)
 
 
+def spc_id(A: torch.Tensor, k: int, r: int, R: Restriction, qc: int = 24, factors: bool = False,
+           want_info: bool = False):
+    """Rank-k row ID by the single-pass SPC-ID (dsk_spc_id, Alg. 5): A ~ P X with
+    X = A_c(I, :) T_r the lifted skeleton rows (k x n, work dtype).  Returns I, P, X
+    [, V_r (s x r), W_r (r x n) with T_r = V_r W_r][, info]."""
+    _check_matrix(A)
+    lib = _lib.load()
+    m, n = A.shape
+    wdt = torch.float64 if A.dtype == torch.float64 else torch.float32
+    s = R.coarse_size()
+    I = torch.empty((k,), dtype=torch.int64, device=A.device)
+    P = torch.empty((m, k), dtype=torch.float64, device=A.device)
+    X = torch.empty((k, n), dtype=wdt, device=A.device)
+    Vr = torch.empty((s, r), dtype=wdt, device=A.device) if factors else None
+    Wr = torch.empty((r, n), dtype=wdt, device=A.device) if factors else None
+    o = _opts()
+    rc = R.to_c()
+    info = _lib.Info()
+    st = lib.dsk_spc_id(_handle(A.device), _ptr(A), _DT[A.dtype], m, n, A.stride(0), int(k), int(r),
+                        ctypes.byref(rc), int(qc), ctypes.byref(o), _ptr(I), _ptr(P), _ptr(X), _ptr(Vr), _ptr(Wr),
+                        ctypes.byref(info) if want_info else None)
+    _lib.check("dsk_spc_id", st)
+    out = [I, P, X]
+    if factors:
+        out += [Vr, Wr]
+    if want_info:
+        out.append(_info_dict(info))
+    return tuple(out)
+
+
 def timing_enable(enable: bool = True, device="cuda"):
     """Bracket each projection kernel (B^T = A^T Q) with HIP events (dsk_timing_enable)."""
     lib = _lib.load()

@@ -467,6 +467,27 @@ int main(int argc, char **argv) {
         write_bin(dir + "/pw_orth.bin", Qo.data(), Qo.size() * 8);
       }
     }
+    // single-pass ID with the lifting operator (Alg. 5) on a matrix with a clear
+    // singular-value drop at r = 12 (from the test): FP64 with the factors of T_r, FP32
+    std::vector<double> As(m * n);
+    if (read_bin(dir + "/Aspc.bin", As)) {
+      const int ks = 6, rs = 12, qc = 8;
+      const int64_t s = R.s;
+      std::vector<int64_t> Is(ks);
+      std::vector<double> Ps(m * ks), Xs(ks * n), Vs(s * rs), Ws(rs * n);
+      check("files spc_id f64", dsk_spc_id(h, As.data(), DSK_F64, m, n, n, ks, rs, &R, qc, &o, Is.data(), Ps.data(),
+                                           Xs.data(), Vs.data(), Ws.data(), nullptr));
+      write_bin(dir + "/spc64_I.bin", Is.data(), ks * 8);
+      write_bin(dir + "/spc64_P.bin", Ps.data(), Ps.size() * 8);
+      write_bin(dir + "/spc64_X.bin", Xs.data(), Xs.size() * 8);
+      write_bin(dir + "/spc64_V.bin", Vs.data(), Vs.size() * 8);
+      write_bin(dir + "/spc64_W.bin", Ws.data(), Ws.size() * 8);
+      std::vector<float> As32(As.begin(), As.end()), X32(ks * n);
+      check("files spc_id f32", dsk_spc_id(h, As32.data(), DSK_F32, m, n, n, ks, rs, &R, qc, &o, Is.data(), Ps.data(),
+                                           X32.data(), nullptr, nullptr, nullptr));
+      write_bin(dir + "/spc32_I.bin", Is.data(), ks * 8);
+      write_bin(dir + "/spc32_X.bin", X32.data(), X32.size() * 4);
+    }
     // nearest-neighbour stencil restriction, FP64, q = 1
     dsk_restriction Rn{};
     Rn.kind = DSK_R_NN;

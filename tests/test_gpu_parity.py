@@ -228,6 +228,21 @@ def test_sketch_svd_exactly_repeated_singular_values():
     assert np.abs(Vg.T @ Vg - np.eye(6)).max() < 1e-6
 
 
+def test_sketch_svd_fp64_range_finder_capped_at_100():
+    # FP64 input with k + p above 100: the range finder is 100 wide (the FP64 core
+    # SVD holds two ell x ell blocks in LDS), the oracle run at the same width
+    say("svd fp64 ell cap")
+    m, N, f, k = 260, 32, 1, 95
+    A_np = synth.heat_exact(m, N, N, seed=12, rate=0.03)
+    A = _A(A_np, torch.float64)
+    R = dsk().Restriction.di_grid(N, N, 2, f + 1)
+    idx = ores.di_index_2d(N, N, 2, f + 1)
+    U, S, V, info = dsk().sketch_svd(A, k, R, q=0, want_info=True)
+    assert info["ell"] == 100, info
+    Uo, So, Vo, sig = _tpc(A_np, k, {"kind": "index", "index": idx}, p=5)
+    _compare_svd(A_np, U, S, V, Uo, So, Vo, TOL[torch.float64], sig_all=sig)
+
+
 def test_sketch_svd_is_deterministic():
     say("svd determinism")
     A = _A(synth.advdiff_exact(256, 32, seed=9, r=256), torch.float32)

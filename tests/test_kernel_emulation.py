@@ -83,14 +83,18 @@ def _files_inputs(d=None):
     w2[0, 2, 2] += 1.0
     gAc = rng.standard_normal((m, sl)).astype("<f4")
     Q0 = rng.standard_normal((m, 6))
+    # SPC-ID input: rank 12 with sigma_j = 0.6^j plus 1e-9 noise (a clear drop at r = 12)
+    Ut = np.linalg.qr(rng.standard_normal((m, 12)))[0]
+    Vt = np.linalg.qr(rng.standard_normal((N * N, 12)))[0]
+    Aspc = (Ut * 0.6 ** np.arange(12)) @ Vt.T + 1e-9 * rng.standard_normal((m, N * N))
     if d is not None:
         (d / "dims.txt").write_text(f"{m} {N} {f} {k} {mc} {taus.size}\n")
         for name, arr, dt in [("A", A, "<f8"), ("taus", taus, "<f8"), ("Abf", bf, "<u2"), ("Q", Q, "<f4"),
                               ("Om", Om, "<f8"), ("w1", w1, "<f4"), ("w2", w2, "<f4"), ("gAc", gAc, "<f4"),
-                              ("Q0", Q0, "<f8")]:
+                              ("Q0", Q0, "<f8"), ("Aspc", Aspc, "<f8")]:
             arr.astype(dt).tofile(d / f"{name}.bin")
     return {"m": m, "N": N, "f": f, "k": k, "mc": mc, "A": A, "idx": idx, "taus": taus, "A_bf": A_bf, "Q": Q,
-            "Om": Om, "w1": w1, "w2": w2, "gAc": gAc, "Q0": Q0}
+            "Om": Om, "w1": w1, "w2": w2, "gAc": gAc, "Q0": Q0, "Aspc": Aspc}
 
 
 @pytest.fixture(scope="module")
@@ -302,7 +306,7 @@ def test_emulated_kernels_match_the_oracle(emu):
     assert r.returncode == 0, out[-4000:]
     assert "ERROR: AddressSanitizer" not in out and "SIMT FATAL" not in out and "runtime error" not in out, out[-4000:]
     rcs = re.findall(r"^(.*?)\s+rc=(-?\d+)$", r.stdout, re.M)
-    assert len(rcs) == 18 and all(int(c) == 0 for _, c in rcs), r.stdout
+    assert len(rcs) == 20 and all(int(c) == 0 for _, c in rcs), r.stdout
 
     n = N * N
     Rd = {"kind": "index", "index": idx}
@@ -396,6 +400,39 @@ def test_emulated_kernels_match_the_oracle(emu):
     Io, Po = orid.tpc_id(A, k, Rd, q=0)
     assert list(I) == list(Io), (I, Io)
     assert np.abs(P - Po).max() <= 1e-8 * max(1.0, np.abs(Po).max()), np.abs(P - Po).max()
+
+    # SPC-ID (Alg. 5): the skeleton and P of the coarse row ID, the lifted rows
+    # X = A_c(I, :) T_r and the factors T_r = V_r W_r against the oracle's T_r.  FP32:
+    # the rounding of H = A^T A_c is amplified by about sigma_1 / sigma_r in X
+    As = inp["Aspc"]
+    ks, rs = 6, 12
+    Io, Po, _, Tro = orid.spc_id(As, ks, Rd, rs)
+    Xo = As[:, idx][Io] @ Tro
+    I = np.fromfile(tmp_path / "spc64_I.bin", dtype="<i8")
+    assert list(I) == list(Io), (I, Io)
+    assert np.abs(load("spc64_P", "<f8", (m, ks)) - Po).max() <= 1e-8 * max(1.0, np.abs(Po).max())
+    X = load("spc64_X", "<f8", (ks, n))
+    assert np.abs(X - Xo).max() <= 1e-9 * np.abs(Xo).max(), np.abs(X - Xo).max() / np.abs(Xo).max()
+    # T_r = V_r W_r: the oracle's literal form (U_c^T U_r U_r^T U_c with every
+    # pseudo-inverted singular value of A_c) carries its own rounding, amplified by
+    # sigma_1 / sigma_min+ (sigma_min+ the smallest it inverts); W_r against its
+    # definition S_r^{-2} V_r^T A_c^T A with the device's V_r, in FP64
+    sc = np.linalg.svd(As[:, idx], compute_uv=False)
+    smin = sc[sc > sc[0] * max(m, idx.size) * np.finfo(np.float64).eps].min()
+    Vg, Wg = load("spc64_V", "<f8", (idx.size, rs)), load("spc64_W", "<f8", (rs, n))
+    assert np.abs(Vg.T @ Vg - np.eye(rs)).max() <= 1e-12
+    Wdef = (1.0 / sc[:rs] ** 2)[:, None] * (Vg.T @ (As[:, idx].T @ As))
+    assert np.abs(Wg - Wdef).max() <= 1e-9 * np.abs(Wdef).max()
+    tolT = 1e-9 + 16 * 2.0 ** -53 * sc[0] / smin
+    assert np.abs(Vg @ Wg - Tro).max() <= tolT * np.abs(Tro).max()
+    As32 = As.astype(np.float32).astype(np.float64)
+    Io32, _, _, Tro32 = orid.spc_id(As32, ks, Rd, rs)
+    Xo32 = As32[:, idx][Io32] @ Tro32
+    assert list(np.fromfile(tmp_path / "spc32_I.bin", dtype="<i8")) == list(Io32)
+    X32 = load("spc32_X", "<f4", (ks, n))
+    tol32 = 8 * 2.0 ** -24 * sc[0] / sc[rs - 1]
+    assert np.abs(X32 - Xo32).max() <= tol32 * np.abs(Xo32).max(), (np.abs(X32 - Xo32).max() / np.abs(Xo32).max(),
+                                                                     tol32)
 
     # SPC-ID-ERR (Alg. 6)
     eps = np.fromfile(tmp_path / "eps64.bin", dtype="<f8")
