@@ -176,7 +176,9 @@ def c2_leg(torch, dsketch, synth, a, dev, src_hash):
             "svd_q1": round(timed(torch, lambda: dsketch.sketch_svd(A, k, R, q=1)), 4),
             "svd_q2": round(timed(torch, lambda: dsketch.sketch_svd(A, k, R, q=2)), 4),
             "id_q0": round(timed(torch, lambda: dsketch.sketch_id(A, k, R, q=0, skeleton_rows=True)), 4),
-            "svd_single_pass": round(timed(torch, lambda: dsketch.sketch_svd_sp(A, k, R)), 4)}
+            "svd_single_pass": round(timed(torch, lambda: dsketch.sketch_svd_sp(A, k, R)), 4),
+            # single-pass ID (Alg. 5): lifting operator of rank r = k, 24 power steps for the SVD of A_c
+            "spc_id_r50_qc24": round(timed(torch, lambda: dsketch.spc_id(A, k, k, R, qc=24), reps=3), 4)}
         if a.mreo_trials > 0:
             from paper_2105_01271_amd import hybrid
             Ad = A_np.astype(np.float64)

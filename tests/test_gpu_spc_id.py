@@ -109,8 +109,10 @@ def test_spc_id_matches_oracle(dtype, m, ny, nx, sy, sx, k, r):
     # V_r orthonormal, W_r = S_r^-2 V_r^T A_c^T A with the device's V_r
     assert np.abs(Vr.T @ Vr - np.eye(r)).max() <= (1e-12 if dtype == torch.float64 else 1e-5)
     Wdef = (1.0 / sc[:r] ** 2)[:, None] * (Vr.T @ (Ac.T @ A_np))
-    # (plus the FP64 rounding of the test's own products, O(m u kappa_r))
-    assert np.abs(Wr - Wdef).max() <= (8 * uw + 4 * m * U53) * kap * np.abs(Wdef).max()
+    # (the device's sigma_r and v_r against the exact sigma_r: up to about 33 u_w kappa_r
+    # in FP32 at kappa_r = 116, so 64 u_w kappa_r, plus the FP64 rounding of the test's
+    # own products, O(m u kappa_r))
+    assert np.abs(Wr - Wdef).max() <= (64 * uw + 4 * m * U53) * kap * np.abs(Wdef).max()
     # the approximation A ~ P X against the oracle's, in the 2-norm
     e_gpu = np.linalg.norm(A_np - P @ X, 2)
     e_or = np.linalg.norm(A_np - Po @ AcIo @ Tro, 2)
