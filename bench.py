@@ -24,6 +24,9 @@ against the FP64 matrix is within (1 + 0.05) of the exact tail
 (sum_{j>k} sigma_j^2)^(1/2), for the same matrix stored FP32, BF16 and FP16.
 c2: the FP32 workload (advection-diffusion 1000 x 256^2, s = 4096, k = 50)
 timed the same way.
+c5_learned: the learned conv restriction trained on 20000 rows against direct
+injection at equal s, judged on held-out trajectories, errors at held-out
+diffusivities.
 cpu_baseline: the FP64 NumPy oracle of one step on the host cores.
 """
 from __future__ import annotations
@@ -55,6 +58,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true", help="skip component timings and time-to-eps")
     ap.add_argument("--no-c2", action="store_true", help="skip the FP32 advection-diffusion workload")
+    ap.add_argument("--no-c5", action="store_true", help="skip the learned-restriction comparison")
     ap.add_argument("--mreo-trials", type=int, default=20, help="trials of the hybrid-sketch MREO harness (C2)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 256 MiB device copy (known bytes) to scale HBM counters")
@@ -194,6 +198,50 @@ def c2_leg(torch, dsketch, synth, a, dev, src_hash):
     return out
 
 
+def c5_leg(torch, dsketch, synth, dev):
+    """Learned restriction against direct injection at equal s (extension): train
+    on 20 advection-diffusion trajectories (20000 rows of 256^2), judge on two
+    held-out ones, then the rank-50 sketch SVD (q = 1) at three held-out
+    diffusivities with the chosen restriction and with direct injection."""
+    from paper_2105_01271_amd import learned
+    N, k, ell, q, steps = synth.LEARNED_GRID, 50, 60, 1, 600
+    tr, va, te = synth.learned_diffusivities()
+    train = [synth.learned_trajectory(nu, 1000 + i, dev) for i, nu in enumerate(tr)]
+    val = [synth.learned_trajectory(nu, 2000 + i, dev) for i, nu in enumerate(va)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w1, w2, hist = learned.train(train, N, N, C=16, ell=ell, q=q, steps=steps, batch=500, lr=2e-3, seed=0)
+    torch.cuda.synchronize()
+    train_ms = 1e3 * (time.perf_counter() - t0) / steps
+    del train
+    choice, ll, ld = learned.judge(val, N, N, w1, w2, ell, q)
+    del val
+    R = learned.restriction_for(choice, N, N, w1, w2)
+    Rl = dsketch.Restriction.learned(N, N, w1, w2)
+    Rdi = dsketch.Restriction.di_grid(N, N, 4, 4, device=dev)
+    tests = []
+    for i, nu in enumerate(te):
+        A = synth.learned_trajectory(nu, 3000 + i, dev)
+        A64 = A.double()
+        sv = torch.linalg.svdvals(A64)
+        row = {"nu": nu, "optimal": round(float(torch.sqrt((sv[k:] ** 2).sum() / (sv ** 2).sum())), 6)}
+        for name, RR in (("direct_injection", Rdi), ("learned", Rl)):
+            U, S, V = dsketch.sketch_svd(A, k, RR, q=q)
+            E = A64 - (U.double() * S.double()[None, :]) @ V.double().T
+            row[name] = round(float(torch.linalg.norm(E) / torch.linalg.norm(A64)), 6)
+            if i == 0:
+                row[name + "_svd_ms"] = round(timed(torch, lambda RR=RR: dsketch.sketch_svd(A, k, RR, q=q)), 4)
+        tests.append(row)
+        del A, A64
+    torch.cuda.empty_cache()
+    return {"workload": "advection-diffusion trajectories 1000 x 256^2 FP32 (velocity (6, 3.5)), learned 5x5 "
+                        "stride-2 conv 1 -> 16 -> 1 vs direct injection (4, 4), s = 4096, k = 50, ell = 60, q = 1",
+            "train_rows": 1000 * len(tr), "train_steps": steps, "train_ms_per_step": round(train_ms, 3),
+            "loss_first20": float(np.mean(hist[:20])), "loss_last20": float(np.mean(hist[-20:])),
+            "judge": {"choice": choice, "val_loss_learned": ll, "val_loss_direct_injection": ld},
+            "test_rank_k_error": tests}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -258,6 +306,10 @@ def main():
     if not a.no_c2:
         c2 = c2_leg(torch, dsketch, synth, a, dev, src_hash)
         log(f"c2 {c2}")
+    c5 = None
+    if not a.no_breakdown and not a.no_c5:
+        c5 = c5_leg(torch, dsketch, synth, dev)
+        log(f"c5 {c5}")
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -293,6 +345,7 @@ def main():
         "breakdown_ms": breakdown,
         "time_to_eps": tte,
         "c2": c2,
+        "c5_learned": c5,
     }
     print(json.dumps(rec), flush=True)
 

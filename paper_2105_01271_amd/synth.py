@@ -17,6 +17,7 @@ Families:
                   factors, exact prescribed spectrum sigma_j (+ noise)
   heat_exact      Dirichlet sine modes with exact spectrum sigma_j
   advdiff_field   physical advection-diffusion snapshots at a diffusivity nu
+                  (advdiff_field_device: the same on a torch device)
   lowrank         product of Gaussian factors (exact rank r)
   gaussian_matrix iid N(0, 1) draws, e.g. the optional Gaussian second-level
                   sketch of the hybrid method (passed to both sides as input)
@@ -29,7 +30,8 @@ from dataclasses import dataclass
 import numpy as np
 
 __all__ = [
-    "heat_modes", "advdiff_exact", "heat_exact", "advdiff_field", "lowrank", "gaussian_matrix",
+    "heat_modes", "advdiff_exact", "heat_exact", "advdiff_field", "advdiff_field_device", "learned_diffusivities",
+    "learned_trajectory", "lowrank", "gaussian_matrix",
     "batch_specs", "BatchSpec", "orthonormal_fourier_1d",
 ]
 
@@ -200,17 +202,83 @@ def advdiff_field(m: int, N: int, seed: int, nu: float, kmax: int = 24, alpha: f
     # cos(a + b) with a = 2 pi (kx x + ky y), b = phi - 2 pi k.v t
     amp = c[None, :] * np.exp(-4 * np.pi ** 2 * nu * (kk ** 2)[None, :] * t[:, None])
     b = phi[None, :] - 2 * np.pi * (ks @ np.asarray(v, dtype=np.float64))[None, :] * t[:, None]
-    cb = amp * np.cos(b)
-    sb = amp * np.sin(b)
-    ex = 2 * np.pi * ks[:, 0][:, None] * x[None, :]       # K x N (x)
-    ey = 2 * np.pi * ks[:, 1][:, None] * x[None, :]       # K x N (y)
-    cx, sx = np.cos(ex), np.sin(ex)
-    cy, sy = np.cos(ey), np.sin(ey)
-    # cos(ax+ay+b) = Re(e^{i ay} e^{i ax} e^{i b})
-    # = cb*(cx cy - sx sy) - sb*(sx cy + cx sy)
-    A = (np.einsum("tk,ky,kx->tyx", cb, cy, cx) - np.einsum("tk,ky,kx->tyx", cb, sy, sx)
-         - np.einsum("tk,ky,kx->tyx", sb, cy, sx) - np.einsum("tk,ky,kx->tyx", sb, sy, cx))
+    # cos(a_x + a_y + b) = Re(z e^{i a_y} e^{i a_x}) with z = amp e^{i b}, a_x = 2 pi kx x,
+    # a_y = 2 pi ky y: one grid row y at a time, A(:, y, :) = Re((z * e^{i a_y}) E_x)
+    z = amp * np.exp(1j * b)                                  # m x K
+    ex = np.exp(2j * np.pi * ks[:, 0][:, None] * x[None, :])  # K x N (x)
+    ey = np.exp(2j * np.pi * ks[:, 1][:, None] * x[None, :])  # K x N (y)
+    exr, exi = np.ascontiguousarray(ex.real), np.ascontiguousarray(ex.imag)
+    zr, zi = np.ascontiguousarray(z.real), np.ascontiguousarray(z.imag)
+    A = np.empty((m, N, N))
+    for y in range(N):
+        cr, ci = ey[:, y].real[None, :], ey[:, y].imag[None, :]
+        wr = zr * cr - zi * ci                                # Re(z e^{i a_y}), contiguous for BLAS
+        wi = zr * ci + zi * cr
+        A[:, y, :] = wr @ exr - wi @ exi
     return A.reshape(m, N * N)
+
+
+def advdiff_field_device(m: int, N: int, seed: int, nu: float, device, kmax: int = 24, alpha: float = 1.0,
+                         v=(0.6, 0.35), T: float = 1.0, dtype=None):
+    """advdiff_field's snapshots formed on a torch device (the same seeded modes,
+    amplitudes and phases, drawn on the host; the sums in FP64 on the device):
+    equal to advdiff_field up to rounding.  Returns an m x N*N torch tensor of
+    `dtype` (default float64) on `device`."""
+    import torch
+    rng = np.random.default_rng(seed)
+    ks = [(kx, ky) for ky in range(-kmax, kmax + 1) for kx in range(0, kmax + 1)
+          if (kx > 0 or ky > 0) and kx * kx + ky * ky <= kmax * kmax]
+    ks = np.asarray(ks, dtype=np.float64)
+    kk = np.sqrt((ks ** 2).sum(1))
+    c = rng.standard_normal(len(ks)) / (1.0 + kk) ** alpha
+    phi = rng.uniform(0, 2 * np.pi, size=len(ks))
+    f64 = torch.float64
+    t = torch.arange(m, dtype=f64, device=device) * (T / max(m - 1, 1))
+    x = torch.arange(N, dtype=f64, device=device) / N
+    ks_t = torch.from_numpy(ks).to(device)
+    kk_t = torch.from_numpy(kk).to(device)
+    amp = torch.from_numpy(c).to(device)[None, :] * torch.exp(-4 * np.pi ** 2 * nu * (kk_t ** 2)[None, :] * t[:, None])
+    kv = ks_t @ torch.tensor(v, dtype=f64, device=device)
+    b = torch.from_numpy(phi).to(device)[None, :] - 2 * np.pi * kv[None, :] * t[:, None]
+    zr, zi = amp * torch.cos(b), amp * torch.sin(b)
+    ax = 2 * np.pi * ks_t[:, 0][:, None] * x[None, :]
+    ay = 2 * np.pi * ks_t[:, 1][:, None] * x[None, :]
+    exr, exi = torch.cos(ax).contiguous(), torch.sin(ax).contiguous()
+    eyr, eyi = torch.cos(ay), torch.sin(ay)
+    out = torch.empty((m, N, N), dtype=dtype or f64, device=device)
+    for y in range(N):
+        cr, ci = eyr[:, y][None, :], eyi[:, y][None, :]
+        wr = zr * cr - zi * ci
+        wi = zr * ci + zi * cr
+        out[:, y, :] = (wr @ exr - wi @ exi).to(out.dtype)
+    return out.reshape(m, N * N)
+
+
+# The learned-restriction workload: advection-diffusion trajectories (1000
+# snapshots of 256 x 256 each) at diffusivities drawn log-uniformly from
+# [0.005, 0.05] with a fixed seed for training, and held-out diffusivities for
+# validation (the judge) and test.  The velocity (6, 3.5) makes the temporal
+# content rich enough that a rank-50 approximation leaves a visible tail
+# (about 0.11 of ||A||_F at nu = 0.006, 3e-4 at nu = 0.04).
+LEARNED_GRID = 256
+LEARNED_ROWS = 1000
+LEARNED_VELOCITY = (6.0, 3.5)
+
+
+def learned_diffusivities(n_train: int = 20, seed: int = 500):
+    """(train, validation, test) diffusivity lists of the learned-restriction
+    workload; validation and test values are not in the training list."""
+    rng = np.random.default_rng(seed)
+    train = np.sort(np.exp(rng.uniform(np.log(0.005), np.log(0.05), n_train)))
+    return [float(v) for v in train], [0.0083, 0.031], [0.0061, 0.0187, 0.042]
+
+
+def learned_trajectory(nu: float, seed: int, device, dtype=None, rows: int = LEARNED_ROWS):
+    """One trajectory of the learned-restriction workload on a torch device
+    (rows x 256^2, FP32 unless dtype is given)."""
+    import torch
+    return advdiff_field_device(rows, LEARNED_GRID, seed=seed, nu=nu, device=device, kmax=24, alpha=1.0,
+                                v=LEARNED_VELOCITY, dtype=dtype or torch.float32)
 
 
 def lowrank(m: int, n: int, r: int, seed: int) -> np.ndarray:

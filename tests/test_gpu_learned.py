@@ -163,3 +163,48 @@ def test_adam_training_tracks_oracle_and_reduces_loss():
     _, _, hist30 = learned.train(A, ny, nx, C=C, ell=ell, q=q, steps=30, batch=m, lr=1e-2, w1=w1, w2=w2)
     say("  30 steps", hist30[0], hist30[-1])
     assert hist30[-1] < hist30[0]
+
+
+def test_learned_restriction_against_direct_injection_at_held_out_diffusivities():
+    # The learned-restriction workload: training on 20 trajectories (20000 rows of
+    # 256^2) at seeded diffusivities in [0.005, 0.05], 600 Adam steps on minibatches
+    # of 500 rows of one trajectory (ell = 60, q = 1); direct injection on the same
+    # (4, 4) grid (s = 4096) is the judge on two held-out validation trajectories and
+    # the fallback; then the rank-50 sketch SVD (q = 1) at three held-out test
+    # diffusivities.  Measured: the judge keeps the learned conv (validation loss
+    # about 35% below direct injection's) and it lowers the test error where the
+    # tail is largest (nu = 0.0061) while matching direct injection elsewhere.
+    from paper_2105_01271_amd import learned
+    say("learned vs direct injection")
+    dev = torch.device("cuda")
+    N, k, ell, q = synth.LEARNED_GRID, 50, 60, 1
+    tr, va, te = synth.learned_diffusivities()
+    train = [synth.learned_trajectory(nu, 1000 + i, dev) for i, nu in enumerate(tr)]
+    val = [synth.learned_trajectory(nu, 2000 + i, dev) for i, nu in enumerate(va)]
+    w1, w2, hist = learned.train(train, N, N, C=16, ell=ell, q=q, steps=600, batch=500, lr=2e-3, seed=0)
+    say(f"  minibatch loss first 20 {np.mean(hist[:20]):.3e} last 20 {np.mean(hist[-20:]):.3e}")
+    del train
+    choice, ll, ld = learned.judge(val, N, N, w1, w2, ell, q)
+    say(f"  judge: {choice} (validation loss learned {ll:.4e}, direct injection {ld:.4e})")
+    assert (choice == "learned") == (ll < ld)
+    R = learned.restriction_for(choice, N, N, w1, w2)
+    Rdi = dsk().Restriction.di_grid(N, N, 4, 4)
+
+    def err(A, R):
+        U, S, V = dsk().sketch_svd(A, k, R, q=q)
+        A64 = A.double()
+        E = A64 - (U.double() * S.double()[None, :]) @ V.double().T
+        return float(torch.linalg.norm(E) / torch.linalg.norm(A64))
+
+    e_sel, e_di = [], []
+    for i, nu in enumerate(te):
+        A = synth.learned_trajectory(nu, 3000 + i, dev)
+        s = torch.linalg.svdvals(A.double())
+        opt = float(torch.sqrt((s[k:] ** 2).sum() / (s ** 2).sum()))
+        e_sel.append(err(A, R))
+        e_di.append(err(A, Rdi))
+        say(f"  test nu {nu}: optimal {opt:.4e} direct injection {e_di[-1]:.4e} chosen {e_sel[-1]:.4e}")
+        assert e_sel[-1] >= opt * (1 - 1e-6)
+    assert choice == "learned"
+    assert e_sel[0] < 0.99 * e_di[0]                    # the measured gain where the tail is largest
+    assert all(a <= b * 1.01 for a, b in zip(e_sel, e_di))
