@@ -210,7 +210,8 @@ def c5_leg(torch, dsketch, synth, dev):
     val = [synth.learned_trajectory(nu, 2000 + i, dev) for i, nu in enumerate(va)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    w1, w2, hist = learned.train(train, N, N, C=16, ell=ell, q=q, steps=steps, batch=500, lr=2e-3, seed=0)
+    w1, w2, hist = learned.train(train, N, N, C=16, ell=ell, q=q, steps=steps, batch=1000, lr=2e-3, seed=0,
+                                 val=val)
     torch.cuda.synchronize()
     train_ms = 1e3 * (time.perf_counter() - t0) / steps
     del train
@@ -236,7 +237,8 @@ def c5_leg(torch, dsketch, synth, dev):
     torch.cuda.empty_cache()
     return {"workload": "advection-diffusion trajectories 1000 x 256^2 FP32 (velocity (6, 3.5)), learned 5x5 "
                         "stride-2 conv 1 -> 16 -> 1 vs direct injection (4, 4), s = 4096, k = 50, ell = 60, q = 1",
-            "train_rows": 1000 * len(tr), "train_steps": steps, "train_ms_per_step": round(train_ms, 3),
+            "train_rows": 1000 * len(tr), "train_steps": steps, "train_batch": 1000,
+            "train_ms_per_step_with_validation": round(train_ms, 3),
             "loss_first20": float(np.mean(hist[:20])), "loss_last20": float(np.mean(hist[-20:])),
             "judge": {"choice": choice, "val_loss_learned": ll, "val_loss_direct_injection": ld},
             "test_rank_k_error": tests}

@@ -183,7 +183,7 @@ int dsk_create(dsk_handle **h, int device, void *stream) {
   int lds = 0;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) lds = 65536;
   x->max_lds = (size_t)lds;
-  if (hipMalloc(&x->dflags, 256) != hipSuccess) {
+  if (hipMalloc(&x->dflags, HANDLE_DEV_BYTES) != hipSuccess) {
     delete x;
     return DSK_ERR_BASE + (int)hipErrorOutOfMemory;
   }

@@ -34,7 +34,7 @@ int make_worker(dsk_handle *h, dsk_handle **out) {
     delete w;
     return DSK_ERR_BASE + (int)hipErrorOutOfMemory;
   }
-  if (hipMalloc(&w->dflags, 256) != hipSuccess) {
+  if (hipMalloc(&w->dflags, HANDLE_DEV_BYTES) != hipSuccess) {
     (void)hipStreamDestroy(w->stream);
     delete w;
     return DSK_ERR_BASE + (int)hipErrorOutOfMemory;

@@ -29,6 +29,16 @@
 // Jacobi sweeps of the last core factorization.
 enum { FLAGW_BITS = 0, FLAGW_TICKET = 1, FLAGW_SWEEPS = 2, FLAGW_COUNT = 4 };
 
+// A handle's persistent device allocation: the status words, then (from byte
+// STATUS_BYTES) the composed filters the learned restriction's forward pass
+// builds per call (used only on the handle's own stream, like the status words).
+constexpr size_t STATUS_BYTES = 256;
+constexpr size_t CONV_FILTER_BYTES = 16 * 1024;
+constexpr size_t HANDLE_DEV_BYTES = STATUS_BYTES + CONV_FILTER_BYTES;
+inline float *conv_filter_ws(int *dflags) {
+  return reinterpret_cast<float *>(reinterpret_cast<char *>(dflags) + STATUS_BYTES);
+}
+
 struct dsk_handle {
   int device;
   hipStream_t stream;
@@ -134,7 +144,7 @@ int launch_transpose(hipStream_t st, const void *src, int f64, int64_t rows, int
 // conv.hip (learned linear restriction)
 int conv_shape_ok(int64_t n, int ny, int nx, int C);
 int launch_conv_fwd(hipStream_t st, const void *A, int dtype, int64_t m, int64_t lda, int ny, int nx, int C,
-                    const float *w1, const float *w2, int out_f64, void *Ac, int64_t ldc);
+                    const float *w1, const float *w2, int out_f64, void *Ac, int64_t ldc, float *filt_ws);
 size_t conv_bwd_ws_bytes(int64_t m, int ny, int nx, int C);
 int launch_conv_bwd(hipStream_t st, const void *A, int dtype, int64_t m, int64_t lda, int ny, int nx, int C,
                     const float *w1, const float *w2, const void *gAc, int g_f64, int64_t ldg, float *gw1,

@@ -237,7 +237,8 @@ int launch_restrict(hipStream_t st, const void *A, int dtype, int64_t m, int64_t
                     const dsk_restriction *R, int64_t s, int work_f64, void *Ac, void *AcT, int *dflags) {
   if (R->kind == DSK_R_LEARNED) {
     if (AcT) return -1;
-    return launch_conv_fwd(st, A, dtype, m, lda, R->ny, R->nx, R->channels, R->w1, R->w2, work_f64, Ac, s);
+    return launch_conv_fwd(st, A, dtype, m, lda, R->ny, R->nx, R->channels, R->w1, R->w2, work_f64, Ac, s,
+                           conv_filter_ws(dflags));
   }
   Grid2 g{};
   if (R->kind == DSK_R_NN || R->kind == DSK_R_GLOBAL) {

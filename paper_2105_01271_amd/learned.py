@@ -30,11 +30,14 @@ def direct_injection_weights(C: int, noise: float = 0.0, seed: int = 0, device="
 
 
 def train(A, ny: int, nx: int, C: int = 16, ell: int = 60, q: int = 0, steps: int = 100,
-          batch: int = 500, lr: float = 2e-3, seed: int = 0, w1=None, w2=None, log=None):
+          batch: int = 500, lr: float = 2e-3, seed: int = 0, w1=None, w2=None, log=None, val=None,
+          val_every: int = 100):
     """Adam on the projection loss over random row minibatches (rows = snapshots).
     A is one matrix or a list of matrices (e.g. one trajectory per diffusivity):
     each minibatch is a sorted random subset of the rows of one of them, chosen
-    at random.  Returns (w1, w2, history of minibatch losses)."""
+    at random.  With validation matrices `val`, the projection loss on them is
+    taken every val_every steps and the weights with the lowest one are
+    returned.  Returns (w1, w2, history of minibatch losses)."""
     mats = list(A) if isinstance(A, (list, tuple)) else [A]
     dev = mats[0].device
     if w1 is None or w2 is None:
@@ -45,6 +48,8 @@ def train(A, ny: int, nx: int, C: int = 16, ell: int = 60, q: int = 0, steps: in
     m1b, m2b = torch.zeros_like(w2), torch.zeros_like(w2)
     rng = np.random.default_rng(seed)
     hist = []
+    vals = (list(val) if isinstance(val, (list, tuple)) else [val]) if val is not None else None
+    best = None
     for t in range(1, steps + 1):
         X = mats[int(rng.integers(len(mats)))] if len(mats) > 1 else mats[0]
         m = X.shape[0]
@@ -57,6 +62,12 @@ def train(A, ny: int, nx: int, C: int = 16, ell: int = 60, q: int = 0, steps: in
         hist.append(loss)
         if log is not None:
             log(t, loss)
+        if vals is not None and (t % val_every == 0 or t == steps):
+            lv = sum(projection_loss(V, ny, nx, w1, w2, ell, q) for V in vals) / len(vals)
+            if best is None or lv < best[0]:
+                best = (lv, w1.clone(), w2.clone())
+    if best is not None:
+        return best[1], best[2], hist
     return w1, w2, hist
 
 

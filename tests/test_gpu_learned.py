@@ -167,13 +167,18 @@ def test_adam_training_tracks_oracle_and_reduces_loss():
 
 def test_learned_restriction_against_direct_injection_at_held_out_diffusivities():
     # The learned-restriction workload: training on 20 trajectories (20000 rows of
-    # 256^2) at seeded diffusivities in [0.005, 0.05], 600 Adam steps on minibatches
-    # of 500 rows of one trajectory (ell = 60, q = 1); direct injection on the same
-    # (4, 4) grid (s = 4096) is the judge on two held-out validation trajectories and
-    # the fallback; then the rank-50 sketch SVD (q = 1) at three held-out test
-    # diffusivities.  Measured: the judge keeps the learned conv (validation loss
-    # about 35% below direct injection's) and it lowers the test error where the
-    # tail is largest (nu = 0.0061) while matching direct injection elsewhere.
+    # 256^2) at seeded diffusivities in [0.005, 0.05], 600 Adam steps, each on one
+    # whole trajectory (ell = 60, q = 1), keeping the weights with the lowest
+    # loss on two held-out validation trajectories (checked every 100 steps);
+    # direct injection on the same (4, 4) grid (s = 4096) is the judge on those
+    # trajectories and the fallback; then the rank-50 sketch SVD (q = 1) at three
+    # held-out test diffusivities.  Measured: training lowers the projection loss
+    # on the validation trajectories by about a quarter against direct
+    # injection's, so the judge keeps the learned conv, but the rank-50 error at
+    # the held-out diffusivities stays within about 1.5% of direct injection's,
+    # better or worse depending on the training run (0.1185 to 0.1220 against
+    # 0.1209 at nu = 0.0061 over the settings tried; optimum 0.1098): no robust
+    # gain on this workload.  The assertions keep to what held in every run.
     from paper_2105_01271_amd import learned
     say("learned vs direct injection")
     dev = torch.device("cuda")
@@ -181,7 +186,7 @@ def test_learned_restriction_against_direct_injection_at_held_out_diffusivities(
     tr, va, te = synth.learned_diffusivities()
     train = [synth.learned_trajectory(nu, 1000 + i, dev) for i, nu in enumerate(tr)]
     val = [synth.learned_trajectory(nu, 2000 + i, dev) for i, nu in enumerate(va)]
-    w1, w2, hist = learned.train(train, N, N, C=16, ell=ell, q=q, steps=600, batch=500, lr=2e-3, seed=0)
+    w1, w2, hist = learned.train(train, N, N, C=16, ell=ell, q=q, steps=600, batch=1000, lr=2e-3, seed=0, val=val)
     say(f"  minibatch loss first 20 {np.mean(hist[:20]):.3e} last 20 {np.mean(hist[-20:]):.3e}")
     del train
     choice, ll, ld = learned.judge(val, N, N, w1, w2, ell, q)
@@ -205,6 +210,7 @@ def test_learned_restriction_against_direct_injection_at_held_out_diffusivities(
         e_di.append(err(A, Rdi))
         say(f"  test nu {nu}: optimal {opt:.4e} direct injection {e_di[-1]:.4e} chosen {e_sel[-1]:.4e}")
         assert e_sel[-1] >= opt * (1 - 1e-6)
-    assert choice == "learned"
-    assert e_sel[0] < 0.99 * e_di[0]                    # the measured gain where the tail is largest
-    assert all(a <= b * 1.01 for a, b in zip(e_sel, e_di))
+    assert ll < ld and choice == "learned"
+    gains = [1.0 - a / b for a, b in zip(e_sel, e_di)]
+    say("  relative change of the rank-50 error against direct injection:", [f"{g:+.4f}" for g in gains])
+    assert all(abs(g) <= 0.03 for g in gains)
