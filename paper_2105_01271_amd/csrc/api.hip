@@ -29,28 +29,33 @@ __global__ void __launch_bounds__(256) k_finish(const double *__restrict__ vals,
                                                 const double *__restrict__ sign, int divide, double *__restrict__ S,
                                                 double *__restrict__ colscale, double *__restrict__ info,
                                                 const double *__restrict__ UB, float *__restrict__ Mv) {
-  __shared__ double cs_sh[128];
-  if (threadIdx.x == 0) {
-    double s1 = 0.0, tot = 0.0;
-    for (int j = 0; j < ell; ++j) {
-      const double v = vals[j];
-      const double sg = is_lam ? sqrt(v > 0.0 ? v : 0.0) : v;
-      tot += sg * sg;
-      if (j == 0) s1 = sg;
-      if (j < k) {
-        S[j] = sg;
-        double cs = sign ? sign[j] : 1.0;
-        if (divide) cs = (sg > 1e-300 && sg > 1e-13 * s1) ? cs / sg : 0.0;
-        colscale[j] = cs;
-        cs_sh[j] = cs;
-      }
-    }
+  __shared__ double cs_sh[128], sq_sh[128];
+  const int t = threadIdx.x;
+  // one thread per singular value (ell <= 128)
+  double sg = 0.0;
+  if (t < ell) {
+    const double v = vals[t];
+    sg = is_lam ? sqrt(v > 0.0 ? v : 0.0) : v;
+    sq_sh[t] = sg * sg;
+  }
+  const double v0 = vals[0];
+  const double s1 = is_lam ? sqrt(v0 > 0.0 ? v0 : 0.0) : v0;
+  if (t < k) {
+    S[t] = sg;
+    double cs = sign ? sign[t] : 1.0;
+    if (divide) cs = (sg > 1e-300 && sg > 1e-13 * s1) ? cs / sg : 0.0;
+    colscale[t] = cs;
+    cs_sh[t] = cs;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double tot = 0.0;   // fixed order
+    for (int j = 0; j < ell; ++j) tot += sq_sh[j];
     info[0] = tot;
     info[1] = (ell > k) ? (is_lam ? sqrt(vals[k] > 0.0 ? vals[k] : 0.0) : vals[k]) : 0.0;
   }
-  __syncthreads();
   if (Mv)
-    for (int e = threadIdx.x; e < ell * k; e += 256) {
+    for (int e = t; e < ell * k; e += 256) {
       const int i = e / k, c = e - (e / k) * k;
       Mv[e] = (float)(UB[i * ell + c] * cs_sh[c]);
     }

@@ -21,6 +21,7 @@
 #include <algorithm>
 
 #include "dsk_internal.h"
+#include "wavechol.h"
 
 namespace {
 
@@ -308,9 +309,10 @@ __global__ void __launch_bounds__(NT) k_cpqr_step_reg(double *__restrict__ W, in
 
 // C = R_1^{-1} R_2 by back substitution; P(piv[b], :) = e_b, P(i, :) = C(:, i)^T.
 // One wave per candidate: lane l holds entries a = l and a = l + 64 of the
-// right-hand side; the k substitution steps broadcast x_b by a lane shuffle and
-// update all a < b in parallel.  R_1 is staged transposed in LDS (column b of
-// R_1 contiguous), shared by the 4 waves of a workgroup.
+// right-hand side; each of the k substitution steps takes x_b from lane b by
+// readlane (b is the same in every lane) and updates all a < b in parallel.
+// R_1 is staged transposed in LDS (column b of R_1 contiguous) with the
+// reciprocals of its diagonal, shared by the waves of a workgroup.
 constexpr int KMAX = 112;
 constexpr int SOLVE_WAVES = 4;
 
@@ -320,6 +322,7 @@ __global__ void __launch_bounds__(64 * SOLVE_WAVES) k_id_solve(const double *__r
                                                                double *__restrict__ P, int *__restrict__ dflags) {
   extern __shared__ double dyn[];
   double *R1t = dyn;             // R1t[b*k + a] = R_1[a][b] = Rk[a, piv[b]] (a <= b)
+  double *rd = dyn + k * k;      // 1 / R_1[b][b], 0 for a negligible pivot
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   for (int e = t; e < k * k; e += 64 * SOLVE_WAVES) {
     const int b = e / k, a = e - (e / k) * k;
@@ -328,6 +331,11 @@ __global__ void __launch_bounds__(64 * SOLVE_WAVES) k_id_solve(const double *__r
   }
   __syncthreads();
   const double dmax = fabs(R1t[0]);
+  for (int b = t; b < k; b += 64 * SOLVE_WAVES) {
+    const double dbb = R1t[b * k + b];
+    rd[b] = fabs(dbb) > 1e-14 * dmax ? 1.0 / dbb : 0.0;
+  }
+  __syncthreads();
   for (int64_t i = (int64_t)blockIdx.x * SOLVE_WAVES + wave; i < m; i += (int64_t)gridDim.x * SOLVE_WAVES) {
     if (nu_final[i] < 0.0) {
       // a pivot: identity row
@@ -337,17 +345,21 @@ __global__ void __launch_bounds__(64 * SOLVE_WAVES) k_id_solve(const double *__r
     double c0 = (lane < k) ? Rk[(int64_t)lane * m + i] : 0.0;
     double c1 = (lane + 64 < k) ? Rk[(int64_t)(lane + 64) * m + i] : 0.0;
     bool deficient = false;
-    for (int b = k - 1; b >= 0; --b) {
-      const double cb = __shfl(b < 64 ? c0 : c1, b & 63, 64);
-      const double dbb = R1t[b * k + b];
-      double x = 0.0;
-      if (fabs(dbb) > 1e-14 * dmax) x = cb / dbb;
-      else deficient = true;
-      if (lane == (b & 63)) {
-        if (b < 64) c0 = x; else c1 = x;
-      }
+    for (int b = k - 1; b >= 64; --b) {
+      const double rb = rd[b];
+      const double x = wc::readlane_f64(c1, b - 64) * rb;
+      deficient |= rb == 0.0;
+      if (lane == b - 64) c1 = x;
+      const double *col = R1t + b * k;
+      c0 = fma(-col[lane], x, c0);                       // every a = lane < 64 <= b
+      if (lane + 64 < b) c1 = fma(-col[lane + 64], x, c1);
+    }
+    for (int b = std::min(k, 64) - 1; b >= 0; --b) {
+      const double rb = rd[b];
+      const double x = wc::readlane_f64(c0, b) * rb;
+      deficient |= rb == 0.0;
+      if (lane == b) c0 = x;
       if (lane < b) c0 = fma(-R1t[b * k + lane], x, c0);
-      if (lane + 64 < b) c1 = fma(-R1t[b * k + lane + 64], x, c1);
     }
     if (deficient && lane == 0) atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_RANK_DEFICIENT);
     if (lane < k) P[i * k + lane] = c0;
@@ -391,7 +403,7 @@ int launch_cpqr(hipStream_t st, double *W, int64_t m, int64_t s, int k, double *
 int launch_id_solve(hipStream_t st, const double *Rk, const int64_t *piv, const double *nu_final, int64_t m, int k,
                     double *P, int *dflags) {
   if (k < 1 || k > KMAX) return -1;
-  const size_t lds = (size_t)k * k * sizeof(double);
+  const size_t lds = ((size_t)k * k + k) * sizeof(double);
   allow_lds(k_id_solve, lds);
   const unsigned blocks = (unsigned)std::min<int64_t>((m + SOLVE_WAVES - 1) / SOLVE_WAVES, 256);
   hipLaunchKernelGGL(k_id_solve, dim3(blocks), dim3(64 * SOLVE_WAVES), lds, st, Rk, piv, nu_final, m, k, P, dflags);

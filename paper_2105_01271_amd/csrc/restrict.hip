@@ -171,6 +171,20 @@ __global__ void k_gather_rows(const T *__restrict__ A, int64_t m, int64_t n, int
     out[(int64_t)r * n + c] = ok ? A[src + c] : T(0);
 }
 
+// The same copy in 16-byte pieces when every row start (of A and of out) is
+// 16-byte aligned: nb16 pieces per row.
+typedef unsigned u32x4g __attribute__((ext_vector_type(4)));
+__global__ void k_gather_rows16(const u32x4g *__restrict__ A, int64_t m, int64_t lda16, int64_t nb16,
+                                const int64_t *__restrict__ rows, u32x4g *__restrict__ out) {
+  const int r = blockIdx.y;
+  const int64_t row = rows[r];
+  const bool ok = row >= 0 && row < m;
+  const int64_t src = ok ? row * lda16 : 0;
+  const u32x4g z = {0u, 0u, 0u, 0u};
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nb16; c += (int64_t)gridDim.x * blockDim.x)
+    out[(int64_t)r * nb16 + c] = ok ? A[src + c] : z;
+}
+
 // out[i, c] = A[i, idx[c]] for 16-bit storage, the bits copied unchanged
 __global__ void __launch_bounds__(256) k_gather_cols16(const unsigned short *__restrict__ A, int64_t m, int64_t lda,
                                                        const int64_t *__restrict__ idx, int64_t s,
@@ -293,6 +307,16 @@ int launch_select_cols(hipStream_t st, const void *Ac, int work_f64, int64_t m, 
 
 int launch_gather_rows(hipStream_t st, const void *A, int dtype, int64_t m, int64_t n, int64_t lda,
                        const int64_t *rows, int k, void *out) {
+  const int64_t es = dtype == DSK_F64 ? 8 : dtype == DSK_F32 ? 4 : 2;
+  if ((n * es) % 16 == 0 && (lda * es) % 16 == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0 &&
+      reinterpret_cast<uintptr_t>(out) % 16 == 0) {
+    const int64_t nb16 = n * es / 16;
+    const unsigned bx16 = (unsigned)std::min<int64_t>((nb16 + 255) / 256, 256);
+    hipLaunchKernelGGL(k_gather_rows16, dim3(bx16, (unsigned)k), dim3(256), 0, st, (const u32x4g *)A, m,
+                       lda * es / 16, nb16, rows, (u32x4g *)out);
+    DSK_TRY(hipGetLastError());
+    return 0;
+  }
   const unsigned bx = (unsigned)std::min<int64_t>((n + 255) / 256, 256);
   dim3 grid(bx, (unsigned)k);
   if (dtype == DSK_F64)
