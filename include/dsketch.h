@@ -278,7 +278,7 @@ int dsk_sketch_id(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_
  * are the leading r singular triplets of A_c (the lifting operator's rank r acts
  * as a regulariser, k <= r <= rank(A_c)), and (I, P) is the row ID of A_c, i.e.
  * exactly dsk_sketch_id's at q = 0.  The singular triplets of A_c come from the
- * sketch SVD of A_c with every coarse column kept and qc orthonormalised power
+ * sketch SVD of A_c with every coarse column kept and qc subspace-iteration
  * steps (range finder width ell = min(m, s, 112), 100 for FP64 input): the r-th singular
  * direction's error falls like (sigma_{ell+1} / sigma_r)^(2 qc + 1), so qc sets
  * how close this is to the exact SVD of Alg. 5.  Singular values at or below

@@ -337,7 +337,8 @@ int svd_check(const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, i
 // only the arena size is computed (nothing is allocated or enqueued).
 int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,
             const dsk_restriction *R, int32_t q, const dsk_opts &od, int64_t s, int L, void *U, double *S, void *V,
-            dsk_info *info, size_t *need, const std::function<int()> *after_projection, bool single_pass) {
+            dsk_info *info, size_t *need, const std::function<int()> *after_projection, bool single_pass,
+            bool orth_z) {
   hipStream_t st = h->stream;
   const int f64 = dtype == DSK_F64;
   const size_t we = f64 ? 8 : 4;
@@ -443,7 +444,7 @@ int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, i
       // Z = A_g^T Q (s x ell), orthonormalised; Q = orth(A_g Z), A_g = A(:, I) the Gram
       // sub-sample of Alg. 7.  tau cancels under re-orthonormalisation.
       DSK_RET(launch_stream(st, Gs, wdt, m, s, s, Q, f64, L, Z, L, od.mode, sws, h->cu_count));
-      DSK_RET(orth(h, Z, f64, s, L, Z, tmp, cws, Rsm, true));
+      if (orth_z) DSK_RET(orth(h, Z, f64, s, L, Z, tmp, cws, Rsm, true));
       DSK_RET(launch_stream_nn(st, Gs, wdt, m, s, s, Z, L, Y, L, od.mode, sws, h->cu_count));
       DSK_RET(orth(h, Y, f64, m, L, Q, tmp, cws, Rsm, it + 1 < q));
     }

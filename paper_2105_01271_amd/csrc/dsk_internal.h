@@ -109,10 +109,13 @@ int svd_check(const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, i
 // (work forked from the handle's stream at that point starts after it).
 // single_pass: SPC-SVD (Alg. 3, q must be 0): the pass over A forms H = A^T Y
 // while a worker stream orthonormalises Y, then B^T = H R^{-1}.
+// orth_z = false: each power step forms Y = A_g (A_g^T Q) without
+// orthonormalising the middle block (the same span; used where the steps are
+// plain subspace iteration, not the paper's C-PWR).
 int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,
             const dsk_restriction *R, int32_t q, const dsk_opts &od, int64_t s, int L, void *U, double *S, void *V,
             dsk_info *info, size_t *need, const std::function<int()> *after_projection = nullptr,
-            bool single_pass = false);
+            bool single_pass = false, bool orth_z = true);
 int ensure_workers(dsk_handle *h, int nw);   // batch.hip
 int id_check(const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k, const dsk_restriction *R,
              int32_t q, const dsk_opts *o, int64_t *skel, double *P, dsk_opts *odp, int64_t *s_out, int64_t *cols_out,

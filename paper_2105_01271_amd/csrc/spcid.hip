@@ -12,7 +12,8 @@
 //             strided column slice of H)
 //   worker 0  top r singular triplets of A_c: the sketch SVD of A_c itself with
 //             every coarse column kept (start block of ell = min(m, s, 112)
-//             nested columns, 100 for FP64 input, qc orthonormalised power steps, core eigensolver);
+//             nested columns, 100 for FP64 input, qc subspace-iteration steps
+//             Q <- orth(A_c A_c^T Q), core eigensolver);
 //             exact as qc grows, the error of the r-th direction falling like
 //             (sigma_{ell+1} / sigma_r)^(2 qc + 1)
 //   worker 1  the row ID of A_c (TPC-ID at q = 0: the same skeleton and P)
@@ -23,6 +24,8 @@
 // the work precision) are treated as zero in S_r^{-2} (the pseudo-inverse
 // S_c^+) and raise DSK_FLAG_RANK_DEFICIENT.
 #include <algorithm>
+#include <cstdlib>
+#include <thread>
 
 #include "dsk_internal.h"
 
@@ -68,6 +71,16 @@ __global__ void __launch_bounds__(NT) k_scale_inv2(const T *__restrict__ V, int6
   const double sg = S[j];
   const double f = sg > thr ? 1.0 / (sg * sg) : 0.0;
   Z[e] = (T)((double)V[e] * f);
+}
+
+// DSK_SERIAL_ENQUEUE=1: enqueue everything from the calling thread (for
+// runtimes that are not thread-safe, such as a host emulation of the kernels)
+bool serial_enqueue() {
+  static const bool serial = [] {
+    const char *e = std::getenv("DSK_SERIAL_ENQUEUE");
+    return e && e[0] == '1';
+  }();
+  return serial;
 }
 
 template <typename T>
@@ -125,7 +138,8 @@ int dsk_spc_id(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n
   {
     int64_t dummy = 0;
     Rall.index = &dummy;   // only the sizing pass reads it (never dereferenced there)
-    DSK_RET(svd_run(wsv, nullptr, wdt, m, s, s, r, &Rall, qc, osv, s, Lc, nullptr, nullptr, nullptr, nullptr, &need_sv));
+    DSK_RET(svd_run(wsv, nullptr, wdt, m, s, s, r, &Rall, qc, osv, s, Lc, nullptr, nullptr, nullptr, nullptr, &need_sv,
+                    nullptr, false, false));
     Rall.index = nullptr;
   }
   DSK_RET(id_run(wid, A, dtype, m, n, lda, k, R, 0, oid, s, cols, ell_id, skel, P, nullptr, nullptr, &need_id));
@@ -168,18 +182,42 @@ int dsk_spc_id(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n
     DSK_TRY(hipEventRecord(h->wev[0], st));
     DSK_TRY(hipStreamWaitEvent(wsv->stream, h->wev[0], 0));
     DSK_TRY(hipStreamWaitEvent(wid->stream, h->wev[0], 0));
-    DSK_RET(svd_run(wsv, Ac, wdt, m, s, s, r, &Rall, qc, osv, s, Lc, Ur, Sr, Vv, nullptr, nullptr));
-    DSK_TRY(hipEventRecord(h->wev[1], wsv->stream));
     DSK_RET(id_run(wid, A, dtype, m, n, lda, k, R, 0, oid, s, cols, ell_id, skel, P, nullptr, nullptr, nullptr));
     DSK_TRY(hipEventRecord(h->wev[2], wid->stream));
+    // The SVD of A_c is several hundred small launches and the pass over A a
+    // hundred; the runtime holds the enqueuing thread back while a stream has
+    // many launches pending, so one host thread would feed the two streams one
+    // after the other.  The SVD sequence is enqueued from a second thread while
+    // this one enqueues the pass.
+    auto enqueue_svd = [&]() -> int {
+      DSK_TRY(hipSetDevice(h->device));
+      DSK_RET(svd_run(wsv, Ac, wdt, m, s, s, r, &Rall, qc, osv, s, Lc, Ur, Sr, Vv, nullptr, nullptr, nullptr, false,
+                      false));
+      DSK_TRY(hipEventRecord(h->wev[1], wsv->stream));
+      return 0;
+    };
     // H = A^T A_c (n x s), block by block: H(:, c0 : c0 + b) = A^T A_c(:, c0 : c0 + b)
-    for (int64_t c0 = 0; c0 < s; c0 += HBLK) {
-      const int b = (int)std::min<int64_t>(HBLK, s - c0);
-      DSK_RET(f64 ? col_block<double>(st, Ac, s, m, c0, b, Qb) : col_block<float>(st, Ac, s, m, c0, b, Qb));
-      hipEvent_t e0, e1;
-      timing_slot(h, &e0, &e1);
-      DSK_RET(launch_stream(st, A, dtype, m, n, lda, Qb, f64, b, H + c0 * we, s, oid.mode, sws, h->cu_count, e0,
-                            e1));
+    auto enqueue_pass = [&]() -> int {
+      for (int64_t c0 = 0; c0 < s; c0 += HBLK) {
+        const int b = (int)std::min<int64_t>(HBLK, s - c0);
+        DSK_RET(f64 ? col_block<double>(st, Ac, s, m, c0, b, Qb) : col_block<float>(st, Ac, s, m, c0, b, Qb));
+        hipEvent_t e0, e1;
+        timing_slot(h, &e0, &e1);
+        DSK_RET(launch_stream(st, A, dtype, m, n, lda, Qb, f64, b, H + c0 * we, s, oid.mode, sws, h->cu_count, e0,
+                              e1));
+      }
+      return 0;
+    };
+    if (serial_enqueue()) {
+      DSK_RET(enqueue_pass());
+      DSK_RET(enqueue_svd());
+    } else {
+      int svd_rc = 0;
+      std::thread worker([&] { svd_rc = enqueue_svd(); });
+      const int pass_rc = enqueue_pass();
+      worker.join();
+      DSK_RET(pass_rc);
+      DSK_RET(svd_rc);
     }
     // lifting: W_r^T = H V_r S_r^{-2}
     DSK_TRY(hipStreamWaitEvent(st, h->wev[1], 0));

@@ -93,6 +93,7 @@ int main(int argc, char **argv) {
   // enough emulated compute units for the one-launch factorization (m <= 4 x units)
   const bool persist = which == "persist" || which == "persist-quick";
   if (persist) setenv("SIMT_CU", "48", 1);
+  setenv("DSK_SERIAL_ENQUEUE", "1", 1);   // the emulated runtime is single-threaded
   dsk_handle *h = nullptr;
   if (dsk_create(&h, 0, nullptr)) return 1;
   dsk_opts o;
