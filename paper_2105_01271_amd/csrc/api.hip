@@ -605,7 +605,7 @@ int id_check(const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, in
 // The row-ID launch sequence on h's stream and arena (need != NULL: size only).
 int id_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,
            const dsk_restriction *R, int32_t q, const dsk_opts &od, int64_t s, int64_t cols, int64_t ell,
-           int64_t *skel, double *P, void *skel_rows, dsk_info *info, size_t *need) {
+           int64_t *skel, double *P, void *skel_rows, dsk_info *info, size_t *need, int phase) {
   hipStream_t st = h->stream;
   const double tau = od.tau > 0.0 ? od.tau : (double)n / (double)s;
   Carve c{nullptr, 0, 0, true};
@@ -647,10 +647,18 @@ int id_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, in
       c.dry = false;
       continue;
     }
-    hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, st, h->dflags);
-    if (rwsb && wstore) {
-      if (dtype == DSK_F32) DSK_RET(launch_restrict(st, A, dtype, m, n, lda, R, s, 0, Acs, nullptr, h->dflags));
-      else DSK_RET(launch_gather_cols16(st, A, m, n, lda, R, s, Acs));
+    const bool split = rwsb && wstore;   // the phases of the one-launch path (see dsk_internal.h)
+    if (phase == 1 && !split) return 0;
+    if (phase != 2 || !split) hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, st, h->dflags);
+    if (split) {
+      if (phase != 2) {
+        if (dtype == DSK_F32) DSK_RET(launch_restrict(st, A, dtype, m, n, lda, R, s, 0, Acs, nullptr, h->dflags));
+        else DSK_RET(launch_gather_cols16(st, A, m, n, lda, R, s, Acs));
+        if (phase == 1) {
+          DSK_TRY(hipGetLastError());
+          return 0;
+        }
+      }
       DSK_RET(launch_rowid_reg(st, Acs, wdt, m, s, k, nu0, Rk, skel, rws, h->cu_count, h->dflags));
       DSK_RET(launch_id_solve(st, Rk, skel, nu0, m, k, P, h->dflags));
       if (skel_rows) DSK_RET(launch_gather_rows(st, A, dtype, m, n, lda, skel, k, skel_rows));

@@ -234,18 +234,23 @@ int dsk_sketch_svd_id(dsk_handle *h, const void *A, int32_t dtype, int64_t m, in
     return r;
   }
   DSK_TRY(hipSetDevice(h->device));
-  DSK_RET(ensure_workers(h, 1));
+  DSK_RET(ensure_workers(h, 2));   // (one worker; the second worker's event marks the call's start)
   dsk_handle *wk = h->workers[0];
   size_t need = 0;
   DSK_RET(id_run(wk, A, dtype, m, n, lda, k, R, q_id, oid, s, cols, ell_id, skel, P, skel_rows, nullptr, &need));
   DSK_RET(arena_reserve(wk, need));
-  // fork once the SVD's pass over A is enqueued: the row ID (worker stream) then
-  // runs beside the SVD's latency-bound small factorizations, not beside the
-  // bandwidth-bound projection
+  // the row ID's first phase (the gather of the restricted columns, which needs
+  // only A) runs beside the SVD's start; the rest forks once the SVD's pass over
+  // A is enqueued, so that the one-launch pivoted QR runs beside the SVD's
+  // latency-bound small factorizations, not beside the bandwidth-bound projection
+  DSK_TRY(hipEventRecord(h->wev[2], h->stream));
+  DSK_TRY(hipStreamWaitEvent(wk->stream, h->wev[2], 0));
+  DSK_RET(id_run(wk, A, dtype, m, n, lda, k, R, q_id, oid, s, cols, ell_id, skel, P, skel_rows, nullptr, nullptr, 1));
   const std::function<int()> fork = [&]() -> int {
     DSK_TRY(hipEventRecord(h->wev[0], h->stream));
     DSK_TRY(hipStreamWaitEvent(wk->stream, h->wev[0], 0));
-    DSK_RET(id_run(wk, A, dtype, m, n, lda, k, R, q_id, oid, s, cols, ell_id, skel, P, skel_rows, nullptr, nullptr));
+    DSK_RET(id_run(wk, A, dtype, m, n, lda, k, R, q_id, oid, s, cols, ell_id, skel, P, skel_rows, nullptr, nullptr,
+                   2));
     DSK_TRY(hipEventRecord(h->wev[1], wk->stream));
     return 0;
   };

@@ -120,9 +120,14 @@ int ensure_workers(dsk_handle *h, int nw);   // batch.hip
 int id_check(const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k, const dsk_restriction *R,
              int32_t q, const dsk_opts *o, int64_t *skel, double *P, dsk_opts *odp, int64_t *s_out, int64_t *cols_out,
              int64_t *ell_out);
+// phase 0: the whole row ID.  phase 1 then phase 2 on the same stream: the
+// same work split where the one-launch pivoted QR reads the restricted columns
+// in their storage dtype (phase 1: the status reset and that gather, which need
+// only A; phase 2: the rest); on the other paths phase 1 does nothing and
+// phase 2 everything.
 int id_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, int64_t lda, int32_t k,
            const dsk_restriction *R, int32_t q, const dsk_opts &od, int64_t s, int64_t cols, int64_t ell,
-           int64_t *skel, double *P, void *skel_rows, dsk_info *info, size_t *need);
+           int64_t *skel, double *P, void *skel_rows, dsk_info *info, size_t *need, int phase = 0);
 int read_info_words(dsk_handle *h, dsk_info *info, int ell);
 
 // ---------------------------------------------------------------- launchers
