@@ -18,6 +18,7 @@ from oracle import metrics as omet
 from oracle import restrict as ores
 from oracle import rowid as orid
 from oracle import sketch as osk
+import svdcheck
 from paper_2105_01271_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -57,13 +58,15 @@ def test_svd_with_gaussian_second_level_matches_oracle(dtype, q):
     Om = synth.gaussian_matrix(idx.size, 22, seed=22)
     R = dsk().Restriction.di_grid(32, 32, 2, 2)
     U, S, V = dsk().sketch_svd(A, 12, R, q=q, S=_A(Om, dtype))
-    Uo, So, Vo = osk.tpc_svd(A_np, 12, {"kind": "index", "index": idx}, q=q, S=Om)
+    Uo, So, Vo, oi = osk.tpc_svd(A_np, 12, {"kind": "index", "index": idx}, q=q, S=Om, return_all=True)
     tol = TOL[dtype]
     Sg = S.cpu().numpy()
     assert np.abs(Sg - So).max() <= tol * So[0]
     e = omet.svd_error(A_np, _up(U), Sg, _up(V))
     eo = omet.svd_error(A_np, Uo, So, Vo)
     assert abs(e - eo) <= tol * eo + 1e-300
+    # singular vectors one by one (or by cluster projectors)
+    svdcheck.compare_vectors(_up(U), Uo, _up(V), Vo, oi["sigma_B"], 12, tol)
 
 
 @pytest.mark.parametrize("q", [0, 1])

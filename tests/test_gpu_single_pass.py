@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 import torch
 
+import svdcheck
 from oracle import metrics as omet
 from oracle import restrict as ores
 from oracle import sketch as osk
@@ -75,12 +76,14 @@ def test_spc_svd_matches_oracle(dtype, m, N, f, k):
     idx = ores.di_index_2d(N, N, f, f)
     R = dsk().Restriction.di_grid(N, N, f, f)
     U, S, V, info = dsk().sketch_svd_sp(A, k, R, want_info=True)
-    Uo, So, Vo = osk.spc_svd(A_np, k, {"kind": "index", "index": idx})
+    Uo, So, Vo, oi = osk.spc_svd(A_np, k, {"kind": "index", "index": idx}, return_all=True)
     ell = info["ell"]
     Y = osk.start_block(A_np[:, idx], ell)
     tol, kF = _spc_tol(A_np, Y, dtype)
     d = _check(A_np, U, S, V, Uo, So, Vo, tol)
-    say("  ell", ell, "kappa_F(Y)", kF, "tol", tol, "sigma diff", d, "flags", info["flags"])
+    # singular vectors one by one (or by cluster projectors) at the same tolerance
+    nchk = svdcheck.compare_vectors(_up(U), Uo, _up(V), Vo, oi["sigma_B"], k, tol, min_checked=0)
+    say("  ell", ell, "kappa_F(Y)", kF, "tol", tol, "sigma diff", d, "flags", info["flags"], "pairs", nchk)
     assert info["flags"] == 0
 
 
