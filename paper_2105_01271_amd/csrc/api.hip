@@ -372,10 +372,9 @@ int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, i
     double *colscale = c.take<double>(L);
     double *dinfo = c.take<double>(4);
     double *fpart = c.take<double>(1024);
-    // single pass: H = A^T Y, M = R^{-1}, the Gram of Y
+    // single pass: H = A^T Y, M = R^{-1} (FP64 input)
     char *Hb = single_pass ? c.take<char>((size_t)n * L * we) : nullptr;
     double *Mr = single_pass ? c.take<double>((size_t)L * L) : nullptr;
-    double *GY = single_pass ? c.take<double>((size_t)L * L) : nullptr;
     // C-PWR's Gram sub-sample A(:, I) (Alg. 7) when the restriction is not an index set
     const bool own_gram = q > 0 && R->kind != DSK_R_INDEX;
     char *Ag = own_gram ? c.take<char>((size_t)m * s * we) : nullptr;
@@ -410,26 +409,26 @@ int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, i
       hipStream_t wst = wk->stream;
       DSK_TRY(hipEventRecord(h->wev[0], st));
       DSK_TRY(hipStreamWaitEvent(wst, h->wev[0], 0));
-      // FP32 / 16-bit, ell <= 64: one CholeskyQR pass, Y^T Y = L L^T (FP64),
-      // Q = Y L^{-T}; then B^T = H L^{-T} by the same blocked substitution
-      const bool chol_tiles = !f64 && L <= 64;
+      // FP32 / 16-bit: one CholeskyQR pass, Y^T Y = L L^T (FP64), Q = Y L^{-T};
+      // then B^T = H L^{-T} by the same blocked substitution (the 64- or the
+      // 128-wide factorization's tiles)
+      const bool chol_tiles = !f64;
       if (f64) {
         DSK_RET(launch_convert(wst, Y, 1, tmp, 1, m * L));
         DSK_RET(launch_hhqr(wst, tmp, m, L, (double *)Q, Rsm, h->dflags));
-        DSK_RET(launch_spc_rinv(wst, Rsm, L, 0, 0x1p-53, Mr, h->dflags));
-      } else if (chol_tiles) {
+        DSK_RET(launch_spc_rinv(wst, Rsm, L, 0x1p-53, Mr, h->dflags));
+      } else if (L <= 64) {
         DSK_RET(launch_cholqr64(wst, Y, 0, m, L, Q, cws, h->dflags, 1));
       } else {
-        DSK_RET(launch_cholqr2(wst, Y, 0, m, L, Q, cws, h->dflags, Rsm, 2));
-        DSK_RET(launch_gram(wst, Y, 0, m, L, GY, part, nparts));
-        DSK_RET(launch_spc_rinv(wst, GY, L, 1, dtype == DSK_F32 ? 0x1p-24 : (dtype == DSK_BF16 ? 0x1p-8 : 0x1p-11), Mr, h->dflags));
+        DSK_RET(launch_cholqr128(wst, Y, 0, m, L, Q, cws, h->dflags, 1));
       }
       DSK_TRY(hipEventRecord(h->wev[1], wst));
       hipEvent_t e0, e1;
       timing_slot(h, &e0, &e1);
       DSK_RET(launch_stream(st, A, dtype, m, n, lda, Y, f64, L, Hb, L, od.mode, sws, h->cu_count, e0, e1));
       DSK_TRY(hipStreamWaitEvent(st, h->wev[1], 0));
-      if (chol_tiles) DSK_RET(launch_cholqr64_apply(st, Hb, 0, n, L, cws, Bt, h->dflags));
+      if (chol_tiles && L <= 64) DSK_RET(launch_cholqr64_apply(st, Hb, 0, n, L, cws, Bt, h->dflags));
+      else if (chol_tiles) DSK_RET(launch_cholqr128_apply(st, Hb, 0, n, L, cws, Bt, h->dflags));
       else DSK_RET(launch_tsmm(st, Hb, f64, n, L, L, Mr, L, L, nullptr, Bt, L));
     } else {
     // intermediate bases of the power iteration only carry a span (one

@@ -418,6 +418,28 @@ size_t cholqr128_ws_bytes(int64_t rows, int ell) {
   return ((size_t)PMAX * PART + 2 * (size_t)PART) * sizeof(double) + (size_t)rows * EMAX * sizeof(double) + 256;
 }
 
+int launch_cholqr128_apply(hipStream_t st, const void *X, int f64, int64_t rows, int ell, const void *ws, void *out,
+                           int *dflags) {
+  if (ell < 1 || ell > EMAX || rows < 1) return -1;
+  // the factor tiles the last factorization on ws left (after the Gram partials and G)
+  const double *Mf = reinterpret_cast<const double *>(ws) + (size_t)PMAX * PART + PART;
+  // about two workgroups per compute unit's worth of row ranges, each a multiple of RCH rows
+  const int64_t rpw = std::max<int64_t>(RCH, ((rows + 511) / 512 + RCH - 1) / RCH * RCH);
+  const unsigned grid = (unsigned)((rows + rpw - 1) / rpw);
+  const size_t alds = (size_t)APPLY_LDS * sizeof(double);
+  if (f64) {
+    allow_lds(k_q8_apply<double>, alds);
+    hipLaunchKernelGGL(k_q8_apply<double>, dim3(grid), dim3(256), alds, st, (const double *)X, rows, ell, Mf,
+                       (double *)out, rpw, (double *)nullptr, dflags, 0, 0);
+  } else {
+    allow_lds(k_q8_apply<float>, alds);
+    hipLaunchKernelGGL(k_q8_apply<float>, dim3(grid), dim3(256), alds, st, (const float *)X, rows, ell, Mf,
+                       (float *)out, rpw, (double *)nullptr, dflags, 0, 0);
+  }
+  DSK_TRY(hipGetLastError());
+  return 0;
+}
+
 int launch_cholqr128(hipStream_t st, const void *Y, int f64, int64_t rows, int ell, void *Q, void *ws, int *dflags,
                      int passes) {
   if (ell < 1 || ell > EMAX || rows < 1 || passes < 1 || passes > 2) return -1;

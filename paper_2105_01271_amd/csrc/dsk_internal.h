@@ -158,11 +158,9 @@ int launch_conv_bwd(hipStream_t st, const void *A, int dtype, int64_t m, int64_t
                     const float *w1, const float *w2, const void *gAc, int g_f64, int64_t ldg, float *gw1,
                     float *gw2, void *ws);
 
-// spc.hip: M = R^{-1} (FP64, upper triangular) from the Gram Y^T Y (from_gram = 1,
-// R = chol(G)^T) or from an upper-triangular R (from_gram = 0); ell <= 112;
-// u_data = unit roundoff of Y's data (rank test)
-int launch_spc_rinv(hipStream_t st, const double *G, int ell, int from_gram, double u_data, double *M,
-                    int *dflags);
+// spc.hip: M = R^{-1} (FP64, upper triangular) from an upper-triangular R
+// (ell x ell row-major); ell <= 112; u_data = unit roundoff of Y's data (rank test)
+int launch_spc_rinv(hipStream_t st, const double *G, int ell, double u_data, double *M, int *dflags);
 
 // smallmat.hip (tall-skinny orthonormalisation, small factorizations)
 size_t cholqr2_ws_bytes(int64_t rows, int ell);
@@ -178,6 +176,10 @@ int launch_cholqr64_apply(hipStream_t st, const void *X, int f64, int64_t rows, 
 // 64 < ell <= 128 (cholqr128.hip): the same contract, Gram partials + fold/factor
 // + blocked-substitution apply per pass.
 size_t cholqr128_ws_bytes(int64_t rows, int ell);
+// out = X L^{-T} with the factor L the last launch_cholqr128 on ws computed
+// (with passes = 1: Y^T Y = L L^T), by the same blocked substitution
+int launch_cholqr128_apply(hipStream_t st, const void *X, int f64, int64_t rows, int ell, const void *ws, void *out,
+                           int *dflags);
 int launch_cholqr128(hipStream_t st, const void *Y, int f64, int64_t rows, int ell, void *Q, void *ws, int *dflags,
                      int passes);
 // passes = 2: CholeskyQR2 (orthonormal to working precision); passes = 1: one

@@ -1,36 +1,30 @@
 // Single-pass coarse-grid SVD (SPC-SVD, Alg. 3): the small factor that turns
-// the one-pass product H = A^T Y into B^T = A^T Q.
+// the one-pass product H = A^T Y into B^T = A^T Q for FP64 input.
 //
 // With Y = Q R (R upper triangular, Q orthonormal), A^T Q = H R^{-1} (the
 // identity derived under Alg. 3), so the pass over A needs only Y, not Q, and
 // can run while Y is being orthonormalised.  This kernel forms M = R^{-1} in
-// FP64 from either
-//   * the FP64 Gram G = Y^T Y (FP32 / 16-bit path): R = chol(G)^T, i.e. the R
-//     of the first CholeskyQR pass, so Y M is orthonormal to O(u kappa(Y)^2)
-//     in FP64, or
-//   * the Householder R of Y (FP64 path).
+// FP64 from the Householder R of Y.  (The FP32 / 16-bit paths apply the
+// CholeskyQR factor of Y to H by the blocked substitution instead.)
 // Y numerically rank deficient at the precision of its data (some
 // |R_jj| <= ell u_data ||Y||_F), where the single-pass formula breaks down,
-// raises DSK_FLAG_RANK_DEFICIENT; a non-positive Cholesky pivot is raised to
-// ell u tr(G) and a zero or non-finite diagonal entry of R gives a zero row of
-// M, so the outputs stay finite.
+// raises DSK_FLAG_RANK_DEFICIENT; a zero or non-finite diagonal entry of R
+// gives a zero row of M, so the outputs stay finite.
 #include "dsk_internal.h"
 
 namespace {
 
 constexpr int NT = 256;
-constexpr double U64 = 1.1102230246251565e-16;
 
 // One workgroup.  LDS: one (ell + 1) x (ell + 1) array holding R in its upper
 // triangle (rows 0..ell-1) and M = R^{-1} transposed strictly below the
 // diagonal: M(r, c), r <= c, at row c + 1, column r.
-__global__ void __launch_bounds__(NT) k_spc_rinv(const double *__restrict__ G, int ell, int from_gram,
-                                                 double u_data, double *__restrict__ M, int *__restrict__ dflags) {
+__global__ void __launch_bounds__(NT) k_spc_rinv(const double *__restrict__ G, int ell, double u_data,
+                                                 double *__restrict__ M, int *__restrict__ dflags) {
   extern __shared__ double sm[];
   const int ld = ell + 1;
   double *Rs = sm;
   auto X = [&](int r, int c) -> double & { return sm[(c + 1) * ld + r]; };
-  __shared__ double thr_sh;
   __shared__ int bad;
   const int t = threadIdx.x;
   if (t == 0) bad = 0;
@@ -39,36 +33,6 @@ __global__ void __launch_bounds__(NT) k_spc_rinv(const double *__restrict__ G, i
     Rs[i * ld + c] = G[e];
   }
   __syncthreads();
-  if (from_gram) {
-    if (t == 0) {
-      double tr = 0.0;
-      for (int j = 0; j < ell; ++j) tr += Rs[j * ld + j];
-      thr_sh = ell * U64 * tr;
-    }
-    __syncthreads();
-    const double thr = thr_sh;
-    // right-looking Cholesky G = R^T R, R upper, kept in the upper triangle of Rs
-    for (int j = 0; j < ell; ++j) {
-      if (t == 0) {
-        double d = Rs[j * ld + j];
-        if (!(d > thr) || !isfinite(d)) {
-          bad = 1;
-          d = thr > 0.0 && isfinite(thr) ? thr : 1.0;
-        }
-        Rs[j * ld + j] = sqrt(d);
-      }
-      __syncthreads();
-      const double rjj = Rs[j * ld + j];
-      for (int c = j + 1 + t; c < ell; c += NT) Rs[j * ld + c] /= rjj;
-      __syncthreads();
-      const int w = ell - j - 1;
-      for (int e = t; e < w * w; e += NT) {
-        const int i = j + 1 + e / w, c = j + 1 + (e - (e / w) * w);
-        if (c >= i) Rs[i * ld + c] = fma(-Rs[j * ld + i], Rs[j * ld + c], Rs[i * ld + c]);
-      }
-      __syncthreads();
-    }
-  }
   // numerical rank at the data precision: ||Y||_F = ||R||_F
   if (t == 0) {
     double f2 = 0.0;
@@ -98,12 +62,11 @@ __global__ void __launch_bounds__(NT) k_spc_rinv(const double *__restrict__ G, i
 
 }  // namespace
 
-int launch_spc_rinv(hipStream_t st, const double *G, int ell, int from_gram, double u_data, double *M,
-                    int *dflags) {
+int launch_spc_rinv(hipStream_t st, const double *G, int ell, double u_data, double *M, int *dflags) {
   if (ell < 1 || ell > 112) return -1;
   const size_t lds = (size_t)(ell + 1) * (ell + 1) * sizeof(double);
   allow_lds(k_spc_rinv, lds);
-  hipLaunchKernelGGL(k_spc_rinv, dim3(1), dim3(NT), lds, st, G, ell, from_gram, u_data, M, dflags);
+  hipLaunchKernelGGL(k_spc_rinv, dim3(1), dim3(NT), lds, st, G, ell, u_data, M, dflags);
   DSK_TRY(hipGetLastError());
   return 0;
 }
