@@ -465,7 +465,8 @@ int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, i
       // V = B^T U_B(:, :k) diag(sign / sigma) on the MFMA stream kernel (n rows, K = ell)
       DSK_RET(launch_stream_nn(st, Bt, DSK_F32, n, L, L, Mv, k, Va, k, od.mode, sws, h->cu_count));
       if (refine)
-        DSK_RET(launch_refine(st, U0, m, V0, n, k, S, (float *)U, (float *)V, part, nparts, rws, h->dflags));
+        DSK_RET(launch_refine(st, U0, m, V0, n, k, S, (float *)U, (float *)V, part, nparts, rws, h->dflags,
+                              od.mode, sws, h->cu_count));
     } else {
       DSK_RET(launch_convert(st, Bt, 1, tmp, 1, n * L));
       DSK_RET(launch_hhqr(st, tmp, n, L, QB, RB, h->dflags));

@@ -201,10 +201,12 @@ int launch_gram_mfma(hipStream_t st, const void *X, int f64, int64_t rows, int e
 int launch_gram_tiles(hipStream_t st, const void *X, int f64, int64_t rows, int ell, int64_t rows_per_blk,
                       double *part);
 // refine.hip: FP64 re-orthonormalisation of the assembled FP32 factors (U0 m x k,
-// V0 n x k, S k) into U, V, S with U S V^T unchanged (k <= 100); ws: refine_ws_bytes(k)
+// V0 n x k, S k) into U, V, S with U S V^T unchanged (k <= 100); ws: refine_ws_bytes(k);
+// sws: the stream workspace of an n-row product with K = k (the mode's FP32 products)
 size_t refine_ws_bytes(int k);
 int launch_refine(hipStream_t st, const float *U0, int64_t m, const float *V0, int64_t n, int k, double *S,
-                  float *U, float *V, double *part, int nparts, double *ws, int *dflags);
+                  float *U, float *V, double *part, int nparts, double *ws, int *dflags, int mode, void *sws,
+                  int cu_count);
 // jacobi.hip
 int launch_core_eig(hipStream_t st, const double *G, int ell, double *lam, double *U, int *dflags);
 // the same, run only where *gate != 0 (gate may be null: always); count matrices, one workgroup each

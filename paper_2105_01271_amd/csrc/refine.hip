@@ -95,12 +95,20 @@ __global__ void __launch_bounds__(RNT) k_refine_post(const double *__restrict__ 
     for (int j = threadIdx.x; j < k; j += RNT) S[j] = sig[j];
 }
 
+// out (k x k, FP32) = F diag(sign)
+__global__ void __launch_bounds__(RNT) k_scale_cols_f32(const double *__restrict__ F, int k,
+                                                        const double *__restrict__ sign, float *__restrict__ out) {
+  const int e = blockIdx.x * RNT + threadIdx.x;
+  if (e < k * k) out[e] = (float)(F[e] * sign[e % k]);
+}
+
 }  // namespace
 
-size_t refine_ws_bytes(int k) { return (size_t)12 * k * k * sizeof(double) + 4 * 256 + (size_t)k * 8 + 4096; }
+size_t refine_ws_bytes(int k) { return (size_t)13 * k * k * sizeof(double) + 4 * 256 + (size_t)k * 8 + 4096; }
 
 int launch_refine(hipStream_t st, const float *U0, int64_t m, const float *V0, int64_t n, int k, double *S,
-                  float *U, float *V, double *part, int nparts, double *ws, int *dflags) {
+                  float *U, float *V, double *part, int nparts, double *ws, int *dflags, int mode, void *sws,
+                  int cu_count) {
   if (k < 1 || k > 100) return -1;
   const size_t k2 = (size_t)k * k;
   double *G = ws;              // G_U, G_V -> R_U, R_V
@@ -111,6 +119,7 @@ int launch_refine(hipStream_t st, const float *U0, int64_t m, const float *V0, i
   double *F = Vm + k2;         // F_U, F_V
   double *sig = F + 2 * k2;
   double *sign = sig + k;
+  float *Fv32 = reinterpret_cast<float *>(sign + k);   // F_V diag(sign) in FP32 (k x k)
   DSK_RET(launch_gram(st, U0, 0, m, k, G, part, nparts));
   DSK_RET(launch_gram(st, V0, 0, n, k, G + k2, part, nparts));
   hipLaunchKernelGGL(k_chol_inv2, dim3(2), dim3(RNT), 0, st, G, k, T, dflags);
@@ -122,6 +131,10 @@ int launch_refine(hipStream_t st, const float *U0, int64_t m, const float *V0, i
   DSK_TRY(hipGetLastError());
   DSK_RET(launch_tsmm(st, U0, 0, m, k, k, F, k, k, nullptr, U, k));
   DSK_RET(launch_sign_fix(st, U, 0, m, k, sign));
-  DSK_RET(launch_tsmm(st, V0, 0, n, k, k, F + k2, k, k, sign, V, k));
+  // V = V0 F_V diag(sign): n x k by k x k on the MFMA stream kernel (FP32 to about 2^-24)
+  hipLaunchKernelGGL(k_scale_cols_f32, dim3((unsigned)((k2 + RNT - 1) / RNT)), dim3(RNT), 0, st, F + k2, k, sign,
+                     Fv32);
+  DSK_TRY(hipGetLastError());
+  DSK_RET(launch_stream_nn(st, V0, DSK_F32, n, k, k, Fv32, k, V, k, mode, sws, cu_count));
   return 0;
 }
