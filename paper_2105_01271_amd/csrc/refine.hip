@@ -9,8 +9,8 @@
 //   U' = U R_U^-1 U_m,  V' = V R_V^-1 V_m,  S' = singular values of M
 //
 // so U S V^T = U' S' V'^T with U', V' orthonormal to the rounding of their
-// FP32 storage.  Small matrices stay in global memory (k <= 112); one
-// workgroup each.
+// FP32 storage.  k <= 100; the two Cholesky factorisations and inverses run
+// in LDS, one workgroup each, the k x k products in global memory.
 #include <algorithm>
 
 #include "dsk_internal.h"
@@ -21,48 +21,58 @@ constexpr int RNT = 256;
 
 // blockIdx.x = b: G_b (k x k, row-major) -> R_b (upper, G = R^T R) in place, then
 // T_b = R_b^-1 (upper).  A non-positive pivot sets the rank flag and the pivot to 1.
+// The matrix is factored in LDS (row stride k + 1), right-looking, one pivot
+// per step; T by one thread per column, reading R from LDS.
+constexpr int CK = 100;   // largest k
 __global__ void __launch_bounds__(RNT) k_chol_inv2(double *__restrict__ G, int k, double *__restrict__ T,
                                                    int *__restrict__ dflags) {
+  __shared__ double Rs[(CK + 1) * (CK + 1)];   // rows 0 .. k (row k: the last column of T)
+  __shared__ double pinv_sh;
+  const int ld = k + 1;
   double *R = G + (size_t)blockIdx.x * k * k;
   double *Ti = T + (size_t)blockIdx.x * k * k;
-  __shared__ double piv_sh;
   const int t = threadIdx.x;
+  for (int e = t; e < k * k; e += RNT) Rs[(e / k) * ld + e % k] = R[e];
+  __syncthreads();
   for (int j = 0; j < k; ++j) {
     if (t == 0) {
-      double d = R[j * k + j];
+      double d = Rs[j * ld + j];
       if (!(d > 0.0) || !isfinite(d)) {
         atomicOr(&dflags[FLAGW_BITS], DSK_FLAG_RANK_DEFICIENT);
         d = 1.0;
       }
-      piv_sh = sqrt(d);
-      R[j * k + j] = piv_sh;
+      const double p = sqrt(d);
+      Rs[j * ld + j] = p;
+      pinv_sh = 1.0 / p;
     }
     __syncthreads();
-    const double pinv = 1.0 / piv_sh;
-    for (int c = j + 1 + t; c < k; c += RNT) R[j * k + c] *= pinv;
-    __syncthreads();
-    // trailing update of the upper triangle: G[i][c] -= R[j][i] R[j][c], j < i <= c
+    const double pinv = pinv_sh;
     const int rem = k - j - 1;
+    // row j right of the pivot scaled; the trailing upper triangle updated from
+    // the scaled row (each thread scales the two entries it reads itself)
     for (int e = t; e < rem * rem; e += RNT) {
       const int i = j + 1 + e / rem, c = j + 1 + e % rem;
-      if (c >= i) R[i * k + c] = fma(-R[j * k + i], R[j * k + c], R[i * k + c]);
+      if (c >= i) Rs[i * ld + c] = fma(-(Rs[j * ld + i] * pinv), Rs[j * ld + c] * pinv, Rs[i * ld + c]);
     }
+    __syncthreads();
+    for (int c = j + 1 + t; c < k; c += RNT) Rs[j * ld + c] *= pinv;
     __syncthreads();
   }
   for (int e = t; e < k * k; e += RNT) {
     const int i = e / k, c = e % k;
-    if (i > c) R[e] = 0.0;
+    R[e] = i > c ? 0.0 : Rs[i * ld + c];
   }
-  __syncthreads();
-  // T = R^-1: column c by back substitution (one thread per column)
+  // T = R^-1: column c by back substitution (one thread per column), the column
+  // kept in the (no longer needed) strictly lower part of Rs: T(i, c) at Rs[(c + 1) * ld + i]
   for (int c = t; c < k; c += RNT) {
-    for (int i = k - 1; i > c; --i) Ti[i * k + c] = 0.0;
-    Ti[c * k + c] = 1.0 / R[c * k + c];
+    double *x = Rs + (size_t)(c + 1) * ld;   // row c + 1 of Rs, entries 0 .. c (below the diagonal of row c + 1)
+    x[c] = 1.0 / Rs[c * ld + c];
     for (int i = c - 1; i >= 0; --i) {
       double s = 0.0;
-      for (int l = i + 1; l <= c; ++l) s = fma(R[i * k + l], Ti[l * k + c], s);
-      Ti[i * k + c] = -s / R[i * k + i];
+      for (int l = i + 1; l <= c; ++l) s = fma(Rs[i * ld + l], x[l], s);
+      x[i] = -s / Rs[i * ld + i];
     }
+    for (int i = 0; i < k; ++i) Ti[i * k + c] = i <= c ? x[i] : 0.0;
   }
 }
 
