@@ -12,11 +12,12 @@
 //  * fold + factor: every workgroup sums 64 entries of the partials in a
 //    fixed order (four threads per entry, partials strided by four, then the
 //    four in order) and publishes them; the last workgroup to arrive factors
-//    G = L L^T in LDS.  Each 16-column panel is factored by one wave in
-//    registers (no barrier inside a panel, only 1 / d on the chain from pivot
-//    to pivot), the trailing tiles A_IJ -= L_IK L_JK^T go to all four waves on
-//    MFMA: two barriers per panel.  Then W_K = L_KK^{-1} for the diagonal
-//    blocks;
+//    G = L L^T in LDS, blocked by 16 columns: one wave factors the diagonal
+//    block A_KK in registers (pivot columns broadcast as scalars, only 1 / d
+//    on the chain from pivot to pivot) and inverts it, W_K = L_KK^{-1}; the
+//    four waves then form the panel below it, L_IK = A_IK W_K^T, on MFMA; the
+//    trailing tiles A_IJ -= L_IK L_JK^T go to three waves while the fourth
+//    updates and factors the next diagonal block: two barriers per block;
 //  * apply: each wave owns 16 rows of a 64-row chunk and forms
 //    Q_J = (Y_J - sum_{K<J} Q_K L_JK^T) W_J^T block column by block column
 //    on MFMA, with no barrier; when the next pass needs the Gram of the
@@ -47,7 +48,7 @@ constexpr int MST = 16 * 17;              // LDS footprint of a factor tile (row
 constexpr int FE = 64;                    // entries per fold workgroup
 constexpr double U64 = 1.1102230246251565e-16;
 
-constexpr int FACT_LDS = EMAX * LDA + 64 + EMAX + 8;       // A, colb, dinv, words
+constexpr int FACT_LDS = EMAX * LDA + NBM * 16 * 17 + 8;   // A, W_K tiles, words
 constexpr int APPLY_LDS = NTM * MST + RCH * LDQ + 4 * MST;  // factor tiles, chunk, per-wave S
 
 __device__ __forceinline__ int ltile(int J, int K) { return J * (J + 1) / 2 + K; }
@@ -60,25 +61,27 @@ __device__ __forceinline__ void tile_ij(int id, int &I, int &J) {
 
 // A (LDS, lower triangle) from the folded Gram (tile-major, published by other
 // workgroups of this launch); identity past ell; shift added to the diagonal.
-// A thread's loads go out in two batches of 18, each issued before its first use.
+// Thread t reads entry t of every tile (so the tile of each load is a
+// compile-time constant); its loads go out in two batches, each issued
+// before its first use.
 __device__ __forceinline__ void load_gram(const double *G, int ell, int nb, double shift, double *A) {
-  constexpr int LG = NTM * TILE / 256 / 2;
-  const int ne = nb * (nb + 1) / 2 * TILE;
-#pragma unroll 1
+  constexpr int LG = NTM / 2;
+  const int nt = nb * (nb + 1) / 2, t = threadIdx.x, r16 = t >> 4, c16 = t & 15;
+#pragma unroll
   for (int h = 0; h < 2; ++h) {
     double v[LG];
 #pragma unroll
     for (int u = 0; u < LG; ++u) {
-      const int e = threadIdx.x + 256 * (u + LG * h);
-      v[u] = e < ne ? ds::ld_dev(&G[e]) : 0.0;
+      const int id = u + LG * h;
+      v[u] = id < nt ? ds::ld_dev(&G[id * TILE + t]) : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < LG; ++u) {
-      const int e = threadIdx.x + 256 * (u + LG * h);
-      if (e >= ne) continue;
+      const int id = u + LG * h;
+      if (id >= nt) continue;
       int I, J;
-      tile_ij(e >> 8, I, J);
-      const int r = 16 * I + ((e >> 4) & 15), c = 16 * J + (e & 15);
+      tile_ij(id, I, J);
+      const int r = 16 * I + r16, c = 16 * J + c16;
       double x = v[u];
       if (r >= ell || c >= ell) x = (r == c) ? 1.0 : 0.0;
       else if (r == c) x += shift;
@@ -87,77 +90,102 @@ __device__ __forceinline__ void load_gram(const double *G, int ell, int nb, doub
   }
 }
 
-// Panel K of the factorization by the calling wave (rows 16 K .. ellp - 1,
-// lane l keeps rows 16 K + l and 16 K + 64 + l): the column of pivot p reaches
-// every lane through one LDS write (colb) and uniform-address reads, the pivot
-// itself by v_readlane; A(i, c) -= A(i, p) A(c, p) / d needs no square root
-// on the chain.  Padded columns (p >= ell) are identity columns.  Writes L's
-// panel (zero above the diagonal) back to A and 1 / L(p, p) to dinv.
-__device__ __forceinline__ bool panel(double *A, int K, int ell, int ellp, double thr, double *colb, double *dinv) {
-  const int l = threadIdx.x & 63, c0 = 16 * K;
-  const int r0 = c0 + l, r1 = c0 + 64 + l;
-  const bool h0 = r0 < ellp, h1 = r1 < ellp;
-  double g0[16], g1[16];
+// Diagonal block K by the calling wave: lane i (mod 16) holds row i of the
+// trailing-updated A_KK.  Pivot by pivot, the pivot column reaches every lane
+// as scalars (v_readlane), so no LDS round trip sits on the chain from one
+// pivot to the next; A(i, c) -= A(i, p) A(c, p) / d needs no square root on
+// it.  Then W_K = L_KK^{-1} by forward substitution, column c in lane c, the
+// entries of L read back from LDS at uniform addresses.  Lanes 0 .. 15 write L_KK (zero above
+// the diagonal) to A, W_K to Wl and to its factor tile.  Padded pivots
+// (p >= ell) are identity columns.
+__device__ __forceinline__ bool diag_block(double *A, double *Wl, double *Mf, int K, int ell, double thr) {
+  const int l = threadIdx.x & 63, i = l & 15, c0 = 16 * K;
+  double a[16];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    g0[j] = h0 ? A[r0 * LDA + c0 + j] : 0.0;
-    g1[j] = h1 ? A[r1 * LDA + c0 + j] : 0.0;
-  }
+  for (int c = 0; c < 16; ++c) a[c] = A[(c0 + i) * LDA + c0 + c];
   bool ok = true;
-  double mydinv = 1.0;
+  double rsv[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    const int p = c0 + j;
-    const bool live = p < ell;
-    const double dp = wc::readlane_f64(g0[j], j);
-    colb[l] = g0[j];
-    wc::wave_lds_sync();
-    double lc[16];
-#pragma unroll
-    for (int c = j + 1; c < 16; ++c) lc[c] = colb[c];
+    const bool live = c0 + j < ell;
+    const double dp = wc::readlane_f64(a[j], j);
     const double d = live ? dp : 1.0;
-    ok = ok && (!live || (d > thr && isfinite(d)));
+    ok = ok & (!live | ((d > thr) & isfinite(d)));
     const double inv = wc::rcp_nr(d), rs = wc::rsq_nr(d);
-    const double t0 = g0[j] * inv, t1 = g1[j] * inv;
+    const double t = a[j] * inv;
 #pragma unroll
-    for (int c = j + 1; c < 16; ++c) {
-      g0[c] = fma(-t0, lc[c], g0[c]);
-      g1[c] = fma(-t1, lc[c], g1[c]);
+    for (int c = j + 1; c < 16; ++c) a[c] = fma(-t, wc::readlane_f64(a[j], c), a[c]);
+    a[j] = live ? (i > j ? a[j] * rs : (i == j ? d * rs : 0.0)) : (i == j ? 1.0 : 0.0);
+    rsv[j] = live ? rs : 1.0;
+  }
+  if (l < 16) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) A[(c0 + i) * LDA + c0 + c] = (c <= i) ? a[c] : 0.0;
+  }
+  wc::wave_lds_sync();
+  // x_r = (delta_rc - sum_{m < r} L(r, m) x_m) / L(r, r), L(r, m) by
+  // uniform-address LDS reads; zero above the diagonal by construction
+  const double *Lk = A + c0 * LDA + c0;
+  double x[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    double s = (r == i) ? 1.0 : 0.0;
+#pragma unroll
+    for (int m = 0; m < r; ++m) s = fma(-Lk[r * LDA + m], x[m], s);
+    x[r] = s * rsv[r];
+  }
+  if (l < 16) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      Wl[K * MST + r * 17 + i] = x[r];
+      Mf[ltile(K, K) * TILE + r * 16 + i] = x[r];
     }
-    g0[j] = live ? (r0 > p ? g0[j] * rs : (r0 == p ? d * rs : 0.0)) : (r0 == p ? 1.0 : 0.0);
-    g1[j] = live ? g1[j] * rs : 0.0;
-    mydinv = (r0 == p) ? (live ? rs : 1.0) : mydinv;
-    wc::wave_lds_sync();   // colb is rewritten by the next step
   }
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    if (h0) A[r0 * LDA + c0 + j] = (r0 >= c0 + j) ? g0[j] : 0.0;
-    if (h1) A[r1 * LDA + c0 + j] = g1[j];
-  }
-  if (l < 16) dinv[c0 + l] = mydinv;
   return ok;
 }
 
-// A_IJ -= L_IK L_JK^T for K < J <= I < nb, tiles dealt to the four waves.
-// MFMA operands: A(i, k) = L(16 I + i, 16 K + k) in lane i + 16 k,
-// B(k, j) = L(16 J + j, 16 K + k) in lane j + 16 k.
-__device__ __forceinline__ void trailing(double *A, int K, int nb) {
+// L_IK = A_IK W_K^T for K < I < nb, tiles dealt to the four waves (in place:
+// a wave reads its whole tile before it writes it), also stored as factor tiles.
+__device__ __forceinline__ void below(double *A, const double *Wl, double *Mf, int K, int nb) {
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6, c0 = 16 * K;
-  const int mrest = nb - 1 - K, cnt = mrest * (mrest + 1) / 2;
-  for (int id = w; id < cnt; id += 4) {
-    int I, J;
-    tile_ij(id, I, J);
-    I += K + 1;
-    J += K + 1;
-    d4 c;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) c[v] = A[(16 * I + (l >> 4) + 4 * v) * LDA + 16 * J + (l & 15)];
+  for (int I = K + 1 + w; I < nb; I += 4) {
+    d4 c = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k4 = 0; k4 < 4; ++k4)
-      c = mfma(-A[(16 * I + (l & 15)) * LDA + c0 + 4 * k4 + (l >> 4)],
-               A[(16 * J + (l & 15)) * LDA + c0 + 4 * k4 + (l >> 4)], c);
+      c = mfma(A[(16 * I + (l & 15)) * LDA + c0 + 4 * k4 + (l >> 4)], Wl[K * MST + (l & 15) * 17 + 4 * k4 + (l >> 4)],
+               c);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) A[(16 * I + (l >> 4) + 4 * v) * LDA + 16 * J + (l & 15)] = c[v];
+    for (int v = 0; v < 4; ++v) {
+      A[(16 * I + (l >> 4) + 4 * v) * LDA + c0 + (l & 15)] = c[v];
+      Mf[ltile(I, K) * TILE + ((l >> 4) + 4 * v) * 16 + (l & 15)] = c[v];
+    }
+  }
+}
+
+// A_IJ -= L_IK L_JK^T for one tile (K < J <= I), by the calling wave.
+// MFMA operands: A(i, k) = L(16 I + i, 16 K + k) in lane i + 16 k,
+// B(k, j) = L(16 J + j, 16 K + k) in lane j + 16 k.
+__device__ __forceinline__ void trail_tile(double *A, int K, int I, int J) {
+  const int l = threadIdx.x & 63, c0 = 16 * K;
+  d4 c;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) c[v] = A[(16 * I + (l >> 4) + 4 * v) * LDA + 16 * J + (l & 15)];
+#pragma unroll
+  for (int k4 = 0; k4 < 4; ++k4)
+    c = mfma(-A[(16 * I + (l & 15)) * LDA + c0 + 4 * k4 + (l >> 4)],
+             A[(16 * J + (l & 15)) * LDA + c0 + 4 * k4 + (l >> 4)], c);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) A[(16 * I + (l >> 4) + 4 * v) * LDA + 16 * J + (l & 15)] = c[v];
+}
+
+// The trailing tiles of block K but the next diagonal one (tile 0 of the
+// enumeration), dealt to the calling waves: tile id0, id0 + stride, ...
+__device__ __forceinline__ void trailing(double *A, int K, int nb, int id0, int stride) {
+  const int mrest = nb - 1 - K, cnt = mrest * (mrest + 1) / 2;
+  for (int id = id0; id < cnt; id += stride) {
+    int I, J;
+    tile_ij(id, I, J);
+    trail_tile(A, K, I + K + 1, J + K + 1);
   }
 }
 
@@ -166,8 +194,8 @@ __device__ __forceinline__ void trailing(double *A, int K, int nb) {
 // tile (J, J) is W_J = L_JJ^{-1}, each 16 x 16 row-major.
 __device__ __forceinline__ void factor(const double *G, int ell, int64_t rows, double *Mf, int *dflags, double *pool) {
   const int t = threadIdx.x, l = t & 63, w = t >> 6;
-  const int nb = (ell + 15) / 16, ellp = 16 * nb, ntile = nb * (nb + 1) / 2;
-  double *A = pool, *colb = A + EMAX * LDA, *dinv = colb + 64, *word = dinv + EMAX;
+  const int nb = (ell + 15) / 16, ntile = nb * (nb + 1) / 2;
+  double *A = pool, *Wl = A + EMAX * LDA, *word = Wl + NBM * MST;
   load_gram(G, ell, nb, 0.0, A);
   __syncthreads();
   if (w == 0) {
@@ -187,11 +215,24 @@ __device__ __forceinline__ void factor(const double *G, int ell, int64_t rows, d
       load_gram(G, ell, nb, 11.0 * ((double)rows * ell + (double)ell * (ell + 1)) * U64 * tr, A);
       __syncthreads();
     }
+    // block K + 1's diagonal tile is updated and factored by wave 0 while the
+    // other three waves update the rest of block K's trailing tiles
+    const double thr = 1e-15 * tr;
     bool okw = true;
-    for (int K = 0; K < nb; ++K) {
-      if (w == 0) okw = panel(A, K, ell, ellp, 1e-15 * tr, colb, dinv) && okw;
+    if (w == 0) okw = diag_block(A, Wl, Mf, 0, ell, thr);
+    __syncthreads();
+    below(A, Wl, Mf, 0, nb);
+    __syncthreads();
+    for (int K = 0; K + 1 < nb; ++K) {
+      if (w == 0) {
+        trail_tile(A, K, K + 1, K + 1);
+        wc::wave_lds_sync();
+        okw = diag_block(A, Wl, Mf, K + 1, ell, thr) && okw;
+      } else {
+        trailing(A, K, nb, w, 3);
+      }
       __syncthreads();
-      trailing(A, K, nb);
+      below(A, Wl, Mf, K + 1, nb);
       __syncthreads();
     }
     if (t == 0) word[1] = okw ? 1.0 : 0.0;
@@ -209,28 +250,6 @@ __device__ __forceinline__ void factor(const double *G, int ell, int64_t rows, d
       Mf[e] = (I == J && ((e >> 4) & 15) == (e & 15)) ? 1.0 : 0.0;
     }
     return;
-  }
-  // W_K = L_KK^{-1} (lower): wave K mod 4, lane j < 16 forms column j
-  for (int K = w; K < nb; K += 4) {
-    if (l < 16) {
-      const int j = l;
-      const double *Lk = A + 16 * K * LDA + 16 * K;
-      double x[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        double s = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-        for (int c = 0; c < i; ++c) s = fma(-Lk[i * LDA + c], x[c], s);
-        x[i] = (i >= j) ? s * dinv[16 * K + i] : 0.0;
-      }
-#pragma unroll
-      for (int i = 0; i < 16; ++i) Mf[ltile(K, K) * TILE + i * 16 + j] = x[i];
-    }
-  }
-  for (int e = t; e < ntile * TILE; e += 256) {
-    int J, K;
-    tile_ij(e >> 8, J, K);
-    if (K < J) Mf[e] = A[(16 * J + ((e >> 4) & 15)) * LDA + 16 * K + (e & 15)];
   }
 }
 
