@@ -360,7 +360,7 @@ int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, i
     sws_b = std::max(sws_b, stream_ws_bytes(f64 ? DSK_F64 : DSK_F32, L, n, k, od.mode));
     char *sws = c.take<char>(sws_b);
     float *Mv = c.take<float>((size_t)L * k);
-    const int nparts = (int)std::min<int64_t>(256, std::max<int64_t>(1, (n + 255) / 256));
+    const int nparts = gram_mfma_blocks(n);
     double *part = c.take<double>((size_t)nparts * L * L);
     double *GB = c.take<double>((size_t)L * L);
     double *lam = c.take<double>(L);

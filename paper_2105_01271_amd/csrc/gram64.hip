@@ -9,8 +9,8 @@
 // I >= J, of its partial Gram with v_mfma_f64_16x16x4f64 (wave w owns tiles
 // w, w + 4, ...); the partial goes to part[block] (lower tiles only), as an
 // ell x ell matrix or tile-major (the 128-wide CholeskyQR).
-// k_gram_fold: G(a, b) = sum over blocks in block order (deterministic), the
-// upper triangle mirrored.
+// k_gram_fold: G(a, b) = sum over the blocks' partials in a fixed order
+// (deterministic), the upper triangle mirrored.
 #include <algorithm>
 
 #include "dsk_internal.h"
@@ -81,36 +81,47 @@ __global__ void __launch_bounds__(256) k_gram_mfma(const T *__restrict__ X, int6
   }
 }
 
-// Sixteen partials are loaded before they are added (a fixed order: in
-// groups of sixteen, each group summed in order), so each thread keeps many
-// loads in flight instead of one.
+// Four threads (a quad) per entry: thread q sums the partials q, q + 4, ...
+// in order, sixteen loads in flight before they are added (in groups of
+// sixteen, each group summed in order), and the quad adds its four sums as
+// (s0 + s1) + (s2 + s3): a fixed order, so repeated runs give the same bytes.
 __global__ void __launch_bounds__(256) k_gram_fold(const double *__restrict__ part, int nparts, int ell,
                                                    double *__restrict__ G) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= ell * ell) return;
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  const int e = g >> 2, q = g & 3;
   const int a = e / ell, b = e - (e / ell) * ell;
-  if (a / 16 < b / 16) return;                 // an upper tile: written as the mirror
+  // an upper tile is written as the mirror
+  const bool live = e < ell * ell && a / 16 >= b / 16;
   const int64_t n2 = (int64_t)ell * ell;
   double s = 0.0;
-  int p = 0;
-  for (; p + 16 <= nparts; p += 16) {
-    double v[16];
+  if (live) {
+    int p = q;
+    for (; p + 60 < nparts; p += 64) {
+      double v[16];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = part[(int64_t)(p + u) * n2 + e];
-    double g = 0.0;
+      for (int u = 0; u < 16; ++u) v[u] = part[(int64_t)(p + 4 * u) * n2 + e];
+      double gs = 0.0;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) g += v[u];
-    s += g;
+      for (int u = 0; u < 16; ++u) gs += v[u];
+      s += gs;
+    }
+    for (; p < nparts; p += 4) s += part[(int64_t)p * n2 + e];
   }
-  for (; p < nparts; ++p) s += part[(int64_t)p * n2 + e];
-  G[e] = s;
-  if (a / 16 > b / 16) G[b * ell + a] = s;
+  s += wc::dpp_f64<0xB1>(s);   // lanes 2i, 2i + 1
+  s += wc::dpp_f64<0x4E>(s);   // the two pairs of the quad
+  if (live && q == 0) {
+    G[e] = s;
+    if (a / 16 > b / 16) G[b * ell + a] = s;
+  }
 }
 
 }  // namespace
 
+// Workgroups of the Gram: 256 rows each at least, at most two per CU of the
+// MI355X (512), so that one workgroup's MFMA chain runs while the other's
+// chunk is staged.
 int gram_mfma_blocks(int64_t rows) {
-  return (int)std::min<int64_t>(256, std::max<int64_t>(1, (rows + 255) / 256));
+  return (int)std::min<int64_t>(512, std::max<int64_t>(1, (rows + 255) / 256));
 }
 
 int launch_gram_mfma(hipStream_t st, const void *X, int f64, int64_t rows, int ell, double *G, double *part,
@@ -126,7 +137,7 @@ int launch_gram_mfma(hipStream_t st, const void *X, int f64, int64_t rows, int e
     hipLaunchKernelGGL((k_gram_mfma<float, false>), dim3(nblk), dim3(256), 0, st, (const float *)X, rows, ell, (int64_t)ell,
                        rpb, part);
   DSK_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_gram_fold, dim3((ell * ell + 255) / 256), dim3(256), 0, st, (const double *)part, nblk, ell, G);
+  hipLaunchKernelGGL(k_gram_fold, dim3((4 * ell * ell + 255) / 256), dim3(256), 0, st, (const double *)part, nblk, ell, G);
   DSK_TRY(hipGetLastError());
   return 0;
 }
