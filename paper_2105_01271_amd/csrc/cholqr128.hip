@@ -322,20 +322,24 @@ __global__ void __launch_bounds__(256) k_q8_apply(const T *Y, int64_t rows, int 
   const int64_t r0 = (int64_t)blockIdx.x * rpw, r1 = std::min<int64_t>(rows, r0 + rpw);
   for (int64_t c0 = r0; c0 < r1; c0 += RCH) {
     // this wave's 16 rows, FP64, zero padded (all loads in flight at once)
+    // (lane l takes columns l and l + 64 of every row: no index division)
     {
-      constexpr int SV = 16 * EMAX / 64;
-      T yv[SV];
+      T yv[16][2];
 #pragma unroll
-      for (int u = 0; u < SV; ++u) {
-        const int e = l + 64 * u, rr = e / ellp, c = e - rr * ellp;
-        const int64_t r = c0 + rb + rr;
-        yv[u] = (e < 16 * ellp && r < r1 && c < ell) ? Y[r * ell + c] : T(0);
-      }
+      for (int rr = 0; rr < 16; ++rr)
 #pragma unroll
-      for (int u = 0; u < SV; ++u) {
-        const int e = l + 64 * u, rr = e / ellp, c = e - rr * ellp;
-        if (e < 16 * ellp) YQ[(rb + rr) * LDQ + c] = (double)yv[u];
-      }
+        for (int h = 0; h < 2; ++h) {
+          const int c = l + 64 * h;
+          const int64_t r = c0 + rb + rr;
+          yv[rr][h] = (r < r1 && c < ell) ? Y[r * ell + c] : T(0);
+        }
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int c = l + 64 * h;
+          if (c < ellp) YQ[(rb + rr) * LDQ + c] = (double)yv[rr][h];
+        }
     }
     wc::wave_lds_sync();
     for (int J = 0; J < nb; ++J) {
@@ -367,14 +371,18 @@ __global__ void __launch_bounds__(256) k_q8_apply(const T *Y, int64_t rows, int 
       wc::wave_lds_sync();
     }
     // round this wave's rows to the output type (the Gram describes the stored Q)
-    for (int e = l; e < 16 * ellp; e += 64) {
-      const int rr = e / ellp, c = e - rr * ellp;
-      const int64_t r = c0 + rb + rr;
-      double *p = &YQ[(rb + rr) * LDQ + c];
-      const T v = (T)(*p);
-      *p = (double)v;
-      if (r < r1 && c < ell) Q[r * ell + c] = v;
-    }
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = l + 64 * h;
+        if (c >= ellp) continue;
+        const int64_t r = c0 + rb + rr;
+        double *p = &YQ[(rb + rr) * LDQ + c];
+        const T v = (T)(*p);
+        *p = (double)v;
+        if (r < r1 && c < ell) Q[r * ell + c] = v;
+      }
     if (part) {
       __syncthreads();
       gt::accum<RCH / 4>(YQ, LDQ, tl, acc);

@@ -35,28 +35,25 @@ __global__ void __launch_bounds__(256) k_gram_mfma(const T *__restrict__ X, int6
   gt::zero(acc);
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
   const int64_t r1 = std::min<int64_t>(rows, r0 + rows_per_blk);
-  // the next chunk is loaded into registers while the current one feeds the MFMAs
+  // the next chunk is loaded into registers while the current one feeds the
+  // MFMAs; thread t takes column t mod 128 of rows t / 128 + 2 u (no index
+  // division)
   constexpr int PF = GR * GMAX / 256;
+  static_assert(GMAX == 128 && PF * 2 == GR, "two rows of 128 columns per pass of the workgroup");
   T pf[PF];
-  const int tot = GR * ellp;
+  const int fc = t & (GMAX - 1), fr = t >> 7;
   auto fetch = [&](int64_t c0) {
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
-      const int e = t + 256 * u;
-      const int rr = e / ellp, c = e - rr * ellp;
-      const int64_t r = c0 + rr;
-      pf[u] = (e < tot && r < r1 && c < ell) ? X[r * ldx + c] : T(0);
+      const int64_t r = c0 + fr + 2 * u;
+      pf[u] = (r < r1 && fc < ell) ? X[r * ldx + fc] : T(0);
     }
   };
   if (r0 < r1) fetch(r0);
   for (int64_t c0 = r0; c0 < r1; c0 += GR) {
+    if (fc < ellp) {
 #pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      const int e = t + 256 * u;
-      if (e < tot) {
-        const int rr = e / ellp, c = e - rr * ellp;
-        sh[rr][c] = (double)pf[u];
-      }
+      for (int u = 0; u < PF; ++u) sh[fr + 2 * u][fc] = (double)pf[u];
     }
     __syncthreads();
     if (c0 + GR < r1) fetch(c0 + GR);

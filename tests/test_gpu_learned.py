@@ -173,12 +173,14 @@ def test_learned_restriction_against_direct_injection_at_held_out_diffusivities(
     # direct injection on the same (4, 4) grid (s = 4096) is the judge on those
     # trajectories and the fallback; then the rank-50 sketch SVD (q = 1) at three
     # held-out test diffusivities.  Measured: training lowers the projection loss
-    # on the validation trajectories by about a quarter against direct
-    # injection's, so the judge keeps the learned conv, but the rank-50 error at
-    # the held-out diffusivities stays within about 1.5% of direct injection's,
-    # better or worse depending on the training run (0.1185 to 0.1220 against
-    # 0.1209 at nu = 0.0061 over the settings tried; optimum 0.1098): no robust
-    # gain on this workload.  The assertions keep to what held in every run.
+    # on the validation trajectories by a quarter to a third against direct
+    # injection's, so the judge keeps the learned conv; the rank-50 error at the
+    # held-out diffusivities moves between 1% worse and 7% better than direct
+    # injection's depending on the training run (0.1128 to 0.1220 against
+    # 0.1209 at nu = 0.0061; optimum 0.1098; rounding-level changes in the
+    # library's reductions are enough to move a run within that range): no
+    # robust gain on this workload, and no loss beyond a few percent.  The
+    # assertions keep to what held in every run.
     from paper_2105_01271_amd import learned
     say("learned vs direct injection")
     dev = torch.device("cuda")
@@ -213,4 +215,4 @@ def test_learned_restriction_against_direct_injection_at_held_out_diffusivities(
     assert ll < ld and choice == "learned"
     gains = [1.0 - a / b for a, b in zip(e_sel, e_di)]
     say("  relative change of the rank-50 error against direct injection:", [f"{g:+.4f}" for g in gains])
-    assert all(abs(g) <= 0.03 for g in gains)
+    assert all(g >= -0.03 for g in gains)
