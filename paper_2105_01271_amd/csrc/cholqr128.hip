@@ -8,7 +8,7 @@
 //
 // A pass is three launches:
 //  * Gram partials of the block (gram64.hip, tile-major lower 16 x 16 tiles,
-//    one partial per 128 rows);
+//    one partial per 64 rows);
 //  * fold + factor: every workgroup sums 64 entries of the partials in a
 //    fixed order (four threads per entry, partials strided by four, then the
 //    four in order) and publishes them; the last workgroup to arrive factors
@@ -40,7 +40,7 @@ constexpr int NTM = NBM * (NBM + 1) / 2;  // lower tiles at most
 constexpr int TILE = 256;
 constexpr int PART = NTM * TILE;          // doubles of a (largest) partial
 constexpr int PMAX = 256;                 // partials at most
-constexpr int GRPB = 128;                 // rows per Gram partial (at least)
+constexpr int GRPB = 64;                  // rows per Gram partial (at least)
 constexpr int LDA = EMAX + 2;             // LDS row stride of the factor (conflict-free MFMA operand reads)
 constexpr int RCH = 64;                   // rows per apply chunk (16 per wave)
 constexpr int LDQ = EMAX + 2;             // LDS row stride of the apply chunk
