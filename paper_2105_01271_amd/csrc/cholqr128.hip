@@ -13,7 +13,7 @@
 //    fixed order (four threads per entry, partials strided by four, then the
 //    four in order) and publishes them; the last workgroup to arrive factors
 //    G = L L^T in LDS, blocked by 16 columns: one wave factors the diagonal
-//    block A_KK in registers (pivot columns broadcast as scalars, only 1 / d
+//    block A_KK in registers (pivot columns by DPP row broadcasts, only 1 / d
 //    on the chain from pivot to pivot) and inverts it, W_K = L_KK^{-1}; the
 //    four waves then form the panel below it, L_IK = A_IK W_K^T, on MFMA; the
 //    trailing tiles A_IJ -= L_IK L_JK^T go to three waves while the fourth
@@ -90,14 +90,37 @@ __device__ __forceinline__ void load_gram(const double *G, int ell, int nb, doub
   }
 }
 
+// Lane c of each row of 16 lanes, in every lane of that row (DPP
+// row_newbcast: a vector-register move, no scalar register on the way).
+__device__ __forceinline__ double row_bcast(double v, int c) {
+  switch (c) {
+    case 0: return wc::dpp_f64<0x150>(v);
+    case 1: return wc::dpp_f64<0x151>(v);
+    case 2: return wc::dpp_f64<0x152>(v);
+    case 3: return wc::dpp_f64<0x153>(v);
+    case 4: return wc::dpp_f64<0x154>(v);
+    case 5: return wc::dpp_f64<0x155>(v);
+    case 6: return wc::dpp_f64<0x156>(v);
+    case 7: return wc::dpp_f64<0x157>(v);
+    case 8: return wc::dpp_f64<0x158>(v);
+    case 9: return wc::dpp_f64<0x159>(v);
+    case 10: return wc::dpp_f64<0x15A>(v);
+    case 11: return wc::dpp_f64<0x15B>(v);
+    case 12: return wc::dpp_f64<0x15C>(v);
+    case 13: return wc::dpp_f64<0x15D>(v);
+    case 14: return wc::dpp_f64<0x15E>(v);
+    default: return wc::dpp_f64<0x15F>(v);
+  }
+}
+
 // Diagonal block K by the calling wave: lane i (mod 16) holds row i of the
-// trailing-updated A_KK.  Pivot by pivot, the pivot column reaches every lane
-// as scalars (v_readlane), so no LDS round trip sits on the chain from one
-// pivot to the next; A(i, c) -= A(i, p) A(c, p) / d needs no square root on
-// it.  Then W_K = L_KK^{-1} by forward substitution, column c in lane c, the
-// entries of L read back from LDS at uniform addresses.  Lanes 0 .. 15 write L_KK (zero above
-// the diagonal) to A, W_K to Wl and to its factor tile.  Padded pivots
-// (p >= ell) are identity columns.
+// trailing-updated A_KK (each row of 16 lanes a copy).  Pivot by pivot, the
+// pivot column reaches every lane by DPP row broadcasts, so no LDS round trip
+// sits on the chain from one pivot to the next; A(i, c) -= A(i, p) A(c, p) / d
+// needs no square root on it.  Then W_K = L_KK^{-1} by forward substitution,
+// column c in lane c, the entries of L read back from LDS at uniform
+// addresses.  Lanes 0 .. 15 write L_KK (zero above the diagonal) to A, W_K to
+// Wl and to its factor tile.  Padded pivots (p >= ell) are identity columns.
 __device__ __forceinline__ bool diag_block(double *A, double *Wl, double *Mf, int K, int ell, double thr) {
   const int l = threadIdx.x & 63, i = l & 15, c0 = 16 * K;
   double a[16];
@@ -108,13 +131,13 @@ __device__ __forceinline__ bool diag_block(double *A, double *Wl, double *Mf, in
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const bool live = c0 + j < ell;
-    const double dp = wc::readlane_f64(a[j], j);
+    const double dp = row_bcast(a[j], j);
     const double d = live ? dp : 1.0;
     ok = ok & (!live | ((d > thr) & isfinite(d)));
     const double inv = wc::rcp_nr(d), rs = wc::rsq_nr(d);
     const double t = a[j] * inv;
 #pragma unroll
-    for (int c = j + 1; c < 16; ++c) a[c] = fma(-t, wc::readlane_f64(a[j], c), a[c]);
+    for (int c = j + 1; c < 16; ++c) a[c] = fma(-t, row_bcast(a[j], c), a[c]);
     a[j] = live ? (i > j ? a[j] * rs : (i == j ? d * rs : 0.0)) : (i == j ? 1.0 : 0.0);
     rsv[j] = live ? rs : 1.0;
   }

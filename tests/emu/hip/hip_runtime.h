@@ -102,6 +102,7 @@ inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int rm, int b
   if (ctrl < 0x100) { s = (lane & ~3) + ((ctrl >> (2 * (lane & 3))) & 3); gsz = 4; }
   else if (ctrl == 0x140) { s = (lane & ~15) + 15 - (lane & 15); gsz = 16; }
   else if (ctrl == 0x141) { s = (lane & ~7) + 7 - (lane & 7); gsz = 8; }
+  else if (ctrl >= 0x150 && ctrl <= 0x15F) { s = (lane & ~15) + (ctrl & 15); gsz = 16; }   // row_newbcast
   else { simt::die("unsupported dpp control"); }
   simt::put(0, src);
   simt::group_sync(gsz);
