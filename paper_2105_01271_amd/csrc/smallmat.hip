@@ -390,7 +390,13 @@ void tsmm_r(hipStream_t st, const T *X, int64_t rows, int ell, int64_t ldx, cons
 template <typename T, int KB>
 void tsmm_t(hipStream_t st, const T *X, int64_t rows, int ell, int64_t ldx, const double *M, int ldm, int kout,
             const double *colscale, T *out, int64_t ldo) {
-  // short inputs: 16- or 32-row blocks so that more workgroups share the work
+  // short inputs: 8-, 16- or 32-row blocks so that more workgroups share the work
+  if constexpr (KB >= 32) {
+    if (rows < 8 * 256) {
+      tsmm_r<T, KB, 8>(st, X, rows, ell, ldx, M, ldm, kout, colscale, out, ldo);
+      return;
+    }
+  }
   if (rows < 16 * 256 && KB >= 16) tsmm_r<T, KB, 16>(st, X, rows, ell, ldx, M, ldm, kout, colscale, out, ldo);
   else if (rows < 64 * 256) tsmm_r<T, KB, 32>(st, X, rows, ell, ldx, M, ldm, kout, colscale, out, ldo);
   else tsmm_r<T, KB, ts_rows<T>()>(st, X, rows, ell, ldx, M, ldm, kout, colscale, out, ldo);
