@@ -21,44 +21,58 @@ __global__ void k_scale(void *x, int f64, int64_t count, double a) {
   }
 }
 
-// sigma from eigenvalues (is_lam) or singular values; S out; V column scale;
-// info scalars: [0] = sum of all sigma^2 (= ||B||_F^2), [1] = sigma_{k+1}.
-// When Mv is given (F32 path) it also writes Mv = UB(:, :k) diag(colscale) as f32 (ell x k),
-// the right factor of V = B^T Mv.
+// sigma_c from eigenvalues (is_lam) or singular values
+__device__ __forceinline__ double finish_sigma(const double *vals, int is_lam, int c) {
+  const double v = vals[c];
+  return is_lam ? sqrt(v > 0.0 ? v : 0.0) : v;
+}
+
+// the column scale of singular value c: its sign, divided by sigma_c when
+// asked (zero for a negligible sigma_c)
+__device__ __forceinline__ double finish_scale(const double *vals, int is_lam, const double *sign, int divide,
+                                               int c) {
+  const double sg = finish_sigma(vals, is_lam, c), s1 = finish_sigma(vals, is_lam, 0);
+  double cs = sign ? sign[c] : 1.0;
+  if (divide) cs = (sg > 1e-300 && sg > 1e-13 * s1) ? cs / sg : 0.0;
+  return cs;
+}
+
+// Block 0: S, the V column scales and the info scalars ([0] = sum of all
+// sigma^2 = ||B||_F^2, [1] = sigma_{k+1}), one thread per singular value
+// (ell <= 128).  With Mv (FP32 path), every block also writes 256 entries of
+// Mv = U_B(:, :k) diag(scale) in FP32 (ell x k, the right factor of
+// V = B^T Mv; grid ceil(ell k / 256) blocks, each entry's scale recomputed by
+// the same operations as block 0's).
 __global__ void __launch_bounds__(256) k_finish(const double *__restrict__ vals, int is_lam, int ell, int k,
                                                 const double *__restrict__ sign, int divide, double *__restrict__ S,
                                                 double *__restrict__ colscale, double *__restrict__ info,
                                                 const double *__restrict__ UB, float *__restrict__ Mv) {
-  __shared__ double cs_sh[128], sq_sh[128];
   const int t = threadIdx.x;
-  // one thread per singular value (ell <= 128)
+  if (Mv) {
+    const int e = blockIdx.x * 256 + t;
+    if (e < ell * k) {
+      const int i = e / k, c = e - (e / k) * k;
+      Mv[e] = (float)(UB[i * ell + c] * finish_scale(vals, is_lam, sign, divide, c));
+    }
+  }
+  if (blockIdx.x != 0) return;
+  __shared__ double sq_sh[128];
   double sg = 0.0;
   if (t < ell) {
-    const double v = vals[t];
-    sg = is_lam ? sqrt(v > 0.0 ? v : 0.0) : v;
+    sg = finish_sigma(vals, is_lam, t);
     sq_sh[t] = sg * sg;
   }
-  const double v0 = vals[0];
-  const double s1 = is_lam ? sqrt(v0 > 0.0 ? v0 : 0.0) : v0;
   if (t < k) {
     S[t] = sg;
-    double cs = sign ? sign[t] : 1.0;
-    if (divide) cs = (sg > 1e-300 && sg > 1e-13 * s1) ? cs / sg : 0.0;
-    colscale[t] = cs;
-    cs_sh[t] = cs;
+    colscale[t] = finish_scale(vals, is_lam, sign, divide, t);
   }
   __syncthreads();
   if (t == 0) {
     double tot = 0.0;   // fixed order
     for (int j = 0; j < ell; ++j) tot += sq_sh[j];
     info[0] = tot;
-    info[1] = (ell > k) ? (is_lam ? sqrt(vals[k] > 0.0 ? vals[k] : 0.0) : vals[k]) : 0.0;
+    info[1] = (ell > k) ? finish_sigma(vals, is_lam, k) : 0.0;
   }
-  if (Mv)
-    for (int e = t; e < ell * k; e += 256) {
-      const int i = e / k, c = e - (e / k) * k;
-      Mv[e] = (float)(UB[i * ell + c] * cs_sh[c]);
-    }
 }
 
 void launch_scale(hipStream_t st, void *x, int f64, int64_t count, double a) {
@@ -460,8 +474,8 @@ int svd_run(dsk_handle *h, const void *A, int32_t dtype, int64_t m, int64_t n, i
       DSK_RET(launch_core_eig_tri(st, GB, L, lam, UB, ews, h->dflags));
       DSK_RET(launch_tsmm(st, Q, 0, m, L, L, UB, L, k, nullptr, Ua, k));
       DSK_RET(launch_sign_fix(st, Ua, 0, m, k, sign));
-      hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, st, lam, 1, L, k, sign, 1, S, colscale, dinfo,
-                         (const double *)UB, Mv);
+      hipLaunchKernelGGL(k_finish, dim3((unsigned)((L * k + 255) / 256)), dim3(256), 0, st, lam, 1, L, k, sign, 1, S,
+                         colscale, dinfo, (const double *)UB, Mv);
       // V = B^T U_B(:, :k) diag(sign / sigma) on the MFMA stream kernel (n rows, K = ell)
       DSK_RET(launch_stream_nn(st, Bt, DSK_F32, n, L, L, Mv, k, Va, k, od.mode, sws, h->cu_count));
       if (refine)
