@@ -304,7 +304,17 @@ __global__ void __launch_bounds__(256) k_sign_fix(T *__restrict__ U, int64_t m, 
   __shared__ int64_t bi[256];
   double best = -1.0;
   int64_t idx = 0;
-  for (int64_t i = threadIdx.x; i < m; i += 256) {
+  // eight loads in flight per thread, compared in ascending row order
+  int64_t i = threadIdx.x;
+  for (; i + 7 * 256 < m; i += 8 * 256) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = fabs((double)U[(i + 256 * u) * k + j]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (v[u] > best) { best = v[u]; idx = i + 256 * u; }
+  }
+  for (; i < m; i += 256) {
     const double v = fabs((double)U[i * k + j]);
     if (v > best) { best = v; idx = i; }
   }
