@@ -324,10 +324,26 @@ __global__ void __launch_bounds__(64 * SOLVE_WAVES) k_id_solve(const double *__r
   double *R1t = dyn;             // R1t[b*k + a] = R_1[a][b] = Rk[a, piv[b]] (a <= b)
   double *rd = dyn + k * k;      // 1 / R_1[b][b], 0 for a negligible pivot
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  for (int e = t; e < k * k; e += 64 * SOLVE_WAVES) {
-    const int b = e / k, a = e - (e / k) * k;
-    const int64_t pb = piv[b];
-    R1t[e] = (a <= b && pb >= 0 && pb < m) ? Rk[(int64_t)a * m + pb] : 0.0;
+  // the gathered R_1 entries, eight loads in flight per thread
+  constexpr int NTS = 64 * SOLVE_WAVES;
+  for (int e0 = 0; e0 < k * k; e0 += 8 * NTS) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + t + NTS * u;
+      double x = 0.0;
+      if (e < k * k) {
+        const int b = e / k, a = e - b * k;
+        const int64_t pb = piv[b];
+        if (a <= b && pb >= 0 && pb < m) x = Rk[(int64_t)a * m + pb];
+      }
+      v[u] = x;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + t + NTS * u;
+      if (e < k * k) R1t[e] = v[u];
+    }
   }
   __syncthreads();
   const double dmax = fabs(R1t[0]);
